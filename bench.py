@@ -1,0 +1,178 @@
+"""Throughput of the two-phase SpGEMM hot path on one MI355X.
+
+One step = one full product C = A*A through the C ABI: symbolic (row
+analysis, binning, row accumulators, row-pointer scan, the nnz(C) read-back)
+then numeric (values, sorted columns) into caller-allocated C arrays.  The
+workload is the 3D 27-point stencil on a 100^3 grid (1M rows, 26.46M nonzeros,
+FP64 values uniform in [-1, 1], diagonal 27), synthetic and seeded.
+
+Printed: one JSON line with GFLOP/s (2 x multiply-adds / step time), C-nnz/s,
+the compulsory-byte HBM fraction, a roofline entry for the dominant kernel
+(the numeric accumulator class that takes the most time, timed with HIP events
+recorded by the library on its own stream) and the CPU oracle timed on a
+bounded row sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "SpGEMM GFLOP/s + C-nnz/s + HBM GB/s fraction; learned/batched vs plain"
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("spg_accum.hip", "spg_internal.h"):
+        with open(os.path.join(ROOT, "paper_2103_11991_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+        ent = d.get(kernel)
+        if not ent or ent.get("source_sha") != kernel_source_sha():
+            return None
+        return float(ent["hbm_bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(A, target_s: float = 12.0):
+    """The oracle (symbolic + numeric) on a contiguous interior row range of the
+    same product, sized to about target_s seconds; reported as GFLOP/s."""
+    import oracle
+    from paper_2103_11991_amd import gen
+    ppr = gen.products_per_row(A, A)
+    mid = A.m // 2
+    probe = 4096
+    t0 = time.perf_counter()
+    oracle.spgemm(A, A, mid, mid + probe)
+    dt = max(time.perf_counter() - t0, 1e-3)
+    rows = int(min(A.m - mid, max(probe, probe * target_s / dt)))
+    t0 = time.perf_counter()
+    rp, _, _, _ = oracle.spgemm(A, A, mid, mid + rows)
+    dt = time.perf_counter() - t0
+    prods = int(ppr[mid:mid + rows].sum())
+    return {"value": round(2.0 * prods / dt / 1e9, 4), "unit": "GFLOP/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"rows {mid}..{mid + rows - 1} of the same product ({rows} rows, {prods} multiply-adds, "
+                      f"nnz {int(rp[-1])}), symbolic+numeric, {dt:.2f} s wall",
+            "c_nnz_per_s": round(int(rp[-1]) / dt, 1)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--grid", type=int, default=100, help="stencil grid edge (100 = the 1M-row workload)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(1)
+
+    import torch
+    from paper_2103_11991_amd import gen
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
+
+    torch.cuda.set_device(0)
+    N = args.grid
+    A = gen.stencil27(N, seed=2)
+    products = int(gen.products_per_row(A, A).sum())
+    dA = DeviceCsr.from_host(A)
+    op = SpGEMM(dA, dA, timing=1)
+    stream = op.stream
+
+    def step():
+        rp, nnz = op.symbolic()
+        col, val = op.numeric()
+        return nnz
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    sym_ms, num_ms, dom = [], [], {}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        nnz = step()
+        st = op.stats()  # waits for this step's events
+        sym_ms.append(st["sym_ms"])
+        num_ms.append(st["num_ms"])
+        for c, ms in enumerate(st["num_class_ms"]):
+            if st["num_rows"][c]:
+                dom.setdefault(c, []).append(ms)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    ms_step = 1e3 * t_total / args.steps
+
+    # numeric alone (symbolic reused), the repeated-product path
+    col, val = op.numeric()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        op.numeric(out_col=col, out_val=val)
+    torch.cuda.synchronize()
+    ms_num_only = 1e3 * (time.perf_counter() - t0) / args.steps
+
+    st = op.stats()
+    nnz_a = A.nnz
+    eb = 8
+    # compulsory bytes of one full product: A and B structure + values read
+    # once, C written once, row pointers and per-row bookkeeping
+    comp = (nnz_a * (4 + eb)) * 2 + nnz * (4 + eb) + (A.m + 1) * 4 * 3 + A.m * 4 * 4
+    gflops = 2.0 * products / (ms_step * 1e-3) / 1e9
+
+    dcls = max(dom, key=lambda c: np.mean(dom[c]))
+    dom_ms = float(np.mean(dom[dcls]))
+    rows_c = st["num_rows"][dcls]
+    frac_prod = st["num_products"][dcls] / max(st["products"], 1)
+    alg_bytes = (st["num_a_nnz"][dcls] * (4 + eb) + st["num_c_nnz"][dcls] * (4 + eb)
+                 + frac_prod * A.nnz * (4 + eb) + rows_c * 12)
+    achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
+    kname = f"numeric class {dcls} (mode {'hashed' if dcls >= 10 else 'direct'}, tier {dcls % 10})"
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(f"num_class_{dcls}"),
+            "kernel": kname, "launch_ms": round(dom_ms, 4), "algorithmic_bytes": int(alg_bytes)}
+
+    out = {
+        "metric": METRIC, "value": round(gflops, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"C=A*A, A = 3D 27-point stencil on {N}^3 (FP64 U[-1,1], diagonal 27), "
+                               "plain two-phase (upper-bound binning)",
+                   "rows": A.m, "nnz_a": nnz_a, "nnz_c": int(nnz), "multiply_adds": products},
+        "c_nnz_per_s": round(nnz / (ms_step * 1e-3), 1),
+        "hbm_frac_compulsory": round(comp / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "t_sym_ms": round(float(np.median(sym_ms)), 4), "t_num_ms": round(float(np.median(num_ms)), 4),
+        "t_num_reuse_ms": round(ms_num_only, 4),
+        "gflops_numeric_reuse": round(2.0 * products / (ms_num_only * 1e-3) / 1e9, 2),
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(A)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

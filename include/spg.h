@@ -1,0 +1,201 @@
+/*
+ * spg -- two-phase CSR sparse matrix-matrix multiply C = A*B on MI355X (gfx950).
+ *
+ * The operation is the one of the Kokkos Kernels paper, section 2.2: A is
+ * m x n, B is n x k, C is m x k, all in compressed row storage (CRS, section
+ * 2: row pointer, column indices, values).  C(i,:) is the sum over the
+ * nonzeros j of A(i,:) of A(i,j) * B(j,:) (section 2.2.1, Eq. (1)).  The work
+ * is split in the paper's two phases (section 2.2.1):
+ *
+ *   symbolic  -- the number of nonzeros of each row of C, scanned into the row
+ *                pointer; its last entry is nnz(C).  The caller then allocates
+ *                the column-index and value arrays of size nnz(C);
+ *   numeric   -- the column indices (ascending within each row) and values.
+ *
+ * A symbolic result is reused by every later numeric call while the sparsity
+ * patterns stay the same (section 2: the split of symbolic and numeric work),
+ * so only values may change between numeric calls.  Runtime choices travel
+ * in a handle (section 6, the handle passed to the dispatch layer).
+ *
+ * Conventions shared by every call:
+ *   - indices and row pointers are int32; nnz(C) must stay below 2^31;
+ *   - "device" pointers are HIP device memory of the handle's device, "host"
+ *     pointers are ordinary host memory;
+ *   - the caller owns every buffer it passes in; the library never returns
+ *     memory.  Input structure arrays are borrowed: they must stay valid and
+ *     unchanged from spg_set_matrices until the last spg_numeric;
+ *   - input rows may be unsorted and may repeat a column (repeats add up);
+ *     explicit zeros produced by cancellation are kept in C;
+ *   - errors are reported as spg_status; no C++ exception crosses this ABI.
+ *     spg_last_error returns a message for the last failing call on a handle;
+ *   - all GPU work runs on the handle's stream, in order.  Only spg_symbolic
+ *     waits for the device (it must return nnz(C) to the host).  One handle
+ *     must not be used from two host threads at once.
+ */
+#ifndef SPG_H
+#define SPG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spg_handle_s* spg_handle;
+
+typedef enum {
+    SPG_OK = 0,
+    SPG_ERR_ARG = 1,          /* null pointer, negative size, bad option value */
+    SPG_ERR_SHAPE = 2,        /* inconsistent dimensions */
+    SPG_ERR_STATE = 3,        /* call out of order, e.g. numeric before symbolic */
+    SPG_ERR_INDEX = 4,        /* row pointer not monotone / not ending at nnz, or a
+                                 column index out of range (always checked) */
+    SPG_ERR_OVERFLOW = 5,     /* nnz(C) >= 2^31 */
+    SPG_ERR_ALLOC = 6,        /* device or pinned-host allocation failed */
+    SPG_ERR_HIP = 7,          /* a HIP runtime call failed */
+    SPG_ERR_UNSUPPORTED = 8   /* feature not available on this device */
+} spg_status;
+
+typedef enum { SPG_F32 = 0, SPG_F64 = 1 } spg_dtype;
+
+/* Options for spg_set_option. */
+typedef enum {
+    /* how symbolic sizes each row's accumulator: 0 = exact upper bound from
+       the row's products and column range (default), 1 = learned predictor
+       set by spg_set_mlp, with overflow detection and an exact retry */
+    SPG_OPT_BINNING = 0,
+    /* record HIP events around every launch (default 0); read with spg_get_stats */
+    SPG_OPT_TIMING = 1,
+    /* force every row of both phases into one accumulator class (-1 = off);
+       class = mode * 10 + tier, see spg_stats.  Rows that do not fit the
+       forced class are placed in the smallest class that fits. */
+    SPG_OPT_FORCE_CLASS = 2,
+    /* products per lane used to size the thread group of a row (default 16) */
+    SPG_OPT_WORK_PER_LANE = 3,
+    /* log2 safety margin added to the predictor's output, times 1000 (default 500) */
+    SPG_OPT_MLP_MARGIN_MILLI = 4,
+    /* lanes that read one B row together, 0 = from B's mean row length (default) */
+    SPG_OPT_VECTOR_WIDTH = 5,
+    /* largest number of occupied column blocks for which numeric uses a
+       hashed block table with an explicit sort (default 64) */
+    SPG_OPT_HASH_MAX_BLOCKS = 6,
+    /* LDS bytes per row at which the global-memory path takes over (power of
+       two, 1024..65536, default 65536) */
+    SPG_OPT_LDS_LIMIT = 7,
+    /* keep each row's predictor features after symbolic even with upper-bound
+       binning, so spg_export_rows can return them (default 0) */
+    SPG_OPT_KEEP_FEATURES = 8
+} spg_option;
+
+#define SPG_NTIER 10
+#define SPG_NCLASS 20
+
+/* Statistics of the last symbolic and numeric calls (spg_get_stats). */
+typedef struct {
+    int32_t size;                       /* sizeof(spg_stats), set by the library */
+    int32_t m, n, k;
+    int64_t products;                   /* sum over rows of the B-row lengths touched = multiply-adds */
+    int64_t nnz_c;
+    int32_t sym_rows[SPG_NCLASS];       /* rows per symbolic accumulator class */
+    int32_t num_rows[SPG_NCLASS];       /* rows per numeric accumulator class */
+    int64_t num_a_nnz[SPG_NCLASS];      /* A nonzeros of the rows in each numeric class */
+    int64_t num_c_nnz[SPG_NCLASS];      /* C nonzeros written by each numeric class */
+    int64_t num_products[SPG_NCLASS];   /* multiply-adds of each numeric class */
+    int32_t empty_rows;                 /* rows of C with no products */
+    int32_t retried_rows;               /* learned binning: rows whose table overflowed */
+    int32_t mispredicted_rows;          /* learned binning: predicted class != class of the true size */
+    int32_t binning;                    /* SPG_OPT_BINNING of the last symbolic call */
+    float sym_ms;                       /* GPU time of the last symbolic call (timing on) */
+    float num_ms;                       /* GPU time of the last numeric call (timing on) */
+    float sym_class_ms[SPG_NCLASS];     /* per symbolic class launch (timing on) */
+    float num_class_ms[SPG_NCLASS];     /* per numeric class launch (timing on) */
+    float analysis_ms;                  /* row analysis and binning (timing on) */
+    float scan_ms;                      /* row-pointer scan (timing on) */
+    float mlp_ms;                       /* predictor inference (timing on) */
+} spg_stats;
+
+/* Human-readable name of a status code (static string). */
+const char* spg_status_string(spg_status s);
+
+/* Message describing the last error on h (valid until the next call on h). */
+const char* spg_last_error(spg_handle h);
+
+/* Creates a handle bound to the current HIP device and to `hip_stream`
+   (a hipStream_t; NULL = the default stream).  *h receives the handle. */
+spg_status spg_create(spg_handle* h, void* hip_stream);
+
+/* Releases every buffer the handle owns. Null is accepted. */
+spg_status spg_destroy(spg_handle h);
+
+/* Rebinds the handle to another stream (later calls run there). */
+spg_status spg_set_stream(spg_handle h, void* hip_stream);
+
+/* Sets A (m x n) and B (n x k) structure, borrowed device arrays:
+   a_row_ptr[m+1], a_col_idx[a_nnz], b_row_ptr[n+1], b_col_idx[b_nnz].
+   `dt` is the value type later passed to spg_numeric.  Invalidates any
+   previous symbolic result.  Index validity is checked by spg_symbolic. */
+spg_status spg_set_matrices(spg_handle h, spg_dtype dt, int32_t m, int32_t n, int32_t k,
+                            const int32_t* a_row_ptr, const int32_t* a_col_idx, int64_t a_nnz,
+                            const int32_t* b_row_ptr, const int32_t* b_col_idx, int64_t b_nnz);
+
+/* Symbolic phase (section 2.2.1): writes C's row pointer into the caller's
+   device array c_row_ptr[m+1] (c_row_ptr[0] = 0) and nnz(C) into *nnz_c
+   (host).  Waits for the stream.  c_row_ptr is borrowed by the handle and
+   must stay valid and unchanged until the last spg_numeric.  Returns
+   SPG_ERR_INDEX for a malformed input and SPG_ERR_OVERFLOW if nnz(C) >= 2^31. */
+spg_status spg_symbolic(spg_handle h, int32_t* c_row_ptr, int64_t* nnz_c);
+
+/* Numeric phase (section 2.2.1): fills the caller's device arrays
+   c_col_idx[nnz(C)] (ascending within each row) and c_vals[nnz(C)] from the
+   device values a_vals[a_nnz] and b_vals[b_nnz] of the handle's dtype.
+   Values may differ from call to call; the structure must not.  Asynchronous:
+   returns once the work is queued.  SPG_ERR_STATE without a symbolic result. */
+spg_status spg_numeric(spg_handle h, const void* a_vals, const void* b_vals,
+                       int32_t* c_col_idx, void* c_vals);
+
+/* Sets an spg_option (see above). */
+spg_status spg_set_option(spg_handle h, int32_t opt, int64_t val);
+
+/* Installs the learned row-size predictor: `nw` = 1217 host floats laid out
+   as W1[32][3], b1[32], W2[32][32], b2[32], w3[32], b3 (row-major).  The
+   network maps (log2(1+len), log2(1+ub), log2(1+mx)) of a row -- the length
+   of A's row, the sum and the max of the B row lengths it touches -- to
+   log2(1 + number of occupied 32-column blocks) of C's row. */
+spg_status spg_set_mlp(spg_handle h, const float* w, int32_t nw);
+
+/* Copies statistics of the last calls into *out (host); `size` = sizeof(spg_stats). */
+spg_status spg_get_stats(spg_handle h, spg_stats* out, int32_t size);
+
+/* After spg_symbolic: training rows for the predictor.  Writes, into the
+   caller's device arrays, x[m*3] (FP32 features as in spg_set_mlp) and
+   y[m] (FP32 log2(1 + occupied 32-column blocks)), and row_nnz[m] (int32,
+   may be NULL).  Rows with no products get y = 0. */
+spg_status spg_export_rows(spg_handle h, float* x, float* y, int32_t* row_nnz);
+
+/* ---- learned predictor kernels (section-free: the paper has no network) ----
+   All pointers are device pointers; `stream` is a hipStream_t (NULL = default).
+   w: 1217 FP32 weights as in spg_set_mlp; x: rows x 3 features. */
+
+/* y[rows] = network(x); if act != NULL also stores the activations needed by
+   backward: act[rows * 64] = (z1[32], z2[32]) per row. */
+spg_status spg_mlp_forward(void* stream, const float* w, const float* x, int32_t rows,
+                           float* y, float* act);
+
+/* dw[1217] = sum over rows of dy[r] * d y[r] / d w, from the activations of
+   spg_mlp_forward.  dw is overwritten. */
+spg_status spg_mlp_backward(void* stream, const float* w, const float* x, const float* act,
+                            const float* dy, int32_t rows, float* dw);
+
+/* Trains w_inout (device, 1217 floats) in place with minibatch Adam
+   (beta1 0.9, beta2 0.999, eps 1e-8) on the mean squared error between the
+   network and y, visiting x/y rows in the given order, `batch` rows per step,
+   for `epochs` passes.  loss_out (device, may be NULL) receives the mean
+   loss of each epoch (`epochs` floats).  Asynchronous on `stream`. */
+spg_status spg_mlp_train(void* stream, const float* x, const float* y, int32_t rows,
+                         int32_t epochs, int32_t batch, float lr, float* w_inout, float* loss_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPG_H */

@@ -1,0 +1,156 @@
+"""ctypes binding of libspg.so: one Python function per C entry point, same names.
+
+Argument marshalling only: pointers are passed as integers (device addresses
+from ``tensor.data_ptr()``, streams from ``torch.cuda.Stream.cuda_stream``),
+every failing status raises :class:`SpgError` with the library's message.
+There is no fallback: if the library was not built, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libspg.so")
+
+SPG_F32, SPG_F64 = 0, 1
+OPT = {
+    "binning": 0, "timing": 1, "force_class": 2, "work_per_lane": 3, "mlp_margin_milli": 4,
+    "vector_width": 5, "hash_max_blocks": 6, "lds_limit": 7, "keep_features": 8,
+}
+NTIER, NCLASS = 10, 20
+STATUS = ["SPG_OK", "SPG_ERR_ARG", "SPG_ERR_SHAPE", "SPG_ERR_STATE", "SPG_ERR_INDEX", "SPG_ERR_OVERFLOW",
+          "SPG_ERR_ALLOC", "SPG_ERR_HIP", "SPG_ERR_UNSUPPORTED"]
+EXPORTS = ["spg_status_string", "spg_last_error", "spg_create", "spg_destroy", "spg_set_stream",
+           "spg_set_matrices", "spg_symbolic", "spg_numeric", "spg_set_option", "spg_set_mlp", "spg_get_stats",
+           "spg_export_rows", "spg_mlp_forward", "spg_mlp_backward", "spg_mlp_train"]
+
+
+class SpgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        self.status = status
+        self.status_name = STATUS[status] if 0 <= status < len(STATUS) else str(status)
+        super().__init__(f"{self.status_name}: {msg}")
+
+
+class spg_stats(ctypes.Structure):
+    _fields_ = [
+        ("size", ctypes.c_int32), ("m", ctypes.c_int32), ("n", ctypes.c_int32), ("k", ctypes.c_int32),
+        ("products", ctypes.c_int64), ("nnz_c", ctypes.c_int64),
+        ("sym_rows", ctypes.c_int32 * NCLASS), ("num_rows", ctypes.c_int32 * NCLASS),
+        ("num_a_nnz", ctypes.c_int64 * NCLASS), ("num_c_nnz", ctypes.c_int64 * NCLASS),
+        ("num_products", ctypes.c_int64 * NCLASS),
+        ("empty_rows", ctypes.c_int32), ("retried_rows", ctypes.c_int32), ("mispredicted_rows", ctypes.c_int32),
+        ("binning", ctypes.c_int32), ("sym_ms", ctypes.c_float), ("num_ms", ctypes.c_float),
+        ("sym_class_ms", ctypes.c_float * NCLASS), ("num_class_ms", ctypes.c_float * NCLASS),
+        ("analysis_ms", ctypes.c_float), ("scan_ms", ctypes.c_float), ("mlp_ms", ctypes.c_float),
+    ]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads libspg.so from the package directory (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -m paper_2103_11991_amd._build)")
+    L = ctypes.CDLL(LIB_PATH)
+    p, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+    sig = {
+        "spg_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        "spg_last_error": ([p], ctypes.c_char_p),
+        "spg_create": ([ctypes.POINTER(p), p], ctypes.c_int),
+        "spg_destroy": ([p], ctypes.c_int),
+        "spg_set_stream": ([p, p], ctypes.c_int),
+        "spg_set_matrices": ([p, ctypes.c_int, i32, i32, i32, p, p, i64, p, p, i64], ctypes.c_int),
+        "spg_symbolic": ([p, p, ctypes.POINTER(i64)], ctypes.c_int),
+        "spg_numeric": ([p, p, p, p, p], ctypes.c_int),
+        "spg_set_option": ([p, i32, i64], ctypes.c_int),
+        "spg_set_mlp": ([p, p, i32], ctypes.c_int),
+        "spg_get_stats": ([p, ctypes.POINTER(spg_stats), i32], ctypes.c_int),
+        "spg_export_rows": ([p, p, p, p], ctypes.c_int),
+        "spg_mlp_forward": ([p, p, p, i32, p, p], ctypes.c_int),
+        "spg_mlp_backward": ([p, p, p, p, p, i32, p], ctypes.c_int),
+        "spg_mlp_train": ([p, p, p, i32, i32, i32, f32, p, p], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _check(rc: int, h=None):
+    if rc != 0:
+        msg = load().spg_last_error(h).decode() if h else ""
+        raise SpgError(rc, msg or STATUS[rc] if 0 <= rc < len(STATUS) else str(rc))
+
+
+def spg_status_string(s: int) -> str:
+    return load().spg_status_string(s).decode()
+
+
+def spg_create(stream: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(load().spg_create(ctypes.byref(h), stream or None))
+    return h.value
+
+
+def spg_destroy(h: int) -> None:
+    _check(load().spg_destroy(h))
+
+
+def spg_set_stream(h: int, stream: int) -> None:
+    _check(load().spg_set_stream(h, stream or None), h)
+
+
+def spg_set_matrices(h: int, dtype: int, m: int, n: int, k: int, a_row_ptr: int, a_col_idx: int, a_nnz: int,
+                     b_row_ptr: int, b_col_idx: int, b_nnz: int) -> None:
+    _check(load().spg_set_matrices(h, dtype, m, n, k, a_row_ptr or None, a_col_idx or None, a_nnz,
+                                   b_row_ptr or None, b_col_idx or None, b_nnz), h)
+
+
+def spg_symbolic(h: int, c_row_ptr: int) -> int:
+    nnz = ctypes.c_int64(-1)
+    _check(load().spg_symbolic(h, c_row_ptr or None, ctypes.byref(nnz)), h)
+    return nnz.value
+
+
+def spg_numeric(h: int, a_vals: int, b_vals: int, c_col_idx: int, c_vals: int) -> None:
+    _check(load().spg_numeric(h, a_vals or None, b_vals or None, c_col_idx or None, c_vals or None), h)
+
+
+def spg_set_option(h: int, opt, val: int) -> None:
+    opt = OPT[opt] if isinstance(opt, str) else int(opt)
+    _check(load().spg_set_option(h, opt, int(val)), h)
+
+
+def spg_set_mlp(h: int, w_host_ptr: int, nw: int) -> None:
+    _check(load().spg_set_mlp(h, w_host_ptr, nw), h)
+
+
+def spg_get_stats(h: int) -> spg_stats:
+    st = spg_stats()
+    _check(load().spg_get_stats(h, ctypes.byref(st), ctypes.sizeof(spg_stats)), h)
+    return st
+
+
+def spg_export_rows(h: int, x: int, y: int, row_nnz: int = 0) -> None:
+    _check(load().spg_export_rows(h, x or None, y or None, row_nnz or None), h)
+
+
+def spg_mlp_forward(stream: int, w: int, x: int, rows: int, y: int, act: int = 0) -> None:
+    _check(load().spg_mlp_forward(stream or None, w, x, rows, y, act or None))
+
+
+def spg_mlp_backward(stream: int, w: int, x: int, act: int, dy: int, rows: int, dw: int) -> None:
+    _check(load().spg_mlp_backward(stream or None, w, x, act, dy, rows, dw))
+
+
+def spg_mlp_train(stream: int, x: int, y: int, rows: int, epochs: int, batch: int, lr: float, w_inout: int,
+                  loss_out: int = 0) -> None:
+    _check(load().spg_mlp_train(stream or None, x, y, rows, epochs, batch, lr, w_inout, loss_out or None))

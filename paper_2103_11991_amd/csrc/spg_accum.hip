@@ -1,0 +1,575 @@
+// Row accumulators of the symbolic and numeric phases (section 2.2.1).
+//
+// One group of G lanes owns one row of C (G from 8 to 1024; several rows
+// share a 256-lane workgroup when G < 256).  Inside the group the work is the
+// flattened double loop of Eq. (1): sub-groups of `vec` lanes take successive
+// nonzeros of A's row, and the lanes of a sub-group read consecutive entries
+// of the referenced B row, so B is read in coalesced runs (the paper's
+// vector-parallel inner loop, section 2.2.1).
+//
+// Tables (see spg_internal.h): masks of 32-column blocks, direct or hashed.
+//   symbolic: OR every product's column bit in; count = sum of popcounts,
+//             and the number of occupied blocks is kept for numeric sizing
+//             and as the learned predictor's target;
+//   numeric:  OR pass, then an exclusive prefix sum of popcounts in
+//             ascending block order (hashed tables first rank their occupied
+//             blocks by key), then every product is added with an LDS atomic
+//             at its column's rank; the row leaves in column order with
+//             coalesced stores.
+// Long rows use the global path: 1024 lanes per row, the mask/prefix table
+// in LDS when it fits else in a per-workgroup global slab, and values added
+// with global atomics directly into C's value array.
+#include <hip/hip_runtime.h>
+
+#include "spg_internal.h"
+
+namespace spg {
+
+namespace {
+
+__device__ inline int hash_slot(int key, int logT) {
+    return (int)(((uint32_t)key * 2654435761u) >> (32 - logT));
+}
+
+// Insert-or-find of a block id (open addressing, linear probing).  Returns the
+// slot, or -1 when all T slots were probed without success.
+__device__ inline int hash_insert(int32_t* keys, int T, int logT, int key, bool& inserted) {
+    int h = hash_slot(key, logT);
+    inserted = false;
+    for (int probe = 0; probe < T; ++probe) {
+        int cur = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (cur == key) return h;
+        if (cur == -1) {
+            int old = atomicCAS(&keys[h], -1, key);
+            if (old == -1) {
+                inserted = true;
+                return h;
+            }
+            if (old == key) return h;
+        }
+        h = (h + 1) & (T - 1);
+    }
+    return -1;
+}
+
+__device__ inline int hash_find(const int32_t* keys, int T, int logT, int key) {
+    int h = hash_slot(key, logT);
+    for (int probe = 0; probe < T; ++probe) {
+        if (keys[h] == key) return h;
+        h = (h + 1) & (T - 1);
+    }
+    return -1;
+}
+
+template <int G>
+__device__ inline int group_sum(int v, int* red) {
+    if constexpr (G <= 64) {
+        for (int d = G / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, G);
+        return v;
+    } else {
+        // several waves per group; the partials of group g sit at red[g * W ..)
+        constexpr int W = G / 64;
+        const int wl = threadIdx.x & 63, wv = (threadIdx.x % G) >> 6, g0 = (threadIdx.x / G) * W;
+        for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+        __syncthreads();
+        if (wl == 0) red[g0 + wv] = v;
+        __syncthreads();
+        int t = 0;
+        for (int u = 0; u < W; ++u) t += red[g0 + u];
+        return t;
+    }
+}
+
+// Exclusive prefix sum over the G lanes of a group; *total gets the sum.
+template <int G>
+__device__ inline int group_excl_scan(int v, int& total, int* red) {
+    if constexpr (G <= 64) {
+        const int lane = threadIdx.x % G;
+        int x = v;
+        for (int d = 1; d < G; d <<= 1) {
+            int y = __shfl_up(x, d, G);
+            if (lane >= d) x += y;
+        }
+        total = __shfl(x, G - 1, G);
+        return x - v;
+    } else {
+        constexpr int W = G / 64;
+        const int wl = threadIdx.x & 63, wv = (threadIdx.x % G) >> 6, g0 = (threadIdx.x / G) * W;
+        int x = v;
+        for (int d = 1; d < 64; d <<= 1) {
+            int y = __shfl_up(x, d, 64);
+            if (wl >= d) x += y;
+        }
+        __syncthreads();
+        if (wl == 63) red[g0 + wv] = x;
+        __syncthreads();
+        int pre = 0, tot = 0;
+        for (int u = 0; u < W; ++u) {
+            int t = red[g0 + u];
+            if (u < wv) pre += t;
+            tot += t;
+        }
+        total = tot;
+        return pre + x - v;
+    }
+}
+
+template <int G>
+constexpr int rows_per_wg() {
+    return G >= 256 ? 1 : 256 / G;
+}
+
+// ------------------------------------------------------------------ symbolic
+
+template <int G, int MODE>
+__global__ __launch_bounds__(G * rows_per_wg<G>()) void k_sym(SymArgs a) {
+    constexpr int RPW = rows_per_wg<G>();
+    extern __shared__ __align__(16) uint32_t smem[];
+    __shared__ int red[16];
+    __shared__ int occ[RPW];
+    __shared__ int ovf[RPW];
+    const int bytes = tier_bytes(a.tier);
+    const int sub = threadIdx.x / G, lane = threadIdx.x % G;
+    const int slot = blockIdx.x * RPW + sub;
+    const bool act = slot < a.count;
+    const int i = act ? a.perm[slot] : 0;
+    uint32_t* tab = smem + sub * (bytes / 4);
+    int base = 0, ncell = 0, T = 0, logT = 0;
+    int32_t* keys = reinterpret_cast<int32_t*>(tab);
+    uint32_t* masks = tab;
+    if constexpr (MODE == MODE_DIRECT) {
+        if (act) {
+            RowInfo ri = a.rinfo[i];
+            base = ri.x >> 5;
+            ncell = (ri.y >> 5) - base + 1;
+        }
+    } else {
+        T = 1 << (31 - __clz(bytes / 8));
+        logT = 31 - __clz(T);
+        masks = tab + T;
+        ncell = act ? T : 0;
+    }
+    for (int c = lane; c < ncell; c += G) {
+        masks[c] = 0;
+        if constexpr (MODE == MODE_HASHED) keys[c] = -1;
+    }
+    if (lane == 0) occ[sub] = 0, ovf[sub] = 0;
+    __syncthreads();
+    if (act) {
+        const int a0 = a.arp[i], a1 = a.arp[i + 1];
+        const int S = a.vec < G ? a.vec : G;
+        const int nsub = G / S, sg = lane / S, vl = lane % S;
+        const int occ_max = (T * 3) / 4;
+        for (int p = a0 + sg; p < a1; p += nsub) {
+            const int j = a.aci[p];
+            const int b0 = a.brp[j], b1 = a.brp[j + 1];
+            for (int q = b0 + vl; q < b1; q += S) {
+                const int c = a.bci[q];
+                const uint32_t bit = 1u << (c & 31);
+                if constexpr (MODE == MODE_DIRECT) {
+                    atomicOr(&masks[(c >> 5) - base], bit);
+                } else {
+                    if (*(volatile int*)&ovf[sub]) break;
+                    bool ins;
+                    int h = hash_insert(keys, T, logT, c >> 5, ins);
+                    if (h < 0) {
+                        ovf[sub] = 1;
+                        break;
+                    }
+                    if (ins && atomicAdd(&occ[sub], 1) >= occ_max) ovf[sub] = 1;
+                    atomicOr(&masks[h], bit);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    int cnt = 0, nb = 0;
+    for (int c = lane; c < ncell; c += G) {
+        uint32_t mk = masks[c];
+        cnt += __popc(mk);
+        nb += mk != 0;
+    }
+    cnt = group_sum<G>(cnt, red);
+    nb = group_sum<G>(nb, red);
+    if (act && lane == 0) {
+        if (MODE == MODE_HASHED && ovf[sub]) {
+            int pos = atomicAdd(&a.ctl->overflow_rows, 1);
+            a.ovf_list[pos] = i;
+        } else {
+            a.row_nnz[i] = cnt;
+            a.row_blocks[i] = nb;
+        }
+    }
+}
+
+template <bool IN_LDS>
+__device__ inline uint32_t ld_tab(const uint32_t* p) {
+    if constexpr (IN_LDS) return *p;
+    else return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool IN_LDS>
+__device__ void wide_sym_row(const SymArgs& a, int i, uint32_t* masks, int* red) {
+    constexpr int G = WIDE_THREADS;
+    const int tid = threadIdx.x;
+    const RowInfo ri = a.rinfo[i];
+    const int base = ri.x >> 5;
+    const int words = (ri.y >> 5) - base + 1;
+    for (int c = tid; c < words; c += G) masks[c] = 0;
+    if (!IN_LDS) __threadfence();
+    __syncthreads();
+    {
+        const int a0 = a.arp[i], a1 = a.arp[i + 1];
+        const int S = a.vec < G ? a.vec : G;
+        const int nsub = G / S, sg = tid / S, vl = tid % S;
+        for (int p = a0 + sg; p < a1; p += nsub) {
+            const int j = a.aci[p];
+            const int b0 = a.brp[j], b1 = a.brp[j + 1];
+            for (int q = b0 + vl; q < b1; q += S) {
+                const int c = a.bci[q];
+                atomicOr(&masks[(c >> 5) - base], 1u << (c & 31));
+            }
+        }
+    }
+    if (!IN_LDS) __threadfence();
+    __syncthreads();
+    int cnt = 0, nb = 0;
+    for (int c = tid; c < words; c += G) {
+        uint32_t mk = ld_tab<IN_LDS>(&masks[c]);
+        cnt += __popc(mk);
+        nb += mk != 0;
+    }
+    cnt = group_sum<G>(cnt, red);
+    nb = group_sum<G>(nb, red);
+    if (tid == 0) {
+        a.row_nnz[i] = cnt;
+        a.row_blocks[i] = nb;
+    }
+    __syncthreads();
+}
+
+// Global path of the symbolic phase: long rows, and the exact retry of rows
+// whose learned-size table overflowed.  Persistent: each workgroup walks the
+// row list with stride gridDim.x.
+__global__ __launch_bounds__(WIDE_THREADS) void k_sym_wide(SymArgs a) {
+    extern __shared__ __align__(16) uint32_t smem[];
+    __shared__ int red[16];
+    const int count = a.count_dev ? *a.count_dev : a.count;
+    uint32_t* slab = a.slab ? a.slab + (int64_t)blockIdx.x * a.slab_words : nullptr;
+    for (int r = blockIdx.x; r < count; r += gridDim.x) {
+        const int i = a.perm[r];
+        const RowInfo ri = a.rinfo[i];
+        const int64_t words = row_words(ri.x, ri.y);
+        if (words * 4 <= a.wide_lds) wide_sym_row<true>(a, i, smem, red);
+        else wide_sym_row<false>(a, i, slab, red);
+    }
+}
+
+// ------------------------------------------------------------------- numeric
+
+template <int G, int MODE, typename T>
+__global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
+    constexpr int RPW = rows_per_wg<G>();
+    extern __shared__ __align__(16) uint32_t smem[];
+    __shared__ int red[16];
+    __shared__ int ncompact[RPW];
+    const int bytes = tier_bytes(a.tier);
+    const int sub = threadIdx.x / G, lane = threadIdx.x % G;
+    const int slot = blockIdx.x * RPW + sub;
+    const bool act = slot < a.count;
+    const int i = act ? a.perm[slot] : 0;
+    uint8_t* tab = reinterpret_cast<uint8_t*>(smem) + (size_t)sub * bytes;
+    int n = 0, off = 0, base = 0, words = 0, nb = 0, TT = 0, logT = 0;
+    if (act) {
+        off = a.crp[i];
+        n = a.crp[i + 1] - off;
+        RowInfo ri = a.rinfo[i];
+        base = ri.x >> 5;
+        words = (ri.y >> 5) - base + 1;
+        nb = a.row_blocks[i];
+    }
+    int32_t* keys = nullptr;
+    int32_t* list = nullptr;
+    int32_t* ord = nullptr;
+    uint32_t* masks;
+    int32_t* pref;
+    T* vals;
+    int ncell, items;
+    if constexpr (MODE == MODE_DIRECT) {
+        masks = reinterpret_cast<uint32_t*>(tab);
+        pref = reinterpret_cast<int32_t*>(masks + words);
+        vals = reinterpret_cast<T*>(tab + align8((int64_t)words * 8));
+        ncell = words;
+        items = words;
+    } else {
+        TT = (int)num_hash_slots(nb);
+        logT = 31 - __clz(TT);
+        keys = reinterpret_cast<int32_t*>(tab);
+        masks = reinterpret_cast<uint32_t*>(keys + TT);
+        pref = reinterpret_cast<int32_t*>(masks + TT);
+        list = pref + TT;
+        ord = list + nb;
+        vals = reinterpret_cast<T*>(tab + align8((int64_t)TT * 12 + (int64_t)nb * 8));
+        ncell = act ? TT : 0;
+        items = nb;
+    }
+    int32_t* colbuf = reinterpret_cast<int32_t*>(vals + n);
+    for (int c = lane; c < ncell; c += G) {
+        masks[c] = 0;
+        if constexpr (MODE == MODE_HASHED) keys[c] = -1;
+    }
+    for (int r = lane; r < n; r += G) vals[r] = T(0);
+    if (lane == 0) ncompact[sub] = 0;
+    __syncthreads();
+
+    const int a0 = act ? a.arp[i] : 0, a1 = act ? a.arp[i + 1] : 0;
+    const int S = a.vec < G ? a.vec : G;
+    const int nsub = G / S, sg = lane / S, vl = lane % S;
+    // pass 1: which columns occur
+    for (int p = a0 + sg; p < a1; p += nsub) {
+        const int j = a.aci[p];
+        const int b0 = a.brp[j], b1 = a.brp[j + 1];
+        for (int q = b0 + vl; q < b1; q += S) {
+            const int c = a.bci[q];
+            const uint32_t bit = 1u << (c & 31);
+            if constexpr (MODE == MODE_DIRECT) {
+                atomicOr(&masks[(c >> 5) - base], bit);
+            } else {
+                bool ins;
+                int h = hash_insert(keys, TT, logT, c >> 5, ins);
+                atomicOr(&masks[h], bit);
+            }
+        }
+    }
+    __syncthreads();
+    if constexpr (MODE == MODE_HASHED) {
+        // occupied slots in ascending block order: compact, then rank by count
+        for (int c = lane; c < ncell; c += G)
+            if (masks[c]) list[atomicAdd(&ncompact[sub], 1)] = c;
+        __syncthreads();
+        for (int e = lane; e < nb; e += G) {
+            const int s = list[e];
+            const int key = keys[s];
+            int r = 0;
+            for (int f = 0; f < nb; ++f) r += keys[list[f]] < key;
+            ord[r] = s;
+        }
+        __syncthreads();
+    }
+    // exclusive prefix of popcounts over blocks in ascending order
+    {
+        const int chunk = (items + G - 1) / G;
+        const int beg = lane * chunk;
+        const int end = min(beg + chunk, items);
+        int local = 0;
+        for (int t = beg; t < end; ++t) local += __popc(masks[MODE == MODE_DIRECT ? t : ord[t]]);
+        int total;
+        int ex = group_excl_scan<G>(local, total, red);
+        for (int t = beg; t < end; ++t) {
+            const int cl = MODE == MODE_DIRECT ? t : ord[t];
+            pref[cl] = ex;
+            ex += __popc(masks[cl]);
+        }
+    }
+    __syncthreads();
+    // pass 2: add every product at its column's rank
+    const T* av = reinterpret_cast<const T*>(a.av);
+    const T* bv = reinterpret_cast<const T*>(a.bv);
+    for (int p = a0 + sg; p < a1; p += nsub) {
+        const int j = a.aci[p];
+        const T x = av[p];
+        const int b0 = a.brp[j], b1 = a.brp[j + 1];
+        for (int q = b0 + vl; q < b1; q += S) {
+            const int c = a.bci[q];
+            const T y = bv[q];
+            const uint32_t below = (1u << (c & 31)) - 1u;
+            int cl;
+            if constexpr (MODE == MODE_DIRECT) cl = (c >> 5) - base;
+            else cl = hash_find(keys, TT, logT, c >> 5);
+            const int rank = pref[cl] + __popc(masks[cl] & below);
+            atomicAdd(&vals[rank], x * y);
+        }
+    }
+    // column of every rank, from the masks
+    for (int t = lane; t < items; t += G) {
+        const int cl = MODE == MODE_DIRECT ? t : ord[t];
+        uint32_t mk = masks[cl];
+        int r = pref[cl];
+        const int blk = MODE == MODE_DIRECT ? base + t : keys[cl];
+        while (mk) {
+            colbuf[r++] = (blk << 5) + (__ffs(mk) - 1);
+            mk &= mk - 1;
+        }
+    }
+    __syncthreads();
+    T* cv = reinterpret_cast<T*>(a.cval);
+    for (int r = lane; r < n; r += G) {
+        a.ccol[off + r] = colbuf[r];
+        cv[off + r] = vals[r];
+    }
+}
+
+template <typename T, bool IN_LDS>
+__device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int* red) {
+    constexpr int G = WIDE_THREADS;
+    const int tid = threadIdx.x;
+    const int off = a.crp[i];
+    const int n = a.crp[i + 1] - off;
+    const RowInfo ri = a.rinfo[i];
+    const int base = ri.x >> 5;
+    const int words = (ri.y >> 5) - base + 1;
+    int32_t* pref = reinterpret_cast<int32_t*>(masks + words);
+    T* cv = reinterpret_cast<T*>(a.cval) + off;
+    int32_t* cc = a.ccol + off;
+    for (int c = tid; c < words; c += G) masks[c] = 0;
+    for (int r = tid; r < n; r += G) cv[r] = T(0);
+    __threadfence();
+    __syncthreads();
+    const int a0 = a.arp[i], a1 = a.arp[i + 1];
+    const int S = a.vec < G ? a.vec : G;
+    const int nsub = G / S, sg = tid / S, vl = tid % S;
+    for (int p = a0 + sg; p < a1; p += nsub) {
+        const int j = a.aci[p];
+        const int b0 = a.brp[j], b1 = a.brp[j + 1];
+        for (int q = b0 + vl; q < b1; q += S) {
+            const int c = a.bci[q];
+            atomicOr(&masks[(c >> 5) - base], 1u << (c & 31));
+        }
+    }
+    if (!IN_LDS) __threadfence();
+    __syncthreads();
+    {
+        const int chunk = (words + G - 1) / G;
+        const int beg = tid * chunk;
+        const int end = min(beg + chunk, words);
+        int local = 0;
+        for (int t = beg; t < end; ++t) local += __popc(ld_tab<IN_LDS>(&masks[t]));
+        int total;
+        int ex = group_excl_scan<G>(local, total, red);
+        for (int t = beg; t < end; ++t) {
+            pref[t] = ex;
+            ex += __popc(ld_tab<IN_LDS>(&masks[t]));
+        }
+    }
+    if (!IN_LDS) __threadfence();
+    __syncthreads();
+    const T* av = reinterpret_cast<const T*>(a.av);
+    const T* bv = reinterpret_cast<const T*>(a.bv);
+    for (int p = a0 + sg; p < a1; p += nsub) {
+        const int j = a.aci[p];
+        const T x = av[p];
+        const int b0 = a.brp[j], b1 = a.brp[j + 1];
+        for (int q = b0 + vl; q < b1; q += S) {
+            const int c = a.bci[q];
+            const int w = (c >> 5) - base;
+            const uint32_t mk = ld_tab<IN_LDS>(&masks[w]);
+            const int rank = (int)ld_tab<IN_LDS>(reinterpret_cast<uint32_t*>(&pref[w])) +
+                             __popc(mk & ((1u << (c & 31)) - 1u));
+            atomicAdd(&cv[rank], x * bv[q]);
+        }
+    }
+    for (int t = tid; t < words; t += G) {
+        uint32_t mk = ld_tab<IN_LDS>(&masks[t]);
+        int r = (int)ld_tab<IN_LDS>(reinterpret_cast<uint32_t*>(&pref[t]));
+        const int blk = base + t;
+        while (mk) {
+            cc[r++] = (blk << 5) + (__ffs(mk) - 1);
+            mk &= mk - 1;
+        }
+    }
+    __threadfence();
+    __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(WIDE_THREADS) void k_num_wide(NumArgs a) {
+    extern __shared__ __align__(16) uint32_t smem[];
+    __shared__ int red[16];
+    uint32_t* slab = a.slab ? a.slab + (int64_t)blockIdx.x * a.slab_words : nullptr;
+    for (int r = blockIdx.x; r < a.count; r += gridDim.x) {
+        const int i = a.perm[r];
+        const RowInfo ri = a.rinfo[i];
+        const int64_t words = row_words(ri.x, ri.y);
+        if (words * 8 <= a.wide_lds) wide_num_row<T, true>(a, i, smem, red);
+        else wide_num_row<T, false>(a, i, slab, red);
+    }
+}
+
+template <int G, int MODE>
+void sym_launch(hipStream_t s, const SymArgs& a) {
+    constexpr int RPW = rows_per_wg<G>();
+    const unsigned grid = (unsigned)((a.count + RPW - 1) / RPW);
+    const size_t smem = (size_t)RPW * tier_bytes(a.tier);
+    hipLaunchKernelGGL((k_sym<G, MODE>), dim3(grid), dim3(G * RPW), smem, s, a);
+}
+
+template <int G, int MODE, typename T>
+void num_launch(hipStream_t s, const NumArgs& a) {
+    constexpr int RPW = rows_per_wg<G>();
+    const unsigned grid = (unsigned)((a.count + RPW - 1) / RPW);
+    const size_t smem = (size_t)RPW * tier_bytes(a.tier);
+    hipLaunchKernelGGL((k_num<G, MODE, T>), dim3(grid), dim3(G * RPW), smem, s, a);
+}
+
+template <int MODE>
+void sym_dispatch(hipStream_t s, const SymArgs& a) {
+    switch (tier_threads(a.tier)) {
+        case 8: sym_launch<8, MODE>(s, a); break;
+        case 16: sym_launch<16, MODE>(s, a); break;
+        case 32: sym_launch<32, MODE>(s, a); break;
+        case 64: sym_launch<64, MODE>(s, a); break;
+        case 128: sym_launch<128, MODE>(s, a); break;
+        case 256: sym_launch<256, MODE>(s, a); break;
+        case 512: sym_launch<512, MODE>(s, a); break;
+        default: sym_launch<1024, MODE>(s, a); break;
+    }
+}
+
+template <int MODE, typename T>
+void num_dispatch(hipStream_t s, const NumArgs& a) {
+    switch (tier_threads(a.tier)) {
+        case 8: num_launch<8, MODE, T>(s, a); break;
+        case 16: num_launch<16, MODE, T>(s, a); break;
+        case 32: num_launch<32, MODE, T>(s, a); break;
+        case 64: num_launch<64, MODE, T>(s, a); break;
+        case 128: num_launch<128, MODE, T>(s, a); break;
+        case 256: num_launch<256, MODE, T>(s, a); break;
+        case 512: num_launch<512, MODE, T>(s, a); break;
+        default: num_launch<1024, MODE, T>(s, a); break;
+    }
+}
+
+}  // namespace
+
+int launch_sym_class(hipStream_t s, const SymArgs& a, int grid_cap) {
+    if (a.tier == TIER_GLOBAL) {
+        int grid = a.count_dev ? grid_cap : (a.count < grid_cap ? a.count : grid_cap);
+        if (grid < 1) return 0;
+        hipLaunchKernelGGL(k_sym_wide, dim3(grid), dim3(WIDE_THREADS), (size_t)a.wide_lds, s, a);
+        return grid;
+    }
+    if (a.count <= 0) return 0;
+    if (a.mode == MODE_DIRECT) sym_dispatch<MODE_DIRECT>(s, a);
+    else sym_dispatch<MODE_HASHED>(s, a);
+    return 1;
+}
+
+int launch_num_class(hipStream_t s, const NumArgs& a, int elem_bytes, int grid_cap) {
+    if (a.count <= 0) return 0;
+    if (a.tier == TIER_GLOBAL) {
+        int grid = a.count < grid_cap ? a.count : grid_cap;
+        if (elem_bytes == 8) hipLaunchKernelGGL(k_num_wide<double>, dim3(grid), dim3(WIDE_THREADS), (size_t)a.wide_lds, s, a);
+        else hipLaunchKernelGGL(k_num_wide<float>, dim3(grid), dim3(WIDE_THREADS), (size_t)a.wide_lds, s, a);
+        return grid;
+    }
+    if (elem_bytes == 8) {
+        if (a.mode == MODE_DIRECT) num_dispatch<MODE_DIRECT, double>(s, a);
+        else num_dispatch<MODE_HASHED, double>(s, a);
+    } else {
+        if (a.mode == MODE_DIRECT) num_dispatch<MODE_DIRECT, float>(s, a);
+        else num_dispatch<MODE_HASHED, float>(s, a);
+    }
+    return 1;
+}
+
+}  // namespace spg

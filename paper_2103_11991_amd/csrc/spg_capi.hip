@@ -1,0 +1,610 @@
+// Handle, host runtime and the extern "C" boundary of the spg library.
+//
+// The call order follows the paper's statement of the two phases (section
+// 2.2.1): the caller allocates C's row pointer, symbolic fills it and returns
+// nnz(C), the caller allocates column indices and values, numeric fills them.
+// The handle carries the runtime algorithm choices (section 6) and every
+// intermediate buffer, so a repeated numeric call reuses the symbolic result
+// (row classes, row permutation and C's row pointer) without recomputing it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "spg_internal.h"
+
+using namespace spg;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+enum EvId { EV_SYM0 = 0, EV_SYM1, EV_ANA1, EV_MLP0, EV_MLP1, EV_SCAN0, EV_SCAN1, EV_NUM0, EV_NUM1, EV_FIXED };
+constexpr int EV_SYMCLS = EV_FIXED;                 // 2 per class
+constexpr int EV_NUMCLS = EV_FIXED + 2 * NCLS;      // 2 per class
+constexpr int EV_TOTAL = EV_FIXED + 4 * NCLS;
+
+}  // namespace
+
+struct spg_handle_s {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int n_cu = 256;
+    int max_lds = 65536;
+    std::string err;
+
+    // inputs
+    bool have_mats = false;
+    spg_dtype dt = SPG_F64;
+    int32_t m = 0, n = 0, k = 0;
+    const int32_t *arp = nullptr, *aci = nullptr, *brp = nullptr, *bci = nullptr;
+    int64_t annz = 0, bnnz = 0;
+
+    // options
+    int binning = 0;
+    int timing = 0;
+    int force_class = -1;
+    int work_per_lane = 16;
+    int vec = 0;
+    int hash_max_blocks = 64;
+    int lds_limit = 65536;
+    int mlp_margin_milli = 500;
+    int keep_features = 0;
+    bool have_mlp = false;
+
+    // scratch
+    DevBuf binfo, rinfo, feats, sym_cls, num_cls, perm_sym, perm_num, row_nnz, row_blocks, tile_status, cursor,
+        ovf_list, ctl, slab_sym, slab_retry, slab_num, mlp_w;
+    Control* hctl = nullptr;  // pinned host copy
+
+    // symbolic result
+    bool have_sym = false;
+    bool have_feats = false;
+    int32_t* crp = nullptr;
+    int64_t nnz_c = 0;
+    int32_t num_hist[NCLS] = {};
+    int32_t num_off[NCLS] = {};
+    int64_t slab_num_words = 0;
+    int nslab_num = 0;
+    int vec_used = 1;
+    ClassCfg cfg{};
+
+    // stats and timing
+    spg_stats stats{};
+    hipEvent_t ev[EV_TOTAL] = {};
+    bool ev_made = false;
+    bool sym_timed = false, num_timed = false;
+    bool sym_cls_timed[NCLS] = {}, num_cls_timed[NCLS] = {};
+};
+
+namespace {
+
+spg_status fail(spg_handle h, spg_status s, const std::string& msg) {
+    if (h) h->err = msg;
+    return s;
+}
+
+spg_status hip_fail(spg_handle h, hipError_t e, const char* what) {
+    return fail(h, SPG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(h, call)                                  \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return hip_fail(h, e_, #call); \
+    } while (0)
+
+spg_status ensure(spg_handle h, DevBuf& b, size_t bytes) {
+    if (bytes <= b.cap && b.p) return SPG_OK;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+        if (e != hipSuccess) return hip_fail(h, e, "hipFree");
+    }
+    size_t want = std::max<size_t>(bytes, 256);
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        return fail(h, SPG_ERR_ALLOC, "device allocation of " + std::to_string(want) + " bytes failed");
+    }
+    b.cap = want;
+    return SPG_OK;
+}
+
+void release(DevBuf& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+#define SPG_TRY(call)                 \
+    do {                              \
+        spg_status s_ = (call);       \
+        if (s_ != SPG_OK) return s_;  \
+    } while (0)
+
+spg_status make_events(spg_handle h) {
+    if (h->ev_made) return SPG_OK;
+    for (int i = 0; i < EV_TOTAL; ++i) HIP_TRY(h, hipEventCreate(&h->ev[i]));
+    h->ev_made = true;
+    return SPG_OK;
+}
+
+void rec(spg_handle h, int id) {
+    if (h->timing) (void)hipEventRecord(h->ev[id], h->stream);
+}
+
+float elapsed(spg_handle h, int a, int b) {
+    float ms = 0.f;
+    if (hipEventSynchronize(h->ev[b]) != hipSuccess) return -1.f;
+    if (hipEventElapsedTime(&ms, h->ev[a], h->ev[b]) != hipSuccess) return -1.f;
+    return ms;
+}
+
+int pick_vec(spg_handle h) {
+    if (h->vec > 0) return h->vec;
+    double mean = h->n > 0 ? (double)h->bnnz / (double)h->n : 1.0;
+    int v = 1;
+    while (v < 64 && 2.0 * v <= mean * 1.5) v *= 2;
+    return v;
+}
+
+ClassCfg make_cfg(spg_handle h) {
+    ClassCfg c{};
+    c.work_per_lane = h->work_per_lane;
+    c.hash_max_blocks = h->hash_max_blocks;
+    c.lds_limit = h->lds_limit;
+    c.force_class = h->force_class;
+    c.elem_bytes = h->dt == SPG_F64 ? 8 : 4;
+    return c;
+}
+
+int wide_lds(spg_handle h) {
+    // LDS of a global-path workgroup: 64 KB, less if the device cannot give it
+    int v = 65536;
+    while (v > 4096 && v + 1024 > h->max_lds) v >>= 1;
+    return v;
+}
+
+spg_status sync_ctl(spg_handle h) {
+    HIP_TRY(h, hipMemcpyAsync(h->hctl, h->ctl.p, sizeof(Control), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return SPG_OK;
+}
+
+spg_status check_input_errors(spg_handle h) {
+    int e = h->hctl->err;
+    if (e & (ERR_A_ROWPTR | ERR_B_ROWPTR))
+        return fail(h, SPG_ERR_INDEX, std::string("malformed row pointer in ") + ((e & ERR_A_ROWPTR) ? "A" : "B"));
+    if (e & (ERR_A_COL | ERR_B_COL))
+        return fail(h, SPG_ERR_INDEX, std::string("column index out of range in ") + ((e & ERR_A_COL) ? "A" : "B"));
+    return SPG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* spg_status_string(spg_status s) {
+    switch (s) {
+        case SPG_OK: return "SPG_OK";
+        case SPG_ERR_ARG: return "SPG_ERR_ARG";
+        case SPG_ERR_SHAPE: return "SPG_ERR_SHAPE";
+        case SPG_ERR_STATE: return "SPG_ERR_STATE";
+        case SPG_ERR_INDEX: return "SPG_ERR_INDEX";
+        case SPG_ERR_OVERFLOW: return "SPG_ERR_OVERFLOW";
+        case SPG_ERR_ALLOC: return "SPG_ERR_ALLOC";
+        case SPG_ERR_HIP: return "SPG_ERR_HIP";
+        case SPG_ERR_UNSUPPORTED: return "SPG_ERR_UNSUPPORTED";
+    }
+    return "SPG_ERR_UNKNOWN";
+}
+
+const char* spg_last_error(spg_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+spg_status spg_create(spg_handle* out, void* stream) {
+    if (!out) return SPG_ERR_ARG;
+    *out = nullptr;
+    try {
+        spg_handle h = new spg_handle_s();
+        h->stream = static_cast<hipStream_t>(stream);
+        hipError_t e = hipGetDevice(&h->device);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&h->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&h->hctl, sizeof(Control), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete h;
+            return SPG_ERR_HIP;
+        }
+        while (h->lds_limit > 1024 && h->lds_limit + 1024 > h->max_lds) h->lds_limit >>= 1;
+        *out = h;
+        return SPG_OK;
+    } catch (...) {
+        return SPG_ERR_ALLOC;
+    }
+}
+
+spg_status spg_destroy(spg_handle h) {
+    if (!h) return SPG_OK;
+    if (h->stream || true) (void)hipStreamSynchronize(h->stream);
+    DevBuf* bufs[] = {&h->binfo, &h->rinfo, &h->feats, &h->sym_cls, &h->num_cls, &h->perm_sym, &h->perm_num,
+                      &h->row_nnz, &h->row_blocks, &h->tile_status, &h->cursor, &h->ovf_list, &h->ctl,
+                      &h->slab_sym, &h->slab_retry, &h->slab_num, &h->mlp_w};
+    for (DevBuf* b : bufs) release(*b);
+    if (h->hctl) (void)hipHostFree(h->hctl);
+    if (h->ev_made)
+        for (auto& e : h->ev) (void)hipEventDestroy(e);
+    delete h;
+    return SPG_OK;
+}
+
+spg_status spg_set_stream(spg_handle h, void* stream) {
+    if (!h) return SPG_ERR_ARG;
+    h->stream = static_cast<hipStream_t>(stream);
+    return SPG_OK;
+}
+
+spg_status spg_set_matrices(spg_handle h, spg_dtype dt, int32_t m, int32_t n, int32_t k, const int32_t* a_row_ptr,
+                            const int32_t* a_col_idx, int64_t a_nnz, const int32_t* b_row_ptr,
+                            const int32_t* b_col_idx, int64_t b_nnz) {
+    if (!h) return SPG_ERR_ARG;
+    try {
+        h->have_mats = false;
+        h->have_sym = false;
+        if (dt != SPG_F32 && dt != SPG_F64) return fail(h, SPG_ERR_ARG, "dtype must be SPG_F32 or SPG_F64");
+        if (m < 0 || n < 0 || k < 0 || a_nnz < 0 || b_nnz < 0)
+            return fail(h, SPG_ERR_ARG, "negative dimension or nnz");
+        if (a_nnz > INT32_MAX || b_nnz > INT32_MAX) return fail(h, SPG_ERR_ARG, "nnz exceeds int32 range");
+        if (!a_row_ptr || !b_row_ptr) return fail(h, SPG_ERR_ARG, "null row pointer");
+        if ((a_nnz > 0 && !a_col_idx) || (b_nnz > 0 && !b_col_idx)) return fail(h, SPG_ERR_ARG, "null column index");
+        if (n == 0 && a_nnz > 0) return fail(h, SPG_ERR_SHAPE, "A has entries but no columns");
+        if (k == 0 && b_nnz > 0) return fail(h, SPG_ERR_SHAPE, "B has entries but no columns");
+        h->dt = dt;
+        h->m = m, h->n = n, h->k = k;
+        h->arp = a_row_ptr, h->aci = a_col_idx, h->annz = a_nnz;
+        h->brp = b_row_ptr, h->bci = b_col_idx, h->bnnz = b_nnz;
+        h->have_mats = true;
+        return SPG_OK;
+    } catch (...) {
+        return fail(h, SPG_ERR_ALLOC, "host exception");
+    }
+}
+
+spg_status spg_symbolic(spg_handle h, int32_t* c_row_ptr, int64_t* nnz_c) {
+    if (!h) return SPG_ERR_ARG;
+    try {
+        if (!h->have_mats) return fail(h, SPG_ERR_STATE, "spg_set_matrices must come first");
+        if (!c_row_ptr || !nnz_c) return fail(h, SPG_ERR_ARG, "null output");
+        if (h->binning == 1 && !h->have_mlp) return fail(h, SPG_ERR_STATE, "learned binning needs spg_set_mlp");
+        h->have_sym = false;
+        const int32_t m = h->m;
+        hipStream_t s = h->stream;
+        const bool learned = h->binning == 1;
+        const bool want_feats = learned || h->keep_features;
+        if (h->timing) SPG_TRY(make_events(h));
+        h->sym_timed = h->timing != 0;
+        std::fill(std::begin(h->sym_cls_timed), std::end(h->sym_cls_timed), false);
+
+        const size_t M = (size_t)std::max(m, 1);
+        SPG_TRY(ensure(h, h->ctl, sizeof(Control)));
+        SPG_TRY(ensure(h, h->binfo, (size_t)std::max(h->n, 1) * sizeof(int4)));
+        SPG_TRY(ensure(h, h->rinfo, M * sizeof(RowInfo)));
+        SPG_TRY(ensure(h, h->sym_cls, M));
+        SPG_TRY(ensure(h, h->num_cls, M));
+        SPG_TRY(ensure(h, h->perm_sym, M * 4));
+        SPG_TRY(ensure(h, h->perm_num, M * 4));
+        SPG_TRY(ensure(h, h->row_nnz, M * 4));
+        SPG_TRY(ensure(h, h->row_blocks, M * 4));
+        SPG_TRY(ensure(h, h->tile_status, (size_t)(scan_tiles(m) + 1) * 8));
+        SPG_TRY(ensure(h, h->cursor, NCLS * 4));
+        if (learned) SPG_TRY(ensure(h, h->ovf_list, M * 4));
+        if (want_feats) SPG_TRY(ensure(h, h->feats, M * 12));
+
+        const ClassCfg cfg = make_cfg(h);
+        h->cfg = cfg;
+        h->vec_used = pick_vec(h);
+        Control* ctl = h->ctl.as<Control>();
+        const int wl = wide_lds(h);
+
+        rec(h, EV_SYM0);
+        launch_fill_u8(s, ctl, 0, sizeof(Control));
+        if (m == 0) {
+            launch_fill_i32(s, c_row_ptr, 0, 1);
+            SPG_TRY(sync_ctl(h));
+            rec(h, EV_SYM1);
+            *nnz_c = 0;
+            h->nnz_c = 0;
+            h->crp = c_row_ptr;
+            std::fill(std::begin(h->num_hist), std::end(h->num_hist), 0);
+            h->have_sym = true;
+            h->have_feats = false;
+            return SPG_OK;
+        }
+        // row analysis: B rows, then A rows (+ classes or features)
+        launch_b_rowinfo(s, h->n, h->k, h->brp, h->bci, h->bnnz, h->binfo.as<int4>(), ctl);
+        launch_a_rowinfo(s, m, h->n, h->arp, h->aci, h->annz, h->binfo.as<int4>(), h->rinfo.as<RowInfo>(),
+                         want_feats ? h->feats.as<float>() : nullptr, cfg, learned ? 1 : 0, h->sym_cls.as<uint8_t>(),
+                         h->row_nnz.as<int32_t>(), h->row_blocks.as<int32_t>(), ctl);
+        rec(h, EV_ANA1);
+        if (learned) {
+            rec(h, EV_MLP0);
+            launch_mlp_classify(s, m, h->feats.as<float>(), h->mlp_w.as<float>(), h->rinfo.as<RowInfo>(), cfg,
+                                h->mlp_margin_milli / 1000.0f, h->sym_cls.as<uint8_t>(), ctl);
+            rec(h, EV_MLP1);
+        }
+        SPG_TRY(sync_ctl(h));  // first synchronisation: validity, class histogram, slab sizes
+        SPG_TRY(check_input_errors(h));
+        const Control hc = *h->hctl;
+
+        // group rows by symbolic class
+        launch_fill_i32(s, h->cursor.as<int32_t>(), 0, NCLS);
+        launch_scatter(s, m, h->sym_cls.as<uint8_t>(), ctl->sym_hist, h->cursor.as<int32_t>(),
+                       h->perm_sym.as<int32_t>());
+        int off[NCLS];
+        {
+            int run = 0;
+            for (int c = 0; c < NCLS; ++c) off[c] = run, run += hc.sym_hist[c];
+        }
+        const int grid_cap = 2 * h->n_cu;
+        uint32_t* slab = nullptr;
+        int64_t slab_words = 0;
+        const int gcls = MODE_DIRECT * NTIER + TIER_GLOBAL;
+        if (hc.sym_hist[gcls] > 0 && hc.max_words_sym_global * 4 > wl) {
+            slab_words = (hc.max_words_sym_global + 63) & ~(int64_t)63;
+            int ns = std::min(hc.sym_hist[gcls], grid_cap);
+            SPG_TRY(ensure(h, h->slab_sym, (size_t)ns * slab_words * 4));
+            slab = h->slab_sym.as<uint32_t>();
+        }
+        for (int c = 0; c < NCLS; ++c) {
+            if (!hc.sym_hist[c]) continue;
+            SymArgs a{};
+            a.perm = h->perm_sym.as<int32_t>() + off[c];
+            a.count = hc.sym_hist[c];
+            a.tier = c % NTIER;
+            a.mode = c / NTIER;
+            a.vec = h->vec_used;
+            a.arp = h->arp, a.aci = h->aci, a.brp = h->brp, a.bci = h->bci;
+            a.rinfo = h->rinfo.as<RowInfo>();
+            a.row_nnz = h->row_nnz.as<int32_t>();
+            a.row_blocks = h->row_blocks.as<int32_t>();
+            a.ovf_list = learned ? h->ovf_list.as<int32_t>() : nullptr;
+            a.ctl = ctl;
+            a.slab = slab;
+            a.slab_words = slab_words;
+            a.count_dev = nullptr;
+            a.wide_lds = wl;
+            rec(h, EV_SYMCLS + 2 * c);
+            launch_sym_class(s, a, grid_cap);
+            rec(h, EV_SYMCLS + 2 * c + 1);
+            h->sym_cls_timed[c] = h->timing != 0;
+        }
+        if (learned) {
+            // exact retry of overflowed rows on the global path (row count read on the device)
+            SymArgs a{};
+            a.perm = h->ovf_list.as<int32_t>();
+            a.count = 0;
+            a.count_dev = &ctl->overflow_rows;
+            a.tier = TIER_GLOBAL;
+            a.mode = MODE_DIRECT;
+            a.vec = h->vec_used;
+            a.arp = h->arp, a.aci = h->aci, a.brp = h->brp, a.bci = h->bci;
+            a.rinfo = h->rinfo.as<RowInfo>();
+            a.row_nnz = h->row_nnz.as<int32_t>();
+            a.row_blocks = h->row_blocks.as<int32_t>();
+            a.ctl = ctl;
+            a.wide_lds = wl;
+            int retry_grid = std::min(grid_cap, 64);
+            if (hc.max_words_all * 4 > wl) {
+                a.slab_words = (hc.max_words_all + 63) & ~(int64_t)63;
+                SPG_TRY(ensure(h, h->slab_retry, (size_t)retry_grid * a.slab_words * 4));
+                a.slab = h->slab_retry.as<uint32_t>();
+            }
+            launch_sym_class(s, a, retry_grid);
+        }
+        // row pointer and numeric classes
+        rec(h, EV_SCAN0);
+        launch_fill_u8(s, h->tile_status.p, 0, (scan_tiles(m) + 1) * 8);
+        launch_scan(s, m, h->row_nnz.as<int32_t>(), h->row_blocks.as<int32_t>(), h->rinfo.as<RowInfo>(), h->arp,
+                    h->sym_cls.as<uint8_t>(), c_row_ptr, h->tile_status.as<uint64_t>(), cfg, h->num_cls.as<uint8_t>(),
+                    ctl);
+        rec(h, EV_SCAN1);
+        launch_fill_i32(s, h->cursor.as<int32_t>(), 0, NCLS);
+        launch_scatter(s, m, h->num_cls.as<uint8_t>(), ctl->num_hist, h->cursor.as<int32_t>(),
+                       h->perm_num.as<int32_t>());
+        SPG_TRY(sync_ctl(h));  // second synchronisation: nnz(C) for the caller's allocation
+        rec(h, EV_SYM1);
+        const Control hc2 = *h->hctl;
+        if (hc2.err & ERR_NNZ_OVERFLOW)
+            return fail(h, SPG_ERR_OVERFLOW, "nnz(C) = " + std::to_string(hc2.nnz_c) + " exceeds the int32 range");
+        h->nnz_c = hc2.nnz_c;
+        *nnz_c = hc2.nnz_c;
+        int run = 0;
+        for (int c = 0; c < NCLS; ++c) {
+            h->num_hist[c] = hc2.num_hist[c];
+            h->num_off[c] = run;
+            run += hc2.num_hist[c];
+        }
+        // global-path slabs for the numeric phase are sized now, not inside numeric
+        h->slab_num_words = 0;
+        h->nslab_num = std::min(std::max(hc2.num_hist[gcls], 0), grid_cap);
+        if (hc2.num_hist[gcls] > 0 && hc2.max_words_num_global * 8 > wl) {
+            h->slab_num_words = 2 * ((hc2.max_words_num_global + 63) & ~(int64_t)63);
+            SPG_TRY(ensure(h, h->slab_num, (size_t)h->nslab_num * h->slab_num_words * 4));
+        }
+        // statistics
+        spg_stats& st = h->stats;
+        st.size = sizeof(spg_stats);
+        st.m = m, st.n = h->n, st.k = h->k;
+        st.products = hc2.products;
+        st.nnz_c = hc2.nnz_c;
+        for (int c = 0; c < NCLS; ++c) {
+            st.sym_rows[c] = hc.sym_hist[c];
+            st.num_rows[c] = hc2.num_hist[c];
+            st.num_a_nnz[c] = hc2.num_a_nnz[c];
+            st.num_c_nnz[c] = hc2.num_c_nnz[c];
+            st.num_products[c] = hc2.num_products[c];
+        }
+        st.empty_rows = hc2.empty_rows;
+        st.retried_rows = hc2.overflow_rows;
+        st.mispredicted_rows = hc2.mispredicted;
+        st.binning = h->binning;
+        h->crp = c_row_ptr;
+        h->have_sym = true;
+        h->have_feats = want_feats;
+        return SPG_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(h, SPG_ERR_ALLOC, "host allocation failed");
+    } catch (...) {
+        return fail(h, SPG_ERR_HIP, "unexpected host exception");
+    }
+}
+
+spg_status spg_numeric(spg_handle h, const void* a_vals, const void* b_vals, int32_t* c_col_idx, void* c_vals) {
+    if (!h) return SPG_ERR_ARG;
+    try {
+        if (!h->have_sym) return fail(h, SPG_ERR_STATE, "spg_symbolic must come first");
+        if ((h->annz > 0 && !a_vals) || (h->bnnz > 0 && !b_vals)) return fail(h, SPG_ERR_ARG, "null input values");
+        if (h->nnz_c > 0 && (!c_col_idx || !c_vals)) return fail(h, SPG_ERR_ARG, "null output");
+        if (h->timing) SPG_TRY(make_events(h));
+        h->num_timed = h->timing != 0;
+        std::fill(std::begin(h->num_cls_timed), std::end(h->num_cls_timed), false);
+        hipStream_t s = h->stream;
+        const int eb = h->dt == SPG_F64 ? 8 : 4;
+        rec(h, EV_NUM0);
+        for (int c = 0; c < NCLS; ++c) {
+            if (!h->num_hist[c]) continue;
+            NumArgs a{};
+            a.perm = h->perm_num.as<int32_t>() + h->num_off[c];
+            a.count = h->num_hist[c];
+            a.tier = c % NTIER;
+            a.mode = c / NTIER;
+            a.vec = h->vec_used;
+            a.arp = h->arp, a.aci = h->aci, a.av = a_vals;
+            a.brp = h->brp, a.bci = h->bci, a.bv = b_vals;
+            a.crp = h->crp;
+            a.rinfo = h->rinfo.as<RowInfo>();
+            a.row_blocks = h->row_blocks.as<int32_t>();
+            a.ccol = c_col_idx;
+            a.cval = c_vals;
+            a.slab = h->slab_num_words ? h->slab_num.as<uint32_t>() : nullptr;
+            a.slab_words = h->slab_num_words;
+            a.wide_lds = wide_lds(h);
+            rec(h, EV_NUMCLS + 2 * c);
+            launch_num_class(s, a, eb, std::max(h->nslab_num, 1));
+            rec(h, EV_NUMCLS + 2 * c + 1);
+            h->num_cls_timed[c] = h->timing != 0;
+        }
+        rec(h, EV_NUM1);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(h, e, "numeric launch");
+        return SPG_OK;
+    } catch (...) {
+        return fail(h, SPG_ERR_HIP, "unexpected host exception");
+    }
+}
+
+spg_status spg_set_option(spg_handle h, int32_t opt, int64_t val) {
+    if (!h) return SPG_ERR_ARG;
+    switch (opt) {
+        case SPG_OPT_BINNING:
+            if (val != 0 && val != 1) return fail(h, SPG_ERR_ARG, "binning must be 0 or 1");
+            h->binning = (int)val;
+            break;
+        case SPG_OPT_TIMING: h->timing = val != 0; break;
+        case SPG_OPT_FORCE_CLASS:
+            if (val < -1 || val >= NCLS) return fail(h, SPG_ERR_ARG, "class out of range");
+            h->force_class = (int)val;
+            break;
+        case SPG_OPT_WORK_PER_LANE:
+            if (val < 1 || val > 1 << 20) return fail(h, SPG_ERR_ARG, "work per lane out of range");
+            h->work_per_lane = (int)val;
+            break;
+        case SPG_OPT_MLP_MARGIN_MILLI:
+            if (val < -20000 || val > 20000) return fail(h, SPG_ERR_ARG, "margin out of range");
+            h->mlp_margin_milli = (int)val;
+            break;
+        case SPG_OPT_VECTOR_WIDTH:
+            if (val != 0 && (val < 1 || val > 64 || (val & (val - 1))))
+                return fail(h, SPG_ERR_ARG, "vector width must be 0 or a power of two up to 64");
+            h->vec = (int)val;
+            break;
+        case SPG_OPT_HASH_MAX_BLOCKS:
+            if (val < 0 || val > 4096) return fail(h, SPG_ERR_ARG, "hash block limit out of range");
+            h->hash_max_blocks = (int)val;
+            break;
+        case SPG_OPT_LDS_LIMIT: {
+            if (val < 1024 || val > 65536 || (val & (val - 1)))
+                return fail(h, SPG_ERR_ARG, "LDS limit must be a power of two in [1024, 65536]");
+            int v = (int)val;
+            while (v > 1024 && v + 1024 > h->max_lds) v >>= 1;
+            h->lds_limit = v;
+            break;
+        }
+        case SPG_OPT_KEEP_FEATURES: h->keep_features = val != 0; break;
+        default: return fail(h, SPG_ERR_ARG, "unknown option " + std::to_string(opt));
+    }
+    // options change how rows are binned: the symbolic result must be redone
+    if (opt != SPG_OPT_TIMING) h->have_sym = false;
+    return SPG_OK;
+}
+
+spg_status spg_set_mlp(spg_handle h, const float* w, int32_t nw) {
+    if (!h) return SPG_ERR_ARG;
+    if (!w || nw != 1217) return fail(h, SPG_ERR_ARG, "the predictor has exactly 1217 weights");
+    SPG_TRY(ensure(h, h->mlp_w, 1217 * sizeof(float)));
+    HIP_TRY(h, hipMemcpyAsync(h->mlp_w.p, w, 1217 * sizeof(float), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    h->have_mlp = true;
+    h->have_sym = false;
+    return SPG_OK;
+}
+
+spg_status spg_get_stats(spg_handle h, spg_stats* out, int32_t size) {
+    if (!h || !out) return SPG_ERR_ARG;
+    if (size != (int32_t)sizeof(spg_stats)) return fail(h, SPG_ERR_ARG, "spg_stats size mismatch");
+    spg_stats& st = h->stats;
+    st.size = sizeof(spg_stats);
+    if (h->ev_made) {
+        if (h->sym_timed) {
+            st.sym_ms = elapsed(h, EV_SYM0, EV_SYM1);
+            st.analysis_ms = elapsed(h, EV_SYM0, EV_ANA1);
+            st.scan_ms = elapsed(h, EV_SCAN0, EV_SCAN1);
+            st.mlp_ms = st.binning == 1 ? elapsed(h, EV_MLP0, EV_MLP1) : 0.f;
+            for (int c = 0; c < NCLS; ++c)
+                st.sym_class_ms[c] = h->sym_cls_timed[c] ? elapsed(h, EV_SYMCLS + 2 * c, EV_SYMCLS + 2 * c + 1) : 0.f;
+        }
+        if (h->num_timed) {
+            st.num_ms = elapsed(h, EV_NUM0, EV_NUM1);
+            for (int c = 0; c < NCLS; ++c)
+                st.num_class_ms[c] = h->num_cls_timed[c] ? elapsed(h, EV_NUMCLS + 2 * c, EV_NUMCLS + 2 * c + 1) : 0.f;
+        }
+    }
+    *out = st;
+    return SPG_OK;
+}
+
+spg_status spg_export_rows(spg_handle h, float* x, float* y, int32_t* row_nnz) {
+    if (!h) return SPG_ERR_ARG;
+    if (!h->have_sym || !h->have_feats)
+        return fail(h, SPG_ERR_STATE, "needs a symbolic result computed with features (learned binning or keep-features)");
+    if (h->m > 0 && (!x || !y)) return fail(h, SPG_ERR_ARG, "null output");
+    launch_export_rows(h->stream, h->m, h->feats.as<float>(), h->row_blocks.as<int32_t>(), h->row_nnz.as<int32_t>(),
+                       x, y, row_nnz);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "export launch");
+    return SPG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,236 @@
+// Internal declarations of the spg library (not part of the C ABI).
+//
+// Accumulator design.  Every row of C is accumulated in a table of 32-column
+// blocks: a block id (column >> 5) carries a 32-bit mask of the columns seen
+// so far.  The symbolic phase ORs masks in, as the paper's compressed
+// accumulator does (section 2.2.1: columns represented by bits, bitwise OR as
+// the accumulate operation); nnz(C(i,:)) is the sum of the masks' popcounts.
+// The numeric phase builds the same masks, turns them into ranks with a
+// prefix sum of popcounts taken in ascending block order, and then adds every
+// product into a compact value array at
+//     rank(c) = prefix[block(c)] + popcount(mask[block(c)] & ((1 << (c & 31)) - 1)),
+// so the output comes out sorted without a sort of the columns themselves.
+//
+// The table is either *direct* (indexed by block - first block of the row:
+// the paper's dense accumulator restricted to the row's column range) or
+// *hashed* (the paper's HashmapAccumulator keyed by block id, open
+// addressing with linear probing), whichever is smaller.  It lives in LDS
+// for rows up to a per-row byte tier; longer rows take the global-memory path
+// (section 2.2.1: second-level accumulator in slow global memory), where the
+// mask table lives in LDS when it fits, else in a global slab, and values
+// accumulate straight into C's own storage with global atomics.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/spg.h"
+
+namespace spg {
+
+constexpr int NTIER = SPG_NTIER;     // tiers 0..8 in LDS, 9 = global memory
+constexpr int NCLS = SPG_NCLASS;     // class = mode * NTIER + tier
+constexpr int TIER_GLOBAL = 9;
+constexpr int MODE_DIRECT = 0;
+constexpr int MODE_HASHED = 1;
+constexpr uint8_t CLS_EMPTY = 255;
+constexpr int WIDE_THREADS = 1024;   // threads per row on the global path
+
+// error flags in Control::err
+constexpr int ERR_A_ROWPTR = 1;
+constexpr int ERR_A_COL = 2;
+constexpr int ERR_B_ROWPTR = 4;
+constexpr int ERR_B_COL = 8;
+constexpr int ERR_NNZ_OVERFLOW = 16;
+
+// Per-tier geometry: LDS bytes per row, threads per row, rows per workgroup.
+__host__ __device__ inline int tier_bytes(int t) { return 256 << t; }
+__host__ __device__ inline int tier_threads(int t) {
+    return t <= 2 ? (8 << t) : t <= 4 ? 64 : t == 5 ? 128 : t == 6 ? 256 : t == 7 ? 512 : 1024;
+}
+__host__ __device__ inline int tier_rows(int t) {
+    int g = tier_threads(t);
+    return g >= 256 ? 1 : 256 / g;
+}
+
+__host__ __device__ inline int64_t pow2ceil64(int64_t x) {
+    int64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// Runtime knobs of the class choice (copied into kernels by value).
+struct ClassCfg {
+    int32_t work_per_lane;    // products per lane that size a row's thread group
+    int32_t hash_max_blocks;  // numeric hashed table only up to this many blocks
+    int32_t lds_limit;        // LDS bytes per row beyond which rows go global
+    int32_t force_class;      // -1 or a class id
+    int32_t elem_bytes;       // 4 (FP32) or 8 (FP64)
+    int32_t pad[3];
+};
+
+// Row facts gathered by the analysis pass.
+//   x = smallest column, y = largest column, z = products (capped at 2^31-1),
+//   w = largest referenced B-row length
+using RowInfo = int4;
+
+// Table sizes, shared by the classifier and the kernels so both agree.
+__host__ __device__ inline int64_t row_words(int32_t cmin, int32_t cmax) {
+    return (int64_t)(cmax >> 5) - (int64_t)(cmin >> 5) + 1;
+}
+__host__ __device__ inline int64_t sym_hash_slots(int64_t est_blocks) {
+    return pow2ceil64(est_blocks * 2 > 16 ? est_blocks * 2 : 16);
+}
+__host__ __device__ inline int64_t num_hash_slots(int64_t blocks) {
+    return pow2ceil64(blocks * 2 > 16 ? blocks * 2 : 16);
+}
+__host__ __device__ inline int64_t align8(int64_t b) { return (b + 7) & ~(int64_t)7; }
+__host__ __device__ inline int64_t num_direct_bytes(int64_t words, int64_t n, int eb) {
+    return align8(words * 8) + n * (eb + 4);
+}
+__host__ __device__ inline int64_t num_hashed_bytes(int64_t blocks, int64_t n, int eb) {
+    return align8(num_hash_slots(blocks) * 12 + blocks * 8) + n * (eb + 4);
+}
+
+// Smallest LDS tier that holds `bytes`, raised until its thread group gives
+// at most work_per_lane products per lane; TIER_GLOBAL if it does not fit.
+__host__ __device__ inline int pick_tier(int64_t bytes, int64_t work, const ClassCfg& c) {
+    if (bytes > c.lds_limit) return TIER_GLOBAL;
+    int t = 0;
+    while (t < TIER_GLOBAL - 1 && tier_bytes(t) < bytes) ++t;
+    if (tier_bytes(t) < bytes) return TIER_GLOBAL;
+    while (t < TIER_GLOBAL - 1 && (int64_t)tier_threads(t) * c.work_per_lane < work &&
+           tier_bytes(t + 1) <= c.lds_limit)
+        ++t;
+    return t;
+}
+
+// Symbolic class of a row from its products, column range and an estimate
+// of its occupied blocks (an upper bound, or the learned prediction).
+__host__ __device__ inline int sym_class(int64_t ub, int32_t cmin, int32_t cmax, int64_t est_blocks,
+                                         const ClassCfg& c) {
+    if (ub <= 0) return CLS_EMPTY;
+    int64_t words = row_words(cmin, cmax);
+    int64_t est = est_blocks < words ? est_blocks : words;
+    if (est < 1) est = 1;
+    int64_t bd = words * 4, bh = sym_hash_slots(est) * 8;
+    if (c.force_class >= 0) {
+        int fm = c.force_class / NTIER, ft = c.force_class % NTIER;
+        if (ft == TIER_GLOBAL) return MODE_DIRECT * NTIER + TIER_GLOBAL;
+        int64_t need = fm == MODE_DIRECT ? bd : bh;
+        if (need <= tier_bytes(ft) && tier_bytes(ft) <= 65536) return c.force_class;
+    }
+    int mode = bd <= bh ? MODE_DIRECT : MODE_HASHED;
+    int t = pick_tier(bd <= bh ? bd : bh, ub, c);
+    if (t == TIER_GLOBAL) mode = MODE_DIRECT;
+    return mode * NTIER + t;
+}
+
+// Numeric class of a row from its exact size n and occupied blocks.
+__host__ __device__ inline int num_class(int64_t ub, int32_t cmin, int32_t cmax, int64_t n, int64_t blocks,
+                                         const ClassCfg& c) {
+    if (n <= 0) return CLS_EMPTY;
+    int64_t words = row_words(cmin, cmax);
+    int eb = c.elem_bytes;
+    int64_t bd = num_direct_bytes(words, n, eb), bh = num_hashed_bytes(blocks, n, eb);
+    if (c.force_class >= 0) {
+        int fm = c.force_class / NTIER, ft = c.force_class % NTIER;
+        if (ft == TIER_GLOBAL) return MODE_DIRECT * NTIER + TIER_GLOBAL;
+        int64_t need = fm == MODE_DIRECT ? bd : bh;
+        if (need <= tier_bytes(ft) && tier_bytes(ft) <= 65536) return c.force_class;
+    }
+    int mode = (blocks <= c.hash_max_blocks && bh < bd) ? MODE_HASHED : MODE_DIRECT;
+    int t = pick_tier(mode == MODE_HASHED ? bh : bd, ub, c);
+    if (t == TIER_GLOBAL) mode = MODE_DIRECT;
+    return mode * NTIER + t;
+}
+
+// Device-side control block: counters and histograms the host reads back
+// in one copy at each of symbolic's two synchronisation points.
+struct Control {
+    int32_t err;
+    int32_t overflow_rows;        // learned binning: rows queued for retry
+    int64_t products;             // sum of per-row products
+    int64_t nnz_c;
+    int32_t sym_hist[NCLS];
+    int32_t num_hist[NCLS];
+    int32_t empty_rows;
+    int32_t mispredicted;
+    int64_t max_words_sym_global; // widest row on the symbolic global path
+    int64_t max_words_all;        // widest row overall (sizes retry slabs)
+    int64_t max_words_num_global; // widest row on the numeric global path
+    int64_t num_a_nnz[NCLS];
+    int64_t num_c_nnz[NCLS];
+    int64_t num_products[NCLS];
+    int32_t tile_counter;         // dynamic tile id of the row-pointer scan
+    int32_t pad;
+};
+
+// ---- launch wrappers (spg_rows.hip) ----
+void launch_fill_i32(hipStream_t s, int32_t* p, int32_t v, int64_t n);
+void launch_fill_u8(hipStream_t s, void* p, uint8_t v, int64_t bytes);
+void launch_b_rowinfo(hipStream_t s, int32_t n, int32_t k, const int32_t* brp, const int32_t* bci, int64_t bnnz,
+                      int4* binfo, Control* ctl);
+void launch_a_rowinfo(hipStream_t s, int32_t m, int32_t n, const int32_t* arp, const int32_t* aci, int64_t annz,
+                      const int4* binfo, RowInfo* rinfo, float* feats, ClassCfg cfg, int learned,
+                      uint8_t* sym_cls, int32_t* row_nnz, int32_t* row_blocks, Control* ctl);
+void launch_mlp_classify(hipStream_t s, int32_t m, const float* feats, const float* w, const RowInfo* rinfo,
+                         ClassCfg cfg, float margin, uint8_t* sym_cls, Control* ctl);
+// groups rows by class; offsets come from the class histogram in device memory
+void launch_scatter(hipStream_t s, int32_t m, const uint8_t* cls, const int32_t* hist, int32_t* cursor, int32_t* perm);
+void launch_scan(hipStream_t s, int32_t m, const int32_t* row_nnz, const int32_t* row_blocks, const RowInfo* rinfo,
+                 const int32_t* arp, const uint8_t* sym_cls, int32_t* c_row_ptr, uint64_t* tile_status,
+                 ClassCfg cfg, uint8_t* num_cls, Control* ctl);
+void launch_export_rows(hipStream_t s, int32_t m, const float* feats, const int32_t* row_blocks,
+                        const int32_t* row_nnz_in, float* x, float* y, int32_t* row_nnz_out);
+int64_t scan_tiles(int32_t m);
+
+// ---- accumulator kernels (spg_accum.hip) ----
+struct SymArgs {
+    const int32_t* perm;
+    int32_t count;
+    int32_t tier;
+    int32_t mode;
+    int32_t vec;                  // lanes sharing one B row (power of two)
+    const int32_t* arp;
+    const int32_t* aci;
+    const int32_t* brp;
+    const int32_t* bci;
+    const RowInfo* rinfo;
+    int32_t* row_nnz;
+    int32_t* row_blocks;
+    int32_t* ovf_list;            // rows whose hashed table overflowed
+    Control* ctl;
+    uint32_t* slab;               // global path: one mask table per workgroup
+    int64_t slab_words;
+    const int32_t* count_dev;     // global path: device-side row count (or null)
+    int32_t wide_lds;             // global path: LDS bytes per workgroup
+};
+
+struct NumArgs {
+    const int32_t* perm;
+    int32_t count;
+    int32_t tier;
+    int32_t mode;
+    int32_t vec;
+    const int32_t* arp;
+    const int32_t* aci;
+    const void* av;
+    const int32_t* brp;
+    const int32_t* bci;
+    const void* bv;
+    const int32_t* crp;
+    const RowInfo* rinfo;
+    const int32_t* row_blocks;
+    int32_t* ccol;
+    void* cval;
+    uint32_t* slab;               // global path: masks and prefixes per workgroup
+    int64_t slab_words;
+    int32_t wide_lds;
+};
+
+// Launches one symbolic class; returns the grid size used.
+int launch_sym_class(hipStream_t s, const SymArgs& a, int grid_cap);
+int launch_num_class(hipStream_t s, const NumArgs& a, int elem_bytes, int grid_cap);
+
+}  // namespace spg

@@ -1,0 +1,435 @@
+// Row analysis, binning, row-pointer scan and small utility kernels.
+//
+// The symbolic phase of section 2.2.1 needs each row's size before C can be
+// allocated.  These kernels produce what the accumulator kernels consume:
+//   - per B row: length and column range (one pass over B's structure);
+//   - per A row: products (the row's FLOP count, which the paper uses to pick
+//     a parallelisation method), column range of C's row, largest referenced
+//     B row, and the row's accumulator class;
+//   - the permutation that groups rows of one class together;
+//   - C's row pointer as the exclusive prefix sum of the row counts (section
+//     2.2.1), single pass with decoupled look-back, plus the numeric-phase
+//     class of every row.
+// Index validity is checked in the same passes that read the indices.
+#include <hip/hip_runtime.h>
+#include <climits>
+
+#include "spg_internal.h"
+
+namespace spg {
+
+namespace {
+
+constexpr int ROW_LANES = 8;        // lanes per row in the analysis passes
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_u8(uint8_t* p, uint8_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <typename T>
+__device__ inline T xor_reduce_sum(T v) {
+    for (int d = ROW_LANES / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, ROW_LANES);
+    return v;
+}
+__device__ inline int xor_reduce_min(int v) {
+    for (int d = ROW_LANES / 2; d > 0; d >>= 1) v = min(v, __shfl_xor(v, d, ROW_LANES));
+    return v;
+}
+__device__ inline int xor_reduce_max(int v) {
+    for (int d = ROW_LANES / 2; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, ROW_LANES));
+    return v;
+}
+
+// B rows: length, smallest and largest column.  Checks B's row pointer and
+// column indices; a malformed row contributes nothing.
+__global__ __launch_bounds__(256) void k_b_rowinfo(int32_t n, int32_t k, const int32_t* __restrict__ brp,
+                                                   const int32_t* __restrict__ bci, int64_t bnnz,
+                                                   int4* __restrict__ binfo, Control* ctl) {
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t row = gid / ROW_LANES;
+    const int lane = (int)(gid % ROW_LANES);
+    int len = 0, mn = INT_MAX, mx = -1, bad = 0;
+    if (row < n) {
+        int32_t s = brp[row], e = brp[row + 1];
+        if (s < 0 || e < s || (int64_t)e > bnnz || (row == 0 && s != 0) || (row == n - 1 && (int64_t)e != bnnz)) {
+            bad = ERR_B_ROWPTR;
+        } else {
+            len = e - s;
+            for (int32_t q = s + lane; q < e; q += ROW_LANES) {
+                int c = bci[q];
+                if (c < 0 || c >= k) { bad = ERR_B_COL; continue; }
+                mn = min(mn, c);
+                mx = max(mx, c);
+            }
+        }
+    }
+    mn = xor_reduce_min(mn);
+    mx = xor_reduce_max(mx);
+    int anybad = xor_reduce_sum(bad);
+    if (row < n && lane == 0) {
+        if (anybad) len = 0, mn = INT_MAX, mx = -1;
+        binfo[row] = make_int4(len, mn, mx, 0);
+    }
+    if (bad) atomicOr(&ctl->err, bad);
+}
+
+__device__ inline float log2p1(int64_t v) { return log2f(1.0f + (float)v); }
+
+// A rows: products, column range, largest B row; symbolic class (upper-bound
+// binning) or features only (learned binning, classified by k_mlp_classify).
+__global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const int32_t* __restrict__ arp,
+                                                   const int32_t* __restrict__ aci, int64_t annz,
+                                                   const int4* __restrict__ binfo, RowInfo* __restrict__ rinfo,
+                                                   float* __restrict__ feats, ClassCfg cfg, int learned,
+                                                   uint8_t* __restrict__ sym_cls, int32_t* __restrict__ row_nnz,
+                                                   int32_t* __restrict__ row_blocks, Control* ctl) {
+    __shared__ int32_t hist[NCLS];
+    __shared__ int32_t empties;
+    __shared__ unsigned long long prod_sum;
+    if (threadIdx.x < NCLS) hist[threadIdx.x] = 0;
+    if (threadIdx.x == 0) empties = 0, prod_sum = 0;
+    __syncthreads();
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t row = gid / ROW_LANES;
+    const int lane = (int)(gid % ROW_LANES);
+    int64_t ub = 0;
+    int mx = 0, cmin = INT_MAX, cmax = -1, bad = 0, len = 0;
+    if (row < m) {
+        int32_t s = arp[row], e = arp[row + 1];
+        if (s < 0 || e < s || (int64_t)e > annz || (row == 0 && s != 0) || (row == m - 1 && (int64_t)e != annz)) {
+            bad = ERR_A_ROWPTR;
+        } else {
+            len = e - s;
+            for (int32_t p = s + lane; p < e; p += ROW_LANES) {
+                int j = aci[p];
+                if (j < 0 || j >= n) { bad = ERR_A_COL; continue; }
+                int4 b = binfo[j];
+                ub += b.x;
+                mx = max(mx, b.x);
+                cmin = min(cmin, b.y);
+                cmax = max(cmax, b.z);
+            }
+        }
+    }
+    ub = xor_reduce_sum(ub);
+    mx = xor_reduce_max(mx);
+    cmin = xor_reduce_min(cmin);
+    cmax = xor_reduce_max(cmax);
+    int anybad = xor_reduce_sum(bad);
+    if (bad) atomicOr(&ctl->err, bad);
+    if (row < m && lane == 0) {
+        if (anybad) ub = 0;
+        int32_t ubc = ub > INT_MAX ? INT_MAX : (int32_t)ub;
+        if (ub == 0) cmin = 0, cmax = 0;
+        rinfo[row] = make_int4(cmin, cmax, ubc, mx);
+        if (feats) {
+            feats[row * 3 + 0] = log2p1(len);
+            feats[row * 3 + 1] = log2p1(ub);
+            feats[row * 3 + 2] = log2p1(mx);
+        }
+        int cls = CLS_EMPTY;
+        if (ub == 0) {
+            row_nnz[row] = 0;
+            row_blocks[row] = 0;
+            atomicAdd(&empties, 1);
+            sym_cls[row] = CLS_EMPTY;
+        } else {
+            int64_t words = row_words(cmin, cmax);
+            atomicMax((unsigned long long*)&ctl->max_words_all, (unsigned long long)words);
+            atomicAdd(&prod_sum, (unsigned long long)ub);
+            if (!learned) {
+                cls = sym_class(ub, cmin, cmax, ub, cfg);
+                sym_cls[row] = (uint8_t)cls;
+                atomicAdd(&hist[cls], 1);
+                if (cls % NTIER == TIER_GLOBAL)
+                    atomicMax((unsigned long long*)&ctl->max_words_sym_global, (unsigned long long)words);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < NCLS && hist[threadIdx.x]) atomicAdd(&ctl->sym_hist[threadIdx.x], hist[threadIdx.x]);
+    if (threadIdx.x == 0) {
+        if (empties) atomicAdd(&ctl->empty_rows, empties);
+        if (prod_sum) atomicAdd((unsigned long long*)&ctl->products, prod_sum);
+    }
+}
+
+// Learned binning: one thread per row evaluates the 3-32-32-1 network on the
+// row's features (weights are wave-uniform, so they are read as scalars) and
+// sizes the symbolic table from 2^(y + margin) - 1 occupied blocks.
+__global__ __launch_bounds__(256) void k_mlp_classify(int32_t m, const float* __restrict__ feats,
+                                                      const float* __restrict__ w, const RowInfo* __restrict__ rinfo,
+                                                      ClassCfg cfg, float margin, uint8_t* __restrict__ sym_cls,
+                                                      Control* ctl) {
+    __shared__ int32_t hist[NCLS];
+    if (threadIdx.x < NCLS) hist[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (row < m) {
+        RowInfo ri = rinfo[row];
+        if (ri.z > 0) {
+            float x0 = feats[row * 3], x1 = feats[row * 3 + 1], x2 = feats[row * 3 + 2];
+            const float* W1 = w;
+            const float* b1 = w + 96;
+            const float* W2 = w + 128;
+            const float* b2 = w + 1152;
+            const float* w3 = w + 1184;
+            const float b3 = w[1216];
+            float h1[32];
+#pragma unroll
+            for (int o = 0; o < 32; ++o) {
+                float z = b1[o] + W1[o * 3] * x0 + W1[o * 3 + 1] * x1 + W1[o * 3 + 2] * x2;
+                h1[o] = z > 0.f ? z : 0.f;
+            }
+            float y = b3;
+#pragma unroll 4
+            for (int o = 0; o < 32; ++o) {
+                float z = b2[o];
+#pragma unroll
+                for (int i = 0; i < 32; ++i) z += W2[o * 32 + i] * h1[i];
+                y += w3[o] * (z > 0.f ? z : 0.f);
+            }
+            float e = exp2f(fminf(y + margin, 40.f)) - 1.f;
+            int64_t est = e < 1.f ? 1 : (int64_t)ceilf(e);
+            int cls = sym_class(ri.z, ri.x, ri.y, est, cfg);
+            sym_cls[row] = (uint8_t)cls;
+            atomicAdd(&hist[cls], 1);
+            if (cls % NTIER == TIER_GLOBAL)
+                atomicMax((unsigned long long*)&ctl->max_words_sym_global,
+                          (unsigned long long)row_words(ri.x, ri.y));
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < NCLS && hist[threadIdx.x]) atomicAdd(&ctl->sym_hist[threadIdx.x], hist[threadIdx.x]);
+}
+
+// Groups rows by class: each workgroup counts its rows per class, reserves a
+// range per class with one atomic, and writes its row ids there.
+__global__ __launch_bounds__(256) void k_scatter(int32_t m, const uint8_t* __restrict__ cls,
+                                                 const int32_t* __restrict__ hist, int32_t* __restrict__ cursor,
+                                                 int32_t* __restrict__ perm) {
+    __shared__ int32_t cnt[NCLS];
+    __shared__ int32_t base[NCLS];
+    __shared__ int32_t off[NCLS];
+    if (threadIdx.x < NCLS) cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int c = 0; c < NCLS; ++c) off[c] = run, run += hist[c];
+    }
+    __syncthreads();
+    const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int c = row < m ? cls[row] : CLS_EMPTY;
+    int local = 0;
+    if (c != CLS_EMPTY) local = atomicAdd(&cnt[c], 1);
+    __syncthreads();
+    if (threadIdx.x < NCLS && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
+    __syncthreads();
+    if (c != CLS_EMPTY) perm[off[c] + base[c] + local] = (int32_t)row;
+}
+
+// Status word of the look-back scan: 2 flag bits over a 62-bit value.
+constexpr uint64_t ST_AGG = 1ull << 62;
+constexpr uint64_t ST_PRE = 2ull << 62;
+constexpr uint64_t ST_VAL = (1ull << 62) - 1;
+
+// Row pointer = exclusive prefix sum of row_nnz, in 64-bit, single pass with
+// decoupled look-back over tiles taken in launch order.  Also assigns each
+// row's numeric class (its exact size is now known) and counts rows whose
+// symbolic class differed from the class their true size asks for.
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan(int32_t m, const int32_t* __restrict__ row_nnz,
+                                                       const int32_t* __restrict__ row_blocks,
+                                                       const RowInfo* __restrict__ rinfo,
+                                                       const int32_t* __restrict__ arp,
+                                                       const uint8_t* __restrict__ sym_cls,
+                                                       int32_t* __restrict__ c_row_ptr, uint64_t* tile_status,
+                                                       ClassCfg cfg, uint8_t* __restrict__ num_cls, Control* ctl) {
+    __shared__ int32_t tile_sh;
+    __shared__ int64_t wsum[SCAN_THREADS / 64];
+    __shared__ int64_t tile_prefix;
+    __shared__ int32_t hist[NCLS];
+    __shared__ unsigned long long s_annz[NCLS], s_cnnz[NCLS], s_prod[NCLS];
+    __shared__ int32_t mispred;
+    if (threadIdx.x == 0) tile_sh = atomicAdd(&ctl->tile_counter, 1), mispred = 0;
+    if (threadIdx.x < NCLS) hist[threadIdx.x] = 0, s_annz[threadIdx.x] = 0, s_cnnz[threadIdx.x] = 0,
+                                    s_prod[threadIdx.x] = 0;
+    __syncthreads();
+    const int tile = tile_sh;
+    const int64_t r0 = (int64_t)tile * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    int64_t v[SCAN_ITEMS];
+    int64_t run = 0;
+#pragma unroll
+    for (int t = 0; t < SCAN_ITEMS; ++t) {
+        int64_t r = r0 + t;
+        int64_t c = 0;
+        if (r < m) {
+            c = row_nnz[r];
+            RowInfo ri = rinfo[r];
+            int blocks = row_blocks[r];
+            int nc = num_class(ri.z, ri.x, ri.y, c, blocks, cfg);
+            num_cls[r] = (uint8_t)nc;
+            if (nc != CLS_EMPTY) {
+                atomicAdd(&hist[nc], 1);
+                atomicAdd(&s_annz[nc], (unsigned long long)(arp[r + 1] - arp[r]));
+                atomicAdd(&s_cnnz[nc], (unsigned long long)c);
+                atomicAdd(&s_prod[nc], (unsigned long long)ri.z);
+                if (nc % NTIER == TIER_GLOBAL)
+                    atomicMax((unsigned long long*)&ctl->max_words_num_global,
+                              (unsigned long long)row_words(ri.x, ri.y));
+                int ideal = sym_class(ri.z, ri.x, ri.y, blocks, cfg);
+                if (ideal != sym_cls[r]) atomicAdd(&mispred, 1);
+            }
+        }
+        run += c;
+        v[t] = run;
+    }
+    // block scan of the per-thread totals
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int64_t x = run;
+    for (int d = 1; d < 64; d <<= 1) {
+        int64_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    int64_t wpre = 0, agg = 0;
+    for (int u = 0; u < SCAN_THREADS / 64; ++u) {
+        if (u < wv) wpre += wsum[u];
+        agg += wsum[u];
+    }
+    const int64_t thread_excl = wpre + x - run;
+    // decoupled look-back: publish the aggregate, then add predecessors
+    if (threadIdx.x == 0) {
+        int64_t prefix = 0;
+        if (tile == 0) {
+            __hip_atomic_store(&tile_status[0], ST_PRE | (uint64_t)agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(&tile_status[tile], ST_AGG | (uint64_t)agg, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            // tiles are numbered in the order they started, so every predecessor
+            // is resident or finished and each wait below ends
+            for (int t = tile - 1; t >= 0; --t) {
+                uint64_t st;
+                do {
+                    st = __hip_atomic_load(&tile_status[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                } while ((st >> 62) == 0);
+                prefix += (int64_t)(st & ST_VAL);
+                if ((st >> 62) == 2) break;
+            }
+            __hip_atomic_store(&tile_status[tile], ST_PRE | (uint64_t)(prefix + agg), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        tile_prefix = prefix;
+    }
+    __syncthreads();
+    const int64_t base = tile_prefix + thread_excl;
+    bool ovf = false;
+#pragma unroll
+    for (int t = 0; t < SCAN_ITEMS; ++t) {
+        int64_t r = r0 + t;
+        if (r < m) {
+            int64_t val = base + v[t];
+            if (val > INT_MAX) ovf = true;
+            c_row_ptr[r + 1] = (int32_t)val;
+            if (r == m - 1) ctl->nnz_c = val;
+        }
+    }
+    if (tile == 0 && threadIdx.x == 0) c_row_ptr[0] = 0;
+    if (ovf) atomicOr(&ctl->err, ERR_NNZ_OVERFLOW);
+    __syncthreads();
+    if (threadIdx.x < NCLS && hist[threadIdx.x]) {
+        atomicAdd(&ctl->num_hist[threadIdx.x], hist[threadIdx.x]);
+        atomicAdd((unsigned long long*)&ctl->num_a_nnz[threadIdx.x], s_annz[threadIdx.x]);
+        atomicAdd((unsigned long long*)&ctl->num_c_nnz[threadIdx.x], s_cnnz[threadIdx.x]);
+        atomicAdd((unsigned long long*)&ctl->num_products[threadIdx.x], s_prod[threadIdx.x]);
+    }
+    if (threadIdx.x == 0 && mispred) atomicAdd(&ctl->mispredicted, mispred);
+}
+
+__global__ void k_export_rows(int32_t m, const float* __restrict__ feats, const int32_t* __restrict__ row_blocks,
+                              const int32_t* __restrict__ row_nnz_in, float* __restrict__ x, float* __restrict__ y,
+                              int32_t* __restrict__ row_nnz_out) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    x[r * 3] = feats[r * 3];
+    x[r * 3 + 1] = feats[r * 3 + 1];
+    x[r * 3 + 2] = feats[r * 3 + 2];
+    y[r] = log2f(1.0f + (float)row_blocks[r]);
+    if (row_nnz_out) row_nnz_out[r] = row_nnz_in[r];
+}
+
+inline unsigned grid_for(int64_t threads, int per_block) {
+    int64_t g = (threads + per_block - 1) / per_block;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+int64_t scan_tiles(int32_t m) { return ((int64_t)m + SCAN_TILE - 1) / SCAN_TILE; }
+
+void launch_fill_i32(hipStream_t s, int32_t* p, int32_t v, int64_t n) {
+    if (n <= 0) return;
+    int64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)g), dim3(256), 0, s, p, v, n);
+}
+
+void launch_fill_u8(hipStream_t s, void* p, uint8_t v, int64_t bytes) {
+    if (bytes <= 0) return;
+    int64_t g = (bytes + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)g), dim3(256), 0, s, (uint8_t*)p, v, bytes);
+}
+
+void launch_b_rowinfo(hipStream_t s, int32_t n, int32_t k, const int32_t* brp, const int32_t* bci, int64_t bnnz,
+                      int4* binfo, Control* ctl) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_b_rowinfo, dim3(grid_for((int64_t)n * ROW_LANES, 256)), dim3(256), 0, s, n, k, brp, bci,
+                       bnnz, binfo, ctl);
+}
+
+void launch_a_rowinfo(hipStream_t s, int32_t m, int32_t n, const int32_t* arp, const int32_t* aci, int64_t annz,
+                      const int4* binfo, RowInfo* rinfo, float* feats, ClassCfg cfg, int learned,
+                      uint8_t* sym_cls, int32_t* row_nnz, int32_t* row_blocks, Control* ctl) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_a_rowinfo, dim3(grid_for((int64_t)m * ROW_LANES, 256)), dim3(256), 0, s, m, n, arp, aci,
+                       annz, binfo, rinfo, feats, cfg, learned, sym_cls, row_nnz, row_blocks, ctl);
+}
+
+void launch_mlp_classify(hipStream_t s, int32_t m, const float* feats, const float* w, const RowInfo* rinfo,
+                         ClassCfg cfg, float margin, uint8_t* sym_cls, Control* ctl) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_mlp_classify, dim3(grid_for(m, 256)), dim3(256), 0, s, m, feats, w, rinfo, cfg, margin,
+                       sym_cls, ctl);
+}
+
+void launch_scatter(hipStream_t s, int32_t m, const uint8_t* cls, const int32_t* hist, int32_t* cursor,
+                    int32_t* perm) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for(m, 256)), dim3(256), 0, s, m, cls, hist, cursor, perm);
+}
+
+void launch_scan(hipStream_t s, int32_t m, const int32_t* row_nnz, const int32_t* row_blocks, const RowInfo* rinfo,
+                 const int32_t* arp, const uint8_t* sym_cls, int32_t* c_row_ptr, uint64_t* tile_status,
+                 ClassCfg cfg, uint8_t* num_cls, Control* ctl) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_scan, dim3((unsigned)scan_tiles(m)), dim3(SCAN_THREADS), 0, s, m, row_nnz, row_blocks,
+                       rinfo, arp, sym_cls, c_row_ptr, tile_status, cfg, num_cls, ctl);
+}
+
+void launch_export_rows(hipStream_t s, int32_t m, const float* feats, const int32_t* row_blocks,
+                        const int32_t* row_nnz_in, float* x, float* y, int32_t* row_nnz_out) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_export_rows, dim3(grid_for(m, 256)), dim3(256), 0, s, m, feats, row_blocks, row_nnz_in, x,
+                       y, row_nnz_out);
+}
+
+}  // namespace spg

@@ -1,0 +1,166 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Structure (row pointer, sorted column indices) must be bit-identical; values
+within 1e-12 (FP64) or 1e-5 (FP32) of the FP64 oracle, componentwise against
+sum |A(i,j)||B(j,c)|; exactly equal where all arithmetic is exact.
+"""
+import numpy as np
+import pytest
+
+from paper_2103_11991_amd import gen
+from gpu_util import compare, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def setup_module(module):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def test_laplace2d_squared_is_bit_exact():
+    A = gen.laplace2d_5pt(64)
+    rp, c, v, op = run_gpu(A, A)
+    assert int(rp[-1]) == 51972
+    compare(A, A, rp, c, v, exact=True)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("seed", range(6))
+def test_random_shapes(seed, dtype):
+    rng = np.random.default_rng(seed)
+    m, n, k = (int(x) for x in rng.integers(1, 700, size=3))
+    A = gen.random_csr(m, n, 0, int(rng.integers(1, 40)), seed=seed, dtype=dtype, empty_frac=0.15,
+                       duplicates=seed % 3 == 0, sorted_rows=seed % 2 == 0)
+    B = gen.random_csr(n, k, 0, int(rng.integers(1, 60)), seed=seed + 77, dtype=dtype, empty_frac=0.1,
+                       duplicates=seed % 4 == 1, sorted_rows=seed % 3 != 1)
+    rp, c, v, _ = run_gpu(A, B)
+    compare(A, B, rp, c, v)
+
+
+@pytest.mark.parametrize("cls", list(range(20)))
+def test_every_accumulator_class(cls):
+    """All rows forced through one (mode, tier) class; rows that cannot fit fall back."""
+    A = gen.random_csr(400, 300, 0, 12, seed=cls, empty_frac=0.1)
+    B = gen.random_csr(300, 2000, 0, 20, seed=cls + 1)
+    rp, c, v, op = run_gpu(A, B, force_class=cls)
+    compare(A, B, rp, c, v)
+    S = gen.stencil27(9, seed=3)
+    rp, c, v, op = run_gpu(S, S, force_class=cls)
+    compare(S, S, rp, c, v)
+
+
+def test_global_path_with_global_slabs():
+    """Rows spanning ~2^21 columns: mask tables exceed LDS and live in global slabs."""
+    A = gen.random_csr(40, 60, 1, 10, seed=5)
+    B = gen.random_csr(60, 1 << 21, 20, 400, seed=6)
+    rp, c, v, op = run_gpu(A, B)
+    st = op.stats()
+    assert st["sym_rows"][9] > 0 and st["num_rows"][9] > 0
+    compare(A, B, rp, c, v)
+
+
+def test_long_rows_accumulate_in_output():
+    """Dense-ish rows with thousands of entries go to the global path (values in C)."""
+    A = gen.random_csr(30, 500, 50, 400, seed=8)
+    B = gen.random_csr(500, 20000, 50, 500, seed=9, dtype=np.float64)
+    rp, c, v, op = run_gpu(A, B)
+    assert op.stats()["num_rows"][9] > 0
+    compare(A, B, rp, c, v)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_identity_products(seed):
+    A = gen.random_csr(500, 400, 0, 30, seed=seed, empty_frac=0.2)
+    for X, Y in ((A, gen.identity(400)), (gen.identity(500), A)):
+        rp, c, v, _ = run_gpu(X, Y)
+        np.testing.assert_array_equal(rp, A.row_ptr.astype(np.int64))
+        np.testing.assert_array_equal(c, A.col_idx)
+        np.testing.assert_array_equal(v, A.values)
+
+
+def test_stencil27_closed_form_and_parity():
+    N = 20
+    A = gen.stencil27(N, seed=2)
+    rp, c, v, op = run_gpu(A, A)
+    assert int(rp[-1]) == (5 * N - 6) ** 3
+    assert op.stats()["products"] == (9 * N - 10) ** 3
+    compare(A, A, rp, c, v)
+
+
+def test_rmat_fp32():
+    A = gen.rmat(12, seed=1)
+    rp, c, v, _ = run_gpu(A, A)
+    compare(A, A, rp, c, v)
+
+
+def test_galerkin_exact():
+    N = 16
+    A = gen.laplace3d_7pt(N)
+    P = gen.aggregation_P(N)
+    R = gen.transpose(P)
+    rp, c, v, _ = run_gpu(A, P)
+    AP = gen.Csr(A.m, P.n, rp.astype(np.int32), c, v)
+    rp2, c2, v2, _ = run_gpu(R, AP)
+    ref = gen.laplace3d_7pt(N // 2, scale=4.0)
+    np.testing.assert_array_equal(rp2, ref.row_ptr.astype(np.int64))
+    np.testing.assert_array_equal(c2, ref.col_idx)
+    np.testing.assert_array_equal(v2, ref.values)
+
+
+def test_symbolic_reuse_with_new_values():
+    import torch
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
+    A0 = gen.laplace3d_7pt(12)
+    P = gen.aggregation_P(12)
+    dA = DeviceCsr.from_host(A0)
+    dP = DeviceCsr.from_host(P)
+    op = SpGEMM(dA, dP)
+    rp, nnz = op.symbolic()
+    rph = rp.cpu().numpy().astype(np.int64)
+    for t in range(1, 4):
+        A = A0.with_values(gen.sweep_values(A0, t))
+        col, val = op.numeric(a_vals=torch.from_numpy(A.values).cuda())
+        torch.cuda.synchronize()
+        compare(A, P, rph, col.cpu().numpy(), val.cpu().numpy())
+
+
+def test_empty_and_degenerate():
+    for m, n, k, la, lb in ((0, 5, 5, 3, 3), (5, 0, 5, 0, 3), (5, 5, 0, 3, 0), (7, 6, 5, 0, 0), (1, 1, 1, 1, 1)):
+        A = gen.random_csr(m, n, 0, la, seed=1)
+        B = gen.random_csr(n, k, 0, lb, seed=2)
+        rp, c, v, _ = run_gpu(A, B)
+        assert rp.shape == (m + 1,)
+        compare(A, B, rp, c, v)
+
+
+def test_bad_index_is_reported():
+    import torch
+    from paper_2103_11991_amd._lib import SpgError
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
+    A = gen.random_csr(50, 40, 1, 5, seed=3)
+    bad = A.col_idx.copy()
+    bad[7] = 40  # one past the last column
+    dA = DeviceCsr.from_host(gen.Csr(50, 40, A.row_ptr, bad, A.values))
+    dB = DeviceCsr.from_host(gen.random_csr(40, 30, 1, 5, seed=4))
+    op = SpGEMM(dA, dB)
+    with pytest.raises(SpgError) as e:
+        op.symbolic()
+    assert e.value.status_name == "SPG_ERR_INDEX"
+    rp = A.row_ptr.copy()
+    rp[10] = rp[11] + 1  # not monotone
+    dA2 = DeviceCsr.from_host(gen.Csr(50, 40, rp, A.col_idx, A.values))
+    with pytest.raises(SpgError):
+        SpGEMM(dA2, dB).symbolic()
+    torch.cuda.synchronize()
+
+
+def test_numeric_before_symbolic_is_state_error():
+    from paper_2103_11991_amd import _lib
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
+    A = DeviceCsr.from_host(gen.random_csr(10, 10, 1, 3, seed=1))
+    op = SpGEMM(A, A)
+    with pytest.raises(_lib.SpgError) as e:
+        _lib.spg_numeric(op.h, A.values.data_ptr(), A.values.data_ptr(), A.col_idx.data_ptr(), A.values.data_ptr())
+    assert e.value.status_name == "SPG_ERR_STATE"
