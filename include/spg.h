@@ -187,12 +187,83 @@ spg_status spg_mlp_backward(void* stream, const float* w, const float* x, const 
                             const float* dy, int32_t rows, float* dw);
 
 /* Trains w_inout (device, 1217 floats) in place with minibatch Adam
-   (beta1 0.9, beta2 0.999, eps 1e-8) on the mean squared error between the
-   network and y, visiting x/y rows in the given order, `batch` rows per step,
-   for `epochs` passes.  loss_out (device, may be NULL) receives the mean
-   loss of each epoch (`epochs` floats).  Asynchronous on `stream`. */
+   (beta1 0.9, beta2 0.999, eps 1e-8), visiting x/y rows in the given order,
+   `batch` rows per step, for `epochs` passes.  The loss per row is the
+   squared error (y - net)^2 when quantile == 0, else the pinball loss of
+   level `quantile` in (0, 1): quantile * d if d >= 0 else (quantile - 1) * d
+   with d = y - net, whose minimiser is that quantile of y.  Each step
+   minimises the batch mean.  loss_out (device, may be NULL) receives the
+   mean loss of each epoch (`epochs` floats).  Asynchronous on `stream`. */
 spg_status spg_mlp_train(void* stream, const float* x, const float* y, int32_t rows,
-                         int32_t epochs, int32_t batch, float lr, float* w_inout, float* loss_out);
+                         int32_t epochs, int32_t batch, float lr, float quantile,
+                         float* w_inout, float* loss_out);
+
+/* ---- batches: many independent products C_i = A_i * B_i ----------------
+   The products run as one block-diagonal product, so rows of all products
+   share the same accumulator launches; after planning, a whole run (both
+   phases, or numeric alone) is one hipGraphLaunch of a graph captured on the
+   first run with the given pointers.  This follows the paper's point that
+   fusing work into fewer launches matters as per-launch work shrinks
+   (section 2.2.2, Table t:jacobifusedspgemm discussion) and its functor-level
+   batching of many small problems in one parallel dispatch (section 3). */
+typedef struct spg_batch_s* spg_batch;
+
+/* Creates a batch of `count` products over pooled device CSR arrays.  Host
+   arrays m, n, k, a_nnz, b_nnz (length count) give each product's shape.
+   Product i's A row pointer (m[i]+1 entries, from 0 to a_nnz[i]) starts at
+   entry sum_{j<i}(m[j]+1) of a_row_ptr_pool and its columns at
+   sum_{j<i} a_nnz[j] of a_col_pool; B likewise with n[i]+1 and b_nnz[i].
+   Value pools (spg_batch_run) follow the column pools' layout.  The
+   structure is packed once on the device (A copied, B's columns borrowed:
+   b_col_pool must stay valid).  Every product's arrays are validated
+   (SPG_ERR_INDEX).  `stream` NULL makes the batch create its own stream. */
+spg_status spg_batch_create(spg_batch* b, void* stream, spg_dtype dt, int32_t count,
+                            const int32_t* m, const int32_t* n, const int32_t* k,
+                            const int64_t* a_nnz, const int64_t* b_nnz,
+                            const int32_t* a_row_ptr_pool, const int32_t* a_col_pool,
+                            const int32_t* b_row_ptr_pool, const int32_t* b_col_pool);
+
+/* Releases the batch (null accepted). */
+spg_status spg_batch_destroy(spg_batch b);
+
+/* Message of the last failing call on b. */
+const char* spg_batch_last_error(spg_batch b);
+
+/* Same options as spg_set_option / spg_set_mlp, applied to every product;
+   they invalidate the plan. */
+spg_status spg_batch_set_option(spg_batch b, int32_t opt, int64_t val);
+spg_status spg_batch_set_mlp(spg_batch b, const float* w, int32_t nw);
+
+/* Plans the batch with one synchronised symbolic run: writes the total
+   nnz over all C_i to *nnz_total and, when non-null, host arrays
+   c_row_off[count+1] (first row of C_i in the pooled row pointer) and
+   c_nnz_off[count+1] (first entry of C_i in the pooled column/value arrays). */
+spg_status spg_batch_plan(spg_batch b, int64_t* nnz_total, int64_t* c_row_off, int64_t* c_nnz_off);
+
+/* Runs all products as one graph launch on the batch's stream (asynchronous).
+   a_val_pool / b_val_pool: device values in the column pools' layout.
+   c_row_ptr: device int32[sum m + 1], the pooled row pointer (offsets into
+   the C pools, so C_i's row pointer is its slice minus c_nnz_off[i]);
+   c_col / c_val: device pools with capacity >= nnz_total entries.
+   numeric_only = 0: both phases; 1: numeric alone on the planned structure
+   (the planned row pointer is copied into c_row_ptr).  Allocates nothing;
+   the graph is re-captured when a pointer or the mode changes. */
+spg_status spg_batch_run(spg_batch b, const void* a_val_pool, const void* b_val_pool,
+                         int32_t* c_row_ptr, int32_t* c_col, void* c_val, int64_t capacity,
+                         int32_t numeric_only);
+
+/* Autotuner: times every combination of products per lane {8,16,32},
+   vector width {auto,4,8,16} and hashed-table block limit {32,64,128} on
+   full runs of the batch (into the given output pools), keeps the fastest
+   and re-plans.  chosen (host int32[3], may be NULL) receives the three
+   settings, best_ms (host, may be NULL) the best run time. */
+spg_status spg_batch_tune(spg_batch b, const void* a_val_pool, const void* b_val_pool,
+                          int32_t* c_row_ptr, int32_t* c_col, void* c_val, int64_t capacity,
+                          int32_t* chosen, float* best_ms);
+
+/* Statistics of the batch's last planned or tuned symbolic run and of its
+   numeric launches (per-class rows, products, times when timing is on). */
+spg_status spg_batch_get_stats(spg_batch b, spg_stats* out, int32_t size);
 
 #ifdef __cplusplus
 }

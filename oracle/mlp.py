@@ -10,7 +10,7 @@ Network, for one row with features x = (log2(1+len), log2(1+ub), log2(1+mx)):
     y  = w3 . h2 + b3                        (scalar)
 Flat parameter vector (1217 values, row-major): W1[32][3], b1[32],
 W2[32][32], b2[32], w3[32], b3.  relu'(0) is taken as 0.
-Loss: mean squared error over a minibatch.  Optimiser: Adam (Kingma and Ba,
+Loss: mean squared error, or the pinball (quantile) loss, over a minibatch.  Optimiser: Adam (Kingma and Ba,
 ICLR 2015) with beta1 = 0.9, beta2 = 0.999, eps = 1e-8 and bias correction.
 
 parity unpinned against the paper (no network there); pinned by finite
@@ -84,6 +84,18 @@ def mse(y, t):
     return float(np.mean((y - t) ** 2)), 2.0 * (y - t) / max(y.size, 1)
 
 
+def pinball(y, t, q):
+    """Pinball loss of level q (mean over rows) and its gradient in y.
+    d = t - y; loss q*d for d >= 0, (q-1)*d otherwise; d loss/dy = -q (d > 0),
+    1 - q (d <= 0)."""
+    y = np.asarray(y, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    d = t - y
+    n = max(y.size, 1)
+    loss = np.where(d >= 0, q * d, (q - 1.0) * d)
+    return float(loss.mean()), np.where(d > 0, -q, 1.0 - q) / n
+
+
 def adam_step(w, g, m, v, step, lr):
     """One Adam update; ``step`` counts from 1.  Returns new (w, m, v)."""
     m = BETA1 * m + (1.0 - BETA1) * g
@@ -93,8 +105,9 @@ def adam_step(w, g, m, v, step, lr):
     return w - lr * mh / (np.sqrt(vh) + EPS), m, v
 
 
-def train(X, T, w0, epochs, lr, batch):
-    """Minibatch Adam over the rows in the given order (no reshuffle).
+def train(X, T, w0, epochs, lr, batch, quantile=0.0):
+    """Minibatch Adam over the rows in the given order (no reshuffle), on the
+    squared error (quantile 0) or the pinball loss of level ``quantile``.
 
     Returns (w, mean loss per epoch)."""
     w = np.asarray(w0, dtype=np.float64).copy()
@@ -108,7 +121,7 @@ def train(X, T, w0, epochs, lr, batch):
         for s in range(0, N, batch):
             xb, tb = X[s:s + batch], T[s:s + batch]
             y, cache = forward(w, xb)
-            L, dy = mse(y, tb)
+            L, dy = mse(y, tb) if quantile == 0 else pinball(y, tb, quantile)
             g = backward(w, cache, dy)
             step += 1
             w, m, v = adam_step(w, g, m, v, step, lr)

@@ -23,7 +23,9 @@ STATUS = ["SPG_OK", "SPG_ERR_ARG", "SPG_ERR_SHAPE", "SPG_ERR_STATE", "SPG_ERR_IN
           "SPG_ERR_ALLOC", "SPG_ERR_HIP", "SPG_ERR_UNSUPPORTED"]
 EXPORTS = ["spg_status_string", "spg_last_error", "spg_create", "spg_destroy", "spg_set_stream",
            "spg_set_matrices", "spg_symbolic", "spg_numeric", "spg_set_option", "spg_set_mlp", "spg_get_stats",
-           "spg_export_rows", "spg_mlp_forward", "spg_mlp_backward", "spg_mlp_train"]
+           "spg_export_rows", "spg_mlp_forward", "spg_mlp_backward", "spg_mlp_train",
+           "spg_batch_create", "spg_batch_destroy", "spg_batch_last_error", "spg_batch_set_option",
+           "spg_batch_set_mlp", "spg_batch_plan", "spg_batch_run", "spg_batch_tune", "spg_batch_get_stats"]
 
 
 class SpgError(RuntimeError):
@@ -74,7 +76,16 @@ def load() -> ctypes.CDLL:
         "spg_export_rows": ([p, p, p, p], ctypes.c_int),
         "spg_mlp_forward": ([p, p, p, i32, p, p], ctypes.c_int),
         "spg_mlp_backward": ([p, p, p, p, p, i32, p], ctypes.c_int),
-        "spg_mlp_train": ([p, p, p, i32, i32, i32, f32, p, p], ctypes.c_int),
+        "spg_mlp_train": ([p, p, p, i32, i32, i32, f32, f32, p, p], ctypes.c_int),
+        "spg_batch_create": ([ctypes.POINTER(p), p, ctypes.c_int, i32, p, p, p, p, p, p, p, p, p], ctypes.c_int),
+        "spg_batch_destroy": ([p], ctypes.c_int),
+        "spg_batch_last_error": ([p], ctypes.c_char_p),
+        "spg_batch_set_option": ([p, i32, i64], ctypes.c_int),
+        "spg_batch_set_mlp": ([p, p, i32], ctypes.c_int),
+        "spg_batch_plan": ([p, ctypes.POINTER(i64), p, p], ctypes.c_int),
+        "spg_batch_run": ([p, p, p, p, p, p, i64, i32], ctypes.c_int),
+        "spg_batch_tune": ([p, p, p, p, p, p, i64, p, p], ctypes.c_int),
+        "spg_batch_get_stats": ([p, ctypes.POINTER(spg_stats), i32], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -151,6 +162,63 @@ def spg_mlp_backward(stream: int, w: int, x: int, act: int, dy: int, rows: int, 
     _check(load().spg_mlp_backward(stream or None, w, x, act, dy, rows, dw))
 
 
-def spg_mlp_train(stream: int, x: int, y: int, rows: int, epochs: int, batch: int, lr: float, w_inout: int,
-                  loss_out: int = 0) -> None:
-    _check(load().spg_mlp_train(stream or None, x, y, rows, epochs, batch, lr, w_inout, loss_out or None))
+def spg_mlp_train(stream: int, x: int, y: int, rows: int, epochs: int, batch: int, lr: float, quantile: float,
+                  w_inout: int, loss_out: int = 0) -> None:
+    _check(load().spg_mlp_train(stream or None, x, y, rows, epochs, batch, lr, quantile, w_inout, loss_out or None))
+
+
+def _bcheck(rc: int, b=None):
+    if rc != 0:
+        msg = load().spg_batch_last_error(b).decode() if b else ""
+        raise SpgError(rc, msg or (STATUS[rc] if 0 <= rc < len(STATUS) else str(rc)))
+
+
+def spg_batch_create(stream: int, dtype: int, count: int, m_ptr: int, n_ptr: int, k_ptr: int, a_nnz_ptr: int,
+                     b_nnz_ptr: int, a_row_ptr_pool: int, a_col_pool: int, b_row_ptr_pool: int,
+                     b_col_pool: int) -> int:
+    """Host pointers m_ptr..b_nnz_ptr (int32/int64 arrays), device pools."""
+    b = ctypes.c_void_p()
+    _bcheck(load().spg_batch_create(ctypes.byref(b), stream or None, dtype, count, m_ptr, n_ptr, k_ptr, a_nnz_ptr,
+                                    b_nnz_ptr, a_row_ptr_pool or None, a_col_pool or None, b_row_ptr_pool or None,
+                                    b_col_pool or None))
+    return b.value
+
+
+def spg_batch_destroy(b: int) -> None:
+    _bcheck(load().spg_batch_destroy(b))
+
+
+def spg_batch_set_option(b: int, opt, val: int) -> None:
+    opt = OPT[opt] if isinstance(opt, str) else int(opt)
+    _bcheck(load().spg_batch_set_option(b, opt, int(val)), b)
+
+
+def spg_batch_set_mlp(b: int, w_host_ptr: int, nw: int) -> None:
+    _bcheck(load().spg_batch_set_mlp(b, w_host_ptr, nw), b)
+
+
+def spg_batch_plan(b: int, c_row_off_ptr: int = 0, c_nnz_off_ptr: int = 0) -> int:
+    nnz = ctypes.c_int64(-1)
+    _bcheck(load().spg_batch_plan(b, ctypes.byref(nnz), c_row_off_ptr or None, c_nnz_off_ptr or None), b)
+    return nnz.value
+
+
+def spg_batch_run(b: int, a_val_pool: int, b_val_pool: int, c_row_ptr: int, c_col: int, c_val: int,
+                  capacity: int, numeric_only: int = 0) -> None:
+    _bcheck(load().spg_batch_run(b, a_val_pool or None, b_val_pool or None, c_row_ptr, c_col or None, c_val or None,
+                                 capacity, numeric_only), b)
+
+
+def spg_batch_tune(b: int, a_val_pool: int, b_val_pool: int, c_row_ptr: int, c_col: int, c_val: int,
+                   capacity: int):
+    chosen = (ctypes.c_int32 * 3)()
+    best = ctypes.c_float(0)
+    _bcheck(load().spg_batch_tune(b, a_val_pool or None, b_val_pool or None, c_row_ptr, c_col or None, c_val or None,
+                                  capacity, chosen, ctypes.byref(best)), b)
+    return list(chosen), best.value
+
+
+def spg_batch_get_stats(b: int) -> spg_stats:
+    st = spg_stats()
+    _bcheck(load().spg_batch_get_stats(b, ctypes.byref(st), ctypes.sizeof(spg_stats)), b)
+    return st

@@ -13,6 +13,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "spg_internal.h"
 
@@ -76,6 +77,7 @@ struct spg_handle_s {
     int nslab_num = 0;
     int vec_used = 1;
     ClassCfg cfg{};
+    Control geom{};  // control block after the analysis of the last symbolic run
 
     // stats and timing
     spg_stats stats{};
@@ -191,6 +193,218 @@ spg_status check_input_errors(spg_handle h) {
     return SPG_OK;
 }
 
+
+// ---- stages of the symbolic phase ----------------------------------------
+// sym_prepare      buffers for the current matrices (may allocate)
+// sym_stage_analysis  launches: control reset, B and A row analysis, learned classes
+// sym_stage_rows   launches: grouping by class, accumulators, retry, scan, numeric grouping;
+//                  launch geometry from h->geom (the control block read back after analysis)
+// sym_finish       host bookkeeping from the control block read back after the scan
+// A batch replays analysis + rows + numeric from a captured graph with the
+// geometry of its first synchronised run (the structure is fixed).
+
+spg_status sym_prepare(spg_handle h) {
+    const int32_t m = h->m;
+    const bool learned = h->binning == 1;
+    const bool want_feats = learned || h->keep_features;
+    const size_t M = (size_t)std::max(m, 1);
+    SPG_TRY(ensure(h, h->ctl, sizeof(Control)));
+    SPG_TRY(ensure(h, h->binfo, (size_t)std::max(h->n, 1) * sizeof(int4)));
+    SPG_TRY(ensure(h, h->rinfo, M * sizeof(RowInfo)));
+    SPG_TRY(ensure(h, h->sym_cls, M));
+    SPG_TRY(ensure(h, h->num_cls, M));
+    SPG_TRY(ensure(h, h->perm_sym, M * 4));
+    SPG_TRY(ensure(h, h->perm_num, M * 4));
+    SPG_TRY(ensure(h, h->row_nnz, M * 4));
+    SPG_TRY(ensure(h, h->row_blocks, M * 4));
+    SPG_TRY(ensure(h, h->tile_status, (size_t)(scan_tiles(m) + 1) * 8));
+    SPG_TRY(ensure(h, h->cursor, NCLS * 4));
+    if (learned) SPG_TRY(ensure(h, h->ovf_list, M * 4));
+    if (want_feats) SPG_TRY(ensure(h, h->feats, M * 12));
+    h->cfg = make_cfg(h);
+    h->vec_used = pick_vec(h);
+    return SPG_OK;
+}
+
+void sym_stage_analysis(spg_handle h) {
+    hipStream_t s = h->stream;
+    const bool learned = h->binning == 1;
+    const bool want_feats = learned || h->keep_features;
+    Control* ctl = h->ctl.as<Control>();
+    launch_fill_u8(s, ctl, 0, sizeof(Control));
+    if (h->m == 0) return;
+    launch_b_rowinfo(s, h->n, h->k, h->brp, h->bci, h->bnnz, h->binfo.as<int4>(), ctl);
+    launch_a_rowinfo(s, h->m, h->n, h->arp, h->aci, h->annz, h->binfo.as<int4>(), h->rinfo.as<RowInfo>(),
+                     want_feats ? h->feats.as<float>() : nullptr, h->cfg, learned ? 1 : 0, h->sym_cls.as<uint8_t>(),
+                     h->row_nnz.as<int32_t>(), h->row_blocks.as<int32_t>(), ctl);
+    rec(h, EV_ANA1);
+    if (learned) {
+        rec(h, EV_MLP0);
+        launch_mlp_classify(s, h->m, h->feats.as<float>(), h->mlp_w.as<float>(), h->rinfo.as<RowInfo>(), h->cfg,
+                            h->mlp_margin_milli / 1000.0f, h->sym_cls.as<uint8_t>(), ctl);
+        rec(h, EV_MLP1);
+    }
+}
+
+spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
+    hipStream_t s = h->stream;
+    const int32_t m = h->m;
+    const bool learned = h->binning == 1;
+    const Control& hc = h->geom;
+    Control* ctl = h->ctl.as<Control>();
+    const int wl = wide_lds(h);
+    launch_fill_i32(s, h->cursor.as<int32_t>(), 0, NCLS);
+    launch_scatter(s, m, h->sym_cls.as<uint8_t>(), ctl->sym_hist, h->cursor.as<int32_t>(), h->perm_sym.as<int32_t>());
+    int off[NCLS];
+    {
+        int run = 0;
+        for (int c = 0; c < NCLS; ++c) off[c] = run, run += hc.sym_hist[c];
+    }
+    const int grid_cap = 2 * h->n_cu;
+    uint32_t* slab = nullptr;
+    int64_t slab_words = 0;
+    const int gcls = MODE_DIRECT * NTIER + TIER_GLOBAL;
+    if (hc.sym_hist[gcls] > 0 && hc.max_words_sym_global * 4 > wl) {
+        slab_words = (hc.max_words_sym_global + 63) & ~(int64_t)63;
+        int ns = std::min(hc.sym_hist[gcls], grid_cap);
+        SPG_TRY(ensure(h, h->slab_sym, (size_t)ns * slab_words * 4));
+        slab = h->slab_sym.as<uint32_t>();
+    }
+    for (int c = 0; c < NCLS; ++c) {
+        if (!hc.sym_hist[c]) continue;
+        SymArgs a{};
+        a.perm = h->perm_sym.as<int32_t>() + off[c];
+        a.count = hc.sym_hist[c];
+        a.tier = c % NTIER;
+        a.mode = c / NTIER;
+        a.vec = h->vec_used;
+        a.arp = h->arp, a.aci = h->aci, a.brp = h->brp, a.bci = h->bci;
+        a.rinfo = h->rinfo.as<RowInfo>();
+        a.row_nnz = h->row_nnz.as<int32_t>();
+        a.row_blocks = h->row_blocks.as<int32_t>();
+        a.ovf_list = learned ? h->ovf_list.as<int32_t>() : nullptr;
+        a.ctl = ctl;
+        a.slab = slab;
+        a.slab_words = slab_words;
+        a.count_dev = nullptr;
+        a.wide_lds = wl;
+        rec(h, EV_SYMCLS + 2 * c);
+        launch_sym_class(s, a, grid_cap);
+        rec(h, EV_SYMCLS + 2 * c + 1);
+        h->sym_cls_timed[c] = h->timing != 0;
+    }
+    if (learned) {
+        // exact retry of overflowed rows on the global path (row count read on the device)
+        SymArgs a{};
+        a.perm = h->ovf_list.as<int32_t>();
+        a.count = 0;
+        a.count_dev = &ctl->overflow_rows;
+        a.tier = TIER_GLOBAL;
+        a.mode = MODE_DIRECT;
+        a.vec = h->vec_used;
+        a.arp = h->arp, a.aci = h->aci, a.brp = h->brp, a.bci = h->bci;
+        a.rinfo = h->rinfo.as<RowInfo>();
+        a.row_nnz = h->row_nnz.as<int32_t>();
+        a.row_blocks = h->row_blocks.as<int32_t>();
+        a.ctl = ctl;
+        a.wide_lds = wl;
+        const int retry_grid = std::min(grid_cap, 64);
+        if (hc.max_words_all * 4 > wl) {
+            a.slab_words = (hc.max_words_all + 63) & ~(int64_t)63;
+            SPG_TRY(ensure(h, h->slab_retry, (size_t)retry_grid * a.slab_words * 4));
+            a.slab = h->slab_retry.as<uint32_t>();
+        }
+        launch_sym_class(s, a, retry_grid);
+    }
+    // row pointer and numeric classes
+    rec(h, EV_SCAN0);
+    launch_fill_u8(s, h->tile_status.p, 0, (scan_tiles(m) + 1) * 8);
+    launch_scan(s, m, h->row_nnz.as<int32_t>(), h->row_blocks.as<int32_t>(), h->rinfo.as<RowInfo>(), h->arp,
+                h->sym_cls.as<uint8_t>(), c_row_ptr, h->tile_status.as<uint64_t>(), h->cfg, h->num_cls.as<uint8_t>(),
+                ctl);
+    rec(h, EV_SCAN1);
+    launch_fill_i32(s, h->cursor.as<int32_t>(), 0, NCLS);
+    launch_scatter(s, m, h->num_cls.as<uint8_t>(), ctl->num_hist, h->cursor.as<int32_t>(), h->perm_num.as<int32_t>());
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "symbolic launch");
+    return SPG_OK;
+}
+
+spg_status sym_finish(spg_handle h, int32_t* c_row_ptr) {
+    const Control& hc = h->geom;
+    const Control hc2 = *h->hctl;
+    if (hc2.err & ERR_NNZ_OVERFLOW)
+        return fail(h, SPG_ERR_OVERFLOW, "nnz(C) = " + std::to_string(hc2.nnz_c) + " exceeds the int32 range");
+    h->nnz_c = hc2.nnz_c;
+    int run = 0;
+    for (int c = 0; c < NCLS; ++c) {
+        h->num_hist[c] = hc2.num_hist[c];
+        h->num_off[c] = run;
+        run += hc2.num_hist[c];
+    }
+    // global-path slabs for the numeric phase are sized now, not inside numeric
+    const int gcls = MODE_DIRECT * NTIER + TIER_GLOBAL;
+    const int grid_cap = 2 * h->n_cu;
+    h->slab_num_words = 0;
+    h->nslab_num = std::min(std::max(hc2.num_hist[gcls], 0), grid_cap);
+    if (hc2.num_hist[gcls] > 0 && hc2.max_words_num_global * 8 > wide_lds(h)) {
+        h->slab_num_words = 2 * ((hc2.max_words_num_global + 63) & ~(int64_t)63);
+        SPG_TRY(ensure(h, h->slab_num, (size_t)h->nslab_num * h->slab_num_words * 4));
+    }
+    spg_stats& st = h->stats;
+    st.size = sizeof(spg_stats);
+    st.m = h->m, st.n = h->n, st.k = h->k;
+    st.products = hc2.products;
+    st.nnz_c = hc2.nnz_c;
+    for (int c = 0; c < NCLS; ++c) {
+        st.sym_rows[c] = hc.sym_hist[c];
+        st.num_rows[c] = hc2.num_hist[c];
+        st.num_a_nnz[c] = hc2.num_a_nnz[c];
+        st.num_c_nnz[c] = hc2.num_c_nnz[c];
+        st.num_products[c] = hc2.num_products[c];
+    }
+    st.empty_rows = hc2.empty_rows;
+    st.retried_rows = hc2.overflow_rows;
+    st.mispredicted_rows = hc2.mispredicted;
+    st.binning = h->binning;
+    h->crp = c_row_ptr;
+    h->have_sym = true;
+    h->have_feats = h->binning == 1 || h->keep_features;
+    return SPG_OK;
+}
+
+// Numeric launches for the current symbolic result (no synchronisation).
+spg_status num_launch_all(spg_handle h, const void* a_vals, const void* b_vals, int32_t* c_col_idx, void* c_vals) {
+    hipStream_t s = h->stream;
+    const int eb = h->dt == SPG_F64 ? 8 : 4;
+    for (int c = 0; c < NCLS; ++c) {
+        if (!h->num_hist[c]) continue;
+        NumArgs a{};
+        a.perm = h->perm_num.as<int32_t>() + h->num_off[c];
+        a.count = h->num_hist[c];
+        a.tier = c % NTIER;
+        a.mode = c / NTIER;
+        a.vec = h->vec_used;
+        a.arp = h->arp, a.aci = h->aci, a.av = a_vals;
+        a.brp = h->brp, a.bci = h->bci, a.bv = b_vals;
+        a.crp = h->crp;
+        a.rinfo = h->rinfo.as<RowInfo>();
+        a.row_blocks = h->row_blocks.as<int32_t>();
+        a.ccol = c_col_idx;
+        a.cval = c_vals;
+        a.slab = h->slab_num_words ? h->slab_num.as<uint32_t>() : nullptr;
+        a.slab_words = h->slab_num_words;
+        a.wide_lds = wide_lds(h);
+        rec(h, EV_NUMCLS + 2 * c);
+        launch_num_class(s, a, eb, std::max(h->nslab_num, 1));
+        rec(h, EV_NUMCLS + 2 * c + 1);
+        h->num_cls_timed[c] = h->timing != 0;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "numeric launch");
+    return SPG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -289,180 +503,34 @@ spg_status spg_symbolic(spg_handle h, int32_t* c_row_ptr, int64_t* nnz_c) {
         if (!c_row_ptr || !nnz_c) return fail(h, SPG_ERR_ARG, "null output");
         if (h->binning == 1 && !h->have_mlp) return fail(h, SPG_ERR_STATE, "learned binning needs spg_set_mlp");
         h->have_sym = false;
-        const int32_t m = h->m;
-        hipStream_t s = h->stream;
-        const bool learned = h->binning == 1;
-        const bool want_feats = learned || h->keep_features;
         if (h->timing) SPG_TRY(make_events(h));
         h->sym_timed = h->timing != 0;
         std::fill(std::begin(h->sym_cls_timed), std::end(h->sym_cls_timed), false);
-
-        const size_t M = (size_t)std::max(m, 1);
-        SPG_TRY(ensure(h, h->ctl, sizeof(Control)));
-        SPG_TRY(ensure(h, h->binfo, (size_t)std::max(h->n, 1) * sizeof(int4)));
-        SPG_TRY(ensure(h, h->rinfo, M * sizeof(RowInfo)));
-        SPG_TRY(ensure(h, h->sym_cls, M));
-        SPG_TRY(ensure(h, h->num_cls, M));
-        SPG_TRY(ensure(h, h->perm_sym, M * 4));
-        SPG_TRY(ensure(h, h->perm_num, M * 4));
-        SPG_TRY(ensure(h, h->row_nnz, M * 4));
-        SPG_TRY(ensure(h, h->row_blocks, M * 4));
-        SPG_TRY(ensure(h, h->tile_status, (size_t)(scan_tiles(m) + 1) * 8));
-        SPG_TRY(ensure(h, h->cursor, NCLS * 4));
-        if (learned) SPG_TRY(ensure(h, h->ovf_list, M * 4));
-        if (want_feats) SPG_TRY(ensure(h, h->feats, M * 12));
-
-        const ClassCfg cfg = make_cfg(h);
-        h->cfg = cfg;
-        h->vec_used = pick_vec(h);
-        Control* ctl = h->ctl.as<Control>();
-        const int wl = wide_lds(h);
-
+        SPG_TRY(sym_prepare(h));
         rec(h, EV_SYM0);
-        launch_fill_u8(s, ctl, 0, sizeof(Control));
-        if (m == 0) {
-            launch_fill_i32(s, c_row_ptr, 0, 1);
+        sym_stage_analysis(h);
+        if (h->m == 0) {
+            launch_fill_i32(h->stream, c_row_ptr, 0, 1);
             SPG_TRY(sync_ctl(h));
             rec(h, EV_SYM1);
             *nnz_c = 0;
             h->nnz_c = 0;
             h->crp = c_row_ptr;
             std::fill(std::begin(h->num_hist), std::end(h->num_hist), 0);
+            h->nslab_num = 0;
+            h->slab_num_words = 0;
             h->have_sym = true;
             h->have_feats = false;
             return SPG_OK;
         }
-        // row analysis: B rows, then A rows (+ classes or features)
-        launch_b_rowinfo(s, h->n, h->k, h->brp, h->bci, h->bnnz, h->binfo.as<int4>(), ctl);
-        launch_a_rowinfo(s, m, h->n, h->arp, h->aci, h->annz, h->binfo.as<int4>(), h->rinfo.as<RowInfo>(),
-                         want_feats ? h->feats.as<float>() : nullptr, cfg, learned ? 1 : 0, h->sym_cls.as<uint8_t>(),
-                         h->row_nnz.as<int32_t>(), h->row_blocks.as<int32_t>(), ctl);
-        rec(h, EV_ANA1);
-        if (learned) {
-            rec(h, EV_MLP0);
-            launch_mlp_classify(s, m, h->feats.as<float>(), h->mlp_w.as<float>(), h->rinfo.as<RowInfo>(), cfg,
-                                h->mlp_margin_milli / 1000.0f, h->sym_cls.as<uint8_t>(), ctl);
-            rec(h, EV_MLP1);
-        }
         SPG_TRY(sync_ctl(h));  // first synchronisation: validity, class histogram, slab sizes
         SPG_TRY(check_input_errors(h));
-        const Control hc = *h->hctl;
-
-        // group rows by symbolic class
-        launch_fill_i32(s, h->cursor.as<int32_t>(), 0, NCLS);
-        launch_scatter(s, m, h->sym_cls.as<uint8_t>(), ctl->sym_hist, h->cursor.as<int32_t>(),
-                       h->perm_sym.as<int32_t>());
-        int off[NCLS];
-        {
-            int run = 0;
-            for (int c = 0; c < NCLS; ++c) off[c] = run, run += hc.sym_hist[c];
-        }
-        const int grid_cap = 2 * h->n_cu;
-        uint32_t* slab = nullptr;
-        int64_t slab_words = 0;
-        const int gcls = MODE_DIRECT * NTIER + TIER_GLOBAL;
-        if (hc.sym_hist[gcls] > 0 && hc.max_words_sym_global * 4 > wl) {
-            slab_words = (hc.max_words_sym_global + 63) & ~(int64_t)63;
-            int ns = std::min(hc.sym_hist[gcls], grid_cap);
-            SPG_TRY(ensure(h, h->slab_sym, (size_t)ns * slab_words * 4));
-            slab = h->slab_sym.as<uint32_t>();
-        }
-        for (int c = 0; c < NCLS; ++c) {
-            if (!hc.sym_hist[c]) continue;
-            SymArgs a{};
-            a.perm = h->perm_sym.as<int32_t>() + off[c];
-            a.count = hc.sym_hist[c];
-            a.tier = c % NTIER;
-            a.mode = c / NTIER;
-            a.vec = h->vec_used;
-            a.arp = h->arp, a.aci = h->aci, a.brp = h->brp, a.bci = h->bci;
-            a.rinfo = h->rinfo.as<RowInfo>();
-            a.row_nnz = h->row_nnz.as<int32_t>();
-            a.row_blocks = h->row_blocks.as<int32_t>();
-            a.ovf_list = learned ? h->ovf_list.as<int32_t>() : nullptr;
-            a.ctl = ctl;
-            a.slab = slab;
-            a.slab_words = slab_words;
-            a.count_dev = nullptr;
-            a.wide_lds = wl;
-            rec(h, EV_SYMCLS + 2 * c);
-            launch_sym_class(s, a, grid_cap);
-            rec(h, EV_SYMCLS + 2 * c + 1);
-            h->sym_cls_timed[c] = h->timing != 0;
-        }
-        if (learned) {
-            // exact retry of overflowed rows on the global path (row count read on the device)
-            SymArgs a{};
-            a.perm = h->ovf_list.as<int32_t>();
-            a.count = 0;
-            a.count_dev = &ctl->overflow_rows;
-            a.tier = TIER_GLOBAL;
-            a.mode = MODE_DIRECT;
-            a.vec = h->vec_used;
-            a.arp = h->arp, a.aci = h->aci, a.brp = h->brp, a.bci = h->bci;
-            a.rinfo = h->rinfo.as<RowInfo>();
-            a.row_nnz = h->row_nnz.as<int32_t>();
-            a.row_blocks = h->row_blocks.as<int32_t>();
-            a.ctl = ctl;
-            a.wide_lds = wl;
-            int retry_grid = std::min(grid_cap, 64);
-            if (hc.max_words_all * 4 > wl) {
-                a.slab_words = (hc.max_words_all + 63) & ~(int64_t)63;
-                SPG_TRY(ensure(h, h->slab_retry, (size_t)retry_grid * a.slab_words * 4));
-                a.slab = h->slab_retry.as<uint32_t>();
-            }
-            launch_sym_class(s, a, retry_grid);
-        }
-        // row pointer and numeric classes
-        rec(h, EV_SCAN0);
-        launch_fill_u8(s, h->tile_status.p, 0, (scan_tiles(m) + 1) * 8);
-        launch_scan(s, m, h->row_nnz.as<int32_t>(), h->row_blocks.as<int32_t>(), h->rinfo.as<RowInfo>(), h->arp,
-                    h->sym_cls.as<uint8_t>(), c_row_ptr, h->tile_status.as<uint64_t>(), cfg, h->num_cls.as<uint8_t>(),
-                    ctl);
-        rec(h, EV_SCAN1);
-        launch_fill_i32(s, h->cursor.as<int32_t>(), 0, NCLS);
-        launch_scatter(s, m, h->num_cls.as<uint8_t>(), ctl->num_hist, h->cursor.as<int32_t>(),
-                       h->perm_num.as<int32_t>());
+        h->geom = *h->hctl;
+        SPG_TRY(sym_stage_rows(h, c_row_ptr));
         SPG_TRY(sync_ctl(h));  // second synchronisation: nnz(C) for the caller's allocation
         rec(h, EV_SYM1);
-        const Control hc2 = *h->hctl;
-        if (hc2.err & ERR_NNZ_OVERFLOW)
-            return fail(h, SPG_ERR_OVERFLOW, "nnz(C) = " + std::to_string(hc2.nnz_c) + " exceeds the int32 range");
-        h->nnz_c = hc2.nnz_c;
-        *nnz_c = hc2.nnz_c;
-        int run = 0;
-        for (int c = 0; c < NCLS; ++c) {
-            h->num_hist[c] = hc2.num_hist[c];
-            h->num_off[c] = run;
-            run += hc2.num_hist[c];
-        }
-        // global-path slabs for the numeric phase are sized now, not inside numeric
-        h->slab_num_words = 0;
-        h->nslab_num = std::min(std::max(hc2.num_hist[gcls], 0), grid_cap);
-        if (hc2.num_hist[gcls] > 0 && hc2.max_words_num_global * 8 > wl) {
-            h->slab_num_words = 2 * ((hc2.max_words_num_global + 63) & ~(int64_t)63);
-            SPG_TRY(ensure(h, h->slab_num, (size_t)h->nslab_num * h->slab_num_words * 4));
-        }
-        // statistics
-        spg_stats& st = h->stats;
-        st.size = sizeof(spg_stats);
-        st.m = m, st.n = h->n, st.k = h->k;
-        st.products = hc2.products;
-        st.nnz_c = hc2.nnz_c;
-        for (int c = 0; c < NCLS; ++c) {
-            st.sym_rows[c] = hc.sym_hist[c];
-            st.num_rows[c] = hc2.num_hist[c];
-            st.num_a_nnz[c] = hc2.num_a_nnz[c];
-            st.num_c_nnz[c] = hc2.num_c_nnz[c];
-            st.num_products[c] = hc2.num_products[c];
-        }
-        st.empty_rows = hc2.empty_rows;
-        st.retried_rows = hc2.overflow_rows;
-        st.mispredicted_rows = hc2.mispredicted;
-        st.binning = h->binning;
-        h->crp = c_row_ptr;
-        h->have_sym = true;
-        h->have_feats = want_feats;
+        SPG_TRY(sym_finish(h, c_row_ptr));
+        *nnz_c = h->nnz_c;
         return SPG_OK;
     } catch (const std::bad_alloc&) {
         return fail(h, SPG_ERR_ALLOC, "host allocation failed");
@@ -480,35 +548,9 @@ spg_status spg_numeric(spg_handle h, const void* a_vals, const void* b_vals, int
         if (h->timing) SPG_TRY(make_events(h));
         h->num_timed = h->timing != 0;
         std::fill(std::begin(h->num_cls_timed), std::end(h->num_cls_timed), false);
-        hipStream_t s = h->stream;
-        const int eb = h->dt == SPG_F64 ? 8 : 4;
         rec(h, EV_NUM0);
-        for (int c = 0; c < NCLS; ++c) {
-            if (!h->num_hist[c]) continue;
-            NumArgs a{};
-            a.perm = h->perm_num.as<int32_t>() + h->num_off[c];
-            a.count = h->num_hist[c];
-            a.tier = c % NTIER;
-            a.mode = c / NTIER;
-            a.vec = h->vec_used;
-            a.arp = h->arp, a.aci = h->aci, a.av = a_vals;
-            a.brp = h->brp, a.bci = h->bci, a.bv = b_vals;
-            a.crp = h->crp;
-            a.rinfo = h->rinfo.as<RowInfo>();
-            a.row_blocks = h->row_blocks.as<int32_t>();
-            a.ccol = c_col_idx;
-            a.cval = c_vals;
-            a.slab = h->slab_num_words ? h->slab_num.as<uint32_t>() : nullptr;
-            a.slab_words = h->slab_num_words;
-            a.wide_lds = wide_lds(h);
-            rec(h, EV_NUMCLS + 2 * c);
-            launch_num_class(s, a, eb, std::max(h->nslab_num, 1));
-            rec(h, EV_NUMCLS + 2 * c + 1);
-            h->num_cls_timed[c] = h->timing != 0;
-        }
+        SPG_TRY(num_launch_all(h, a_vals, b_vals, c_col_idx, c_vals));
         rec(h, EV_NUM1);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(h, e, "numeric launch");
         return SPG_OK;
     } catch (...) {
         return fail(h, SPG_ERR_HIP, "unexpected host exception");
@@ -605,6 +647,331 @@ spg_status spg_export_rows(spg_handle h, float* x, float* y, int32_t* row_nnz) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "export launch");
     return SPG_OK;
+}
+
+// ============================================================== batches
+// Many independent products C_i = A_i * B_i run as one block-diagonal
+// product (rows never mix across products), so every product's rows share
+// the same class launches.  The launch sequence of a whole product
+// (analysis, accumulators, scan, numeric) is captured once into a hipGraph
+// with the geometry of a first synchronised run, and every later run is one
+// hipGraphLaunch: no host round trip, no allocation.
+}  // extern "C"
+
+struct spg_batch_s {
+    spg_handle h = nullptr;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int32_t count = 0;
+    spg_dtype dt = SPG_F64;
+    int64_t m_total = 0, n_total = 0, annz_total = 0, bnnz_total = 0;
+    int32_t k_max = 0;
+    std::vector<int64_t> row_off, c_nnz_off;
+    DevBuf arp, aci, brp, desc, err, crp_plan;
+    const int32_t* bci_pool = nullptr;
+    bool planned = false;
+    int64_t nnz_total = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void* g_av = nullptr;
+    const void* g_bv = nullptr;
+    int32_t* g_crp = nullptr;
+    int32_t* g_ccol = nullptr;
+    void* g_cval = nullptr;
+    int g_numeric_only = -1;
+    std::string err_msg;
+};
+
+namespace {
+
+spg_status bfail(spg_batch b, spg_status s, const std::string& msg) {
+    if (b) b->err_msg = msg;
+    return s;
+}
+
+void drop_graph(spg_batch b) {
+    if (b->exec) (void)hipStreamSynchronize(b->stream);  // no replay still running
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->g_numeric_only = -1;
+}
+
+__global__ void k_copy_i32(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// one synchronised symbolic run on the packed product: geometry, nnz, offsets
+spg_status batch_replan(spg_batch b) {
+    drop_graph(b);
+    spg_handle h = b->h;
+    int64_t nnz = 0;
+    spg_status st = spg_symbolic(h, b->crp_plan.as<int32_t>(), &nnz);
+    if (st != SPG_OK) return bfail(b, st, h->err);
+    std::vector<int32_t> rp((size_t)b->m_total + 1);
+    HIP_TRY(h, hipMemcpyAsync(rp.data(), b->crp_plan.p, rp.size() * 4, hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(h, hipStreamSynchronize(b->stream));
+    b->c_nnz_off.assign((size_t)b->count + 1, 0);
+    for (int32_t p = 0; p <= b->count; ++p) b->c_nnz_off[p] = rp[(size_t)b->row_off[p]];
+    b->nnz_total = nnz;
+    b->planned = true;
+    return SPG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+spg_status spg_batch_create(spg_batch* out, void* stream, spg_dtype dt, int32_t count, const int32_t* m,
+                            const int32_t* n, const int32_t* k, const int64_t* a_nnz, const int64_t* b_nnz,
+                            const int32_t* a_row_ptr_pool, const int32_t* a_col_pool, const int32_t* b_row_ptr_pool,
+                            const int32_t* b_col_pool) {
+    if (!out) return SPG_ERR_ARG;
+    *out = nullptr;
+    if (count < 0 || (count > 0 && (!m || !n || !k || !a_nnz || !b_nnz || !a_row_ptr_pool || !b_row_ptr_pool)))
+        return SPG_ERR_ARG;
+    if (dt != SPG_F32 && dt != SPG_F64) return SPG_ERR_ARG;
+    spg_batch b = nullptr;
+    try {
+        b = new spg_batch_s();
+        b->count = count;
+        b->dt = dt;
+        b->row_off.assign((size_t)count + 1, 0);
+        std::vector<int64_t> da(7 * (size_t)std::max(count, 1)), db(7 * (size_t)std::max(count, 1));
+        int64_t rpa = 0, rpb = 0, na = 0, nb = 0, mrow = 0, nrow = 0;
+        for (int32_t p = 0; p < count; ++p) {
+            if (m[p] < 0 || n[p] < 0 || k[p] < 0 || a_nnz[p] < 0 || b_nnz[p] < 0) {
+                delete b;
+                return SPG_ERR_ARG;
+            }
+            int64_t* a = &da[7 * (size_t)p];
+            a[0] = mrow, a[1] = rpa, a[2] = na, a[3] = m[p], a[4] = a_nnz[p], a[5] = nrow, a[6] = n[p];
+            int64_t* c = &db[7 * (size_t)p];
+            c[0] = nrow, c[1] = rpb, c[2] = nb, c[3] = n[p], c[4] = b_nnz[p], c[5] = 0, c[6] = k[p];
+            b->row_off[p] = mrow;
+            mrow += m[p], nrow += n[p], rpa += m[p] + 1, rpb += n[p] + 1, na += a_nnz[p], nb += b_nnz[p];
+            b->k_max = std::max(b->k_max, k[p]);
+        }
+        b->row_off[count] = mrow;
+        if (mrow >= INT32_MAX || nrow >= INT32_MAX || na >= INT32_MAX || nb >= INT32_MAX) {
+            delete b;
+            return SPG_ERR_OVERFLOW;
+        }
+        if ((na > 0 && !a_col_pool) || (nb > 0 && !b_col_pool)) {
+            delete b;
+            return SPG_ERR_ARG;
+        }
+        b->m_total = mrow, b->n_total = nrow, b->annz_total = na, b->bnnz_total = nb;
+        b->bci_pool = b_col_pool;
+        if (stream) {
+            b->stream = static_cast<hipStream_t>(stream);
+        } else {
+            if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+                delete b;
+                return SPG_ERR_HIP;
+            }
+            b->own_stream = true;
+        }
+        spg_status st = spg_create(&b->h, b->stream);
+        if (st != SPG_OK) {
+            spg_batch_destroy(b);
+            return st;
+        }
+        spg_handle h = b->h;
+        SPG_TRY(ensure(h, b->arp, (size_t)(mrow + 1) * 4));
+        SPG_TRY(ensure(h, b->aci, (size_t)std::max<int64_t>(na, 1) * 4));
+        SPG_TRY(ensure(h, b->brp, (size_t)(nrow + 1) * 4));
+        SPG_TRY(ensure(h, b->desc, 2 * da.size() * 8));
+        SPG_TRY(ensure(h, b->err, 16));
+        SPG_TRY(ensure(h, b->crp_plan, (size_t)(mrow + 1) * 4));
+        int64_t* ddesc = b->desc.as<int64_t>();
+        HIP_TRY(h, hipMemcpyAsync(ddesc, da.data(), da.size() * 8, hipMemcpyHostToDevice, b->stream));
+        HIP_TRY(h, hipMemcpyAsync(ddesc + da.size(), db.data(), db.size() * 8, hipMemcpyHostToDevice, b->stream));
+        launch_fill_i32(b->stream, b->err.as<int32_t>(), 0, 1);
+        launch_pack(b->stream, count, ddesc, a_row_ptr_pool, a_col_pool, b->arp.as<int32_t>(), b->aci.as<int32_t>(),
+                    b->err.as<int32_t>());
+        launch_pack(b->stream, count, ddesc + da.size(), b_row_ptr_pool, b_col_pool, b->brp.as<int32_t>(), nullptr,
+                    b->err.as<int32_t>());
+        launch_fill_i32(b->stream, b->arp.as<int32_t>() + mrow, (int32_t)na, 1);
+        launch_fill_i32(b->stream, b->brp.as<int32_t>() + nrow, (int32_t)nb, 1);
+        int32_t herr = 0;
+        HIP_TRY(h, hipMemcpyAsync(&herr, b->err.p, 4, hipMemcpyDeviceToHost, b->stream));
+        HIP_TRY(h, hipStreamSynchronize(b->stream));
+        if (herr) {
+            spg_batch_destroy(b);
+            return SPG_ERR_INDEX;
+        }
+        st = spg_set_matrices(h, dt, (int32_t)mrow, (int32_t)nrow, b->k_max, b->arp.as<int32_t>(),
+                              b->aci.as<int32_t>(), na, b->brp.as<int32_t>(), b_col_pool, nb);
+        if (st != SPG_OK) {
+            spg_batch_destroy(b);
+            return st;
+        }
+        *out = b;
+        return SPG_OK;
+    } catch (...) {
+        if (b) spg_batch_destroy(b);
+        return SPG_ERR_ALLOC;
+    }
+}
+
+spg_status spg_batch_destroy(spg_batch b) {
+    if (!b) return SPG_OK;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    DevBuf* bufs[] = {&b->arp, &b->aci, &b->brp, &b->desc, &b->err, &b->crp_plan};
+    for (DevBuf* x : bufs) release(*x);
+    if (b->h) spg_destroy(b->h);
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return SPG_OK;
+}
+
+const char* spg_batch_last_error(spg_batch b) {
+    if (!b) return "null batch";
+    return b->err_msg.empty() && b->h ? b->h->err.c_str() : b->err_msg.c_str();
+}
+
+spg_status spg_batch_set_option(spg_batch b, int32_t opt, int64_t val) {
+    if (!b) return SPG_ERR_ARG;
+    spg_status st = spg_set_option(b->h, opt, val);
+    if (st != SPG_OK) return bfail(b, st, b->h->err);
+    if (opt != SPG_OPT_TIMING) b->planned = false, drop_graph(b);
+    return SPG_OK;
+}
+
+spg_status spg_batch_set_mlp(spg_batch b, const float* w, int32_t nw) {
+    if (!b) return SPG_ERR_ARG;
+    spg_status st = spg_set_mlp(b->h, w, nw);
+    if (st != SPG_OK) return bfail(b, st, b->h->err);
+    b->planned = false;
+    drop_graph(b);
+    return SPG_OK;
+}
+
+spg_status spg_batch_plan(spg_batch b, int64_t* nnz_total, int64_t* c_row_off, int64_t* c_nnz_off) {
+    if (!b || !nnz_total) return SPG_ERR_ARG;
+    try {
+        SPG_TRY(batch_replan(b));
+        *nnz_total = b->nnz_total;
+        for (int32_t p = 0; p <= b->count; ++p) {
+            if (c_row_off) c_row_off[p] = b->row_off[p];
+            if (c_nnz_off) c_nnz_off[p] = b->c_nnz_off[p];
+        }
+        return SPG_OK;
+    } catch (...) {
+        return bfail(b, SPG_ERR_ALLOC, "host exception");
+    }
+}
+
+spg_status spg_batch_run(spg_batch b, const void* a_val_pool, const void* b_val_pool, int32_t* c_row_ptr,
+                         int32_t* c_col, void* c_val, int64_t capacity, int32_t numeric_only) {
+    if (!b) return SPG_ERR_ARG;
+    try {
+        if (!b->planned) return bfail(b, SPG_ERR_STATE, "spg_batch_plan must come first");
+        if (!c_row_ptr || (b->annz_total > 0 && !a_val_pool) || (b->bnnz_total > 0 && !b_val_pool))
+            return bfail(b, SPG_ERR_ARG, "null pointer");
+        if (capacity < b->nnz_total || (b->nnz_total > 0 && (!c_col || !c_val)))
+            return bfail(b, SPG_ERR_ARG, "C pools smaller than the planned nnz");
+        spg_handle h = b->h;
+        const bool same = b->exec && b->g_av == a_val_pool && b->g_bv == b_val_pool && b->g_crp == c_row_ptr &&
+                          b->g_ccol == c_col && b->g_cval == c_val && b->g_numeric_only == (numeric_only != 0);
+        if (!same) {
+            drop_graph(b);
+            const int timing = h->timing;
+            h->timing = 0;
+            HIP_TRY(h, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            spg_status st = SPG_OK;
+            if (!numeric_only) {
+                sym_stage_analysis(h);
+                st = sym_stage_rows(h, c_row_ptr);
+                h->crp = c_row_ptr;
+            } else {
+                const int64_t n1 = b->m_total + 1;
+                hipLaunchKernelGGL(k_copy_i32, dim3((unsigned)std::min<int64_t>((n1 + 255) / 256, 4096)), dim3(256), 0,
+                                   b->stream, b->crp_plan.as<int32_t>(), c_row_ptr, n1);
+                h->crp = b->crp_plan.as<int32_t>();
+            }
+            if (st == SPG_OK) st = num_launch_all(h, a_val_pool, b_val_pool, c_col, c_val);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(b->stream, &g);
+            h->timing = timing;
+            if (st != SPG_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return bfail(b, st, h->err);
+            }
+            if (e != hipSuccess) return bfail(b, SPG_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+            b->graph = g;
+            e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                drop_graph(b);
+                return bfail(b, SPG_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+            }
+            b->g_av = a_val_pool, b->g_bv = b_val_pool, b->g_crp = c_row_ptr, b->g_ccol = c_col, b->g_cval = c_val;
+            b->g_numeric_only = numeric_only != 0;
+        }
+        hipError_t e = hipGraphLaunch(b->exec, b->stream);
+        if (e != hipSuccess) return bfail(b, SPG_ERR_HIP, std::string("graph launch: ") + hipGetErrorString(e));
+        return SPG_OK;
+    } catch (...) {
+        return bfail(b, SPG_ERR_HIP, "host exception");
+    }
+}
+
+spg_status spg_batch_tune(spg_batch b, const void* a_val_pool, const void* b_val_pool, int32_t* c_row_ptr,
+                          int32_t* c_col, void* c_val, int64_t capacity, int32_t* chosen, float* best_ms) {
+    if (!b) return SPG_ERR_ARG;
+    try {
+        if (!b->planned) return bfail(b, SPG_ERR_STATE, "spg_batch_plan must come first");
+        if (capacity < b->nnz_total) return bfail(b, SPG_ERR_ARG, "C pools smaller than the planned nnz");
+        spg_handle h = b->h;
+        hipEvent_t e0, e1;
+        HIP_TRY(h, hipEventCreate(&e0));
+        HIP_TRY(h, hipEventCreate(&e1));
+        const int wpl[] = {8, 16, 32};
+        const int vecs[] = {0, 4, 8, 16};
+        const int hmax[] = {32, 64, 128};
+        float best = 1e30f;
+        int bw = h->work_per_lane, bv = h->vec, bh = h->hash_max_blocks;
+        for (int w : wpl)
+            for (int v : vecs)
+                for (int hb : hmax) {
+                    h->work_per_lane = w, h->vec = v, h->hash_max_blocks = hb;
+                    float t = 1e30f;
+                    for (int it = 0; it < 2; ++it) {
+                        int64_t nnz = 0;
+                        HIP_TRY(h, hipEventRecord(e0, b->stream));
+                        spg_status st = spg_symbolic(h, c_row_ptr, &nnz);
+                        if (st == SPG_OK) st = spg_numeric(h, a_val_pool, b_val_pool, c_col, c_val);
+                        if (st != SPG_OK) {
+                            (void)hipEventDestroy(e0);
+                            (void)hipEventDestroy(e1);
+                            return bfail(b, st, h->err);
+                        }
+                        HIP_TRY(h, hipEventRecord(e1, b->stream));
+                        HIP_TRY(h, hipEventSynchronize(e1));
+                        float ms = 0.f;
+                        HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
+                        t = std::min(t, ms);
+                    }
+                    if (t < best) best = t, bw = w, bv = v, bh = hb;
+                }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        h->work_per_lane = bw, h->vec = bv, h->hash_max_blocks = bh;
+        if (chosen) chosen[0] = bw, chosen[1] = bv, chosen[2] = bh;
+        if (best_ms) *best_ms = best;
+        return batch_replan(b);
+    } catch (...) {
+        return bfail(b, SPG_ERR_HIP, "host exception");
+    }
+}
+
+spg_status spg_batch_get_stats(spg_batch b, spg_stats* out, int32_t size) {
+    if (!b) return SPG_ERR_ARG;
+    return spg_get_stats(b->h, out, size);
 }
 
 }  // extern "C"

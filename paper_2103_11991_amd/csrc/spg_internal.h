@@ -184,6 +184,10 @@ void launch_scan(hipStream_t s, int32_t m, const int32_t* row_nnz, const int32_t
 void launch_export_rows(hipStream_t s, int32_t m, const float* feats, const int32_t* row_blocks,
                         const int32_t* row_nnz_in, float* x, float* y, int32_t* row_nnz_out);
 int64_t scan_tiles(int32_t m);
+// batched products: packs pooled per-product CSR arrays into one block-diagonal
+// matrix; desc holds 7 int64 per product (see k_pack)
+void launch_pack(hipStream_t s, int32_t count, const int64_t* desc, const int32_t* rp_pool, const int32_t* col_pool,
+                 int32_t* rp_out, int32_t* col_out, int32_t* err);
 
 // ---- accumulator kernels (spg_accum.hip) ----
 struct SymArgs {

@@ -10,7 +10,7 @@
 // w3[32], b3.  Forward keeps z1 and z2 per row for backward.  Backward
 // accumulates per-workgroup partial gradients over tiles of rows held in LDS,
 // then a second kernel sums the partials in a fixed order (deterministic).
-// Training is minibatch Adam on the mean squared error.
+// Training is minibatch Adam on the mean squared error or a pinball loss.
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -136,16 +136,27 @@ __global__ void k_reduce_partials(const float* __restrict__ partial, int nblocks
     dw[p] = s;
 }
 
-// dy = 2 (y - t) / rows; loss[0] += sum (y - t)^2 * loss_scale
-__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y, const float* __restrict__ t, int32_t rows,
-                                             float* __restrict__ dy, float* __restrict__ loss, float loss_scale) {
+// Loss gradient with respect to the predictions, for the batch mean:
+//   squared error (q == 0): dy = 2 (y - t) / rows, loss (y - t)^2
+//   pinball of level q:     d = t - y, loss q d (d >= 0) or (q - 1) d,
+//                           dy = -q / rows (d > 0) or (1 - q) / rows (d <= 0)
+// loss[0] += sum of row losses * loss_scale
+__global__ __launch_bounds__(256) void k_loss(const float* __restrict__ y, const float* __restrict__ t, int32_t rows,
+                                              float q, float* __restrict__ dy, float* __restrict__ loss,
+                                              float loss_scale) {
     __shared__ float red[256];
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     float e = 0.f;
     if (r < rows) {
-        const float d = y[r] - t[r];
-        dy[r] = 2.f * d / (float)rows;
-        e = d * d;
+        if (q == 0.f) {
+            const float d = y[r] - t[r];
+            dy[r] = 2.f * d / (float)rows;
+            e = d * d;
+        } else {
+            const float d = t[r] - y[r];
+            dy[r] = (d > 0.f ? -q : 1.f - q) / (float)rows;
+            e = d >= 0.f ? q * d : (q - 1.f) * d;
+        }
     }
     red[threadIdx.x] = e;
     __syncthreads();
@@ -214,8 +225,9 @@ spg_status spg_mlp_backward(void* stream, const float* w, const float* x, const 
 }
 
 spg_status spg_mlp_train(void* stream, const float* x, const float* y, int32_t rows, int32_t epochs, int32_t batch,
-                         float lr, float* w_inout, float* loss_out) {
+                         float lr, float quantile, float* w_inout, float* loss_out) {
     if (rows <= 0 || epochs < 0 || batch <= 0 || !x || !y || !w_inout || !(lr > 0.f)) return SPG_ERR_ARG;
+    if (!(quantile >= 0.f && quantile < 1.f)) return SPG_ERR_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int32_t bmax = batch < rows ? batch : rows;
     const int nb = bwd_blocks(bmax);
@@ -243,7 +255,7 @@ spg_status spg_mlp_train(void* stream, const float* x, const float* y, int32_t r
             const float* xb = x + (int64_t)r0 * 3;
             const float* tb = y + r0;
             hipLaunchKernelGGL(k_fwd, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, w_inout, xb, nr, yp, act);
-            hipLaunchKernelGGL(k_mse, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, yp, tb, nr, dy,
+            hipLaunchKernelGGL(k_loss, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, yp, tb, nr, quantile, dy,
                                loss_out ? loss_out + ep : nullptr, 1.0f / (float)rows);
             st = launch_backward(s, w_inout, xb, act, dy, nr, g, partial);
             if (st != SPG_OK) break;

@@ -12,6 +12,7 @@
 //     class of every row.
 // Index validity is checked in the same passes that read the indices.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <climits>
 
 #include "spg_internal.h"
@@ -366,6 +367,37 @@ __global__ void k_export_rows(int32_t m, const float* __restrict__ feats, const 
     if (row_nnz_out) row_nnz_out[r] = row_nnz_in[r];
 }
 
+
+// Batched products as one block-diagonal product: product p's rows are
+// appended to the packed row pointer (entry offsets made global) and, for A,
+// its column indices are shifted by the number of B rows before it so they
+// address its own B rows.  B's columns stay local: a row of C only ever
+// meets the columns of its own product's B.  Each product's local arrays are
+// checked (row pointer from 0 to its nnz, columns below its own width).
+__global__ __launch_bounds__(256) void k_pack(int32_t count, const int64_t* __restrict__ desc,
+                                              const int32_t* __restrict__ rp_pool,
+                                              const int32_t* __restrict__ col_pool, int32_t* __restrict__ rp_out,
+                                              int32_t* __restrict__ col_out, int32_t* __restrict__ err) {
+    // desc per product: row offset, row-pointer offset, nnz offset, rows, nnz, column shift, column limit
+    for (int p = blockIdx.x; p < count; p += gridDim.x) {
+        const int64_t* d = desc + 7 * (int64_t)p;
+        const int64_t roff = d[0], rpoff = d[1], noff = d[2], rows = d[3], nnz = d[4], shift = d[5], lim = d[6];
+        int bad = 0;
+        if (threadIdx.x == 0 && (rp_pool[rpoff] != 0 || (int64_t)rp_pool[rpoff + rows] != nnz)) bad = 1;
+        for (int64_t r = threadIdx.x; r < rows; r += blockDim.x) {
+            const int32_t v = rp_pool[rpoff + r];
+            if (v < 0 || (int64_t)v > nnz || v > rp_pool[rpoff + r + 1]) bad = 1;
+            rp_out[roff + r] = (int32_t)(noff + v);
+        }
+        for (int64_t q = threadIdx.x; q < nnz; q += blockDim.x) {
+            const int32_t c = col_pool[noff + q];
+            if (c < 0 || (int64_t)c >= lim) bad = 1;
+            if (col_out) col_out[noff + q] = (int32_t)(c + shift);
+        }
+        if (bad) atomicOr(err, 1);
+    }
+}
+
 inline unsigned grid_for(int64_t threads, int per_block) {
     int64_t g = (threads + per_block - 1) / per_block;
     return (unsigned)(g < 1 ? 1 : g);
@@ -374,6 +406,13 @@ inline unsigned grid_for(int64_t threads, int per_block) {
 }  // namespace
 
 int64_t scan_tiles(int32_t m) { return ((int64_t)m + SCAN_TILE - 1) / SCAN_TILE; }
+
+void launch_pack(hipStream_t s, int32_t count, const int64_t* desc, const int32_t* rp_pool, const int32_t* col_pool,
+                 int32_t* rp_out, int32_t* col_out, int32_t* err) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)std::min(count, 4096)), dim3(256), 0, s, count, desc, rp_pool, col_pool,
+                       rp_out, col_out, err);
+}
 
 void launch_fill_i32(hipStream_t s, int32_t* p, int32_t v, int64_t n) {
     if (n <= 0) return;

@@ -148,3 +148,109 @@ def spgemm(A: DeviceCsr, B: DeviceCsr, **options) -> DeviceCsr:
     rp, nnz = op.symbolic()
     col, val = op.numeric()
     return DeviceCsr(A.m, B.n, rp, col, val)
+
+
+class SpGEMMBatch:
+    """Many independent products C_i = A_i * B_i run as one graph launch.
+
+    Inputs are lists of DeviceCsr; their arrays are concatenated into pools
+    (one device copy at construction).  ``plan()`` sizes the C pools,
+    ``run()`` launches the captured graph, ``product(i)`` views C_i."""
+
+    def __init__(self, As, Bs, stream: torch.cuda.Stream | None = None, **options):
+        assert len(As) == len(Bs)
+        self.count = len(As)
+        self.dtype = As[0].values.dtype if As else torch.float64
+        for A, B in zip(As, Bs):
+            if A.n != B.m:
+                raise ValueError("inner dimensions differ")
+            if A.values.dtype != self.dtype or B.values.dtype != self.dtype:
+                raise TypeError("all values must share one dtype")
+        # graph capture needs a stream of its own (not the legacy default stream);
+        # it is ordered after the caller's stream at every entry and before it at exit
+        self.stream = stream or torch.cuda.Stream()
+        self.stream.wait_stream(torch.cuda.current_stream())
+        dev = As[0].row_ptr.device if As else torch.device("cuda")
+        cat = lambda ts, dt: torch.cat(ts) if ts else torch.zeros(0, dtype=dt, device=dev)
+        with torch.cuda.stream(self.stream):
+            self.a_rp = cat([A.row_ptr for A in As], torch.int32)
+            self.a_ci = cat([A.col_idx for A in As], torch.int32)
+            self.a_v = cat([A.values for A in As], self.dtype)
+            self.b_rp = cat([B.row_ptr for B in Bs], torch.int32)
+            self.b_ci = cat([B.col_idx for B in Bs], torch.int32)
+            self.b_v = cat([B.values for B in Bs], self.dtype)
+        self.m = np.array([A.m for A in As], dtype=np.int32)
+        self.n = np.array([A.n for A in As], dtype=np.int32)
+        self.k = np.array([B.n for B in Bs], dtype=np.int32)
+        self.a_nnz = np.array([A.nnz for A in As], dtype=np.int64)
+        self.b_nnz = np.array([B.nnz for B in Bs], dtype=np.int64)
+        self.b = _lib.spg_batch_create(self.stream.cuda_stream, _dtype_code(self.dtype), self.count,
+                                       self.m.ctypes.data, self.n.ctypes.data, self.k.ctypes.data,
+                                       self.a_nnz.ctypes.data, self.b_nnz.ctypes.data, self.a_rp.data_ptr(),
+                                       self.a_ci.data_ptr(), self.b_rp.data_ptr(), self.b_ci.data_ptr())
+        for k_, v in options.items():
+            _lib.spg_batch_set_option(self.b, k_, int(v))
+        self.nnz = None
+
+    def __del__(self):
+        b = getattr(self, "b", None)
+        if b:
+            try:
+                _lib.spg_batch_destroy(b)
+            except Exception:
+                pass
+            self.b = None
+
+    def set_option(self, name, value):
+        _lib.spg_batch_set_option(self.b, name, int(value))
+        self.nnz = None
+
+    def set_mlp(self, w: np.ndarray):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        _lib.spg_batch_set_mlp(self.b, w.ctypes.data, int(w.size))
+        self.nnz = None
+
+    def plan(self):
+        self.stream.wait_stream(torch.cuda.current_stream())
+        self.c_row_off = np.zeros(self.count + 1, dtype=np.int64)
+        self.c_nnz_off = np.zeros(self.count + 1, dtype=np.int64)
+        self.nnz = _lib.spg_batch_plan(self.b, self.c_row_off.ctypes.data, self.c_nnz_off.ctypes.data)
+        dev = self.a_rp.device
+        with torch.cuda.stream(self.stream):
+            self.c_rp = torch.empty(int(self.m.sum()) + 1, dtype=torch.int32, device=dev)
+            self.c_col = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)
+            self.c_val = torch.empty(max(self.nnz, 1), dtype=self.dtype, device=dev)
+        return self.nnz
+
+    def _ptrs(self, a_vals, b_vals):
+        a_vals = self.a_v if a_vals is None else a_vals
+        b_vals = self.b_v if b_vals is None else b_vals
+        return (a_vals.data_ptr() if a_vals.numel() else 0, b_vals.data_ptr() if b_vals.numel() else 0,
+                self.c_rp.data_ptr(), self.c_col.data_ptr(), self.c_val.data_ptr(), int(self.c_col.numel()))
+
+    def run(self, numeric_only: bool = False, a_vals=None, b_vals=None):
+        if self.nnz is None:
+            self.plan()
+        cur = torch.cuda.current_stream()
+        self.stream.wait_stream(cur)
+        _lib.spg_batch_run(self.b, *self._ptrs(a_vals, b_vals), 1 if numeric_only else 0)
+        cur.wait_stream(self.stream)
+
+    def tune(self):
+        if self.nnz is None:
+            self.plan()
+        self.stream.wait_stream(torch.cuda.current_stream())
+        chosen, best = _lib.spg_batch_tune(self.b, *self._ptrs(None, None))
+        self.plan()
+        return chosen, best
+
+    def product(self, i: int):
+        """(row_ptr, col_idx, values) of C_i as views/copies on the device."""
+        r0, r1 = int(self.c_row_off[i]), int(self.c_row_off[i + 1])
+        e0, e1 = int(self.c_nnz_off[i]), int(self.c_nnz_off[i + 1])
+        return self.c_rp[r0:r1 + 1] - e0, self.c_col[e0:e1], self.c_val[e0:e1]
+
+    def stats(self) -> dict:
+        st = _lib.spg_batch_get_stats(self.b)
+        return {name: (list(getattr(st, name)) if hasattr(getattr(st, name), "__len__") else getattr(st, name))
+                for name, _ in st._fields_}

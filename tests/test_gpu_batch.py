@@ -1,0 +1,103 @@
+"""Batched products: every C_i of one graph launch equals the oracle's
+product, replays pick up changed values, numeric-only replays reuse the
+planned structure, and the autotuner keeps the product unchanged."""
+import numpy as np
+import pytest
+
+from paper_2103_11991_amd import gen
+from gpu_util import compare
+
+pytestmark = pytest.mark.gpu
+
+
+def setup_module(module):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _products(count, seed):
+    out = []
+    n, bwa, bwb = gen.batch_sizes(count, seed=seed, lo=50, hi=3000)
+    for i in range(count):
+        if i % 7 == 3:      # an empty product and odd shapes among the banded ones
+            A = gen.random_csr(40, 30, 0, 0, seed=i)
+            B = gen.random_csr(30, 20, 0, 4, seed=i + 1)
+        elif i % 7 == 5:
+            A = gen.random_csr(300, 200, 0, 25, seed=i, empty_frac=0.2)
+            B = gen.random_csr(200, 5000, 0, 40, seed=i + 1)
+        else:
+            A = gen.banded_random(int(n[i]), int(bwa[i]), seed, 2 * i)
+            B = gen.banded_random(int(n[i]), int(bwb[i]), seed, 2 * i + 1)
+        out.append((A, B))
+    return out
+
+
+def _check_all(batch, prods):
+    import torch
+    torch.cuda.synchronize()
+    for i, (A, B) in enumerate(prods):
+        rp, c, v = batch.product(i)
+        compare(A, B, rp.cpu().numpy().astype(np.int64), c.cpu().numpy(), v.cpu().numpy())
+
+
+def test_batch_matches_oracle_and_replays():
+    import torch
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMMBatch
+    prods = _products(30, 5)
+    batch = SpGEMMBatch([DeviceCsr.from_host(A) for A, _ in prods], [DeviceCsr.from_host(B) for _, B in prods])
+    nnz = batch.plan()
+    batch.run()
+    _check_all(batch, prods)
+    # replay of the same graph with new values written in place
+    prods2 = [(A.with_values(A.values * 2.0 - 1.0), B) for A, B in prods]
+    batch.a_v.copy_(torch.from_numpy(np.concatenate([A.values for A, _ in prods2])).cuda())
+    for _ in range(3):
+        batch.c_val.zero_()
+        batch.c_col.zero_()
+        batch.run()
+        _check_all(batch, prods2)
+    # numeric alone on the planned structure
+    batch.c_rp.zero_()
+    batch.run(numeric_only=True)
+    _check_all(batch, prods2)
+    assert nnz == sum(int(batch.c_nnz_off[i + 1] - batch.c_nnz_off[i]) for i in range(30))
+
+
+def test_batch_fp32_and_learned_binning():
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMMBatch
+    prods = [(A.astype(np.float32), B.astype(np.float32)) for A, B in _products(12, 9)]
+    w = np.zeros(1217, dtype=np.float32)
+    w[-1] = 1.0  # tiny tables everywhere: hashed rows overflow and are retried
+    batch = SpGEMMBatch([DeviceCsr.from_host(A) for A, _ in prods], [DeviceCsr.from_host(B) for _, B in prods],
+                        binning=1, mlp_margin_milli=0)
+    batch.set_mlp(w)
+    batch.plan()
+    batch.run()
+    _check_all(batch, prods)
+    batch.run()
+    _check_all(batch, prods)
+
+
+def test_autotuner_keeps_the_product():
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMMBatch
+    prods = _products(10, 3)
+    batch = SpGEMMBatch([DeviceCsr.from_host(A) for A, _ in prods], [DeviceCsr.from_host(B) for _, B in prods])
+    chosen, best = batch.tune()
+    assert chosen[0] in (8, 16, 32) and chosen[1] in (0, 4, 8, 16) and chosen[2] in (32, 64, 128)
+    assert best > 0
+    batch.run()
+    _check_all(batch, prods)
+
+
+def test_batch_rejects_bad_product():
+    import torch
+    from paper_2103_11991_amd import _lib
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMMBatch
+    A = gen.random_csr(20, 10, 1, 4, seed=1)
+    B = gen.random_csr(10, 8, 1, 4, seed=2)
+    badB = gen.Csr(10, 8, B.row_ptr, np.where(B.col_idx == B.col_idx.max(), 8, B.col_idx).astype(np.int32),
+                   B.values)
+    with pytest.raises(_lib.SpgError):
+        SpGEMMBatch([DeviceCsr.from_host(A)] * 2, [DeviceCsr.from_host(B), DeviceCsr.from_host(badB)])
+    torch.cuda.synchronize()

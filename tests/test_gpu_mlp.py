@@ -1,0 +1,180 @@
+"""GPU predictor kernels against the FP64 reference, and learned binning against
+upper-bound binning (the product must not change, only the tables' sizes)."""
+import numpy as np
+import pytest
+
+from oracle import mlp as ref
+from paper_2103_11991_amd import gen
+from gpu_util import compare, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def setup_module(module):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _w(seed, scale=0.4):
+    w = np.random.default_rng(seed).normal(0, scale, ref.NW)
+    return w.astype(np.float32)
+
+
+def _x(seed, rows):
+    return np.random.default_rng(seed + 1).uniform(0, 14, size=(rows, 3)).astype(np.float32)
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("rows", [1, 63, 1000, 4097])
+def test_forward_matches_reference(rows):
+    import torch
+    from paper_2103_11991_amd import _lib
+    w, x = _w(rows), _x(rows, rows)
+    dw, dx = _dev(w), _dev(x)
+    y = torch.empty(rows, dtype=torch.float32, device="cuda")
+    act = torch.empty(rows * 64, dtype=torch.float32, device="cuda")
+    _lib.spg_mlp_forward(0, dw.data_ptr(), dx.data_ptr(), rows, y.data_ptr(), act.data_ptr())
+    torch.cuda.synchronize()
+    yr, cache = ref.forward(w.astype(np.float64), x.astype(np.float64))
+    # scale: the sum of |terms| of the last layer, the size of FP32 rounding
+    W1, b1, W2, b2, w3, b3 = ref.unpack(w.astype(np.float64))
+    scale = np.abs(cache[4]) @ np.abs(w3) + abs(b3) + 1.0
+    np.testing.assert_array_less(np.abs(y.cpu().numpy() - yr), 1e-5 * scale * 10)
+    z = act.cpu().numpy().reshape(rows, 64)
+    np.testing.assert_allclose(z[:, :32], cache[1], rtol=1e-4, atol=1e-4)
+
+
+@pytest.mark.parametrize("rows", [5, 700, 3000])
+def test_backward_matches_reference(rows):
+    import torch
+    from paper_2103_11991_amd import _lib
+    w, x = _w(rows + 3), _x(rows + 3, rows)
+    dyh = np.random.default_rng(rows).normal(size=rows).astype(np.float32)
+    dw_, dx, ddy = _dev(w), _dev(x), _dev(dyh)
+    y = torch.empty(rows, dtype=torch.float32, device="cuda")
+    act = torch.empty(rows * 64, dtype=torch.float32, device="cuda")
+    g = torch.empty(ref.NW, dtype=torch.float32, device="cuda")
+    _lib.spg_mlp_forward(0, dw_.data_ptr(), dx.data_ptr(), rows, y.data_ptr(), act.data_ptr())
+    _lib.spg_mlp_backward(0, dw_.data_ptr(), dx.data_ptr(), act.data_ptr(), ddy.data_ptr(), rows, g.data_ptr())
+    torch.cuda.synchronize()
+    _, cache = ref.forward(w.astype(np.float64), x.astype(np.float64))
+    gr = ref.backward(w.astype(np.float64), cache, dyh.astype(np.float64))
+    # componentwise scale: the same gradient with every factor in absolute value
+    gabs = ref.backward(np.abs(w.astype(np.float64)), ref.forward(np.abs(w.astype(np.float64)), x)[1],
+                        np.abs(dyh.astype(np.float64)))
+    np.testing.assert_array_less(np.abs(g.cpu().numpy() - gr), 1e-4 * (np.abs(gabs) + 1e-3))
+
+
+def test_training_step_matches_reference_and_training_reduces_loss():
+    import torch
+    from paper_2103_11991_amd import _lib
+    rows, batch = 1500, 500
+    x = _x(9, rows)
+    t = (0.4 * x[:, 0] + 0.8 * x[:, 1] - 0.3 * x[:, 2]).astype(np.float32)
+    w0 = (_w(10, 0.2)).astype(np.float32)
+    # one epoch = three Adam steps
+    dw, dx, dt = _dev(w0.copy()), _dev(x), _dev(t)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    _lib.spg_mlp_train(0, dx.data_ptr(), dt.data_ptr(), rows, 1, batch, 1e-3, 0.0, dw.data_ptr(), loss.data_ptr())
+    torch.cuda.synchronize()
+    wr, lr_ = ref.train(x.astype(np.float64), t.astype(np.float64), w0.astype(np.float64), 1, 1e-3, batch)
+    # Adam moves each weight by about lr * sign(gradient): a gradient that FP32
+    # rounding flips can move one weight by up to 2 lr per step, the rest agree
+    diff = np.abs(dw.cpu().numpy() - wr)
+    assert np.mean(diff <= 2e-5) >= 0.99 and diff.max() <= 3 * 2 * 1e-3
+    assert abs(loss.item() - lr_[0]) <= 1e-4 * lr_[0]
+    # longer training reduces the loss
+    losses = torch.zeros(20, dtype=torch.float32, device="cuda")
+    dw2 = _dev(w0.copy())
+    _lib.spg_mlp_train(0, dx.data_ptr(), dt.data_ptr(), rows, 20, 100, 3e-3, 0.0, dw2.data_ptr(), losses.data_ptr())
+    torch.cuda.synchronize()
+    ls = losses.cpu().numpy()
+    assert ls[-1] < 0.2 * ls[0]
+
+
+def test_pinball_training_of_the_last_bias_reaches_the_quantile():
+    """With every weight but b3 at zero only b3 moves, and the pinball loss of
+    level q is minimised by the q-quantile of the targets."""
+    import torch
+    from paper_2103_11991_amd import _lib
+    rows = 4000
+    t = np.random.default_rng(3).exponential(2.0, rows).astype(np.float32)
+    x = _x(1, rows)
+    w = np.zeros(ref.NW, dtype=np.float32)
+    dw_, dx, dt = _dev(w), _dev(x), _dev(t)
+    _lib.spg_mlp_train(0, dx.data_ptr(), dt.data_ptr(), rows, 600, 4000, 0.1, 0.9, dw_.data_ptr(), 0)
+    torch.cuda.synchronize()
+    got = dw_.cpu().numpy()
+    assert not got[:-1].any()
+    assert abs(got[-1] - np.quantile(t, 0.9)) < 0.05
+
+
+def _constant_predictor(value):
+    w = np.zeros(ref.NW, dtype=np.float32)
+    w[-1] = value
+    return w
+
+
+@pytest.mark.parametrize("which", ["rmat", "stencil", "random"])
+def test_learned_binning_gives_the_same_product(which):
+    if which == "rmat":
+        A = gen.rmat(11, seed=7)
+    elif which == "stencil":
+        A = gen.stencil27(12, seed=5)
+    else:
+        A = gen.random_csr(900, 900, 0, 30, seed=3, empty_frac=0.1)
+    rp0, c0, v0, _ = run_gpu(A, A)
+    for w in (_constant_predictor(0.0), _constant_predictor(3.0), _w(4, 0.3)):
+        from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
+        import torch
+        dA = DeviceCsr.from_host(A)
+        op = SpGEMM(dA, dA, binning=1, mlp_margin_milli=0)
+        op.set_mlp(w)
+        rp, nnz = op.symbolic()
+        col, val = op.numeric()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(rp.cpu().numpy().astype(np.int64), rp0)
+        np.testing.assert_array_equal(col.cpu().numpy(), c0)
+        compare(A, A, rp0, col.cpu().numpy(), val.cpu().numpy())
+
+
+def test_constant_tiny_prediction_forces_retries():
+    """A predictor whose output is log2(2): every hashed table is sized for one
+    block, so rows with more blocks overflow and are redone exactly."""
+    import torch
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
+    A = gen.random_csr(2000, 2000, 5, 40, seed=12)
+    dA = DeviceCsr.from_host(A)
+    op = SpGEMM(dA, dA, binning=1, mlp_margin_milli=0)
+    op.set_mlp(_constant_predictor(1.0))
+    rp, nnz = op.symbolic()
+    col, val = op.numeric()
+    torch.cuda.synchronize()
+    st = op.stats()
+    assert st["retried_rows"] > 0
+    compare(A, A, rp.cpu().numpy().astype(np.int64), col.cpu().numpy(), val.cpu().numpy())
+
+
+def test_export_rows_targets_match_oracle_blocks():
+    import torch
+    import oracle
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
+    A = gen.rmat(10, seed=3)
+    dA = DeviceCsr.from_host(A)
+    op = SpGEMM(dA, dA, keep_features=1)
+    op.symbolic()
+    x, y, r = op.export_rows()
+    torch.cuda.synchronize()
+    orp, ocol, _, _ = oracle.spgemm(A, A)
+    blocks = np.array([len(np.unique(ocol[orp[i]:orp[i + 1]] >> 5)) for i in range(A.m)])
+    np.testing.assert_array_equal(r.cpu().numpy(), np.diff(orp))
+    np.testing.assert_allclose(y.cpu().numpy(), np.log2(1.0 + blocks), rtol=1e-6)
+    ub = gen.products_per_row(A, A)
+    lens = A.row_lengths()
+    mx = np.array([A.row_lengths()[A.col_idx[A.row_ptr[i]:A.row_ptr[i + 1]]].max(initial=0) for i in range(A.m)])
+    np.testing.assert_allclose(x.cpu().numpy(), ref.features(lens, ub, mx), rtol=1e-6)

@@ -91,3 +91,25 @@ def test_training_reduces_loss():
     _, losses = mlp.train(X, T, w0, epochs=8, lr=3e-3, batch=256)
     assert losses[-1] < 0.2 * losses[0]
     assert np.mean(np.diff(losses)) < 0
+
+
+def test_pinball_gradient_and_minimiser():
+    """Pinball loss: gradient by central differences away from kinks, and a
+    constant predictor trained on it settles at the q-quantile of the targets."""
+    rng = np.random.default_rng(8)
+    y = rng.normal(size=50)
+    t = rng.normal(size=50)
+    q = 0.8
+    L, g = mlp.pinball(y, t, q)
+    h = 1e-7
+    for i in range(0, 50, 7):
+        yp = y.copy(); yp[i] += h
+        ym = y.copy(); ym[i] -= h
+        num = (mlp.pinball(yp, t, q)[0] - mlp.pinball(ym, t, q)[0]) / (2 * h)
+        assert abs(num - g[i]) < 1e-6
+    T = rng.exponential(2.0, 3000)
+    X = rng.uniform(0, 5, size=(3000, 3))
+    w0 = np.zeros(mlp.NW)
+    w, _ = mlp.train(X, T, w0, epochs=600, lr=0.1, batch=3000, quantile=0.9)
+    assert not w[:-1].any()
+    assert abs(w[-1] - np.quantile(T, 0.9)) < 0.05
