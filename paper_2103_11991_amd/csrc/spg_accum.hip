@@ -1,24 +1,30 @@
 // Row accumulators of the symbolic and numeric phases (section 2.2.1).
 //
-// One group of G lanes owns one row of C (G from 8 to 1024; several rows
-// share a 256-lane workgroup when G < 256).  Inside the group the work is the
-// flattened double loop of Eq. (1): sub-groups of `vec` lanes take successive
-// nonzeros of A's row, and the lanes of a sub-group read consecutive entries
-// of the referenced B row, so B is read in coalesced runs (the paper's
-// vector-parallel inner loop, section 2.2.1).
+// One group of G lanes owns one row of C.  Groups of up to 64 lanes live
+// inside one wavefront (several rows per 256-lane workgroup, no workgroup
+// barriers); groups of 128 and more lanes own a whole workgroup.
 //
-// Tables (see spg_internal.h): masks of 32-column blocks, direct or hashed.
-//   symbolic: OR every product's column bit in; count = sum of popcounts,
-//             and the number of occupied blocks is kept for numeric sizing
-//             and as the learned predictor's target;
+// Work distribution is the flattened double loop of Eq. (1) (the paper's
+// method for rows with many FLOPs, section 2.2.1): a chunk of up to G
+// nonzeros of A's row is staged in LDS with the exclusive prefix sum of
+// their B-row lengths, and lane l then takes products l, l+G, l+2G, ... of
+// the chunk.  Consecutive lanes read consecutive entries of a B row
+// (coalesced), every lane's loads are independent of each other (they are
+// issued in batches of four), and the work per lane is even whatever the
+// B-row lengths are.
+//
+// Tables (spg_internal.h): 32-column block masks, direct or hashed.
+//   symbolic: OR each product's column bit in; the value returned by the
+//             atomic OR says whether the bit (and the block) is new, so the
+//             row size and its occupied blocks are counted on the fly;
 //   numeric:  OR pass, then an exclusive prefix sum of popcounts in
-//             ascending block order (hashed tables first rank their occupied
-//             blocks by key), then every product is added with an LDS atomic
-//             at its column's rank; the row leaves in column order with
+//             ascending block order (hashed tables rank their occupied
+//             blocks by key first), then every product is added with an LDS
+//             atomic at its column's rank; the row leaves sorted, with
 //             coalesced stores.
-// Long rows use the global path: 1024 lanes per row, the mask/prefix table
-// in LDS when it fits else in a per-workgroup global slab, and values added
-// with global atomics directly into C's value array.
+// Long rows use the global path: 1024 lanes per row, the table in LDS when
+// it fits else in a per-workgroup global slab, values added with global
+// atomics straight into C's value array.
 #include <hip/hip_runtime.h>
 
 #include "spg_internal.h"
@@ -26,6 +32,8 @@
 namespace spg {
 
 namespace {
+
+constexpr int UNROLL = 4;
 
 __device__ inline int hash_slot(int key, int logT) {
     return (int)(((uint32_t)key * 2654435761u) >> (32 - logT));
@@ -62,25 +70,41 @@ __device__ inline int hash_find(const int32_t* keys, int T, int logT, int key) {
 }
 
 template <int G>
+constexpr int rows_per_wg() {
+    return G <= 64 ? 256 / G : 1;
+}
+
+// Orders LDS accesses among the lanes of one group.
+template <int G>
+__device__ inline void group_sync() {
+    if constexpr (G <= 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    } else {
+        __syncthreads();
+    }
+}
+
+template <int G>
 __device__ inline int group_sum(int v, int* red) {
     if constexpr (G <= 64) {
         for (int d = G / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, G);
         return v;
     } else {
-        // several waves per group; the partials of group g sit at red[g * W ..)
         constexpr int W = G / 64;
-        const int wl = threadIdx.x & 63, wv = (threadIdx.x % G) >> 6, g0 = (threadIdx.x / G) * W;
+        const int wl = threadIdx.x & 63, wv = threadIdx.x >> 6;
         for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
         __syncthreads();
-        if (wl == 0) red[g0 + wv] = v;
+        if (wl == 0) red[wv] = v;
         __syncthreads();
         int t = 0;
-        for (int u = 0; u < W; ++u) t += red[g0 + u];
+        for (int u = 0; u < W; ++u) t += red[u];
         return t;
     }
 }
 
-// Exclusive prefix sum over the G lanes of a group; *total gets the sum.
+// Exclusive prefix sum over the G lanes of a group; total gets the sum.
 template <int G>
 __device__ inline int group_excl_scan(int v, int& total, int* red) {
     if constexpr (G <= 64) {
@@ -94,18 +118,18 @@ __device__ inline int group_excl_scan(int v, int& total, int* red) {
         return x - v;
     } else {
         constexpr int W = G / 64;
-        const int wl = threadIdx.x & 63, wv = (threadIdx.x % G) >> 6, g0 = (threadIdx.x / G) * W;
+        const int wl = threadIdx.x & 63, wv = threadIdx.x >> 6;
         int x = v;
         for (int d = 1; d < 64; d <<= 1) {
             int y = __shfl_up(x, d, 64);
             if (wl >= d) x += y;
         }
         __syncthreads();
-        if (wl == 63) red[g0 + wv] = x;
+        if (wl == 63) red[wv] = x;
         __syncthreads();
         int pre = 0, tot = 0;
         for (int u = 0; u < W; ++u) {
-            int t = red[g0 + u];
+            int t = red[u];
             if (u < wv) pre += t;
             tot += t;
         }
@@ -114,9 +138,51 @@ __device__ inline int group_excl_scan(int v, int& total, int* red) {
     }
 }
 
-template <int G>
-constexpr int rows_per_wg() {
-    return G >= 256 ? 1 : 256 / G;
+// Visits every product (A(i,p), B(j,q)) of the row whose nonzeros are
+// [a0, a1): stage(e, p) runs once per staged A entry (chunk slot e),
+// load(q) fetches what a product needs from B, apply(v, e) consumes it.
+// st: G int2 of LDS per group (B-row start minus prefix, prefix).
+template <int G, typename Stage, typename Load, typename Apply>
+__device__ inline void walk_products(int a0, int a1, const int32_t* __restrict__ aci,
+                                     const int32_t* __restrict__ brp, int lane, int2* st, int* red, Stage stage,
+                                     Load load, Apply apply) {
+    for (int cb = a0; cb < a1; cb += G) {
+        const int cnt = min(G, a1 - cb);
+        int len = 0, b0 = 0;
+        if (lane < cnt) {
+            const int j = aci[cb + lane];
+            b0 = brp[j];
+            len = brp[j + 1] - b0;
+            stage(lane, cb + lane);
+        }
+        int total;
+        const int ex = group_excl_scan<G>(len, total, red);
+        if (lane < cnt) st[lane] = make_int2(b0 - ex, ex);
+        group_sync<G>();
+        int t = 0;
+        for (int f = lane; f < total;) {
+            int q[UNROLL], e[UNROLL];
+            int nq = 0;
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                if (f < total) {
+                    while (t + 1 < cnt && st[t + 1].y <= f) ++t;
+                    q[u] = st[t].x + f;
+                    e[u] = t;
+                    f += G;
+                    nq = u + 1;
+                }
+            }
+            decltype(load(0)) v[UNROLL];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u)
+                if (u < nq) v[u] = load(q[u]);
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u)
+                if (u < nq) apply(v[u], e[u]);
+        }
+        group_sync<G>();
+    }
 }
 
 // ------------------------------------------------------------------ symbolic
@@ -129,71 +195,63 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_sym(SymArgs a) {
     __shared__ int occ[RPW];
     __shared__ int ovf[RPW];
     const int bytes = tier_bytes(a.tier);
+    const int per_row = bytes + G * 8;
     const int sub = threadIdx.x / G, lane = threadIdx.x % G;
     const int slot = blockIdx.x * RPW + sub;
-    const bool act = slot < a.count;
-    const int i = act ? a.perm[slot] : 0;
-    uint32_t* tab = smem + sub * (bytes / 4);
-    int base = 0, ncell = 0, T = 0, logT = 0;
+    if (slot >= a.count) return;  // uniform in the group (in the workgroup when G >= 128)
+    const int i = a.perm[slot];
+    uint8_t* row_lds = reinterpret_cast<uint8_t*>(smem) + (size_t)sub * per_row;
+    uint32_t* tab = reinterpret_cast<uint32_t*>(row_lds);
+    int2* st = reinterpret_cast<int2*>(row_lds + bytes);
+    int base = 0, ncell, T = 0, logT = 0;
     int32_t* keys = reinterpret_cast<int32_t*>(tab);
     uint32_t* masks = tab;
     if constexpr (MODE == MODE_DIRECT) {
-        if (act) {
-            RowInfo ri = a.rinfo[i];
-            base = ri.x >> 5;
-            ncell = (ri.y >> 5) - base + 1;
-        }
+        const RowInfo ri = a.rinfo[i];
+        base = ri.x >> 5;
+        ncell = (ri.y >> 5) - base + 1;
     } else {
         T = 1 << (31 - __clz(bytes / 8));
         logT = 31 - __clz(T);
         masks = tab + T;
-        ncell = act ? T : 0;
+        ncell = T;
     }
     for (int c = lane; c < ncell; c += G) {
         masks[c] = 0;
         if constexpr (MODE == MODE_HASHED) keys[c] = -1;
     }
     if (lane == 0) occ[sub] = 0, ovf[sub] = 0;
-    __syncthreads();
-    if (act) {
-        const int a0 = a.arp[i], a1 = a.arp[i + 1];
-        const int S = a.vec < G ? a.vec : G;
-        const int nsub = G / S, sg = lane / S, vl = lane % S;
-        const int occ_max = (T * 3) / 4;
-        for (int p = a0 + sg; p < a1; p += nsub) {
-            const int j = a.aci[p];
-            const int b0 = a.brp[j], b1 = a.brp[j + 1];
-            for (int q = b0 + vl; q < b1; q += S) {
-                const int c = a.bci[q];
-                const uint32_t bit = 1u << (c & 31);
-                if constexpr (MODE == MODE_DIRECT) {
-                    atomicOr(&masks[(c >> 5) - base], bit);
-                } else {
-                    if (*(volatile int*)&ovf[sub]) break;
-                    bool ins;
-                    int h = hash_insert(keys, T, logT, c >> 5, ins);
-                    if (h < 0) {
-                        ovf[sub] = 1;
-                        break;
-                    }
-                    if (ins && atomicAdd(&occ[sub], 1) >= occ_max) ovf[sub] = 1;
-                    atomicOr(&masks[h], bit);
-                }
-            }
-        }
-    }
-    __syncthreads();
+    group_sync<G>();
     int cnt = 0, nb = 0;
-    for (int c = lane; c < ncell; c += G) {
-        uint32_t mk = masks[c];
-        cnt += __popc(mk);
-        nb += mk != 0;
-    }
+    const int occ_max = (T * 3) / 4;
+    walk_products<G>(
+        a.arp[i], a.arp[i + 1], a.aci, a.brp, lane, st, red, [](int, int) {},
+        [&](int q) { return a.bci[q]; },
+        [&](int c, int) {
+            const uint32_t bit = 1u << (c & 31);
+            int cell;
+            if constexpr (MODE == MODE_DIRECT) {
+                cell = (c >> 5) - base;
+            } else {
+                if (*(volatile int*)&ovf[sub]) return;
+                bool ins;
+                cell = hash_insert(keys, T, logT, c >> 5, ins);
+                if (cell < 0) {
+                    ovf[sub] = 1;
+                    return;
+                }
+                if (ins && atomicAdd(&occ[sub], 1) >= occ_max) ovf[sub] = 1;
+            }
+            const uint32_t old = atomicOr(&masks[cell], bit);
+            cnt += (old & bit) == 0;
+            nb += old == 0;
+        });
     cnt = group_sum<G>(cnt, red);
     nb = group_sum<G>(nb, red);
-    if (act && lane == 0) {
+    group_sync<G>();
+    if (lane == 0) {
         if (MODE == MODE_HASHED && ovf[sub]) {
-            int pos = atomicAdd(&a.ctl->overflow_rows, 1);
+            const int pos = atomicAdd(&a.ctl->overflow_rows, 1);
             a.ovf_list[pos] = i;
         } else {
             a.row_nnz[i] = cnt;
@@ -209,7 +267,7 @@ __device__ inline uint32_t ld_tab(const uint32_t* p) {
 }
 
 template <bool IN_LDS>
-__device__ void wide_sym_row(const SymArgs& a, int i, uint32_t* masks, int* red) {
+__device__ void wide_sym_row(const SymArgs& a, int i, uint32_t* masks, int2* st, int* red) {
     constexpr int G = WIDE_THREADS;
     const int tid = threadIdx.x;
     const RowInfo ri = a.rinfo[i];
@@ -218,27 +276,15 @@ __device__ void wide_sym_row(const SymArgs& a, int i, uint32_t* masks, int* red)
     for (int c = tid; c < words; c += G) masks[c] = 0;
     if (!IN_LDS) __threadfence();
     __syncthreads();
-    {
-        const int a0 = a.arp[i], a1 = a.arp[i + 1];
-        const int S = a.vec < G ? a.vec : G;
-        const int nsub = G / S, sg = tid / S, vl = tid % S;
-        for (int p = a0 + sg; p < a1; p += nsub) {
-            const int j = a.aci[p];
-            const int b0 = a.brp[j], b1 = a.brp[j + 1];
-            for (int q = b0 + vl; q < b1; q += S) {
-                const int c = a.bci[q];
-                atomicOr(&masks[(c >> 5) - base], 1u << (c & 31));
-            }
-        }
-    }
-    if (!IN_LDS) __threadfence();
-    __syncthreads();
     int cnt = 0, nb = 0;
-    for (int c = tid; c < words; c += G) {
-        uint32_t mk = ld_tab<IN_LDS>(&masks[c]);
-        cnt += __popc(mk);
-        nb += mk != 0;
-    }
+    walk_products<G>(
+        a.arp[i], a.arp[i + 1], a.aci, a.brp, tid, st, red, [](int, int) {}, [&](int q) { return a.bci[q]; },
+        [&](int c, int) {
+            const uint32_t bit = 1u << (c & 31);
+            const uint32_t old = atomicOr(&masks[(c >> 5) - base], bit);
+            cnt += (old & bit) == 0;
+            nb += old == 0;
+        });
     cnt = group_sum<G>(cnt, red);
     nb = group_sum<G>(nb, red);
     if (tid == 0) {
@@ -250,18 +296,19 @@ __device__ void wide_sym_row(const SymArgs& a, int i, uint32_t* masks, int* red)
 
 // Global path of the symbolic phase: long rows, and the exact retry of rows
 // whose learned-size table overflowed.  Persistent: each workgroup walks the
-// row list with stride gridDim.x.
+// row list with stride gridDim.x (the count may be read on the device).
 __global__ __launch_bounds__(WIDE_THREADS) void k_sym_wide(SymArgs a) {
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int red[16];
     const int count = a.count_dev ? *a.count_dev : a.count;
     uint32_t* slab = a.slab ? a.slab + (int64_t)blockIdx.x * a.slab_words : nullptr;
+    int2* st = reinterpret_cast<int2*>(reinterpret_cast<uint8_t*>(smem) + a.wide_lds);
     for (int r = blockIdx.x; r < count; r += gridDim.x) {
         const int i = a.perm[r];
         const RowInfo ri = a.rinfo[i];
         const int64_t words = row_words(ri.x, ri.y);
-        if (words * 4 <= a.wide_lds) wide_sym_row<true>(a, i, smem, red);
-        else wide_sym_row<false>(a, i, slab, red);
+        if (words * 4 <= a.wide_lds) wide_sym_row<true>(a, i, smem, st, red);
+        else wide_sym_row<false>(a, i, slab, st, red);
     }
 }
 
@@ -274,27 +321,28 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     __shared__ int red[16];
     __shared__ int ncompact[RPW];
     const int bytes = tier_bytes(a.tier);
+    const int per_row = bytes + G * 16;
     const int sub = threadIdx.x / G, lane = threadIdx.x % G;
     const int slot = blockIdx.x * RPW + sub;
-    const bool act = slot < a.count;
-    const int i = act ? a.perm[slot] : 0;
-    uint8_t* tab = reinterpret_cast<uint8_t*>(smem) + (size_t)sub * bytes;
-    int n = 0, off = 0, base = 0, words = 0, nb = 0, TT = 0, logT = 0;
-    if (act) {
-        off = a.crp[i];
-        n = a.crp[i + 1] - off;
-        RowInfo ri = a.rinfo[i];
-        base = ri.x >> 5;
-        words = (ri.y >> 5) - base + 1;
-        nb = a.row_blocks[i];
-    }
+    if (slot >= a.count) return;
+    const int i = a.perm[slot];
+    uint8_t* row_lds = reinterpret_cast<uint8_t*>(smem) + (size_t)sub * per_row;
+    uint8_t* tab = row_lds;
+    int2* st = reinterpret_cast<int2*>(row_lds + bytes);
+    T* ast = reinterpret_cast<T*>(row_lds + bytes + G * 8);
+    const int off = a.crp[i];
+    const int n = a.crp[i + 1] - off;
+    const RowInfo ri = a.rinfo[i];
+    const int base = ri.x >> 5;
+    const int words = (ri.y >> 5) - base + 1;
+    const int nb = a.row_blocks[i];
     int32_t* keys = nullptr;
     int32_t* list = nullptr;
     int32_t* ord = nullptr;
     uint32_t* masks;
     int32_t* pref;
     T* vals;
-    int ncell, items;
+    int ncell, items, TT = 0, logT = 0;
     if constexpr (MODE == MODE_DIRECT) {
         masks = reinterpret_cast<uint32_t*>(tab);
         pref = reinterpret_cast<int32_t*>(masks + words);
@@ -310,7 +358,7 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
         list = pref + TT;
         ord = list + nb;
         vals = reinterpret_cast<T*>(tab + align8((int64_t)TT * 12 + (int64_t)nb * 8));
-        ncell = act ? TT : 0;
+        ncell = TT;
         items = nb;
     }
     int32_t* colbuf = reinterpret_cast<int32_t*>(vals + n);
@@ -320,33 +368,27 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     }
     for (int r = lane; r < n; r += G) vals[r] = T(0);
     if (lane == 0) ncompact[sub] = 0;
-    __syncthreads();
+    group_sync<G>();
 
-    const int a0 = act ? a.arp[i] : 0, a1 = act ? a.arp[i + 1] : 0;
-    const int S = a.vec < G ? a.vec : G;
-    const int nsub = G / S, sg = lane / S, vl = lane % S;
+    const int a0 = a.arp[i], a1 = a.arp[i + 1];
     // pass 1: which columns occur
-    for (int p = a0 + sg; p < a1; p += nsub) {
-        const int j = a.aci[p];
-        const int b0 = a.brp[j], b1 = a.brp[j + 1];
-        for (int q = b0 + vl; q < b1; q += S) {
-            const int c = a.bci[q];
-            const uint32_t bit = 1u << (c & 31);
+    walk_products<G>(
+        a0, a1, a.aci, a.brp, lane, st, red, [](int, int) {}, [&](int q) { return a.bci[q]; },
+        [&](int c, int) {
+            int cell;
             if constexpr (MODE == MODE_DIRECT) {
-                atomicOr(&masks[(c >> 5) - base], bit);
+                cell = (c >> 5) - base;
             } else {
                 bool ins;
-                int h = hash_insert(keys, TT, logT, c >> 5, ins);
-                atomicOr(&masks[h], bit);
+                cell = hash_insert(keys, TT, logT, c >> 5, ins);
             }
-        }
-    }
-    __syncthreads();
+            atomicOr(&masks[cell], 1u << (c & 31));
+        });
     if constexpr (MODE == MODE_HASHED) {
         // occupied slots in ascending block order: compact, then rank by count
         for (int c = lane; c < ncell; c += G)
             if (masks[c]) list[atomicAdd(&ncompact[sub], 1)] = c;
-        __syncthreads();
+        group_sync<G>();
         for (int e = lane; e < nb; e += G) {
             const int s = list[e];
             const int key = keys[s];
@@ -354,7 +396,7 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
             for (int f = 0; f < nb; ++f) r += keys[list[f]] < key;
             ord[r] = s;
         }
-        __syncthreads();
+        group_sync<G>();
     }
     // exclusive prefix of popcounts over blocks in ascending order
     {
@@ -371,25 +413,24 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
             ex += __popc(masks[cl]);
         }
     }
-    __syncthreads();
+    group_sync<G>();
     // pass 2: add every product at its column's rank
     const T* av = reinterpret_cast<const T*>(a.av);
     const T* bv = reinterpret_cast<const T*>(a.bv);
-    for (int p = a0 + sg; p < a1; p += nsub) {
-        const int j = a.aci[p];
-        const T x = av[p];
-        const int b0 = a.brp[j], b1 = a.brp[j + 1];
-        for (int q = b0 + vl; q < b1; q += S) {
-            const int c = a.bci[q];
-            const T y = bv[q];
-            const uint32_t below = (1u << (c & 31)) - 1u;
+    struct CV {
+        int c;
+        T y;
+    };
+    walk_products<G>(
+        a0, a1, a.aci, a.brp, lane, st, red, [&](int e, int p) { ast[e] = av[p]; },
+        [&](int q) { return CV{a.bci[q], bv[q]}; },
+        [&](const CV& v, int e) {
             int cl;
-            if constexpr (MODE == MODE_DIRECT) cl = (c >> 5) - base;
-            else cl = hash_find(keys, TT, logT, c >> 5);
-            const int rank = pref[cl] + __popc(masks[cl] & below);
-            atomicAdd(&vals[rank], x * y);
-        }
-    }
+            if constexpr (MODE == MODE_DIRECT) cl = (v.c >> 5) - base;
+            else cl = hash_find(keys, TT, logT, v.c >> 5);
+            const int rank = pref[cl] + __popc(masks[cl] & ((1u << (v.c & 31)) - 1u));
+            atomicAdd(&vals[rank], ast[e] * v.y);
+        });
     // column of every rank, from the masks
     for (int t = lane; t < items; t += G) {
         const int cl = MODE == MODE_DIRECT ? t : ord[t];
@@ -401,7 +442,7 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
             mk &= mk - 1;
         }
     }
-    __syncthreads();
+    group_sync<G>();
     T* cv = reinterpret_cast<T*>(a.cval);
     for (int r = lane; r < n; r += G) {
         a.ccol[off + r] = colbuf[r];
@@ -410,7 +451,7 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
 }
 
 template <typename T, bool IN_LDS>
-__device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int* red) {
+__device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int2* st, T* ast, int* red) {
     constexpr int G = WIDE_THREADS;
     const int tid = threadIdx.x;
     const int off = a.crp[i];
@@ -426,16 +467,9 @@ __device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int* red)
     __threadfence();
     __syncthreads();
     const int a0 = a.arp[i], a1 = a.arp[i + 1];
-    const int S = a.vec < G ? a.vec : G;
-    const int nsub = G / S, sg = tid / S, vl = tid % S;
-    for (int p = a0 + sg; p < a1; p += nsub) {
-        const int j = a.aci[p];
-        const int b0 = a.brp[j], b1 = a.brp[j + 1];
-        for (int q = b0 + vl; q < b1; q += S) {
-            const int c = a.bci[q];
-            atomicOr(&masks[(c >> 5) - base], 1u << (c & 31));
-        }
-    }
+    walk_products<G>(
+        a0, a1, a.aci, a.brp, tid, st, red, [](int, int) {}, [&](int q) { return a.bci[q]; },
+        [&](int c, int) { atomicOr(&masks[(c >> 5) - base], 1u << (c & 31)); });
     if (!IN_LDS) __threadfence();
     __syncthreads();
     {
@@ -455,19 +489,20 @@ __device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int* red)
     __syncthreads();
     const T* av = reinterpret_cast<const T*>(a.av);
     const T* bv = reinterpret_cast<const T*>(a.bv);
-    for (int p = a0 + sg; p < a1; p += nsub) {
-        const int j = a.aci[p];
-        const T x = av[p];
-        const int b0 = a.brp[j], b1 = a.brp[j + 1];
-        for (int q = b0 + vl; q < b1; q += S) {
-            const int c = a.bci[q];
-            const int w = (c >> 5) - base;
+    struct CV {
+        int c;
+        T y;
+    };
+    walk_products<G>(
+        a0, a1, a.aci, a.brp, tid, st, red, [&](int e, int p) { ast[e] = av[p]; },
+        [&](int q) { return CV{a.bci[q], bv[q]}; },
+        [&](const CV& v, int e) {
+            const int w = (v.c >> 5) - base;
             const uint32_t mk = ld_tab<IN_LDS>(&masks[w]);
             const int rank = (int)ld_tab<IN_LDS>(reinterpret_cast<uint32_t*>(&pref[w])) +
-                             __popc(mk & ((1u << (c & 31)) - 1u));
-            atomicAdd(&cv[rank], x * bv[q]);
-        }
-    }
+                             __popc(mk & ((1u << (v.c & 31)) - 1u));
+            atomicAdd(&cv[rank], ast[e] * v.y);
+        });
     for (int t = tid; t < words; t += G) {
         uint32_t mk = ld_tab<IN_LDS>(&masks[t]);
         int r = (int)ld_tab<IN_LDS>(reinterpret_cast<uint32_t*>(&pref[t]));
@@ -486,12 +521,14 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_num_wide(NumArgs a) {
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int red[16];
     uint32_t* slab = a.slab ? a.slab + (int64_t)blockIdx.x * a.slab_words : nullptr;
+    int2* st = reinterpret_cast<int2*>(reinterpret_cast<uint8_t*>(smem) + a.wide_lds);
+    T* ast = reinterpret_cast<T*>(reinterpret_cast<uint8_t*>(smem) + a.wide_lds + WIDE_THREADS * 8);
     for (int r = blockIdx.x; r < a.count; r += gridDim.x) {
         const int i = a.perm[r];
         const RowInfo ri = a.rinfo[i];
         const int64_t words = row_words(ri.x, ri.y);
-        if (words * 8 <= a.wide_lds) wide_num_row<T, true>(a, i, smem, red);
-        else wide_num_row<T, false>(a, i, slab, red);
+        if (words * 8 <= a.wide_lds) wide_num_row<T, true>(a, i, smem, st, ast, red);
+        else wide_num_row<T, false>(a, i, slab, st, ast, red);
     }
 }
 
@@ -499,7 +536,7 @@ template <int G, int MODE>
 void sym_launch(hipStream_t s, const SymArgs& a) {
     constexpr int RPW = rows_per_wg<G>();
     const unsigned grid = (unsigned)((a.count + RPW - 1) / RPW);
-    const size_t smem = (size_t)RPW * tier_bytes(a.tier);
+    const size_t smem = (size_t)RPW * (tier_bytes(a.tier) + G * 8);
     hipLaunchKernelGGL((k_sym<G, MODE>), dim3(grid), dim3(G * RPW), smem, s, a);
 }
 
@@ -507,7 +544,7 @@ template <int G, int MODE, typename T>
 void num_launch(hipStream_t s, const NumArgs& a) {
     constexpr int RPW = rows_per_wg<G>();
     const unsigned grid = (unsigned)((a.count + RPW - 1) / RPW);
-    const size_t smem = (size_t)RPW * tier_bytes(a.tier);
+    const size_t smem = (size_t)RPW * (tier_bytes(a.tier) + G * 16);
     hipLaunchKernelGGL((k_num<G, MODE, T>), dim3(grid), dim3(G * RPW), smem, s, a);
 }
 
@@ -541,11 +578,13 @@ void num_dispatch(hipStream_t s, const NumArgs& a) {
 
 }  // namespace
 
+size_t wide_smem_bytes(int wide_lds, int phase) { return (size_t)wide_lds + WIDE_THREADS * (phase ? 16 : 8); }
+
 int launch_sym_class(hipStream_t s, const SymArgs& a, int grid_cap) {
     if (a.tier == TIER_GLOBAL) {
         int grid = a.count_dev ? grid_cap : (a.count < grid_cap ? a.count : grid_cap);
         if (grid < 1) return 0;
-        hipLaunchKernelGGL(k_sym_wide, dim3(grid), dim3(WIDE_THREADS), (size_t)a.wide_lds, s, a);
+        hipLaunchKernelGGL(k_sym_wide, dim3(grid), dim3(WIDE_THREADS), wide_smem_bytes(a.wide_lds, 0), s, a);
         return grid;
     }
     if (a.count <= 0) return 0;
@@ -558,8 +597,9 @@ int launch_num_class(hipStream_t s, const NumArgs& a, int elem_bytes, int grid_c
     if (a.count <= 0) return 0;
     if (a.tier == TIER_GLOBAL) {
         int grid = a.count < grid_cap ? a.count : grid_cap;
-        if (elem_bytes == 8) hipLaunchKernelGGL(k_num_wide<double>, dim3(grid), dim3(WIDE_THREADS), (size_t)a.wide_lds, s, a);
-        else hipLaunchKernelGGL(k_num_wide<float>, dim3(grid), dim3(WIDE_THREADS), (size_t)a.wide_lds, s, a);
+        const size_t smem = wide_smem_bytes(a.wide_lds, 1);
+        if (elem_bytes == 8) hipLaunchKernelGGL(k_num_wide<double>, dim3(grid), dim3(WIDE_THREADS), smem, s, a);
+        else hipLaunchKernelGGL(k_num_wide<float>, dim3(grid), dim3(WIDE_THREADS), smem, s, a);
         return grid;
     }
     if (elem_bytes == 8) {

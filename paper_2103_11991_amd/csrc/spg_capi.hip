@@ -172,9 +172,21 @@ ClassCfg make_cfg(spg_handle h) {
 }
 
 int wide_lds(spg_handle h) {
-    // LDS of a global-path workgroup: 64 KB, less if the device cannot give it
+    // table LDS of a global-path workgroup: 64 KB, less if the device cannot
+    // give it together with the 16 KB of staged A entries
     int v = 65536;
-    while (v > 4096 && v + 1024 > h->max_lds) v >>= 1;
+    while (v > 4096 && v + WIDE_THREADS * 16 + 1024 > h->max_lds) v >>= 1;
+    return v;
+}
+
+int clamp_lds_limit(spg_handle h, int v) {
+    // largest tier whose workgroup (tables + staging) fits the device's LDS
+    while (v > 1024) {
+        int t = 0;
+        while (tier_bytes(t) < v) ++t;
+        if (tier_smem_bytes(t) + 1024 <= h->max_lds) break;
+        v >>= 1;
+    }
     return v;
 }
 
@@ -442,7 +454,7 @@ spg_status spg_create(spg_handle* out, void* stream) {
             delete h;
             return SPG_ERR_HIP;
         }
-        while (h->lds_limit > 1024 && h->lds_limit + 1024 > h->max_lds) h->lds_limit >>= 1;
+        h->lds_limit = clamp_lds_limit(h, h->lds_limit);
         *out = h;
         return SPG_OK;
     } catch (...) {
@@ -589,9 +601,7 @@ spg_status spg_set_option(spg_handle h, int32_t opt, int64_t val) {
         case SPG_OPT_LDS_LIMIT: {
             if (val < 1024 || val > 65536 || (val & (val - 1)))
                 return fail(h, SPG_ERR_ARG, "LDS limit must be a power of two in [1024, 65536]");
-            int v = (int)val;
-            while (v > 1024 && v + 1024 > h->max_lds) v >>= 1;
-            h->lds_limit = v;
+            h->lds_limit = clamp_lds_limit(h, (int)val);
             break;
         }
         case SPG_OPT_KEEP_FEATURES: h->keep_features = val != 0; break;

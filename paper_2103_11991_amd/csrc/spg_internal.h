@@ -48,9 +48,15 @@ __host__ __device__ inline int tier_bytes(int t) { return 256 << t; }
 __host__ __device__ inline int tier_threads(int t) {
     return t <= 2 ? (8 << t) : t <= 4 ? 64 : t == 5 ? 128 : t == 6 ? 256 : t == 7 ? 512 : 1024;
 }
+// rows per workgroup: groups of up to 64 lanes share a 256-lane workgroup
 __host__ __device__ inline int tier_rows(int t) {
     int g = tier_threads(t);
-    return g >= 256 ? 1 : 256 / g;
+    return g <= 64 ? 256 / g : 1;
+}
+// dynamic LDS of one workgroup of tier t: the rows' tables plus 16 bytes of
+// staged A entries per lane (numeric; 8 in symbolic)
+__host__ __device__ inline int64_t tier_smem_bytes(int t) {
+    return (int64_t)tier_rows(t) * (tier_bytes(t) + 16 * tier_threads(t));
 }
 
 __host__ __device__ inline int64_t pow2ceil64(int64_t x) {
@@ -118,7 +124,7 @@ __host__ __device__ inline int sym_class(int64_t ub, int32_t cmin, int32_t cmax,
         int fm = c.force_class / NTIER, ft = c.force_class % NTIER;
         if (ft == TIER_GLOBAL) return MODE_DIRECT * NTIER + TIER_GLOBAL;
         int64_t need = fm == MODE_DIRECT ? bd : bh;
-        if (need <= tier_bytes(ft) && tier_bytes(ft) <= 65536) return c.force_class;
+        if (need <= tier_bytes(ft) && tier_bytes(ft) <= c.lds_limit) return c.force_class;
     }
     int mode = bd <= bh ? MODE_DIRECT : MODE_HASHED;
     int t = pick_tier(bd <= bh ? bd : bh, ub, c);
@@ -137,7 +143,7 @@ __host__ __device__ inline int num_class(int64_t ub, int32_t cmin, int32_t cmax,
         int fm = c.force_class / NTIER, ft = c.force_class % NTIER;
         if (ft == TIER_GLOBAL) return MODE_DIRECT * NTIER + TIER_GLOBAL;
         int64_t need = fm == MODE_DIRECT ? bd : bh;
-        if (need <= tier_bytes(ft) && tier_bytes(ft) <= 65536) return c.force_class;
+        if (need <= tier_bytes(ft) && tier_bytes(ft) <= c.lds_limit) return c.force_class;
     }
     int mode = (blocks <= c.hash_max_blocks && bh < bd) ? MODE_HASHED : MODE_DIRECT;
     int t = pick_tier(mode == MODE_HASHED ? bh : bd, ub, c);

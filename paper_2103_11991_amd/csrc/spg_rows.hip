@@ -95,9 +95,9 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
                                                    int32_t* __restrict__ row_blocks, Control* ctl) {
     __shared__ int32_t hist[NCLS];
     __shared__ int32_t empties;
-    __shared__ unsigned long long prod_sum;
+    __shared__ unsigned long long prod_sum, wmax_all, wmax_glob;
     if (threadIdx.x < NCLS) hist[threadIdx.x] = 0;
-    if (threadIdx.x == 0) empties = 0, prod_sum = 0;
+    if (threadIdx.x == 0) empties = 0, prod_sum = 0, wmax_all = 0, wmax_glob = 0;
     __syncthreads();
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t row = gid / ROW_LANES;
@@ -145,22 +145,24 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
             sym_cls[row] = CLS_EMPTY;
         } else {
             int64_t words = row_words(cmin, cmax);
-            atomicMax((unsigned long long*)&ctl->max_words_all, (unsigned long long)words);
+            atomicMax(&wmax_all, (unsigned long long)words);
             atomicAdd(&prod_sum, (unsigned long long)ub);
             if (!learned) {
                 cls = sym_class(ub, cmin, cmax, ub, cfg);
                 sym_cls[row] = (uint8_t)cls;
                 atomicAdd(&hist[cls], 1);
-                if (cls % NTIER == TIER_GLOBAL)
-                    atomicMax((unsigned long long*)&ctl->max_words_sym_global, (unsigned long long)words);
+                if (cls % NTIER == TIER_GLOBAL) atomicMax(&wmax_glob, (unsigned long long)words);
             }
         }
     }
     __syncthreads();
+    // one global update per workgroup
     if (threadIdx.x < NCLS && hist[threadIdx.x]) atomicAdd(&ctl->sym_hist[threadIdx.x], hist[threadIdx.x]);
     if (threadIdx.x == 0) {
         if (empties) atomicAdd(&ctl->empty_rows, empties);
         if (prod_sum) atomicAdd((unsigned long long*)&ctl->products, prod_sum);
+        if (wmax_all) atomicMax((unsigned long long*)&ctl->max_words_all, wmax_all);
+        if (wmax_glob) atomicMax((unsigned long long*)&ctl->max_words_sym_global, wmax_glob);
     }
 }
 
@@ -172,7 +174,9 @@ __global__ __launch_bounds__(256) void k_mlp_classify(int32_t m, const float* __
                                                       ClassCfg cfg, float margin, uint8_t* __restrict__ sym_cls,
                                                       Control* ctl) {
     __shared__ int32_t hist[NCLS];
+    __shared__ unsigned long long wmax_glob;
     if (threadIdx.x < NCLS) hist[threadIdx.x] = 0;
+    if (threadIdx.x == 0) wmax_glob = 0;
     __syncthreads();
     const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (row < m) {
@@ -204,13 +208,12 @@ __global__ __launch_bounds__(256) void k_mlp_classify(int32_t m, const float* __
             int cls = sym_class(ri.z, ri.x, ri.y, est, cfg);
             sym_cls[row] = (uint8_t)cls;
             atomicAdd(&hist[cls], 1);
-            if (cls % NTIER == TIER_GLOBAL)
-                atomicMax((unsigned long long*)&ctl->max_words_sym_global,
-                          (unsigned long long)row_words(ri.x, ri.y));
+            if (cls % NTIER == TIER_GLOBAL) atomicMax(&wmax_glob, (unsigned long long)row_words(ri.x, ri.y));
         }
     }
     __syncthreads();
     if (threadIdx.x < NCLS && hist[threadIdx.x]) atomicAdd(&ctl->sym_hist[threadIdx.x], hist[threadIdx.x]);
+    if (threadIdx.x == 0 && wmax_glob) atomicMax((unsigned long long*)&ctl->max_words_sym_global, wmax_glob);
 }
 
 // Groups rows by class: each workgroup counts its rows per class, reserves a
@@ -259,7 +262,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(int32_t m, const int32_t*
     __shared__ int32_t hist[NCLS];
     __shared__ unsigned long long s_annz[NCLS], s_cnnz[NCLS], s_prod[NCLS];
     __shared__ int32_t mispred;
-    if (threadIdx.x == 0) tile_sh = atomicAdd(&ctl->tile_counter, 1), mispred = 0;
+    __shared__ unsigned long long wmax_glob;
+    if (threadIdx.x == 0) tile_sh = atomicAdd(&ctl->tile_counter, 1), mispred = 0, wmax_glob = 0;
     if (threadIdx.x < NCLS) hist[threadIdx.x] = 0, s_annz[threadIdx.x] = 0, s_cnnz[threadIdx.x] = 0,
                                     s_prod[threadIdx.x] = 0;
     __syncthreads();
@@ -282,9 +286,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(int32_t m, const int32_t*
                 atomicAdd(&s_annz[nc], (unsigned long long)(arp[r + 1] - arp[r]));
                 atomicAdd(&s_cnnz[nc], (unsigned long long)c);
                 atomicAdd(&s_prod[nc], (unsigned long long)ri.z);
-                if (nc % NTIER == TIER_GLOBAL)
-                    atomicMax((unsigned long long*)&ctl->max_words_num_global,
-                              (unsigned long long)row_words(ri.x, ri.y));
+                if (nc % NTIER == TIER_GLOBAL) atomicMax(&wmax_glob, (unsigned long long)row_words(ri.x, ri.y));
                 int ideal = sym_class(ri.z, ri.x, ri.y, blocks, cfg);
                 if (ideal != sym_cls[r]) atomicAdd(&mispred, 1);
             }
@@ -353,6 +355,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(int32_t m, const int32_t*
         atomicAdd((unsigned long long*)&ctl->num_products[threadIdx.x], s_prod[threadIdx.x]);
     }
     if (threadIdx.x == 0 && mispred) atomicAdd(&ctl->mispredicted, mispred);
+    if (threadIdx.x == 0 && wmax_glob) atomicMax((unsigned long long*)&ctl->max_words_num_global, wmax_glob);
 }
 
 __global__ void k_export_rows(int32_t m, const float* __restrict__ feats, const int32_t* __restrict__ row_blocks,

@@ -56,8 +56,11 @@ def test_global_path_with_global_slabs():
     A = gen.random_csr(40, 60, 1, 10, seed=5)
     B = gen.random_csr(60, 1 << 21, 20, 400, seed=6)
     rp, c, v, op = run_gpu(A, B)
+    compare(A, B, rp, c, v)
+    # the same rows forced onto the global path: their tables exceed LDS
+    rp, c, v, op = run_gpu(A, B, force_class=9)
     st = op.stats()
-    assert st["sym_rows"][9] > 0 and st["num_rows"][9] > 0
+    assert st["sym_rows"][9] == st["num_rows"][9] == A.m - st["empty_rows"] > 0
     compare(A, B, rp, c, v)
 
 
