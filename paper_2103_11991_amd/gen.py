@@ -323,47 +323,67 @@ def random_csr(m: int, n: int, min_len: int = 0, max_len: int = 8, seed: int = 0
     return csr_from_rows_cols(m, n, rows, cols, vals.astype(dtype))
 
 
-def _floyd_masks(w: np.ndarray, k: np.ndarray, draw):
-    """Uniform k-subsets of {0..w-1} per row by Floyd's sampling algorithm
-    (Bentley and Floyd, CACM 1987), vectorised over rows; w <= 192.
+_GEN_LIB = None
 
-    ``draw(s)`` returns one uniform [0,1) per row for step s.  Returns a
-    bool matrix rows x 192 of selected slots.
-    """
-    R = w.size
-    sel = np.zeros((R, 192), dtype=bool)
-    ar = np.arange(R)
-    kmax = int(k.max()) if R else 0
-    for s in range(kmax):
-        act = k > s
-        j = w - k + s                      # current top of the range
-        u = draw(s)
-        t = np.minimum((u * (j + 1)).astype(np.int64), j)
-        taken = sel[ar, np.where(act, t, 0)]
-        pick = np.where(taken, j, t)
-        sel[ar[act], pick[act]] = True
-    return sel
+
+def build_native(force: bool = True) -> str:
+    """Compiles gen_banded.c (the banded-matrix generator) into libspggen.so."""
+    import os
+    import subprocess
+    here = os.path.dirname(os.path.abspath(__file__))
+    out = os.path.join(here, "libspggen.so")
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", os.path.join(here, "gen_banded.c"),
+                               "-o", tmp, "-lm"])
+        os.replace(tmp, out)
+    return out
+
+
+def _native():
+    global _GEN_LIB
+    if _GEN_LIB is None:
+        import ctypes
+        L = ctypes.CDLL(build_native(force=False))
+        p, i32, u64_ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64
+        L.gen_banded_nnz.argtypes = [i32, p, p, u64_, p, ctypes.c_int, ctypes.c_int, p]
+        L.gen_banded_nnz.restype = None
+        L.gen_banded_fill.argtypes = [i32, p, p, u64_, p, ctypes.c_int, ctypes.c_int, p, p, p]
+        L.gen_banded_fill.restype = ctypes.c_int
+        _GEN_LIB = L
+    return _GEN_LIB
+
+
+def _banded_pool(n, bw, seed: int, streams, lo: int = 3, hi: int = 30):
+    """Rows of several square banded random matrices at once (see gen_banded.c
+    for the exact draws): matrix t has n[t] rows, bandwidth bw[t], counter
+    stream streams[t]; row r has k_r ~ U{lo..hi} (capped at its window)
+    distinct columns uniform in [r-bw, r+bw] cut to [0, n), values N(0,1).
+    Returns (row_ptr pool with one n[t]+1 block per matrix, columns, values,
+    nnz per matrix)."""
+    n = np.ascontiguousarray(n, dtype=np.int64)
+    bw = np.ascontiguousarray(bw, dtype=np.int64)
+    st = np.ascontiguousarray(streams, dtype=np.uint64)
+    P = n.size
+    L = _native()
+    nnz = np.zeros(P, dtype=np.int64)
+    L.gen_banded_nnz(P, n.ctypes.data, bw.ctypes.data, seed, st.ctypes.data, lo, hi, nnz.ctypes.data)
+    tot = int(nnz.sum())
+    rp = np.empty(int(n.sum()) + P, dtype=np.int32)
+    cols = np.empty(tot, dtype=np.int32)
+    vals = np.empty(tot, dtype=np.float64)
+    rc = L.gen_banded_fill(P, n.ctypes.data, bw.ctypes.data, seed, st.ctypes.data, lo, hi, rp.ctypes.data,
+                           cols.ctypes.data, vals.ctypes.data)
+    if rc != 0:
+        raise ValueError("band window wider than 192 columns")
+    return rp, cols, vals, nnz
 
 
 def banded_random(n: int, bw: int, seed: int, stream_base: int, lo: int = 3, hi: int = 30) -> Csr:
     """Square banded random matrix: row r has k_r ~ U{lo..hi} (capped at the window
     width) distinct columns uniform in [r-bw, r+bw] cut to [0, n), values N(0,1)."""
-    r = np.arange(n, dtype=np.int64)
-    lo_c = np.maximum(r - bw, 0)
-    hi_c = np.minimum(r + bw, n - 1)
-    w = hi_c - lo_c + 1
-    base = np.uint64(stream_base) << np.uint64(32)
-    k = lo + (u64(seed, S_ROWLEN, base + r.astype(np.uint64)) % np.uint64(hi - lo + 1)).astype(np.int64)
-    k = np.minimum(k, w)
-
-    def draw(s):
-        return uniform(seed, S_COLS, ((base + r.astype(np.uint64)) << np.uint64(6)) + np.uint64(s))
-
-    sel = _floyd_masks(w, k, draw)
-    rr, slot = np.nonzero(sel)
-    cols = lo_c[rr] + slot
-    vals = normal(seed, S_VALUES, base + np.arange(rr.size, dtype=np.uint64))
-    return csr_from_rows_cols(n, n, rr, cols, vals)
+    rp, cols, vals, _ = _banded_pool([n], [bw], seed, [stream_base], lo, hi)
+    return Csr(n, n, rp, cols, vals)
 
 
 def batch_sizes(count: int, seed: int = 12345, lo: int = 200, hi: int = 50000):
@@ -376,15 +396,39 @@ def batch_sizes(count: int, seed: int = 12345, lo: int = 200, hi: int = 50000):
     return n, bwa, bwb
 
 
+def banded_batch_pools(count: int, seed: int = 12345, lo: int = 200, hi: int = 50000):
+    """The ``count`` banded products as pooled arrays (the batch API's layout):
+    dict with n (rows = columns of every A_i, B_i), per-product nnz and
+    (row_ptr, col, val) pools for A and for B.  A_i uses stream 2i, B_i 2i+1."""
+    n, bwa, bwb = batch_sizes(count, seed, lo, hi)
+    i = np.arange(count, dtype=np.uint64)
+    a = _banded_pool(n, bwa, seed, 2 * i)
+    b = _banded_pool(n, bwb, seed, 2 * i + np.uint64(1))
+    return {"n": n, "a_rp": a[0], "a_ci": a[1], "a_v": a[2], "a_nnz": a[3],
+            "b_rp": b[0], "b_ci": b[1], "b_v": b[2], "b_nnz": b[3]}
+
+
+def pools_to_pairs(pools):
+    """Splits pooled batch arrays into a list of (A_i, B_i) CSR pairs."""
+    n = pools["n"]
+    out = []
+    ra = eb = ea = 0
+    for t in range(n.size):
+        m = int(n[t])
+        A = Csr(m, m, pools["a_rp"][ra: ra + m + 1], pools["a_ci"][ea: ea + pools["a_nnz"][t]],
+                pools["a_v"][ea: ea + pools["a_nnz"][t]])
+        B = Csr(m, m, pools["b_rp"][ra: ra + m + 1], pools["b_ci"][eb: eb + pools["b_nnz"][t]],
+                pools["b_v"][eb: eb + pools["b_nnz"][t]])
+        out.append((A, B))
+        ra += m + 1
+        ea += int(pools["a_nnz"][t])
+        eb += int(pools["b_nnz"][t])
+    return out
+
+
 def banded_batch(count: int, seed: int = 12345, lo: int = 200, hi: int = 50000):
     """``count`` independent products (A_i, B_i), each banded random, FP64."""
-    n, bwa, bwb = batch_sizes(count, seed, lo, hi)
-    out = []
-    for i in range(count):
-        A = banded_random(int(n[i]), int(bwa[i]), seed, 2 * i)
-        B = banded_random(int(n[i]), int(bwb[i]), seed, 2 * i + 1)
-        out.append((A, B))
-    return out
+    return pools_to_pairs(banded_batch_pools(count, seed, lo, hi))
 
 
 def products_per_row(A: Csr, B: Csr) -> np.ndarray:
