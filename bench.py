@@ -88,6 +88,120 @@ def cpu_baseline(A, target_s: float = 12.0):
             "c_nnz_per_s": round(int(rp[-1]) / dt, 1)}
 
 
+def time_full_products(op, steps):
+    """Median GPU time of symbolic+numeric (events recorded by the library) and
+    the wall time per full product."""
+    import torch
+    sym, num = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        op.symbolic()
+        op.numeric()
+        st = op.stats()
+        sym.append(st["sym_ms"])
+        num.append(st["num_ms"])
+    torch.cuda.synchronize()
+    wall = 1e3 * (time.perf_counter() - t0) / steps
+    return float(np.median(sym)), float(np.median(num)), wall, st
+
+
+def learned_vs_plain(dA, steps, plain):
+    """The same product with the learned row-size predictor sizing the symbolic
+    tables (committed model), against upper-bound binning."""
+    from paper_2103_11991_amd import learned
+    from paper_2103_11991_amd.spgemm import SpGEMM
+    if not os.path.exists(learned.DEFAULT_MODEL):
+        return None
+    w, margin, meta = learned.load()
+    op = SpGEMM(dA, dA, timing=1, binning=1, mlp_margin_milli=int(round(margin * 1000)))
+    op.set_mlp(w)
+    for _ in range(2):
+        op.symbolic()
+        op.numeric()
+    sym, num, wall, st = time_full_products(op, steps)
+    rows = st["m"] - st["empty_rows"]
+    return {"t_sym_plain_ms": round(plain["sym"], 4), "t_sym_learned_ms": round(sym, 4),
+            "t_full_plain_ms": round(plain["wall"], 4), "t_full_learned_ms": round(wall, 4),
+            "speedup_sym": round(plain["sym"] / sym, 3), "speedup_full": round(plain["wall"] / wall, 3),
+            "retry_rate": round(st["retried_rows"] / max(rows, 1), 5),
+            "mispredict_rate": round(st["mispredicted_rows"] / max(rows, 1), 5),
+            "plain_overestimate_rate": round(plain["mispredicted"] / max(rows, 1), 5),
+            "mlp_ms": round(st["mlp_ms"], 4), "model_rows": meta.get("rows"),
+            "model_quantile": meta.get("quantile"), "margin_log2": round(margin, 3)}
+
+
+def batched_vs_loop(count, steps):
+    """The banded batch: one graph launch (autotuned) against a loop of plain
+    two-phase products, each with its own handle."""
+    import torch
+    from paper_2103_11991_amd import gen
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM, SpGEMMBatch
+    t0 = time.perf_counter()
+    pools = gen.banded_batch_pools(count)
+    gen_s = time.perf_counter() - t0
+    dev = {k: torch.from_numpy(v).cuda() for k, v in pools.items() if k not in ("n", "a_nnz", "b_nnz")}
+    n = pools["n"]
+    batch = SpGEMMBatch.from_pools(n, n, n, pools["a_nnz"], pools["b_nnz"], dev["a_rp"], dev["a_ci"], dev["a_v"],
+                                   dev["b_rp"], dev["b_ci"], dev["b_v"])
+    batch.plan()
+    chosen, tuned_ms = batch.tune()
+    for _ in range(2):
+        batch.run()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    times = []
+    for _ in range(steps):
+        ev[0].record(batch.stream)
+        batch.run()
+        ev[1].record(batch.stream)
+        ev[1].synchronize()
+        times.append(ev[0].elapsed_time(ev[1]))
+    t_batch = float(np.median(times))
+    numeric_times = []
+    for _ in range(steps):
+        ev[0].record(batch.stream)
+        batch.run(numeric_only=True)
+        ev[1].record(batch.stream)
+        ev[1].synchronize()
+        numeric_times.append(ev[0].elapsed_time(ev[1]))
+    st = batch.stats()
+    products = st["products"]
+    # loop of plain launches: every product symbolic + numeric + synchronise
+    pairs = gen.pools_to_pairs(pools)
+    ops = []
+    for A, B in pairs:
+        dA, dB = DeviceCsr.from_host(A), DeviceCsr.from_host(B)
+        ops.append((SpGEMM(dA, dB), dA, dB))
+    outs = []
+    for op, _, _ in ops:  # warm-up pass that also allocates every C once
+        op.symbolic()
+        outs.append(op.numeric())
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for (op, _, _), (col, val) in zip(ops, outs):
+        t1 = time.perf_counter()
+        op.symbolic()
+        op.numeric(out_col=col, out_val=val)
+        torch.cuda.synchronize()
+        lat.append(1e3 * (time.perf_counter() - t1))
+    t_loop = 1e3 * (time.perf_counter() - t0)
+    return {"products": count, "rows": int(n.sum()), "multiply_adds": int(products), "nnz_c": int(batch.nnz),
+            "batched_ms": round(t_batch, 3), "batched_numeric_only_ms": round(float(np.median(numeric_times)), 3),
+            "loop_ms": round(t_loop, 3),
+            "batched_gflops": round(2.0 * products / (t_batch * 1e-3) / 1e9, 2),
+            "loop_gflops": round(2.0 * products / (t_loop * 1e-3) / 1e9, 2),
+            "speedup": round(t_loop / t_batch, 2),
+            "loop_latency_p50_ms": round(float(np.percentile(lat, 50)), 4),
+            "loop_latency_p99_ms": round(float(np.percentile(lat, 99)), 4),
+            "batched_latency_ms": round(t_batch, 3),
+            "batched_latency_note": "all products complete with the single graph launch: each product's "
+                                    "latency from launch is the batch time",
+            "autotuned": {"work_per_lane": chosen[0], "vector_width": chosen[1], "hash_max_blocks": chosen[2],
+                          "best_full_run_ms": round(tuned_ms, 3)},
+            "generation_s": round(gen_s, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +210,10 @@ def main():
     ap.add_argument("--grid", type=int, default=100, help="stencil grid edge (100 = the 1M-row workload)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--verbose", action="store_true", help="per-class rows and times on stderr")
+    ap.add_argument("--batch", type=int, default=1024, help="products in the batched comparison (0 = skip)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-binning comparison")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy 5 times (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -107,6 +225,15 @@ def main():
     from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # a plain copy of known size: 2^27 doubles read and written (1 GiB each way)
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": src.numel() * 8, "launches": 5}), flush=True)
+        return
     N = args.grid
     A = gen.stencil27(N, seed=2)
     products = int(gen.products_per_row(A, A).sum())
@@ -188,6 +315,11 @@ def main():
                   "analysis_ms": st["analysis_ms"], "scan_ms": st["scan_ms"], "sym_ms": st["sym_ms"],
                   "num_ms": st["num_ms"]}
         print(json.dumps(detail), file=sys.stderr, flush=True)
+    plain = {"sym": out["t_sym_ms"], "wall": ms_step, "mispredicted": st["mispredicted_rows"]}
+    if not args.no_learned:
+        out["learned_vs_plain"] = learned_vs_plain(dA, args.steps, plain)
+    if args.batch > 0:
+        out["batched_vs_loop"] = batched_vs_loop(args.batch, max(3, args.steps // 2))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(A)
     print(json.dumps(out), flush=True)

@@ -4,14 +4,13 @@
 // inside one wavefront (several rows per 256-lane workgroup, no workgroup
 // barriers); groups of 128 and more lanes own a whole workgroup.
 //
-// Work distribution is the flattened double loop of Eq. (1) (the paper's
-// method for rows with many FLOPs, section 2.2.1): a chunk of up to G
-// nonzeros of A's row is staged in LDS with the exclusive prefix sum of
-// their B-row lengths, and lane l then takes products l, l+G, l+2G, ... of
-// the chunk.  Consecutive lanes read consecutive entries of a B row
-// (coalesced), every lane's loads are independent of each other (they are
-// issued in batches of four), and the work per lane is even whatever the
-// B-row lengths are.
+// Work distribution follows the paper's vector-parallel inner loop (section
+// 2.2.1): a chunk of up to G nonzeros of A's row is staged in LDS (their B
+// rows' start and length), sub-groups of `vec` lanes take staged entries in
+// turn and the lanes of a sub-group read consecutive entries of that B row,
+// so B is read in coalesced runs and the dependent index chain A -> B row
+// pointer -> B column is broken by the staging.  Four entries are handled
+// per step with their loads issued together.
 //
 // Tables (spg_internal.h): 32-column block masks, direct or hashed.
 //   symbolic: OR each product's column bit in; the value returned by the
@@ -139,47 +138,46 @@ __device__ inline int group_excl_scan(int v, int& total, int* red) {
 }
 
 // Visits every product (A(i,p), B(j,q)) of the row whose nonzeros are
-// [a0, a1): stage(e, p) runs once per staged A entry (chunk slot e),
-// load(q) fetches what a product needs from B, apply(v, e) consumes it.
-// st: G int2 of LDS per group (B-row start minus prefix, prefix).
+// [a0, a1).  A chunk of up to G nonzeros of A is staged in LDS (B-row start
+// and length of each, plus stage(e, p) for anything else the caller keeps per
+// entry); then sub-groups of S lanes take staged entries in turn, and the S
+// lanes of a sub-group read consecutive entries of that B row (coalesced).
+// UNROLL entries are handled per step with their loads issued together;
+// B rows longer than S finish in a tail loop.  load(q) fetches what a product
+// needs from B, apply(v, e) consumes it.
 template <int G, typename Stage, typename Load, typename Apply>
 __device__ inline void walk_products(int a0, int a1, const int32_t* __restrict__ aci,
-                                     const int32_t* __restrict__ brp, int lane, int2* st, int* red, Stage stage,
+                                     const int32_t* __restrict__ brp, int lane, int S, int2* st, Stage stage,
                                      Load load, Apply apply) {
+    const int nsub = G / S, sg = lane / S, vl = lane % S;
     for (int cb = a0; cb < a1; cb += G) {
         const int cnt = min(G, a1 - cb);
-        int len = 0, b0 = 0;
         if (lane < cnt) {
             const int j = aci[cb + lane];
-            b0 = brp[j];
-            len = brp[j + 1] - b0;
+            const int b0 = brp[j];
+            st[lane] = make_int2(b0, brp[j + 1] - b0);
             stage(lane, cb + lane);
         }
-        int total;
-        const int ex = group_excl_scan<G>(len, total, red);
-        if (lane < cnt) st[lane] = make_int2(b0 - ex, ex);
         group_sync<G>();
-        int t = 0;
-        for (int f = lane; f < total;) {
-            int q[UNROLL], e[UNROLL];
-            int nq = 0;
+        for (int e0 = sg; e0 < cnt; e0 += nsub * UNROLL) {
+            int2 sb[UNROLL];
+            bool ok[UNROLL];
 #pragma unroll
             for (int u = 0; u < UNROLL; ++u) {
-                if (f < total) {
-                    while (t + 1 < cnt && st[t + 1].y <= f) ++t;
-                    q[u] = st[t].x + f;
-                    e[u] = t;
-                    f += G;
-                    nq = u + 1;
-                }
+                const int e = e0 + u * nsub;
+                sb[u] = e < cnt ? st[e] : make_int2(0, 0);
+                ok[u] = vl < sb[u].y;
             }
             decltype(load(0)) v[UNROLL];
 #pragma unroll
             for (int u = 0; u < UNROLL; ++u)
-                if (u < nq) v[u] = load(q[u]);
+                if (ok[u]) v[u] = load(sb[u].x + vl);
 #pragma unroll
             for (int u = 0; u < UNROLL; ++u)
-                if (u < nq) apply(v[u], e[u]);
+                if (ok[u]) apply(v[u], e0 + u * nsub);
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u)
+                for (int q = sb[u].x + vl + S; q < sb[u].x + sb[u].y; q += S) apply(load(q), e0 + u * nsub);
         }
         group_sync<G>();
     }
@@ -197,6 +195,7 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_sym(SymArgs a) {
     const int bytes = tier_bytes(a.tier);
     const int per_row = bytes + G * 8;
     const int sub = threadIdx.x / G, lane = threadIdx.x % G;
+    const int vec = a.vec < G ? a.vec : G;
     const int slot = blockIdx.x * RPW + sub;
     if (slot >= a.count) return;  // uniform in the group (in the workgroup when G >= 128)
     const int i = a.perm[slot];
@@ -225,7 +224,7 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_sym(SymArgs a) {
     int cnt = 0, nb = 0;
     const int occ_max = (T * 3) / 4;
     walk_products<G>(
-        a.arp[i], a.arp[i + 1], a.aci, a.brp, lane, st, red, [](int, int) {},
+        a.arp[i], a.arp[i + 1], a.aci, a.brp, lane, vec, st, [](int, int) {},
         [&](int q) { return a.bci[q]; },
         [&](int c, int) {
             const uint32_t bit = 1u << (c & 31);
@@ -270,6 +269,7 @@ template <bool IN_LDS>
 __device__ void wide_sym_row(const SymArgs& a, int i, uint32_t* masks, int2* st, int* red) {
     constexpr int G = WIDE_THREADS;
     const int tid = threadIdx.x;
+    const int vec = a.vec < G ? a.vec : G;
     const RowInfo ri = a.rinfo[i];
     const int base = ri.x >> 5;
     const int words = (ri.y >> 5) - base + 1;
@@ -278,7 +278,7 @@ __device__ void wide_sym_row(const SymArgs& a, int i, uint32_t* masks, int2* st,
     __syncthreads();
     int cnt = 0, nb = 0;
     walk_products<G>(
-        a.arp[i], a.arp[i + 1], a.aci, a.brp, tid, st, red, [](int, int) {}, [&](int q) { return a.bci[q]; },
+        a.arp[i], a.arp[i + 1], a.aci, a.brp, tid, vec, st, [](int, int) {}, [&](int q) { return a.bci[q]; },
         [&](int c, int) {
             const uint32_t bit = 1u << (c & 31);
             const uint32_t old = atomicOr(&masks[(c >> 5) - base], bit);
@@ -314,6 +314,22 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_sym_wide(SymArgs a) {
 
 // ------------------------------------------------------------------- numeric
 
+// Hashed numeric slot {block id, mask, prefix, -}: insert-or-find by block id.
+__device__ inline int slot_insert(int4* slots, int T, int logT, int key) {
+    int h = hash_slot(key, logT);
+    for (int probe = 0; probe < T; ++probe) {
+        int* kp = &slots[h].x;
+        int cur = __hip_atomic_load(kp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (cur == key) return h;
+        if (cur == -1) {
+            int old = atomicCAS(kp, -1, key);
+            if (old == -1 || old == key) return h;
+        }
+        h = (h + 1) & (T - 1);
+    }
+    return -1;
+}
+
 template <int G, int MODE, typename T>
 __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     constexpr int RPW = rows_per_wg<G>();
@@ -323,6 +339,7 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     const int bytes = tier_bytes(a.tier);
     const int per_row = bytes + G * 16;
     const int sub = threadIdx.x / G, lane = threadIdx.x % G;
+    const int vec = a.vec < G ? a.vec : G;
     const int slot = blockIdx.x * RPW + sub;
     if (slot >= a.count) return;
     const int i = a.perm[slot];
@@ -336,35 +353,34 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     const int base = ri.x >> 5;
     const int words = (ri.y >> 5) - base + 1;
     const int nb = a.row_blocks[i];
-    int32_t* keys = nullptr;
-    int32_t* list = nullptr;
+    const int nb4 = (nb + 3) & ~3;
+    // direct: one {mask, prefix} pair per 32-column word of the row's range
+    uint2* dw = reinterpret_cast<uint2*>(tab);
+    // hashed: slots, compact keys (padded), their slots, slots in block order
+    int4* slots = reinterpret_cast<int4*>(tab);
+    int32_t* ck = nullptr;
+    int32_t* cs = nullptr;
     int32_t* ord = nullptr;
-    uint32_t* masks;
-    int32_t* pref;
     T* vals;
     int ncell, items, TT = 0, logT = 0;
     if constexpr (MODE == MODE_DIRECT) {
-        masks = reinterpret_cast<uint32_t*>(tab);
-        pref = reinterpret_cast<int32_t*>(masks + words);
         vals = reinterpret_cast<T*>(tab + align8((int64_t)words * 8));
         ncell = words;
         items = words;
     } else {
         TT = (int)num_hash_slots(nb);
         logT = 31 - __clz(TT);
-        keys = reinterpret_cast<int32_t*>(tab);
-        masks = reinterpret_cast<uint32_t*>(keys + TT);
-        pref = reinterpret_cast<int32_t*>(masks + TT);
-        list = pref + TT;
-        ord = list + nb;
-        vals = reinterpret_cast<T*>(tab + align8((int64_t)TT * 12 + (int64_t)nb * 8));
+        ck = reinterpret_cast<int32_t*>(slots + TT);
+        cs = ck + nb4;
+        ord = cs + nb;
+        vals = reinterpret_cast<T*>(tab + align8((int64_t)TT * 16 + (int64_t)nb4 * 4 + (int64_t)nb * 8));
         ncell = TT;
         items = nb;
     }
     int32_t* colbuf = reinterpret_cast<int32_t*>(vals + n);
     for (int c = lane; c < ncell; c += G) {
-        masks[c] = 0;
-        if constexpr (MODE == MODE_HASHED) keys[c] = -1;
+        if constexpr (MODE == MODE_DIRECT) dw[c] = make_uint2(0u, 0u);
+        else slots[c] = make_int4(-1, 0, 0, 0);
     }
     for (int r = lane; r < n; r += G) vals[r] = T(0);
     if (lane == 0) ncompact[sub] = 0;
@@ -373,28 +389,36 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     const int a0 = a.arp[i], a1 = a.arp[i + 1];
     // pass 1: which columns occur
     walk_products<G>(
-        a0, a1, a.aci, a.brp, lane, st, red, [](int, int) {}, [&](int q) { return a.bci[q]; },
+        a0, a1, a.aci, a.brp, lane, vec, st, [](int, int) {}, [&](int q) { return a.bci[q]; },
         [&](int c, int) {
-            int cell;
             if constexpr (MODE == MODE_DIRECT) {
-                cell = (c >> 5) - base;
+                atomicOr(&dw[(c >> 5) - base].x, 1u << (c & 31));
             } else {
-                bool ins;
-                cell = hash_insert(keys, TT, logT, c >> 5, ins);
+                const int h = slot_insert(slots, TT, logT, c >> 5);
+                atomicOr(reinterpret_cast<unsigned int*>(&slots[h].y), 1u << (c & 31));
             }
-            atomicOr(&masks[cell], 1u << (c & 31));
         });
     if constexpr (MODE == MODE_HASHED) {
-        // occupied slots in ascending block order: compact, then rank by count
-        for (int c = lane; c < ncell; c += G)
-            if (masks[c]) list[atomicAdd(&ncompact[sub], 1)] = c;
+        // occupied blocks in ascending order: compact, then rank by count
+        for (int c = lane; c < ncell; c += G) {
+            const int4 sl = slots[c];
+            if (sl.y) {
+                const int pos = atomicAdd(&ncompact[sub], 1);
+                ck[pos] = sl.x;
+                cs[pos] = c;
+            }
+        }
+        for (int e = nb + lane; e < nb4; e += G) ck[e] = 0x7fffffff;
         group_sync<G>();
+        const int4* ck4 = reinterpret_cast<const int4*>(ck);
         for (int e = lane; e < nb; e += G) {
-            const int s = list[e];
-            const int key = keys[s];
+            const int key = ck[e];
             int r = 0;
-            for (int f = 0; f < nb; ++f) r += keys[list[f]] < key;
-            ord[r] = s;
+            for (int f = 0; f < nb4 / 4; ++f) {
+                const int4 k4 = ck4[f];
+                r += (k4.x < key) + (k4.y < key) + (k4.z < key) + (k4.w < key);
+            }
+            ord[r] = cs[e];
         }
         group_sync<G>();
     }
@@ -404,13 +428,19 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
         const int beg = lane * chunk;
         const int end = min(beg + chunk, items);
         int local = 0;
-        for (int t = beg; t < end; ++t) local += __popc(masks[MODE == MODE_DIRECT ? t : ord[t]]);
+        for (int t = beg; t < end; ++t)
+            local += __popc(MODE == MODE_DIRECT ? dw[t].x : (uint32_t)slots[ord[t]].y);
         int total;
         int ex = group_excl_scan<G>(local, total, red);
         for (int t = beg; t < end; ++t) {
-            const int cl = MODE == MODE_DIRECT ? t : ord[t];
-            pref[cl] = ex;
-            ex += __popc(masks[cl]);
+            if constexpr (MODE == MODE_DIRECT) {
+                dw[t].y = (uint32_t)ex;
+                ex += __popc(dw[t].x);
+            } else {
+                const int cl = ord[t];
+                slots[cl].z = ex;
+                ex += __popc((uint32_t)slots[cl].y);
+            }
         }
     }
     group_sync<G>();
@@ -422,21 +452,37 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
         T y;
     };
     walk_products<G>(
-        a0, a1, a.aci, a.brp, lane, st, red, [&](int e, int p) { ast[e] = av[p]; },
+        a0, a1, a.aci, a.brp, lane, vec, st, [&](int e, int p) { ast[e] = av[p]; },
         [&](int q) { return CV{a.bci[q], bv[q]}; },
         [&](const CV& v, int e) {
-            int cl;
-            if constexpr (MODE == MODE_DIRECT) cl = (v.c >> 5) - base;
-            else cl = hash_find(keys, TT, logT, v.c >> 5);
-            const int rank = pref[cl] + __popc(masks[cl] & ((1u << (v.c & 31)) - 1u));
+            const uint32_t below = (1u << (v.c & 31)) - 1u;
+            int rank;
+            if constexpr (MODE == MODE_DIRECT) {
+                const uint2 mp = dw[(v.c >> 5) - base];
+                rank = (int)mp.y + __popc(mp.x & below);
+            } else {
+                const int key = v.c >> 5;
+                int h = hash_slot(key, logT);
+                int4 sl = slots[h];
+                for (int probe = 1; sl.x != key && probe < TT; ++probe) {
+                    h = (h + 1) & (TT - 1);
+                    sl = slots[h];
+                }
+                rank = sl.z + __popc((uint32_t)sl.y & below);
+            }
             atomicAdd(&vals[rank], ast[e] * v.y);
         });
     // column of every rank, from the masks
     for (int t = lane; t < items; t += G) {
-        const int cl = MODE == MODE_DIRECT ? t : ord[t];
-        uint32_t mk = masks[cl];
-        int r = pref[cl];
-        const int blk = MODE == MODE_DIRECT ? base + t : keys[cl];
+        uint32_t mk;
+        int r, blk;
+        if constexpr (MODE == MODE_DIRECT) {
+            const uint2 mp = dw[t];
+            mk = mp.x, r = (int)mp.y, blk = base + t;
+        } else {
+            const int4 sl = slots[ord[t]];
+            mk = (uint32_t)sl.y, r = sl.z, blk = sl.x;
+        }
         while (mk) {
             colbuf[r++] = (blk << 5) + (__ffs(mk) - 1);
             mk &= mk - 1;
@@ -454,6 +500,7 @@ template <typename T, bool IN_LDS>
 __device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int2* st, T* ast, int* red) {
     constexpr int G = WIDE_THREADS;
     const int tid = threadIdx.x;
+    const int vec = a.vec < G ? a.vec : G;
     const int off = a.crp[i];
     const int n = a.crp[i + 1] - off;
     const RowInfo ri = a.rinfo[i];
@@ -468,7 +515,7 @@ __device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int2* st,
     __syncthreads();
     const int a0 = a.arp[i], a1 = a.arp[i + 1];
     walk_products<G>(
-        a0, a1, a.aci, a.brp, tid, st, red, [](int, int) {}, [&](int q) { return a.bci[q]; },
+        a0, a1, a.aci, a.brp, tid, vec, st, [](int, int) {}, [&](int q) { return a.bci[q]; },
         [&](int c, int) { atomicOr(&masks[(c >> 5) - base], 1u << (c & 31)); });
     if (!IN_LDS) __threadfence();
     __syncthreads();
@@ -494,7 +541,7 @@ __device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int2* st,
         T y;
     };
     walk_products<G>(
-        a0, a1, a.aci, a.brp, tid, st, red, [&](int e, int p) { ast[e] = av[p]; },
+        a0, a1, a.aci, a.brp, tid, vec, st, [&](int e, int p) { ast[e] = av[p]; },
         [&](int q) { return CV{a.bci[q], bv[q]}; },
         [&](const CV& v, int e) {
             const int w = (v.c >> 5) - base;

@@ -94,8 +94,11 @@ __host__ __device__ inline int64_t align8(int64_t b) { return (b + 7) & ~(int64_
 __host__ __device__ inline int64_t num_direct_bytes(int64_t words, int64_t n, int eb) {
     return align8(words * 8) + n * (eb + 4);
 }
+// hashed numeric table: 16-byte slots {block, mask, prefix, -}, the occupied
+// block ids compacted (padded to a multiple of 4) with their slots, and the
+// slots in ascending block order
 __host__ __device__ inline int64_t num_hashed_bytes(int64_t blocks, int64_t n, int eb) {
-    return align8(num_hash_slots(blocks) * 12 + blocks * 8) + n * (eb + 4);
+    return align8(num_hash_slots(blocks) * 16 + ((blocks + 3) / 4) * 16 + blocks * 8) + n * (eb + 4);
 }
 
 // Smallest LDS tier that holds `bytes`, raised until its thread group gives

@@ -99,59 +99,73 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
     if (threadIdx.x < NCLS) hist[threadIdx.x] = 0;
     if (threadIdx.x == 0) empties = 0, prod_sum = 0, wmax_all = 0, wmax_glob = 0;
     __syncthreads();
-    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t row = gid / ROW_LANES;
-    const int lane = (int)(gid % ROW_LANES);
-    int64_t ub = 0;
-    int mx = 0, cmin = INT_MAX, cmax = -1, bad = 0, len = 0;
-    if (row < m) {
-        int32_t s = arp[row], e = arp[row + 1];
-        if (s < 0 || e < s || (int64_t)e > annz || (row == 0 && s != 0) || (row == m - 1 && (int64_t)e != annz)) {
-            bad = ERR_A_ROWPTR;
-        } else {
-            len = e - s;
-            for (int32_t p = s + lane; p < e; p += ROW_LANES) {
-                int j = aci[p];
-                if (j < 0 || j >= n) { bad = ERR_A_COL; continue; }
-                int4 b = binfo[j];
-                ub += b.x;
-                mx = max(mx, b.x);
-                cmin = min(cmin, b.y);
-                cmax = max(cmax, b.z);
+    const int lane = (int)(threadIdx.x % ROW_LANES);
+    const int64_t rows_per_block = blockDim.x / ROW_LANES;
+    // grid-stride: few workgroups, one flush of the counters each
+    for (int64_t rb = blockIdx.x * rows_per_block; rb < m; rb += (int64_t)gridDim.x * rows_per_block) {
+        const int64_t row = rb + threadIdx.x / ROW_LANES;
+        int64_t ub = 0;
+        int mx = 0, cmin = INT_MAX, cmax = -1, bad = 0, len = 0;
+        if (row < m) {
+            int32_t s = arp[row], e = arp[row + 1];
+            if (s < 0 || e < s || (int64_t)e > annz || (row == 0 && s != 0) || (row == m - 1 && (int64_t)e != annz)) {
+                bad = ERR_A_ROWPTR;
+            } else {
+                len = e - s;
+                // four independent index loads, then their four gathers
+                for (int32_t p0 = s + lane; p0 < e; p0 += 4 * ROW_LANES) {
+                    int jj[4];
+    #pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int32_t p = p0 + u * ROW_LANES;
+                        jj[u] = p < e ? aci[p] : -1;
+                        if (p < e && (jj[u] < 0 || jj[u] >= n)) bad = ERR_A_COL, jj[u] = -1;
+                    }
+                    int4 bb[4];
+    #pragma unroll
+                    for (int u = 0; u < 4; ++u) bb[u] = jj[u] >= 0 ? binfo[jj[u]] : make_int4(0, INT_MAX, -1, 0);
+    #pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        ub += bb[u].x;
+                        mx = max(mx, bb[u].x);
+                        cmin = min(cmin, bb[u].y);
+                        cmax = max(cmax, bb[u].z);
+                    }
+                }
             }
         }
-    }
-    ub = xor_reduce_sum(ub);
-    mx = xor_reduce_max(mx);
-    cmin = xor_reduce_min(cmin);
-    cmax = xor_reduce_max(cmax);
-    int anybad = xor_reduce_sum(bad);
-    if (bad) atomicOr(&ctl->err, bad);
-    if (row < m && lane == 0) {
-        if (anybad) ub = 0;
-        int32_t ubc = ub > INT_MAX ? INT_MAX : (int32_t)ub;
-        if (ub == 0) cmin = 0, cmax = 0;
-        rinfo[row] = make_int4(cmin, cmax, ubc, mx);
-        if (feats) {
-            feats[row * 3 + 0] = log2p1(len);
-            feats[row * 3 + 1] = log2p1(ub);
-            feats[row * 3 + 2] = log2p1(mx);
-        }
-        int cls = CLS_EMPTY;
-        if (ub == 0) {
-            row_nnz[row] = 0;
-            row_blocks[row] = 0;
-            atomicAdd(&empties, 1);
-            sym_cls[row] = CLS_EMPTY;
-        } else {
-            int64_t words = row_words(cmin, cmax);
-            atomicMax(&wmax_all, (unsigned long long)words);
-            atomicAdd(&prod_sum, (unsigned long long)ub);
-            if (!learned) {
-                cls = sym_class(ub, cmin, cmax, ub, cfg);
-                sym_cls[row] = (uint8_t)cls;
-                atomicAdd(&hist[cls], 1);
-                if (cls % NTIER == TIER_GLOBAL) atomicMax(&wmax_glob, (unsigned long long)words);
+        ub = xor_reduce_sum(ub);
+        mx = xor_reduce_max(mx);
+        cmin = xor_reduce_min(cmin);
+        cmax = xor_reduce_max(cmax);
+        int anybad = xor_reduce_sum(bad);
+        if (bad) atomicOr(&ctl->err, bad);
+        if (row < m && lane == 0) {
+            if (anybad) ub = 0;
+            int32_t ubc = ub > INT_MAX ? INT_MAX : (int32_t)ub;
+            if (ub == 0) cmin = 0, cmax = 0;
+            rinfo[row] = make_int4(cmin, cmax, ubc, mx);
+            if (feats) {
+                feats[row * 3 + 0] = log2p1(len);
+                feats[row * 3 + 1] = log2p1(ub);
+                feats[row * 3 + 2] = log2p1(mx);
+            }
+            int cls = CLS_EMPTY;
+            if (ub == 0) {
+                row_nnz[row] = 0;
+                row_blocks[row] = 0;
+                atomicAdd(&empties, 1);
+                sym_cls[row] = CLS_EMPTY;
+            } else {
+                int64_t words = row_words(cmin, cmax);
+                atomicMax(&wmax_all, (unsigned long long)words);
+                atomicAdd(&prod_sum, (unsigned long long)ub);
+                if (!learned) {
+                    cls = sym_class(ub, cmin, cmax, ub, cfg);
+                    sym_cls[row] = (uint8_t)cls;
+                    atomicAdd(&hist[cls], 1);
+                    if (cls % NTIER == TIER_GLOBAL) atomicMax(&wmax_glob, (unsigned long long)words);
+                }
             }
         }
     }
@@ -178,8 +192,8 @@ __global__ __launch_bounds__(256) void k_mlp_classify(int32_t m, const float* __
     if (threadIdx.x < NCLS) hist[threadIdx.x] = 0;
     if (threadIdx.x == 0) wmax_glob = 0;
     __syncthreads();
-    const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (row < m) {
+    for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < m;
+         row += (int64_t)gridDim.x * blockDim.x) {
         RowInfo ri = rinfo[row];
         if (ri.z > 0) {
             float x0 = feats[row * 3], x1 = feats[row * 3 + 1], x2 = feats[row * 3 + 2];
@@ -216,28 +230,39 @@ __global__ __launch_bounds__(256) void k_mlp_classify(int32_t m, const float* __
     if (threadIdx.x == 0 && wmax_glob) atomicMax((unsigned long long*)&ctl->max_words_sym_global, wmax_glob);
 }
 
-// Groups rows by class: each workgroup counts its rows per class, reserves a
-// range per class with one atomic, and writes its row ids there.
+// Groups rows by class: a workgroup takes chunks of 4096 consecutive rows,
+// ranks each row inside its class with LDS atomics, reserves one range per
+// class and chunk with a single global atomic, and writes the row ids there.
+constexpr int SCATTER_ITEMS = 16;
 __global__ __launch_bounds__(256) void k_scatter(int32_t m, const uint8_t* __restrict__ cls,
                                                  const int32_t* __restrict__ hist, int32_t* __restrict__ cursor,
                                                  int32_t* __restrict__ perm) {
     __shared__ int32_t cnt[NCLS];
     __shared__ int32_t base[NCLS];
     __shared__ int32_t off[NCLS];
-    if (threadIdx.x < NCLS) cnt[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         int32_t run = 0;
         for (int c = 0; c < NCLS; ++c) off[c] = run, run += hist[c];
     }
-    __syncthreads();
-    const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int c = row < m ? cls[row] : CLS_EMPTY;
-    int local = 0;
-    if (c != CLS_EMPTY) local = atomicAdd(&cnt[c], 1);
-    __syncthreads();
-    if (threadIdx.x < NCLS && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
-    __syncthreads();
-    if (c != CLS_EMPTY) perm[off[c] + base[c] + local] = (int32_t)row;
+    const int64_t chunk = 256 * SCATTER_ITEMS;
+    for (int64_t r0 = blockIdx.x * chunk; r0 < m; r0 += (int64_t)gridDim.x * chunk) {
+        if (threadIdx.x < NCLS) cnt[threadIdx.x] = 0;
+        __syncthreads();
+        int c[SCATTER_ITEMS], local[SCATTER_ITEMS];
+#pragma unroll
+        for (int t = 0; t < SCATTER_ITEMS; ++t) {
+            const int64_t row = r0 + t * 256 + threadIdx.x;
+            c[t] = row < m ? cls[row] : CLS_EMPTY;
+            local[t] = c[t] != CLS_EMPTY ? atomicAdd(&cnt[c[t]], 1) : 0;
+        }
+        __syncthreads();
+        if (threadIdx.x < NCLS && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < SCATTER_ITEMS; ++t)
+            if (c[t] != CLS_EMPTY) perm[off[c[t]] + base[c[t]] + local[t]] = (int32_t)(r0 + t * 256 + threadIdx.x);
+        __syncthreads();
+    }
 }
 
 // Status word of the look-back scan: 2 flag bits over a 62-bit value.
@@ -442,21 +467,24 @@ void launch_a_rowinfo(hipStream_t s, int32_t m, int32_t n, const int32_t* arp, c
                       const int4* binfo, RowInfo* rinfo, float* feats, ClassCfg cfg, int learned,
                       uint8_t* sym_cls, int32_t* row_nnz, int32_t* row_blocks, Control* ctl) {
     if (m <= 0) return;
-    hipLaunchKernelGGL(k_a_rowinfo, dim3(grid_for((int64_t)m * ROW_LANES, 256)), dim3(256), 0, s, m, n, arp, aci,
+    hipLaunchKernelGGL(k_a_rowinfo, dim3(std::min(grid_for((int64_t)m * ROW_LANES, 256), 1024u)), dim3(256), 0, s, m, n,
+                       arp, aci,
                        annz, binfo, rinfo, feats, cfg, learned, sym_cls, row_nnz, row_blocks, ctl);
 }
 
 void launch_mlp_classify(hipStream_t s, int32_t m, const float* feats, const float* w, const RowInfo* rinfo,
                          ClassCfg cfg, float margin, uint8_t* sym_cls, Control* ctl) {
     if (m <= 0) return;
-    hipLaunchKernelGGL(k_mlp_classify, dim3(grid_for(m, 256)), dim3(256), 0, s, m, feats, w, rinfo, cfg, margin,
+    hipLaunchKernelGGL(k_mlp_classify, dim3(std::min(grid_for(m, 256), 1024u)), dim3(256), 0, s, m, feats, w, rinfo,
+                       cfg, margin,
                        sym_cls, ctl);
 }
 
 void launch_scatter(hipStream_t s, int32_t m, const uint8_t* cls, const int32_t* hist, int32_t* cursor,
                     int32_t* perm) {
     if (m <= 0) return;
-    hipLaunchKernelGGL(k_scatter, dim3(grid_for(m, 256)), dim3(256), 0, s, m, cls, hist, cursor, perm);
+    hipLaunchKernelGGL(k_scatter, dim3(std::min(grid_for(m, 256 * SCATTER_ITEMS), 1024u)), dim3(256), 0, s, m, cls, hist,
+                       cursor, perm);
 }
 
 void launch_scan(hipStream_t s, int32_t m, const int32_t* row_nnz, const int32_t* row_blocks, const RowInfo* rinfo,

@@ -157,6 +157,24 @@ class SpGEMMBatch:
     (one device copy at construction).  ``plan()`` sizes the C pools,
     ``run()`` launches the captured graph, ``product(i)`` views C_i."""
 
+    @classmethod
+    def from_pools(cls, m, n, k, a_nnz, b_nnz, a_rp, a_ci, a_v, b_rp, b_ci, b_v,
+                   stream: torch.cuda.Stream | None = None, **options) -> "SpGEMMBatch":
+        """Batch over already pooled device arrays (layout of spg_batch_create)."""
+        self = cls.__new__(cls)
+        self.count = len(m)
+        self.dtype = a_v.dtype
+        self.stream = stream or torch.cuda.Stream()
+        self.stream.wait_stream(torch.cuda.current_stream())
+        self.a_rp, self.a_ci, self.a_v, self.b_rp, self.b_ci, self.b_v = a_rp, a_ci, a_v, b_rp, b_ci, b_v
+        self.m = np.ascontiguousarray(m, dtype=np.int32)
+        self.n = np.ascontiguousarray(n, dtype=np.int32)
+        self.k = np.ascontiguousarray(k, dtype=np.int32)
+        self.a_nnz = np.ascontiguousarray(a_nnz, dtype=np.int64)
+        self.b_nnz = np.ascontiguousarray(b_nnz, dtype=np.int64)
+        self._create(options)
+        return self
+
     def __init__(self, As, Bs, stream: torch.cuda.Stream | None = None, **options):
         assert len(As) == len(Bs)
         self.count = len(As)
@@ -184,10 +202,14 @@ class SpGEMMBatch:
         self.k = np.array([B.n for B in Bs], dtype=np.int32)
         self.a_nnz = np.array([A.nnz for A in As], dtype=np.int64)
         self.b_nnz = np.array([B.nnz for B in Bs], dtype=np.int64)
+        self._create(options)
+
+    def _create(self, options):
         self.b = _lib.spg_batch_create(self.stream.cuda_stream, _dtype_code(self.dtype), self.count,
                                        self.m.ctypes.data, self.n.ctypes.data, self.k.ctypes.data,
                                        self.a_nnz.ctypes.data, self.b_nnz.ctypes.data, self.a_rp.data_ptr(),
-                                       self.a_ci.data_ptr(), self.b_rp.data_ptr(), self.b_ci.data_ptr())
+                                       self.a_ci.data_ptr() if self.a_ci.numel() else 0, self.b_rp.data_ptr(),
+                                       self.b_ci.data_ptr() if self.b_ci.numel() else 0)
         for k_, v in options.items():
             _lib.spg_batch_set_option(self.b, k_, int(v))
         self.nnz = None
