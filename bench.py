@@ -130,6 +130,109 @@ def learned_vs_plain(dA, steps, plain):
             "model_quantile": meta.get("quantile"), "margin_log2": round(margin, 3)}
 
 
+def _learned_opts():
+    from paper_2103_11991_amd import learned
+    if not os.path.exists(learned.DEFAULT_MODEL):
+        return None, None
+    w, margin, _ = learned.load()
+    return w, {"binning": 1, "mlp_margin_milli": int(round(margin * 1000))}
+
+
+def rmat_learned_vs_plain(steps, scale=18, seed=1):
+    """R-MAT scale 18 (FP32) A*A with upper-bound and with learned binning."""
+    import torch
+    from paper_2103_11991_amd import gen
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
+    A = gen.rmat(scale, seed=seed)
+    dA = DeviceCsr.from_host(A)
+    out = {"workload": f"C=A*A, A = R-MAT scale {scale} edge factor 16 (a=0.57, b=c=0.19), seed {seed}, FP32",
+           "rows": A.m, "nnz_a": A.nnz}
+    w, lopts = _learned_opts()
+    for label, opts in (("plain", {}), ("learned", lopts)):
+        if opts is None:
+            out[label] = None
+            continue
+        op = SpGEMM(dA, dA, timing=1, **opts)
+        if w is not None and opts:
+            op.set_mlp(w)
+        for _ in range(2):
+            op.symbolic()
+            op.numeric()
+        sym, num, wall, st = time_full_products(op, steps)
+        rows = st["m"] - st["empty_rows"]
+        out[label] = {"t_sym_ms": round(sym, 3), "t_num_ms": round(num, 3), "t_full_ms": round(wall, 3),
+                      "gflops": round(2.0 * st["products"] / (wall * 1e-3) / 1e9, 2),
+                      "c_nnz_per_s": round(st["nnz_c"] / (wall * 1e-3), 1),
+                      "retry_rate": round(st["retried_rows"] / max(rows, 1), 5),
+                      "mispredict_rate": round(st["mispredicted_rows"] / max(rows, 1), 5)}
+        out["multiply_adds"] = int(st["products"])
+        out["nnz_c"] = int(st["nnz_c"])
+        del op
+        torch.cuda.synchronize()
+    if out.get("plain") and out.get("learned"):
+        out["speedup_full"] = round(out["plain"]["t_full_ms"] / out["learned"]["t_full_ms"], 3)
+        out["speedup_sym"] = round(out["plain"]["t_sym_ms"] / out["learned"]["t_sym_ms"], 3)
+    return out
+
+
+def galerkin_chain(sweeps=10, n0=128, levels=5):
+    """R*(A*P) over 5 aggregation levels from a 7-point Laplacian on 128^3:
+    the whole chain with both phases, then `sweeps` numeric-only passes with
+    changed fine-level values (symbolic reused), for upper-bound and learned
+    binning."""
+    import torch
+    from paper_2103_11991_amd import gen
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
+    A0 = gen.laplace3d_7pt(n0)
+    hier = [(N, DeviceCsr.from_host(P), DeviceCsr.from_host(R)) for N, P, R in gen.galerkin_hierarchy(n0, levels)]
+    sweep_vals = [torch.from_numpy(gen.sweep_values(A0, t)).cuda() for t in range(1, sweeps + 1)]
+    out = {"workload": f"Galerkin R*(A*P), 7-point Laplacian {n0}^3, 2x2x2 aggregation, {levels} levels, FP64, "
+                       f"{sweeps} changed-value numeric sweeps"}
+    w, lopts = _learned_opts()
+    for label, opts in (("plain", {}), ("learned", lopts)):
+        if opts is None:
+            out[label] = None
+            continue
+        times, ops = [], None
+        for rep in range(3):
+            dA = DeviceCsr.from_host(A0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cur, ops, products = dA, [], 0
+            for N, dP, dR in hier:
+                for X, Y in ((None, dP), (dR, None)):
+                    left, right = (cur, Y) if X is None else (X, cur)
+                    op = SpGEMM(left, right, **opts)
+                    if opts:
+                        op.set_mlp(w)
+                    rp, nnz = op.symbolic()
+                    col, val = op.numeric()
+                    nxt = DeviceCsr(left.m, right.n, rp, col, val)
+                    ops.append((op, left, right, nxt))
+                    products += op.stats()["products"]
+                    cur = nxt
+            torch.cuda.synchronize()
+            times.append(1e3 * (time.perf_counter() - t0))
+        # numeric sweeps: new fine-level values flow through the whole chain
+        t0 = time.perf_counter()
+        for sv in sweep_vals:
+            ops[0][1].values.copy_(sv)
+            for op, left, right, nxt in ops:
+                op.numeric(a_vals=left.values, b_vals=right.values, out_col=nxt.col_idx, out_val=nxt.values)
+        torch.cuda.synchronize()
+        t_sweeps = 1e3 * (time.perf_counter() - t0)
+        out[label] = {"t_chain_full_ms": round(float(np.median(times)), 3),
+                      "t_sweep_numeric_ms": round(t_sweeps / sweeps, 3),
+                      "reuse_speedup": round(float(np.median(times)) / (t_sweeps / sweeps), 2),
+                      "products": 2 * len(hier)}
+        out["multiply_adds"] = int(products)
+        del ops
+        torch.cuda.synchronize()
+    if out.get("plain") and out.get("learned"):
+        out["learned_speedup_chain"] = round(out["plain"]["t_chain_full_ms"] / out["learned"]["t_chain_full_ms"], 3)
+    return out
+
+
 def batched_vs_loop(count, steps):
     """The banded batch: one graph launch (autotuned) against a loop of plain
     two-phase products, each with its own handle."""
@@ -212,6 +315,10 @@ def main():
     ap.add_argument("--verbose", action="store_true", help="per-class rows and times on stderr")
     ap.add_argument("--batch", type=int, default=1024, help="products in the batched comparison (0 = skip)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-binning comparison")
+    ap.add_argument("--no-rmat", action="store_true", help="skip the R-MAT plain/learned comparison")
+    ap.add_argument("--no-galerkin", action="store_true", help="skip the Galerkin chain")
+    ap.add_argument("--opt", action="append", default=[], metavar="NAME=VALUE",
+                    help="library option for the timed product (e.g. work_per_lane=32); repeatable")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -238,7 +345,8 @@ def main():
     A = gen.stencil27(N, seed=2)
     products = int(gen.products_per_row(A, A).sum())
     dA = DeviceCsr.from_host(A)
-    op = SpGEMM(dA, dA, timing=1)
+    opts = dict(kv.split("=", 1) for kv in args.opt)
+    op = SpGEMM(dA, dA, timing=1, **{k: int(v) for k, v in opts.items()})
     stream = op.stream
 
     def step():
@@ -299,7 +407,8 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"C=A*A, A = 3D 27-point stencil on {N}^3 (FP64 U[-1,1], diagonal 27), "
                                "plain two-phase (upper-bound binning)",
-                   "rows": A.m, "nnz_a": nnz_a, "nnz_c": int(nnz), "multiply_adds": products},
+                   "rows": A.m, "nnz_a": nnz_a, "nnz_c": int(nnz), "multiply_adds": products,
+                   **({"options": opts} if opts else {})},
         "c_nnz_per_s": round(nnz / (ms_step * 1e-3), 1),
         "hbm_frac_compulsory": round(comp / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "t_sym_ms": round(float(np.median(sym_ms)), 4), "t_num_ms": round(float(np.median(num_ms)), 4),
@@ -320,6 +429,10 @@ def main():
         out["learned_vs_plain"] = learned_vs_plain(dA, args.steps, plain)
     if args.batch > 0:
         out["batched_vs_loop"] = batched_vs_loop(args.batch, max(3, args.steps // 2))
+    if not args.no_rmat:
+        out["rmat_s18"] = rmat_learned_vs_plain(max(3, args.steps // 2))
+    if not args.no_galerkin:
+        out["galerkin"] = galerkin_chain()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(A)
     print(json.dumps(out), flush=True)

@@ -145,40 +145,54 @@ __device__ inline int group_excl_scan(int v, int& total, int* red) {
 // UNROLL entries are handled per step with their loads issued together;
 // B rows longer than S finish in a tail loop.  load(q) fetches what a product
 // needs from B, apply(v, e) consumes it.
+// Stages A entries [cb, cb + cnt): B-row start and length per entry, plus
+// stage(e, p) for anything else the caller keeps per entry.
+template <int G, typename Stage>
+__device__ inline void stage_chunk(int cb, int cnt, const int32_t* __restrict__ aci, const int32_t* __restrict__ brp,
+                                   int lane, int2* st, Stage stage) {
+    if (lane < cnt) {
+        const int j = aci[cb + lane];
+        const int b0 = brp[j];
+        st[lane] = make_int2(b0, brp[j + 1] - b0);
+        stage(lane, cb + lane);
+    }
+}
+
+// Products of a staged chunk of cnt entries, sub-groups of S lanes per entry.
+template <int G, typename Load, typename Apply>
+__device__ inline void walk_chunk(int cnt, int lane, int S, const int2* st, Load load, Apply apply) {
+    const int nsub = G / S, sg = lane / S, vl = lane % S;
+    for (int e0 = sg; e0 < cnt; e0 += nsub * UNROLL) {
+        int2 sb[UNROLL];
+        bool ok[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const int e = e0 + u * nsub;
+            sb[u] = e < cnt ? st[e] : make_int2(0, 0);
+            ok[u] = vl < sb[u].y;
+        }
+        decltype(load(0)) v[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+            if (ok[u]) v[u] = load(sb[u].x + vl);
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+            if (ok[u]) apply(v[u], e0 + u * nsub);
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+            for (int q = sb[u].x + vl + S; q < sb[u].x + sb[u].y; q += S) apply(load(q), e0 + u * nsub);
+    }
+}
+
 template <int G, typename Stage, typename Load, typename Apply>
 __device__ inline void walk_products(int a0, int a1, const int32_t* __restrict__ aci,
                                      const int32_t* __restrict__ brp, int lane, int S, int2* st, Stage stage,
                                      Load load, Apply apply) {
-    const int nsub = G / S, sg = lane / S, vl = lane % S;
     for (int cb = a0; cb < a1; cb += G) {
         const int cnt = min(G, a1 - cb);
-        if (lane < cnt) {
-            const int j = aci[cb + lane];
-            const int b0 = brp[j];
-            st[lane] = make_int2(b0, brp[j + 1] - b0);
-            stage(lane, cb + lane);
-        }
+        stage_chunk<G>(cb, cnt, aci, brp, lane, st, stage);
         group_sync<G>();
-        for (int e0 = sg; e0 < cnt; e0 += nsub * UNROLL) {
-            int2 sb[UNROLL];
-            bool ok[UNROLL];
-#pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
-                const int e = e0 + u * nsub;
-                sb[u] = e < cnt ? st[e] : make_int2(0, 0);
-                ok[u] = vl < sb[u].y;
-            }
-            decltype(load(0)) v[UNROLL];
-#pragma unroll
-            for (int u = 0; u < UNROLL; ++u)
-                if (ok[u]) v[u] = load(sb[u].x + vl);
-#pragma unroll
-            for (int u = 0; u < UNROLL; ++u)
-                if (ok[u]) apply(v[u], e0 + u * nsub);
-#pragma unroll
-            for (int u = 0; u < UNROLL; ++u)
-                for (int q = sb[u].x + vl + S; q < sb[u].x + sb[u].y; q += S) apply(load(q), e0 + u * nsub);
-        }
+        walk_chunk<G>(cnt, lane, S, st, load, apply);
         group_sync<G>();
     }
 }
@@ -387,17 +401,29 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     group_sync<G>();
 
     const int a0 = a.arp[i], a1 = a.arp[i + 1];
+    const T* av = reinterpret_cast<const T*>(a.av);
+    const T* bv = reinterpret_cast<const T*>(a.bv);
+    // a row whose A nonzeros fit one chunk is staged once for both passes
+    const bool one_chunk = a1 - a0 <= G;
+    auto or_pass = [&](int c, int) {
+        if constexpr (MODE == MODE_DIRECT) {
+            atomicOr(&dw[(c >> 5) - base].x, 1u << (c & 31));
+        } else {
+            const int h = slot_insert(slots, TT, logT, c >> 5);
+            atomicOr(reinterpret_cast<unsigned int*>(&slots[h].y), 1u << (c & 31));
+        }
+    };
+    auto load_col = [&](int q) { return a.bci[q]; };
+    auto stage_val = [&](int e, int p) { ast[e] = av[p]; };
     // pass 1: which columns occur
-    walk_products<G>(
-        a0, a1, a.aci, a.brp, lane, vec, st, [](int, int) {}, [&](int q) { return a.bci[q]; },
-        [&](int c, int) {
-            if constexpr (MODE == MODE_DIRECT) {
-                atomicOr(&dw[(c >> 5) - base].x, 1u << (c & 31));
-            } else {
-                const int h = slot_insert(slots, TT, logT, c >> 5);
-                atomicOr(reinterpret_cast<unsigned int*>(&slots[h].y), 1u << (c & 31));
-            }
-        });
+    if (one_chunk) {
+        stage_chunk<G>(a0, a1 - a0, a.aci, a.brp, lane, st, stage_val);
+        group_sync<G>();
+        walk_chunk<G>(a1 - a0, lane, vec, st, load_col, or_pass);
+        group_sync<G>();
+    } else {
+        walk_products<G>(a0, a1, a.aci, a.brp, lane, vec, st, [](int, int) {}, load_col, or_pass);
+    }
     if constexpr (MODE == MODE_HASHED) {
         // occupied blocks in ascending order: compact, then rank by count
         for (int c = lane; c < ncell; c += G) {
@@ -445,33 +471,31 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     }
     group_sync<G>();
     // pass 2: add every product at its column's rank
-    const T* av = reinterpret_cast<const T*>(a.av);
-    const T* bv = reinterpret_cast<const T*>(a.bv);
     struct CV {
         int c;
         T y;
     };
-    walk_products<G>(
-        a0, a1, a.aci, a.brp, lane, vec, st, [&](int e, int p) { ast[e] = av[p]; },
-        [&](int q) { return CV{a.bci[q], bv[q]}; },
-        [&](const CV& v, int e) {
-            const uint32_t below = (1u << (v.c & 31)) - 1u;
-            int rank;
-            if constexpr (MODE == MODE_DIRECT) {
-                const uint2 mp = dw[(v.c >> 5) - base];
-                rank = (int)mp.y + __popc(mp.x & below);
-            } else {
-                const int key = v.c >> 5;
-                int h = hash_slot(key, logT);
-                int4 sl = slots[h];
-                for (int probe = 1; sl.x != key && probe < TT; ++probe) {
-                    h = (h + 1) & (TT - 1);
-                    sl = slots[h];
-                }
-                rank = sl.z + __popc((uint32_t)sl.y & below);
+    auto load_cv = [&](int q) { return CV{a.bci[q], bv[q]}; };
+    auto add_pass = [&](const CV& v, int e) {
+        const uint32_t below = (1u << (v.c & 31)) - 1u;
+        int rank;
+        if constexpr (MODE == MODE_DIRECT) {
+            const uint2 mp = dw[(v.c >> 5) - base];
+            rank = (int)mp.y + __popc(mp.x & below);
+        } else {
+            const int key = v.c >> 5;
+            int h = hash_slot(key, logT);
+            int4 sl = slots[h];
+            for (int probe = 1; sl.x != key && probe < TT; ++probe) {
+                h = (h + 1) & (TT - 1);
+                sl = slots[h];
             }
-            atomicAdd(&vals[rank], ast[e] * v.y);
-        });
+            rank = sl.z + __popc((uint32_t)sl.y & below);
+        }
+        atomicAdd(&vals[rank], ast[e] * v.y);
+    };
+    if (one_chunk) walk_chunk<G>(a1 - a0, lane, vec, st, load_cv, add_pass);
+    else walk_products<G>(a0, a1, a.aci, a.brp, lane, vec, st, stage_val, load_cv, add_pass);
     // column of every rank, from the masks
     for (int t = lane; t < items; t += G) {
         uint32_t mk;
