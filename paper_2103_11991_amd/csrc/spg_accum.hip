@@ -229,9 +229,14 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_sym(SymArgs a) {
         masks = tab + T;
         ncell = T;
     }
-    for (int c = lane; c < ncell; c += G) {
-        masks[c] = 0;
-        if constexpr (MODE == MODE_HASHED) keys[c] = -1;
+    // 16-byte clears (tables start 256-byte aligned and tiers are multiples of 16 bytes)
+    if constexpr (MODE == MODE_DIRECT) {
+        for (int c = 4 * lane; c < ncell; c += 4 * G) *reinterpret_cast<uint4*>(&masks[c]) = make_uint4(0, 0, 0, 0);
+    } else {
+        for (int c = 4 * lane; c < ncell; c += 4 * G) {
+            *reinterpret_cast<int4*>(&keys[c]) = make_int4(-1, -1, -1, -1);
+            *reinterpret_cast<uint4*>(&masks[c]) = make_uint4(0, 0, 0, 0);
+        }
     }
     if (lane == 0) occ[sub] = 0, ovf[sub] = 0;
     group_sync<G>();
@@ -392,9 +397,11 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
         items = nb;
     }
     int32_t* colbuf = reinterpret_cast<int32_t*>(vals + n);
-    for (int c = lane; c < ncell; c += G) {
-        if constexpr (MODE == MODE_DIRECT) dw[c] = make_uint2(0u, 0u);
-        else slots[c] = make_int4(-1, 0, 0, 0);
+    if constexpr (MODE == MODE_DIRECT) {
+        // pairs of words per 16-byte store; an odd last word spills 8 bytes into vals, cleared below
+        for (int c = 2 * lane; c < ncell; c += 2 * G) *reinterpret_cast<uint4*>(&dw[c]) = make_uint4(0, 0, 0, 0);
+    } else {
+        for (int c = lane; c < ncell; c += G) slots[c] = make_int4(-1, 0, 0, 0);
     }
     for (int r = lane; r < n; r += G) vals[r] = T(0);
     if (lane == 0) ncompact[sub] = 0;
