@@ -396,7 +396,7 @@ def main():
     alg_bytes = (st["num_a_nnz"][dcls] * (4 + eb) + st["num_c_nnz"][dcls] * (4 + eb)
                  + frac_prod * A.nnz * (4 + eb) + rows_c * 12)
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
-    kname = f"numeric class {dcls} (mode {'hashed' if dcls >= 10 else 'direct'}, tier {dcls % 10})"
+    kname = f"numeric class {dcls} (mode {('direct', 'hashed', 'two-level')[dcls // 10]}, tier {dcls % 10})"
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(f"num_class_{dcls}"),
             "kernel": kname, "launch_ms": round(dom_ms, 4), "algorithmic_bytes": int(alg_bytes)}
@@ -417,10 +417,10 @@ def main():
         "roofline": roof,
     }
     if args.verbose:
-        detail = {"sym_rows": {c: st["sym_rows"][c] for c in range(20) if st["sym_rows"][c]},
-                  "sym_class_ms": {c: round(st["sym_class_ms"][c], 4) for c in range(20) if st["sym_rows"][c]},
-                  "num_rows": {c: st["num_rows"][c] for c in range(20) if st["num_rows"][c]},
-                  "num_class_ms": {c: round(st["num_class_ms"][c], 4) for c in range(20) if st["num_rows"][c]},
+        detail = {"sym_rows": {c: st["sym_rows"][c] for c in range(len(st["sym_rows"])) if st["sym_rows"][c]},
+                  "sym_class_ms": {c: round(st["sym_class_ms"][c], 4) for c in range(len(st["sym_rows"])) if st["sym_rows"][c]},
+                  "num_rows": {c: st["num_rows"][c] for c in range(len(st["num_rows"])) if st["num_rows"][c]},
+                  "num_class_ms": {c: round(st["num_class_ms"][c], 4) for c in range(len(st["num_rows"])) if st["num_rows"][c]},
                   "analysis_ms": st["analysis_ms"], "scan_ms": st["scan_ms"], "sym_ms": st["sym_ms"],
                   "num_ms": st["num_ms"]}
         print(json.dumps(detail), file=sys.stderr, flush=True)

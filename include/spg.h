@@ -67,8 +67,9 @@ typedef enum {
     /* record HIP events around every launch (default 0); read with spg_get_stats */
     SPG_OPT_TIMING = 1,
     /* force every row of both phases into one accumulator class (-1 = off);
-       class = mode * 10 + tier, see spg_stats.  Rows that do not fit the
-       forced class are placed in the smallest class that fits. */
+       class = mode * 10 + tier with mode 0 direct, 1 hashed, 2 two-level
+       (numeric only) and tier 0..8 LDS, 9 global memory.  Rows that do not
+       fit the forced class are placed in the class they would get anyway. */
     SPG_OPT_FORCE_CLASS = 2,
     /* products per lane used to size the thread group of a row (default 16) */
     SPG_OPT_WORK_PER_LANE = 3,
@@ -88,7 +89,7 @@ typedef enum {
 } spg_option;
 
 #define SPG_NTIER 10
-#define SPG_NCLASS 20
+#define SPG_NCLASS 30
 
 /* Statistics of the last symbolic and numeric calls (spg_get_stats). */
 typedef struct {

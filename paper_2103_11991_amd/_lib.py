@@ -18,7 +18,7 @@ OPT = {
     "binning": 0, "timing": 1, "force_class": 2, "work_per_lane": 3, "mlp_margin_milli": 4,
     "vector_width": 5, "hash_max_blocks": 6, "lds_limit": 7, "keep_features": 8,
 }
-NTIER, NCLASS = 10, 20
+NTIER, NCLASS = 10, 30
 STATUS = ["SPG_OK", "SPG_ERR_ARG", "SPG_ERR_SHAPE", "SPG_ERR_STATE", "SPG_ERR_INDEX", "SPG_ERR_OVERFLOW",
           "SPG_ERR_ALLOC", "SPG_ERR_HIP", "SPG_ERR_UNSUPPORTED"]
 EXPORTS = ["spg_status_string", "spg_last_error", "spg_create", "spg_destroy", "spg_set_stream",

@@ -198,6 +198,9 @@ __device__ inline void walk_products(int a0, int a1, const int32_t* __restrict__
 }
 
 // ------------------------------------------------------------------ symbolic
+// Every entry of compressed B is a {block, mask} run: the row's table gets
+// the mask OR-ed in, and the bits that were not yet set (and blocks that were
+// empty) are counted from the value the atomic OR returns.
 
 template <int G, int MODE>
 __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_sym(SymArgs a) {
@@ -243,25 +246,24 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_sym(SymArgs a) {
     int cnt = 0, nb = 0;
     const int occ_max = (T * 3) / 4;
     walk_products<G>(
-        a.arp[i], a.arp[i + 1], a.aci, a.brp, lane, vec, st, [](int, int) {},
-        [&](int q) { return a.bci[q]; },
-        [&](int c, int) {
-            const uint32_t bit = 1u << (c & 31);
+        a.arp[i], a.arp[i + 1], a.aci, a.bcrp, lane, vec, st, [](int, int) {}, [&](int q) { return a.bc[q]; },
+        [&](int2 run, int) {
+            const uint32_t bits = (uint32_t)run.y;
             int cell;
             if constexpr (MODE == MODE_DIRECT) {
-                cell = (c >> 5) - base;
+                cell = run.x - base;
             } else {
                 if (*(volatile int*)&ovf[sub]) return;
                 bool ins;
-                cell = hash_insert(keys, T, logT, c >> 5, ins);
+                cell = hash_insert(keys, T, logT, run.x, ins);
                 if (cell < 0) {
                     ovf[sub] = 1;
                     return;
                 }
                 if (ins && atomicAdd(&occ[sub], 1) >= occ_max) ovf[sub] = 1;
             }
-            const uint32_t old = atomicOr(&masks[cell], bit);
-            cnt += (old & bit) == 0;
+            const uint32_t old = atomicOr(&masks[cell], bits);
+            cnt += __popc(bits & ~old);
             nb += old == 0;
         });
     cnt = group_sum<G>(cnt, red);
@@ -297,11 +299,10 @@ __device__ void wide_sym_row(const SymArgs& a, int i, uint32_t* masks, int2* st,
     __syncthreads();
     int cnt = 0, nb = 0;
     walk_products<G>(
-        a.arp[i], a.arp[i + 1], a.aci, a.brp, tid, vec, st, [](int, int) {}, [&](int q) { return a.bci[q]; },
-        [&](int c, int) {
-            const uint32_t bit = 1u << (c & 31);
-            const uint32_t old = atomicOr(&masks[(c >> 5) - base], bit);
-            cnt += (old & bit) == 0;
+        a.arp[i], a.arp[i + 1], a.aci, a.bcrp, tid, vec, st, [](int, int) {}, [&](int q) { return a.bc[q]; },
+        [&](int2 run, int) {
+            const uint32_t old = atomicOr(&masks[run.x - base], (uint32_t)run.y);
+            cnt += __popc((uint32_t)run.y & ~old);
             nb += old == 0;
         });
     cnt = group_sum<G>(cnt, red);
@@ -332,6 +333,15 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_sym_wide(SymArgs a) {
 }
 
 // ------------------------------------------------------------------- numeric
+// Pass 1 finds the occupied columns from compressed B; a prefix sum of
+// popcounts in ascending block order turns them into ranks; pass 2 walks B
+// itself and adds each product at its column's rank.
+//   direct:    one {mask, prefix} pair per 32-column word of the row's range;
+//   two-level: a {bits, prefix} pair per 32 blocks marks occupied blocks, so
+//              a block's compact index (already in block order) is a popcount;
+//              per occupied block {mask, prefix} and its id.  Pass 1 is split
+//              in two walks of compressed B: blocks first, then masks;
+//   hashed:    {block, mask, prefix} slots, occupied blocks ranked by count.
 
 // Hashed numeric slot {block id, mask, prefix, -}: insert-or-find by block id.
 __device__ inline int slot_insert(int4* slots, int T, int logT, int key) {
@@ -349,6 +359,8 @@ __device__ inline int slot_insert(int4* slots, int T, int logT, int key) {
     return -1;
 }
 
+__device__ inline uint32_t below(int b) { return (1u << b) - 1u; }
+
 template <int G, int MODE, typename T>
 __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     constexpr int RPW = rows_per_wg<G>();
@@ -356,16 +368,18 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     __shared__ int red[16];
     __shared__ int ncompact[RPW];
     const int bytes = tier_bytes(a.tier);
-    const int per_row = bytes + G * 16;
+    const int per_row = bytes + G * 24;
     const int sub = threadIdx.x / G, lane = threadIdx.x % G;
     const int vec = a.vec < G ? a.vec : G;
+    const int vecc = a.vecc < G ? a.vecc : G;
     const int slot = blockIdx.x * RPW + sub;
     if (slot >= a.count) return;
     const int i = a.perm[slot];
     uint8_t* row_lds = reinterpret_cast<uint8_t*>(smem) + (size_t)sub * per_row;
     uint8_t* tab = row_lds;
-    int2* st = reinterpret_cast<int2*>(row_lds + bytes);
-    T* ast = reinterpret_cast<T*>(row_lds + bytes + G * 8);
+    int2* stc = reinterpret_cast<int2*>(row_lds + bytes);              // compressed-B staging
+    int2* stb = reinterpret_cast<int2*>(row_lds + bytes + G * 8);      // B staging
+    T* ast = reinterpret_cast<T*>(row_lds + bytes + G * 16);           // A values
     const int off = a.crp[i];
     const int n = a.crp[i + 1] - off;
     const RowInfo ri = a.rinfo[i];
@@ -373,19 +387,26 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     const int words = (ri.y >> 5) - base + 1;
     const int nb = a.row_blocks[i];
     const int nb4 = (nb + 3) & ~3;
-    // direct: one {mask, prefix} pair per 32-column word of the row's range
+    const int w1 = (words + 31) >> 5;
+    // direct: {mask, prefix} per word.  two-level: l1 {bits, prefix} per 32
+    // blocks, cm {mask, prefix} and blk per occupied block.  hashed: slots,
+    // compact keys (padded), their slots, slots in block order.
     uint2* dw = reinterpret_cast<uint2*>(tab);
-    // hashed: slots, compact keys (padded), their slots, slots in block order
+    uint2* l1 = reinterpret_cast<uint2*>(tab);
+    uint2* cm = l1 + w1;
+    int32_t* blk = reinterpret_cast<int32_t*>(cm + nb);
     int4* slots = reinterpret_cast<int4*>(tab);
     int32_t* ck = nullptr;
     int32_t* cs = nullptr;
     int32_t* ord = nullptr;
     T* vals;
-    int ncell, items, TT = 0, logT = 0;
+    int items, TT = 0, logT = 0;
     if constexpr (MODE == MODE_DIRECT) {
         vals = reinterpret_cast<T*>(tab + align8((int64_t)words * 8));
-        ncell = words;
         items = words;
+    } else if constexpr (MODE == MODE_TWOLEVEL) {
+        vals = reinterpret_cast<T*>(tab + align8((int64_t)w1 * 8 + (int64_t)nb * 12));
+        items = nb;
     } else {
         TT = (int)num_hash_slots(nb);
         logT = 31 - __clz(TT);
@@ -393,47 +414,84 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
         cs = ck + nb4;
         ord = cs + nb;
         vals = reinterpret_cast<T*>(tab + align8((int64_t)TT * 16 + (int64_t)nb4 * 4 + (int64_t)nb * 8));
-        ncell = TT;
         items = nb;
     }
     int32_t* colbuf = reinterpret_cast<int32_t*>(vals + n);
     if constexpr (MODE == MODE_DIRECT) {
         // pairs of words per 16-byte store; an odd last word spills 8 bytes into vals, cleared below
-        for (int c = 2 * lane; c < ncell; c += 2 * G) *reinterpret_cast<uint4*>(&dw[c]) = make_uint4(0, 0, 0, 0);
+        for (int c = 2 * lane; c < words; c += 2 * G) *reinterpret_cast<uint4*>(&dw[c]) = make_uint4(0, 0, 0, 0);
+    } else if constexpr (MODE == MODE_TWOLEVEL) {
+        for (int c = lane; c < w1 + nb; c += G) l1[c] = make_uint2(0u, 0u);
     } else {
-        for (int c = lane; c < ncell; c += G) slots[c] = make_int4(-1, 0, 0, 0);
+        for (int c = lane; c < TT; c += G) slots[c] = make_int4(-1, 0, 0, 0);
     }
     for (int r = lane; r < n; r += G) vals[r] = T(0);
     if (lane == 0) ncompact[sub] = 0;
-    group_sync<G>();
 
     const int a0 = a.arp[i], a1 = a.arp[i + 1];
     const T* av = reinterpret_cast<const T*>(a.av);
     const T* bv = reinterpret_cast<const T*>(a.bv);
-    // a row whose A nonzeros fit one chunk is staged once for both passes
+    // a row whose A nonzeros fit one chunk is staged once for all passes
     const bool one_chunk = a1 - a0 <= G;
-    auto or_pass = [&](int c, int) {
-        if constexpr (MODE == MODE_DIRECT) {
-            atomicOr(&dw[(c >> 5) - base].x, 1u << (c & 31));
-        } else {
-            const int h = slot_insert(slots, TT, logT, c >> 5);
-            atomicOr(reinterpret_cast<unsigned int*>(&slots[h].y), 1u << (c & 31));
-        }
+    auto load_run = [&](int q) { return a.bc[q]; };
+    auto nothing = [](int, int) {};
+    auto walk_runs = [&](auto&& apply) {
+        if (one_chunk) walk_chunk<G>(a1 - a0, lane, vecc, stc, load_run, apply);
+        else walk_products<G>(a0, a1, a.aci, a.bcrp, lane, vecc, stc, nothing, load_run, apply);
     };
-    auto load_col = [&](int q) { return a.bci[q]; };
-    auto stage_val = [&](int e, int p) { ast[e] = av[p]; };
-    // pass 1: which columns occur
     if (one_chunk) {
-        stage_chunk<G>(a0, a1 - a0, a.aci, a.brp, lane, st, stage_val);
-        group_sync<G>();
-        walk_chunk<G>(a1 - a0, lane, vec, st, load_col, or_pass);
-        group_sync<G>();
-    } else {
-        walk_products<G>(a0, a1, a.aci, a.brp, lane, vec, st, [](int, int) {}, load_col, or_pass);
+        if (lane < a1 - a0) {
+            const int j = a.aci[a0 + lane];
+            const int c0 = a.bcrp[j], b0 = a.brp[j];
+            stc[lane] = make_int2(c0, a.bcrp[j + 1] - c0);
+            stb[lane] = make_int2(b0, a.brp[j + 1] - b0);
+            ast[lane] = av[a0 + lane];
+        }
     }
+    group_sync<G>();
+    // pass 1: which columns occur
+    if constexpr (MODE == MODE_TWOLEVEL) {
+        walk_runs([&](int2 run, int) {
+            const int w = run.x - base;
+            atomicOr(&l1[w >> 5].x, 1u << (w & 31));
+        });
+        group_sync<G>();
+        // compact index of each occupied block: prefix of popcounts over l1
+        {
+            const int chunk = (w1 + G - 1) / G;
+            const int beg = lane * chunk;
+            const int end = min(beg + chunk, w1);
+            int local = 0;
+            for (int t = beg; t < end; ++t) local += __popc(l1[t].x);
+            int total;
+            int ex = group_excl_scan<G>(local, total, red);
+            for (int t = beg; t < end; ++t) {
+                l1[t].y = (uint32_t)ex;
+                ex += __popc(l1[t].x);
+            }
+        }
+        group_sync<G>();
+        walk_runs([&](int2 run, int) {
+            const int w = run.x - base;
+            const uint2 L = l1[w >> 5];
+            const int ci = (int)L.y + __popc(L.x & below(w & 31));
+            atomicOr(&cm[ci].x, (uint32_t)run.y);
+            blk[ci] = run.x;
+        });
+    } else {
+        walk_runs([&](int2 run, int) {
+            if constexpr (MODE == MODE_DIRECT) {
+                atomicOr(&dw[run.x - base].x, (uint32_t)run.y);
+            } else {
+                const int h = slot_insert(slots, TT, logT, run.x);
+                atomicOr(reinterpret_cast<unsigned int*>(&slots[h].y), (uint32_t)run.y);
+            }
+        });
+    }
+    group_sync<G>();
     if constexpr (MODE == MODE_HASHED) {
         // occupied blocks in ascending order: compact, then rank by count
-        for (int c = lane; c < ncell; c += G) {
+        for (int c = lane; c < TT; c += G) {
             const int4 sl = slots[c];
             if (sl.y) {
                 const int pos = atomicAdd(&ncompact[sub], 1);
@@ -455,20 +513,26 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
         }
         group_sync<G>();
     }
-    // exclusive prefix of popcounts over blocks in ascending order
+    // exclusive prefix of popcounts over occupied blocks in ascending order
     {
         const int chunk = (items + G - 1) / G;
         const int beg = lane * chunk;
         const int end = min(beg + chunk, items);
         int local = 0;
-        for (int t = beg; t < end; ++t)
-            local += __popc(MODE == MODE_DIRECT ? dw[t].x : (uint32_t)slots[ord[t]].y);
+        for (int t = beg; t < end; ++t) {
+            if constexpr (MODE == MODE_DIRECT) local += __popc(dw[t].x);
+            else if constexpr (MODE == MODE_TWOLEVEL) local += __popc(cm[t].x);
+            else local += __popc((uint32_t)slots[ord[t]].y);
+        }
         int total;
         int ex = group_excl_scan<G>(local, total, red);
         for (int t = beg; t < end; ++t) {
             if constexpr (MODE == MODE_DIRECT) {
                 dw[t].y = (uint32_t)ex;
                 ex += __popc(dw[t].x);
+            } else if constexpr (MODE == MODE_TWOLEVEL) {
+                cm[t].y = (uint32_t)ex;
+                ex += __popc(cm[t].x);
             } else {
                 const int cl = ord[t];
                 slots[cl].z = ex;
@@ -484,11 +548,15 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     };
     auto load_cv = [&](int q) { return CV{a.bci[q], bv[q]}; };
     auto add_pass = [&](const CV& v, int e) {
-        const uint32_t below = (1u << (v.c & 31)) - 1u;
         int rank;
         if constexpr (MODE == MODE_DIRECT) {
             const uint2 mp = dw[(v.c >> 5) - base];
-            rank = (int)mp.y + __popc(mp.x & below);
+            rank = (int)mp.y + __popc(mp.x & below(v.c & 31));
+        } else if constexpr (MODE == MODE_TWOLEVEL) {
+            const int w = (v.c >> 5) - base;
+            const uint2 L = l1[w >> 5];
+            const uint2 mp = cm[(int)L.y + __popc(L.x & below(w & 31))];
+            rank = (int)mp.y + __popc(mp.x & below(v.c & 31));
         } else {
             const int key = v.c >> 5;
             int h = hash_slot(key, logT);
@@ -497,25 +565,29 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
                 h = (h + 1) & (TT - 1);
                 sl = slots[h];
             }
-            rank = sl.z + __popc((uint32_t)sl.y & below);
+            rank = sl.z + __popc((uint32_t)sl.y & below(v.c & 31));
         }
         atomicAdd(&vals[rank], ast[e] * v.y);
     };
-    if (one_chunk) walk_chunk<G>(a1 - a0, lane, vec, st, load_cv, add_pass);
-    else walk_products<G>(a0, a1, a.aci, a.brp, lane, vec, st, stage_val, load_cv, add_pass);
+    if (one_chunk) walk_chunk<G>(a1 - a0, lane, vec, stb, load_cv, add_pass);
+    else walk_products<G>(a0, a1, a.aci, a.brp, lane, vec, stb, [&](int e, int p) { ast[e] = av[p]; }, load_cv,
+                          add_pass);
     // column of every rank, from the masks
     for (int t = lane; t < items; t += G) {
         uint32_t mk;
-        int r, blk;
+        int r, b;
         if constexpr (MODE == MODE_DIRECT) {
             const uint2 mp = dw[t];
-            mk = mp.x, r = (int)mp.y, blk = base + t;
+            mk = mp.x, r = (int)mp.y, b = base + t;
+        } else if constexpr (MODE == MODE_TWOLEVEL) {
+            const uint2 mp = cm[t];
+            mk = mp.x, r = (int)mp.y, b = blk[t];
         } else {
             const int4 sl = slots[ord[t]];
-            mk = (uint32_t)sl.y, r = sl.z, blk = sl.x;
+            mk = (uint32_t)sl.y, r = sl.z, b = sl.x;
         }
         while (mk) {
-            colbuf[r++] = (blk << 5) + (__ffs(mk) - 1);
+            colbuf[r++] = (b << 5) + (__ffs(mk) - 1);
             mk &= mk - 1;
         }
     }
@@ -545,9 +617,10 @@ __device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int2* st,
     __threadfence();
     __syncthreads();
     const int a0 = a.arp[i], a1 = a.arp[i + 1];
+    const int vecc = a.vecc < G ? a.vecc : G;
     walk_products<G>(
-        a0, a1, a.aci, a.brp, tid, vec, st, [](int, int) {}, [&](int q) { return a.bci[q]; },
-        [&](int c, int) { atomicOr(&masks[(c >> 5) - base], 1u << (c & 31)); });
+        a0, a1, a.aci, a.bcrp, tid, vecc, st, [](int, int) {}, [&](int q) { return a.bc[q]; },
+        [&](int2 run, int) { atomicOr(&masks[run.x - base], (uint32_t)run.y); });
     if (!IN_LDS) __threadfence();
     __syncthreads();
     {
@@ -577,16 +650,15 @@ __device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int2* st,
         [&](const CV& v, int e) {
             const int w = (v.c >> 5) - base;
             const uint32_t mk = ld_tab<IN_LDS>(&masks[w]);
-            const int rank = (int)ld_tab<IN_LDS>(reinterpret_cast<uint32_t*>(&pref[w])) +
-                             __popc(mk & ((1u << (v.c & 31)) - 1u));
+            const int rank = (int)ld_tab<IN_LDS>(reinterpret_cast<uint32_t*>(&pref[w])) + __popc(mk & below(v.c & 31));
             atomicAdd(&cv[rank], ast[e] * v.y);
         });
     for (int t = tid; t < words; t += G) {
         uint32_t mk = ld_tab<IN_LDS>(&masks[t]);
         int r = (int)ld_tab<IN_LDS>(reinterpret_cast<uint32_t*>(&pref[t]));
-        const int blk = base + t;
+        const int b = base + t;
         while (mk) {
-            cc[r++] = (blk << 5) + (__ffs(mk) - 1);
+            cc[r++] = (b << 5) + (__ffs(mk) - 1);
             mk &= mk - 1;
         }
     }
@@ -622,7 +694,7 @@ template <int G, int MODE, typename T>
 void num_launch(hipStream_t s, const NumArgs& a) {
     constexpr int RPW = rows_per_wg<G>();
     const unsigned grid = (unsigned)((a.count + RPW - 1) / RPW);
-    const size_t smem = (size_t)RPW * (tier_bytes(a.tier) + G * 16);
+    const size_t smem = (size_t)RPW * (tier_bytes(a.tier) + G * 24);
     hipLaunchKernelGGL((k_num<G, MODE, T>), dim3(grid), dim3(G * RPW), smem, s, a);
 }
 
@@ -682,10 +754,12 @@ int launch_num_class(hipStream_t s, const NumArgs& a, int elem_bytes, int grid_c
     }
     if (elem_bytes == 8) {
         if (a.mode == MODE_DIRECT) num_dispatch<MODE_DIRECT, double>(s, a);
-        else num_dispatch<MODE_HASHED, double>(s, a);
+        else if (a.mode == MODE_HASHED) num_dispatch<MODE_HASHED, double>(s, a);
+        else num_dispatch<MODE_TWOLEVEL, double>(s, a);
     } else {
         if (a.mode == MODE_DIRECT) num_dispatch<MODE_DIRECT, float>(s, a);
-        else num_dispatch<MODE_HASHED, float>(s, a);
+        else if (a.mode == MODE_HASHED) num_dispatch<MODE_HASHED, float>(s, a);
+        else num_dispatch<MODE_TWOLEVEL, float>(s, a);
     }
     return 1;
 }

@@ -63,7 +63,7 @@ struct spg_handle_s {
 
     // scratch
     DevBuf binfo, rinfo, feats, sym_cls, num_cls, perm_sym, perm_num, row_nnz, row_blocks, tile_status, cursor,
-        ovf_list, ctl, slab_sym, slab_retry, slab_num, mlp_w;
+        ovf_list, ctl, slab_sym, slab_retry, slab_num, mlp_w, bcrp, bc;
     Control* hctl = nullptr;  // pinned host copy
 
     // symbolic result
@@ -76,6 +76,7 @@ struct spg_handle_s {
     int64_t slab_num_words = 0;
     int nslab_num = 0;
     int vec_used = 1;
+    int vecc_used = 1;
     ClassCfg cfg{};
     Control geom{};  // control block after the analysis of the last symbolic run
 
@@ -153,12 +154,17 @@ float elapsed(spg_handle h, int a, int b) {
     return ms;
 }
 
-int pick_vec(spg_handle h) {
-    if (h->vec > 0) return h->vec;
-    double mean = h->n > 0 ? (double)h->bnnz / (double)h->n : 1.0;
+// lanes that read one row together: the largest power of two up to 1.5x
+// the mean row length (of B for values, of compressed B for the OR passes)
+int vec_for(double mean) {
     int v = 1;
     while (v < 64 && 2.0 * v <= mean * 1.5) v *= 2;
     return v;
+}
+
+int pick_vec(spg_handle h) {
+    if (h->vec > 0) return h->vec;
+    return vec_for(h->n > 0 ? (double)h->bnnz / (double)h->n : 1.0);
 }
 
 ClassCfg make_cfg(spg_handle h) {
@@ -175,7 +181,7 @@ int wide_lds(spg_handle h) {
     // table LDS of a global-path workgroup: 64 KB, less if the device cannot
     // give it together with the 16 KB of staged A entries
     int v = 65536;
-    while (v > 4096 && v + WIDE_THREADS * 16 + 1024 > h->max_lds) v >>= 1;
+    while (v > 4096 && v + WIDE_THREADS * 24 + 1024 > h->max_lds) v >>= 1;
     return v;
 }
 
@@ -229,7 +235,8 @@ spg_status sym_prepare(spg_handle h) {
     SPG_TRY(ensure(h, h->perm_num, M * 4));
     SPG_TRY(ensure(h, h->row_nnz, M * 4));
     SPG_TRY(ensure(h, h->row_blocks, M * 4));
-    SPG_TRY(ensure(h, h->tile_status, (size_t)(scan_tiles(m) + 1) * 8));
+    SPG_TRY(ensure(h, h->tile_status, (size_t)(scan_tiles(std::max(m, h->n)) + 1) * 8));
+    SPG_TRY(ensure(h, h->bcrp, ((size_t)h->n + 1) * 4));
     SPG_TRY(ensure(h, h->cursor, NCLS * 4));
     if (learned) SPG_TRY(ensure(h, h->ovf_list, M * 4));
     if (want_feats) SPG_TRY(ensure(h, h->feats, M * 12));
@@ -265,6 +272,11 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
     const Control& hc = h->geom;
     Control* ctl = h->ctl.as<Control>();
     const int wl = wide_lds(h);
+    // compressed B, read by both phases
+    SPG_TRY(ensure(h, h->bc, (size_t)std::max<int64_t>(hc.bc_total, 1) * sizeof(int2)));
+    h->vecc_used = h->vec > 0 ? h->vec : vec_for(h->n > 0 ? (double)hc.bc_total / (double)h->n : 1.0);
+    launch_compress_b(s, h->n, h->brp, h->bci, h->binfo.as<int4>(), h->bcrp.as<int32_t>(), h->tile_status.as<uint64_t>(),
+                      &ctl->tile_counter_b, h->bc.as<int2>());
     launch_fill_i32(s, h->cursor.as<int32_t>(), 0, NCLS);
     launch_scatter(s, m, h->sym_cls.as<uint8_t>(), ctl->sym_hist, h->cursor.as<int32_t>(), h->perm_sym.as<int32_t>());
     int off[NCLS];
@@ -289,8 +301,9 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
         a.count = hc.sym_hist[c];
         a.tier = c % NTIER;
         a.mode = c / NTIER;
-        a.vec = h->vec_used;
+        a.vec = h->vecc_used;
         a.arp = h->arp, a.aci = h->aci, a.brp = h->brp, a.bci = h->bci;
+        a.bcrp = h->bcrp.as<int32_t>(), a.bc = h->bc.as<int2>();
         a.rinfo = h->rinfo.as<RowInfo>();
         a.row_nnz = h->row_nnz.as<int32_t>();
         a.row_blocks = h->row_blocks.as<int32_t>();
@@ -313,8 +326,9 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
         a.count_dev = &ctl->overflow_rows;
         a.tier = TIER_GLOBAL;
         a.mode = MODE_DIRECT;
-        a.vec = h->vec_used;
+        a.vec = h->vecc_used;
         a.arp = h->arp, a.aci = h->aci, a.brp = h->brp, a.bci = h->bci;
+        a.bcrp = h->bcrp.as<int32_t>(), a.bc = h->bc.as<int2>();
         a.rinfo = h->rinfo.as<RowInfo>();
         a.row_nnz = h->row_nnz.as<int32_t>();
         a.row_blocks = h->row_blocks.as<int32_t>();
@@ -399,6 +413,8 @@ spg_status num_launch_all(spg_handle h, const void* a_vals, const void* b_vals, 
         a.vec = h->vec_used;
         a.arp = h->arp, a.aci = h->aci, a.av = a_vals;
         a.brp = h->brp, a.bci = h->bci, a.bv = b_vals;
+        a.bcrp = h->bcrp.as<int32_t>(), a.bc = h->bc.as<int2>();
+        a.vecc = h->vecc_used;
         a.crp = h->crp;
         a.rinfo = h->rinfo.as<RowInfo>();
         a.row_blocks = h->row_blocks.as<int32_t>();
@@ -467,7 +483,7 @@ spg_status spg_destroy(spg_handle h) {
     if (h->stream || true) (void)hipStreamSynchronize(h->stream);
     DevBuf* bufs[] = {&h->binfo, &h->rinfo, &h->feats, &h->sym_cls, &h->num_cls, &h->perm_sym, &h->perm_num,
                       &h->row_nnz, &h->row_blocks, &h->tile_status, &h->cursor, &h->ovf_list, &h->ctl,
-                      &h->slab_sym, &h->slab_retry, &h->slab_num, &h->mlp_w};
+                      &h->slab_sym, &h->slab_retry, &h->slab_num, &h->mlp_w, &h->bcrp, &h->bc};
     for (DevBuf* b : bufs) release(*b);
     if (h->hctl) (void)hipHostFree(h->hctl);
     if (h->ev_made)

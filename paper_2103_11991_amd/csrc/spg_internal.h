@@ -33,6 +33,7 @@ constexpr int NCLS = SPG_NCLASS;     // class = mode * NTIER + tier
 constexpr int TIER_GLOBAL = 9;
 constexpr int MODE_DIRECT = 0;
 constexpr int MODE_HASHED = 1;
+constexpr int MODE_TWOLEVEL = 2;  // numeric only
 constexpr uint8_t CLS_EMPTY = 255;
 constexpr int WIDE_THREADS = 1024;   // threads per row on the global path
 
@@ -53,10 +54,10 @@ __host__ __device__ inline int tier_rows(int t) {
     int g = tier_threads(t);
     return g <= 64 ? 256 / g : 1;
 }
-// dynamic LDS of one workgroup of tier t: the rows' tables plus 16 bytes of
+// dynamic LDS of one workgroup of tier t: the rows' tables plus 24 bytes of
 // staged A entries per lane (numeric; 8 in symbolic)
 __host__ __device__ inline int64_t tier_smem_bytes(int t) {
-    return (int64_t)tier_rows(t) * (tier_bytes(t) + 16 * tier_threads(t));
+    return (int64_t)tier_rows(t) * (tier_bytes(t) + 24 * tier_threads(t));
 }
 
 __host__ __device__ inline int64_t pow2ceil64(int64_t x) {
@@ -100,6 +101,13 @@ __host__ __device__ inline int64_t num_direct_bytes(int64_t words, int64_t n, in
 __host__ __device__ inline int64_t num_hashed_bytes(int64_t blocks, int64_t n, int eb) {
     return align8(num_hash_slots(blocks) * 16 + ((blocks + 3) / 4) * 16 + blocks * 8) + n * (eb + 4);
 }
+// two-level numeric table: a {bits, prefix} pair per 32 words of the row's
+// block range (which blocks are occupied, and their compact index), then per
+// occupied block {mask, prefix} and its block id
+__host__ __device__ inline int64_t twolevel_words(int64_t words) { return (words + 31) / 32; }
+__host__ __device__ inline int64_t num_twolevel_bytes(int64_t words, int64_t blocks, int64_t n, int eb) {
+    return align8(twolevel_words(words) * 8 + blocks * 12) + n * (eb + 4);
+}
 
 // Smallest LDS tier that holds `bytes`, raised until its thread group gives
 // at most work_per_lane products per lane; TIER_GLOBAL if it does not fit.
@@ -135,21 +143,29 @@ __host__ __device__ inline int sym_class(int64_t ub, int32_t cmin, int32_t cmax,
     return mode * NTIER + t;
 }
 
-// Numeric class of a row from its exact size n and occupied blocks.
+// Numeric class of a row from its exact size n and occupied blocks: the
+// direct table when the row's block range is about as small as its block
+// count, else the two-level table; the hashed table only for very wide, very
+// sparse rows (its block ranking costs blocks^2 / G).
 __host__ __device__ inline int num_class(int64_t ub, int32_t cmin, int32_t cmax, int64_t n, int64_t blocks,
                                          const ClassCfg& c) {
     if (n <= 0) return CLS_EMPTY;
     int64_t words = row_words(cmin, cmax);
     int eb = c.elem_bytes;
     int64_t bd = num_direct_bytes(words, n, eb), bh = num_hashed_bytes(blocks, n, eb);
+    int64_t b2 = num_twolevel_bytes(words, blocks, n, eb);
     if (c.force_class >= 0) {
         int fm = c.force_class / NTIER, ft = c.force_class % NTIER;
         if (ft == TIER_GLOBAL) return MODE_DIRECT * NTIER + TIER_GLOBAL;
-        int64_t need = fm == MODE_DIRECT ? bd : bh;
+        int64_t need = fm == MODE_DIRECT ? bd : fm == MODE_HASHED ? bh : b2;
         if (need <= tier_bytes(ft) && tier_bytes(ft) <= c.lds_limit) return c.force_class;
     }
-    int mode = (blocks <= c.hash_max_blocks && bh < bd) ? MODE_HASHED : MODE_DIRECT;
-    int t = pick_tier(mode == MODE_HASHED ? bh : bd, ub, c);
+    int mode;
+    int64_t bytes;
+    if (words <= 2 * blocks + 8) mode = MODE_DIRECT, bytes = bd;
+    else if (blocks <= c.hash_max_blocks && bh * 8 < b2) mode = MODE_HASHED, bytes = bh;
+    else mode = MODE_TWOLEVEL, bytes = b2;
+    int t = pick_tier(bytes, ub, c);
     if (t == TIER_GLOBAL) mode = MODE_DIRECT;
     return mode * NTIER + t;
 }
@@ -172,7 +188,8 @@ struct Control {
     int64_t num_c_nnz[NCLS];
     int64_t num_products[NCLS];
     int32_t tile_counter;         // dynamic tile id of the row-pointer scan
-    int32_t pad;
+    int32_t tile_counter_b;       // dynamic tile id of the compressed-B scan
+    int64_t bc_total;             // runs of compressed B
 };
 
 // ---- launch wrappers (spg_rows.hip) ----
@@ -180,6 +197,12 @@ void launch_fill_i32(hipStream_t s, int32_t* p, int32_t v, int64_t n);
 void launch_fill_u8(hipStream_t s, void* p, uint8_t v, int64_t bytes);
 void launch_b_rowinfo(hipStream_t s, int32_t n, int32_t k, const int32_t* brp, const int32_t* bci, int64_t bnnz,
                       int4* binfo, Control* ctl);
+// compressed B (section 2.2.1): per B row, runs of consecutive entries in one
+// 32-column block become one {block, OR of the column bits} entry.  binfo.w
+// holds each row's run count; bcrp gets their exclusive scan (n+1 entries,
+// tile status scratch of scan_tiles(n)+1 words), bc the runs.
+void launch_compress_b(hipStream_t s, int32_t n, const int32_t* brp, const int32_t* bci, const int4* binfo,
+                       int32_t* bcrp, uint64_t* tile_status, int32_t* tile_counter, int2* bc);
 void launch_a_rowinfo(hipStream_t s, int32_t m, int32_t n, const int32_t* arp, const int32_t* aci, int64_t annz,
                       const int4* binfo, RowInfo* rinfo, float* feats, ClassCfg cfg, int learned,
                       uint8_t* sym_cls, int32_t* row_nnz, int32_t* row_blocks, Control* ctl);
@@ -204,11 +227,13 @@ struct SymArgs {
     int32_t count;
     int32_t tier;
     int32_t mode;
-    int32_t vec;                  // lanes sharing one B row (power of two)
+    int32_t vec;                  // lanes sharing one compressed-B row (power of two)
     const int32_t* arp;
     const int32_t* aci;
     const int32_t* brp;
     const int32_t* bci;
+    const int32_t* bcrp;          // compressed B: row pointer and {block, mask} runs
+    const int2* bc;
     const RowInfo* rinfo;
     int32_t* row_nnz;
     int32_t* row_blocks;
@@ -232,6 +257,9 @@ struct NumArgs {
     const int32_t* brp;
     const int32_t* bci;
     const void* bv;
+    const int32_t* bcrp;
+    const int2* bc;
+    int32_t vecc;                 // lanes sharing one compressed-B row
     const int32_t* crp;
     const RowInfo* rinfo;
     const int32_t* row_blocks;

@@ -50,37 +50,50 @@ __device__ inline int xor_reduce_max(int v) {
     return v;
 }
 
-// B rows: length, smallest and largest column.  Checks B's row pointer and
-// column indices; a malformed row contributes nothing.
+// B rows: length, smallest and largest column, and the number of runs of
+// consecutive entries that share a 32-column block (the length of the row in
+// compressed B).  Checks B's row pointer and column indices; a malformed row
+// contributes nothing.  Grid-stride, one flush of the run total per workgroup.
 __global__ __launch_bounds__(256) void k_b_rowinfo(int32_t n, int32_t k, const int32_t* __restrict__ brp,
                                                    const int32_t* __restrict__ bci, int64_t bnnz,
                                                    int4* __restrict__ binfo, Control* ctl) {
-    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t row = gid / ROW_LANES;
-    const int lane = (int)(gid % ROW_LANES);
-    int len = 0, mn = INT_MAX, mx = -1, bad = 0;
-    if (row < n) {
-        int32_t s = brp[row], e = brp[row + 1];
-        if (s < 0 || e < s || (int64_t)e > bnnz || (row == 0 && s != 0) || (row == n - 1 && (int64_t)e != bnnz)) {
-            bad = ERR_B_ROWPTR;
-        } else {
-            len = e - s;
-            for (int32_t q = s + lane; q < e; q += ROW_LANES) {
-                int c = bci[q];
-                if (c < 0 || c >= k) { bad = ERR_B_COL; continue; }
-                mn = min(mn, c);
-                mx = max(mx, c);
+    __shared__ unsigned long long runs_sum;
+    if (threadIdx.x == 0) runs_sum = 0;
+    __syncthreads();
+    const int lane = (int)(threadIdx.x % ROW_LANES);
+    const int64_t rows_per_block = blockDim.x / ROW_LANES;
+    for (int64_t rb = blockIdx.x * rows_per_block; rb < n; rb += (int64_t)gridDim.x * rows_per_block) {
+        const int64_t row = rb + threadIdx.x / ROW_LANES;
+        int len = 0, mn = INT_MAX, mx = -1, bad = 0, runs = 0;
+        if (row < n) {
+            int32_t s = brp[row], e = brp[row + 1];
+            if (s < 0 || e < s || (int64_t)e > bnnz || (row == 0 && s != 0) ||
+                (row == n - 1 && (int64_t)e != bnnz)) {
+                bad = ERR_B_ROWPTR;
+            } else {
+                len = e - s;
+                for (int32_t q = s + lane; q < e; q += ROW_LANES) {
+                    int c = bci[q];
+                    if (c < 0 || c >= k) { bad = ERR_B_COL; continue; }
+                    mn = min(mn, c);
+                    mx = max(mx, c);
+                    runs += q == s || (bci[q - 1] >> 5) != (c >> 5);
+                }
             }
         }
+        mn = xor_reduce_min(mn);
+        mx = xor_reduce_max(mx);
+        runs = xor_reduce_sum(runs);
+        int anybad = xor_reduce_sum(bad);
+        if (row < n && lane == 0) {
+            if (anybad) len = 0, mn = INT_MAX, mx = -1, runs = 0;
+            binfo[row] = make_int4(len, mn, mx, runs);
+            if (runs) atomicAdd(&runs_sum, (unsigned long long)runs);
+        }
+        if (bad) atomicOr(&ctl->err, bad);
     }
-    mn = xor_reduce_min(mn);
-    mx = xor_reduce_max(mx);
-    int anybad = xor_reduce_sum(bad);
-    if (row < n && lane == 0) {
-        if (anybad) len = 0, mn = INT_MAX, mx = -1;
-        binfo[row] = make_int4(len, mn, mx, 0);
-    }
-    if (bad) atomicOr(&ctl->err, bad);
+    __syncthreads();
+    if (threadIdx.x == 0 && runs_sum) atomicAdd((unsigned long long*)&ctl->bc_total, runs_sum);
 }
 
 __device__ inline float log2p1(int64_t v) { return log2f(1.0f + (float)v); }
@@ -426,6 +439,91 @@ __global__ __launch_bounds__(256) void k_pack(int32_t count, const int64_t* __re
     }
 }
 
+// Exclusive scan of the run counts (binfo[j].w) into compressed B's row
+// pointer, single pass with decoupled look-back (same scheme as k_scan).
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_runs(int32_t n, const int4* __restrict__ binfo,
+                                                            int32_t* __restrict__ bcrp, uint64_t* tile_status,
+                                                            int32_t* tile_counter) {
+    __shared__ int32_t tile_sh;
+    __shared__ int64_t wsum[SCAN_THREADS / 64];
+    __shared__ int64_t tile_prefix;
+    if (threadIdx.x == 0) tile_sh = atomicAdd(tile_counter, 1);
+    __syncthreads();
+    const int tile = tile_sh;
+    const int64_t r0 = (int64_t)tile * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    int64_t v[SCAN_ITEMS];
+    int64_t run = 0;
+#pragma unroll
+    for (int t = 0; t < SCAN_ITEMS; ++t) {
+        const int64_t r = r0 + t;
+        run += r < n ? binfo[r].w : 0;
+        v[t] = run;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int64_t x = run;
+    for (int d = 1; d < 64; d <<= 1) {
+        int64_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    int64_t wpre = 0, agg = 0;
+    for (int u = 0; u < SCAN_THREADS / 64; ++u) {
+        if (u < wv) wpre += wsum[u];
+        agg += wsum[u];
+    }
+    if (threadIdx.x == 0) {
+        int64_t prefix = 0;
+        if (tile == 0) {
+            __hip_atomic_store(&tile_status[0], ST_PRE | (uint64_t)agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(&tile_status[tile], ST_AGG | (uint64_t)agg, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            for (int t = tile - 1; t >= 0; --t) {
+                uint64_t st;
+                do {
+                    st = __hip_atomic_load(&tile_status[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                } while ((st >> 62) == 0);
+                prefix += (int64_t)(st & ST_VAL);
+                if ((st >> 62) == 2) break;
+            }
+            __hip_atomic_store(&tile_status[tile], ST_PRE | (uint64_t)(prefix + agg), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        tile_prefix = prefix;
+    }
+    __syncthreads();
+    const int64_t base = tile_prefix + wpre + x - run;
+#pragma unroll
+    for (int t = 0; t < SCAN_ITEMS; ++t) {
+        const int64_t r = r0 + t;
+        if (r < n) bcrp[r + 1] = (int32_t)(base + v[t]);
+    }
+    if (tile == 0 && threadIdx.x == 0) bcrp[0] = 0;
+}
+
+// Writes each B row's runs: {block id, OR of the bits of its columns}.
+__global__ __launch_bounds__(256) void k_compress_b(int32_t n, const int32_t* __restrict__ brp,
+                                                    const int32_t* __restrict__ bci, const int32_t* __restrict__ bcrp,
+                                                    int2* __restrict__ bc) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t s = brp[j], e = brp[j + 1];
+        int32_t o = bcrp[j];
+        int cur = -1;
+        uint32_t mask = 0;
+        for (int32_t q = s; q < e; ++q) {
+            const int c = bci[q];
+            if ((c >> 5) != cur) {
+                if (cur >= 0) bc[o++] = make_int2(cur, (int)mask);
+                cur = c >> 5;
+                mask = 0;
+            }
+            mask |= 1u << (c & 31);
+        }
+        if (cur >= 0) bc[o] = make_int2(cur, (int)mask);
+    }
+}
+
 inline unsigned grid_for(int64_t threads, int per_block) {
     int64_t g = (threads + per_block - 1) / per_block;
     return (unsigned)(g < 1 ? 1 : g);
@@ -459,8 +557,20 @@ void launch_fill_u8(hipStream_t s, void* p, uint8_t v, int64_t bytes) {
 void launch_b_rowinfo(hipStream_t s, int32_t n, int32_t k, const int32_t* brp, const int32_t* bci, int64_t bnnz,
                       int4* binfo, Control* ctl) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_b_rowinfo, dim3(grid_for((int64_t)n * ROW_LANES, 256)), dim3(256), 0, s, n, k, brp, bci,
-                       bnnz, binfo, ctl);
+    hipLaunchKernelGGL(k_b_rowinfo, dim3(std::min(grid_for((int64_t)n * ROW_LANES, 256), 1024u)), dim3(256), 0, s, n,
+                       k, brp, bci, bnnz, binfo, ctl);
+}
+
+void launch_compress_b(hipStream_t s, int32_t n, const int32_t* brp, const int32_t* bci, const int4* binfo,
+                       int32_t* bcrp, uint64_t* tile_status, int32_t* tile_counter, int2* bc) {
+    if (n <= 0) {
+        launch_fill_i32(s, bcrp, 0, 1);
+        return;
+    }
+    launch_fill_u8(s, tile_status, 0, (scan_tiles(n) + 1) * 8);
+    hipLaunchKernelGGL(k_scan_runs, dim3((unsigned)scan_tiles(n)), dim3(SCAN_THREADS), 0, s, n, binfo, bcrp,
+                       tile_status, tile_counter);
+    hipLaunchKernelGGL(k_compress_b, dim3(std::min(grid_for(n, 256), 4096u)), dim3(256), 0, s, n, brp, bci, bcrp, bc);
 }
 
 void launch_a_rowinfo(hipStream_t s, int32_t m, int32_t n, const int32_t* arp, const int32_t* aci, int64_t annz,
