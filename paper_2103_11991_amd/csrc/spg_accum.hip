@@ -26,6 +26,9 @@
 // atomics straight into C's value array.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "spg_internal.h"
 
 namespace spg {
@@ -197,28 +200,194 @@ __device__ inline void walk_products(int a0, int a1, const int32_t* __restrict__
     }
 }
 
+// ------------------------------------------------------- flat product mapping
+// The row kernels stage a chunk of up to G nonzeros of A's row and number
+// the products of the chunk 0..P-1 in A order (entry e's B row takes products
+// pb_e .. pb_e + len_e - 1).  A batch hands lane l the products
+// P0 + l + G*k, k < K: every lane busy, consecutive lanes on consecutive
+// entries of one B row (coalesced), and all K loads of a lane issued at once.
+// The entry owning product p comes from a window table: per window of G
+// products (and per wavefront of the group) a mask of the positions where a
+// staged entry's products begin and the number of entries begun earlier, so
+//     entry(p) = cum + popcount(mask & lanes_at_or_below) - 1.
+// Compressed-B runs are numbered and handed out the same way.
+
+struct Win {
+    unsigned long long mask;
+    int cum;
+    int pad;
+};
+
+template <int G>
+constexpr int waves_of() {
+    return G > 64 ? G / 64 : 1;
+}
+
+// Workgroups are spread round-robin over the XCDs; renumber them so that
+// each XCD takes a contiguous range of rows (its L2 then holds the B rows
+// that neighbouring rows share).  A bijection of [0, nblk).
+__device__ inline int xcd_block(int b, int nblk) {
+    constexpr int NXCD = 8;
+    const int q = nblk / NXCD, r = nblk % NXCD;
+    const int x = b % NXCD, k = b / NXCD;
+    return x * q + min(x, r) + k;
+}
+
+template <int G>
+__device__ inline int3 group_excl_scan3(int3 v, int3& total, int* red) {
+    if constexpr (G <= 64) {
+        const int lane = threadIdx.x % G;
+        int3 x = v;
+        for (int d = 1; d < G; d <<= 1) {
+            const int yx = __shfl_up(x.x, d, G), yy = __shfl_up(x.y, d, G), yz = __shfl_up(x.z, d, G);
+            if (lane >= d) x.x += yx, x.y += yy, x.z += yz;
+        }
+        total = make_int3(__shfl(x.x, G - 1, G), __shfl(x.y, G - 1, G), __shfl(x.z, G - 1, G));
+        return make_int3(x.x - v.x, x.y - v.y, x.z - v.z);
+    } else {
+        constexpr int W = G / 64;
+        const int wl = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        int3 x = v;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int yx = __shfl_up(x.x, d, 64), yy = __shfl_up(x.y, d, 64), yz = __shfl_up(x.z, d, 64);
+            if (wl >= d) x.x += yx, x.y += yy, x.z += yz;
+        }
+        __syncthreads();
+        if (wl == 63) red[3 * wv] = x.x, red[3 * wv + 1] = x.y, red[3 * wv + 2] = x.z;
+        __syncthreads();
+        int3 pre = make_int3(0, 0, 0), tot = make_int3(0, 0, 0);
+        for (int u = 0; u < W; ++u) {
+            const int3 t = make_int3(red[3 * u], red[3 * u + 1], red[3 * u + 2]);
+            if (u < wv) pre.x += t.x, pre.y += t.y, pre.z += t.z;
+            tot.x += t.x, tot.y += t.y, tot.z += t.z;
+        }
+        total = tot;
+        return make_int3(pre.x + x.x - v.x, pre.y + x.y - v.y, pre.z + x.z - v.z);
+    }
+}
+
+// Sets the start bit of a staged entry whose first product p0 falls in the
+// batch [P0, P0 + K*G).
+template <int G, int K>
+__device__ inline void win_mark(Win* win, bool ne, int p0, int P0) {
+    constexpr int W = waves_of<G>();
+    const int d = p0 - P0;
+    if (ne && d >= 0 && d < K * G) {
+        const int dl = d % G;
+        atomicOr(&win[(d / G) * W + (dl >> 6)].mask, 1ull << (dl & 63));
+    }
+}
+
+// Fills the cum fields of two window tables (KA and KB windows) from their
+// masks: exclusive prefix of popcounts in order, plus the entries begun
+// before each batch (before_a, before_b).  Both counts stay below 2^16.
+template <int G, int KA, int KB>
+__device__ inline void win_scan(Win* wa, Win* wb, int before_a, int before_b, int lane, int* red) {
+    constexpr int W = waves_of<G>();
+    constexpr int NA = KA * W, NB = KB * W;
+    constexpr int CA = (NA + G - 1) / G, CB = (NB + G - 1) / G;
+    int local = 0;
+#pragma unroll
+    for (int t = 0; t < CA; ++t)
+        if (lane * CA + t < NA) local += __popcll(wa[lane * CA + t].mask);
+#pragma unroll
+    for (int t = 0; t < CB; ++t)
+        if (lane * CB + t < NB) local += __popcll(wb[lane * CB + t].mask) << 16;
+    int total;
+    const int ex = group_excl_scan<G>(local, total, red);
+    int ca = before_a + (ex & 0xffff), cb = before_b + (ex >> 16);
+#pragma unroll
+    for (int t = 0; t < CA; ++t)
+        if (lane * CA + t < NA) {
+            wa[lane * CA + t].cum = ca;
+            ca += __popcll(wa[lane * CA + t].mask);
+        }
+#pragma unroll
+    for (int t = 0; t < CB; ++t)
+        if (lane * CB + t < NB) {
+            wb[lane * CB + t].cum = cb;
+            cb += __popcll(wb[lane * CB + t].mask);
+        }
+}
+
+template <int G, int K>
+__device__ inline void win_clear(Win* win, int lane) {
+    constexpr int NW = K * waves_of<G>();
+    for (int t = lane; t < NW; t += G) win[t] = Win{0ull, 0, 0};
+}
+
+// Staged entry index of the lane's product in window k of the batch.
+template <int G>
+__device__ inline int win_entry(const Win* win, int k, int wv, unsigned long long le) {
+    const Win w = win[k * waves_of<G>() + wv];
+    return w.cum + __popcll(w.mask & le) - 1;
+}
+
+// One batch: issue the K loads of the lane (slot k holds product
+// P0 + lane + G*k when below P), then hand each to apply(value, entry).
+// FIELD 0 takes the B offset of the entry (ent.x), 1 the run offset (ent.y).
+template <int G, int K, int FIELD, typename Load>
+struct Batch {
+    using V = decltype(std::declval<Load>()(0));
+    V v[K];
+    __device__ inline void issue(const int4* ent, const Win* win, int P0, int P, int lane, int wv,
+                                 unsigned long long le, Load& load) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int p = P0 + k * G + lane;
+            if (p < P) {
+                const int4 en = ent[win_entry<G>(win, k, wv, le)];
+                v[k] = load((FIELD == 0 ? en.x : en.y) + p);
+            }
+        }
+    }
+    // the entry is looked up again here rather than held in a register
+    // across the wait (the window table is unchanged until then)
+    template <typename Apply>
+    __device__ inline void consume(const Win* win, int P0, int P, int lane, int wv, unsigned long long le,
+                                   Apply& apply) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (P0 + k * G + lane < P) apply(v[k], win_entry<G>(win, k, wv, le));
+    }
+};
+
+// Staged chunk of A's row, kept in the lanes' registers while it is in use.
+struct Chunk {
+    int pb, pc;      // first product / first run of the lane's entry
+    bool ne;         // the entry's B row is nonempty
+    int nr, P, PC;   // nonempty entries, products and runs of the chunk
+};
+
 // ------------------------------------------------------------------ symbolic
 // Every entry of compressed B is a {block, mask} run: the row's table gets
 // the mask OR-ed in, and the bits that were not yet set (and blocks that were
 // empty) are counted from the value the atomic OR returns.
 
 template <int G, int MODE>
-__global__ __launch_bounds__(G * rows_per_wg<G>()) void k_sym(SymArgs a) {
+// (up to 128 lanes per row the symbolic kernel fits 64 VGPRs: full occupancy)
+__global__ __launch_bounds__(G * rows_per_wg<G>()) __attribute__((amdgpu_waves_per_eu(G <= 128 ? 8 : 4)))
+void k_sym(SymArgs a) {
     constexpr int RPW = rows_per_wg<G>();
+    constexpr int KC = FLAT_KC;
     extern __shared__ __align__(16) uint32_t smem[];
-    __shared__ int red[16];
+    __shared__ int red[48];
     __shared__ int occ[RPW];
     __shared__ int ovf[RPW];
     const int bytes = tier_bytes(a.tier);
-    const int per_row = bytes + G * 8;
-    const int sub = threadIdx.x / G, lane = threadIdx.x % G;
-    const int vec = a.vec < G ? a.vec : G;
-    const int slot = blockIdx.x * RPW + sub;
+    const int per_row = bytes + sym_stage_bytes(G);
+    // a group of 64 or more lanes owns whole wavefronts: its row is wave-uniform
+    const int sub = G >= 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / G) : threadIdx.x / G;
+    const int lane = threadIdx.x % G, wv = lane >> 6;
+    const unsigned long long le = (2ull << (lane & 63)) - 1;
+    const int slot = xcd_block(blockIdx.x, gridDim.x) * RPW + sub;
     if (slot >= a.count) return;  // uniform in the group (in the workgroup when G >= 128)
     const int i = a.perm[slot];
+    const int a0 = a.arp[i], a1 = a.arp[i + 1];
     uint8_t* row_lds = reinterpret_cast<uint8_t*>(smem) + (size_t)sub * per_row;
     uint32_t* tab = reinterpret_cast<uint32_t*>(row_lds);
-    int2* st = reinterpret_cast<int2*>(row_lds + bytes);
+    int4* ent = reinterpret_cast<int4*>(row_lds + bytes);
+    Win* win = reinterpret_cast<Win*>(row_lds + bytes + 16 * G);
     int base = 0, ncell, T = 0, logT = 0;
     int32_t* keys = reinterpret_cast<int32_t*>(tab);
     uint32_t* masks = tab;
@@ -241,38 +410,77 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_sym(SymArgs a) {
             *reinterpret_cast<uint4*>(&masks[c]) = make_uint4(0, 0, 0, 0);
         }
     }
+    win_clear<G, KC>(win, lane);
     if (lane == 0) occ[sub] = 0, ovf[sub] = 0;
     group_sync<G>();
     int cnt = 0, nb = 0;
     const int occ_max = (T * 3) / 4;
-    walk_products<G>(
-        a.arp[i], a.arp[i + 1], a.aci, a.bcrp, lane, vec, st, [](int, int) {}, [&](int q) { return a.bc[q]; },
-        [&](int2 run, int) {
-            const uint32_t bits = (uint32_t)run.y;
-            int cell;
-            if constexpr (MODE == MODE_DIRECT) {
-                cell = run.x - base;
-            } else {
-                if (*(volatile int*)&ovf[sub]) return;
-                bool ins;
-                cell = hash_insert(keys, T, logT, run.x, ins);
-                if (cell < 0) {
-                    ovf[sub] = 1;
-                    return;
-                }
-                if (ins && atomicAdd(&occ[sub], 1) >= occ_max) ovf[sub] = 1;
+    auto load_run = [&](int q) { return a.bc[q]; };
+    auto apply = [&](int2 run, int) {
+        const uint32_t bits = (uint32_t)run.y;
+        int cell;
+        if constexpr (MODE == MODE_DIRECT) {
+            cell = run.x - base;
+        } else {
+            if (*(volatile int*)&ovf[sub]) return;
+            bool ins;
+            cell = hash_insert(keys, T, logT, run.x, ins);
+            if (cell < 0) {
+                ovf[sub] = 1;
+                return;
             }
-            const uint32_t old = atomicOr(&masks[cell], bits);
-            cnt += __popc(bits & ~old);
-            nb += old == 0;
-        });
+            if (ins && atomicAdd(&occ[sub], 1) >= occ_max) ovf[sub] = 1;
+        }
+        const uint32_t old = atomicOr(&masks[cell], bits);
+        cnt += __popc(bits & ~old);
+        nb += old == 0;
+    };
+    for (int e0 = a0; e0 < a1; e0 += G) {
+        if (e0 > a0) {
+            group_sync<G>();
+            win_clear<G, KC>(win, lane);
+            group_sync<G>();
+        }
+        // stage: the chunk's nonempty entries in order, numbered runs
+        int4 h = make_int4(0, 0, 0, 0);
+        if (lane < a1 - e0) h = a.bhdr[a.aci[e0 + lane]];
+        const bool ne = h.w > 0;
+        int3 tot;
+        const int3 ex = group_excl_scan3<G>(make_int3(ne, h.w, 0), tot, red);
+        if (ne) ent[ex.x] = make_int4(0, h.z - ex.y, 0, ex.y);
+        win_mark<G, KC>(win, ne, ex.y, 0);
+        group_sync<G>();
+        win_scan<G, KC, 0>(win, nullptr, 0, 0, lane, red);
+        group_sync<G>();
+        for (int P0 = 0; P0 < tot.y; P0 += KC * G) {
+            if (P0 > 0) {
+                group_sync<G>();
+                win_clear<G, KC>(win, lane);
+                group_sync<G>();
+                win_mark<G, KC>(win, ne, ex.y, P0);
+                const int before = group_sum<G>(ne && ex.y < P0, red);
+                group_sync<G>();
+                win_scan<G, KC, 0>(win, nullptr, before, 0, lane, red);
+                group_sync<G>();
+            }
+            Batch<G, KC, 1, decltype(load_run)> bt;
+            bt.issue(ent, win, P0, tot.y, lane, wv, le, load_run);
+            bt.consume(win, P0, tot.y, lane, wv, le, apply);
+        }
+    }
     cnt = group_sum<G>(cnt, red);
     nb = group_sum<G>(nb, red);
     group_sync<G>();
     if (lane == 0) {
         if (MODE == MODE_HASHED && ovf[sub]) {
-            const int pos = atomicAdd(&a.ctl->overflow_rows, 1);
-            a.ovf_list[pos] = i;
+            // queued for the exact retry; a table sized from an upper bound
+            // (no retry list) cannot overflow, so that would be an internal error
+            if (a.ovf_list) {
+                const int pos = atomicAdd(&a.ctl->overflow_rows, 1);
+                a.ovf_list[pos] = i;
+            } else {
+                atomicOr(&a.ctl->err, ERR_TABLE_OVERFLOW);
+            }
         } else {
             a.row_nnz[i] = cnt;
             a.row_blocks[i] = nb;
@@ -364,30 +572,36 @@ __device__ inline uint32_t below(int b) { return (1u << b) - 1u; }
 template <int G, int MODE, typename T>
 __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     constexpr int RPW = rows_per_wg<G>();
+    constexpr int W = waves_of<G>();
+    constexpr int KB = sizeof(T) == 8 ? FLAT_KB_F64 : FLAT_KB_F32;
+    constexpr int KC = sizeof(T) == 8 ? FLAT_KC_F64 : FLAT_KC_F32;
     extern __shared__ __align__(16) uint32_t smem[];
-    __shared__ int red[16];
+    __shared__ int red[48];
     __shared__ int ncompact[RPW];
     const int bytes = tier_bytes(a.tier);
-    const int per_row = bytes + G * 24;
-    const int sub = threadIdx.x / G, lane = threadIdx.x % G;
-    const int vec = a.vec < G ? a.vec : G;
-    const int vecc = a.vecc < G ? a.vecc : G;
-    const int slot = blockIdx.x * RPW + sub;
+    const int per_row = bytes + stage_bytes(G);
+    // a group of 64 or more lanes owns whole wavefronts: its row is wave-uniform
+    const int sub = G >= 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / G) : threadIdx.x / G;
+    const int lane = threadIdx.x % G, wv = lane >> 6;
+    const unsigned long long le = (2ull << (lane & 63)) - 1;
+    const int slot = xcd_block(blockIdx.x, gridDim.x) * RPW + sub;
     if (slot >= a.count) return;
     const int i = a.perm[slot];
-    uint8_t* row_lds = reinterpret_cast<uint8_t*>(smem) + (size_t)sub * per_row;
-    uint8_t* tab = row_lds;
-    int2* stc = reinterpret_cast<int2*>(row_lds + bytes);              // compressed-B staging
-    int2* stb = reinterpret_cast<int2*>(row_lds + bytes + G * 8);      // B staging
-    T* ast = reinterpret_cast<T*>(row_lds + bytes + G * 16);           // A values
     const int off = a.crp[i];
     const int n = a.crp[i + 1] - off;
     const RowInfo ri = a.rinfo[i];
+    const int nb = a.row_blocks[i];
+    const int a0 = a.arp[i], a1 = a.arp[i + 1];
     const int base = ri.x >> 5;
     const int words = (ri.y >> 5) - base + 1;
-    const int nb = a.row_blocks[i];
     const int nb4 = (nb + 3) & ~3;
     const int w1 = (words + 31) >> 5;
+    uint8_t* row_lds = reinterpret_cast<uint8_t*>(smem) + (size_t)sub * per_row;
+    uint8_t* tab = row_lds;
+    int4* ent = reinterpret_cast<int4*>(row_lds + bytes);           // staged entries
+    T* ava = reinterpret_cast<T*>(row_lds + bytes + G * 16);         // their A values
+    Win* winb = reinterpret_cast<Win*>(row_lds + bytes + G * 24);    // product windows
+    Win* winc = winb + FLAT_KB_F32 * W;                              // run windows
     // direct: {mask, prefix} per word.  two-level: l1 {bits, prefix} per 32
     // blocks, cm {mask, prefix} and blk per occupied block.  hashed: slots,
     // compact keys (padded), their slots, slots in block order.
@@ -416,7 +630,6 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
         vals = reinterpret_cast<T*>(tab + align8((int64_t)TT * 16 + (int64_t)nb4 * 4 + (int64_t)nb * 8));
         items = nb;
     }
-    int32_t* colbuf = reinterpret_cast<int32_t*>(vals + n);
     if constexpr (MODE == MODE_DIRECT) {
         // pairs of words per 16-byte store; an odd last word spills 8 bytes into vals, cleared below
         for (int c = 2 * lane; c < words; c += 2 * G) *reinterpret_cast<uint4*>(&dw[c]) = make_uint4(0, 0, 0, 0);
@@ -426,176 +639,245 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
         for (int c = lane; c < TT; c += G) slots[c] = make_int4(-1, 0, 0, 0);
     }
     for (int r = lane; r < n; r += G) vals[r] = T(0);
+    win_clear<G, KB>(winb, lane);
+    win_clear<G, KC>(winc, lane);
     if (lane == 0) ncompact[sub] = 0;
+    group_sync<G>();
 
-    const int a0 = a.arp[i], a1 = a.arp[i + 1];
     const T* av = reinterpret_cast<const T*>(a.av);
     const T* bv = reinterpret_cast<const T*>(a.bv);
-    // a row whose A nonzeros fit one chunk is staged once for all passes
-    const bool one_chunk = a1 - a0 <= G;
-    auto load_run = [&](int q) { return a.bc[q]; };
-    auto nothing = [](int, int) {};
-    auto walk_runs = [&](auto&& apply) {
-        if (one_chunk) walk_chunk<G>(a1 - a0, lane, vecc, stc, load_run, apply);
-        else walk_products<G>(a0, a1, a.aci, a.bcrp, lane, vecc, stc, nothing, load_run, apply);
+    // ---- staging (chunks of G entries of A's row; window tables of one batch each)
+    Chunk ch;
+    int staged = -1;         // first A entry of the staged chunk
+    int wb0 = 0, wc0 = 0;    // batch held by each window table
+    auto stage = [&](int e0) {  // window tables cleared and synchronised by the caller
+        int4 h = make_int4(0, 0, 0, 0);
+        T v = T(0);
+        if (lane < a1 - e0) {
+            h = a.bhdr[a.aci[e0 + lane]];
+            v = av[e0 + lane];
+        }
+        ch.ne = h.y > 0;
+        int3 tot;
+        const int3 ex = group_excl_scan3<G>(make_int3(ch.ne, h.y, h.w), tot, red);
+        ch.pb = ex.y, ch.pc = ex.z, ch.nr = tot.x, ch.P = tot.y, ch.PC = tot.z;
+        if (ch.ne) {
+            ent[ex.x] = make_int4(h.x - ex.y, h.z - ex.z, ex.y, ex.z);
+            ava[ex.x] = v;
+        }
+        win_mark<G, KB>(winb, ch.ne, ch.pb, 0);
+        win_mark<G, KC>(winc, ch.ne, ch.pc, 0);
+        group_sync<G>();
+        win_scan<G, KB, KC>(winb, winc, 0, 0, lane, red);
+        group_sync<G>();
+        staged = e0, wb0 = 0, wc0 = 0;
     };
-    if (one_chunk) {
-        if (lane < a1 - a0) {
-            const int j = a.aci[a0 + lane];
-            const int c0 = a.bcrp[j], b0 = a.brp[j];
-            stc[lane] = make_int2(c0, a.bcrp[j + 1] - c0);
-            stb[lane] = make_int2(b0, a.brp[j + 1] - b0);
-            ast[lane] = av[a0 + lane];
-        }
-    }
-    group_sync<G>();
-    // pass 1: which columns occur
-    if constexpr (MODE == MODE_TWOLEVEL) {
-        walk_runs([&](int2 run, int) {
-            const int w = run.x - base;
-            atomicOr(&l1[w >> 5].x, 1u << (w & 31));
-        });
+    auto restage = [&](int e0) {
+        if (staged == e0) return;
         group_sync<G>();
-        // compact index of each occupied block: prefix of popcounts over l1
-        {
-            const int chunk = (w1 + G - 1) / G;
-            const int beg = lane * chunk;
-            const int end = min(beg + chunk, w1);
-            int local = 0;
-            for (int t = beg; t < end; ++t) local += __popc(l1[t].x);
-            int total;
-            int ex = group_excl_scan<G>(local, total, red);
-            for (int t = beg; t < end; ++t) {
-                l1[t].y = (uint32_t)ex;
-                ex += __popc(l1[t].x);
-            }
-        }
+        win_clear<G, KB>(winb, lane);
+        win_clear<G, KC>(winc, lane);
         group_sync<G>();
-        walk_runs([&](int2 run, int) {
-            const int w = run.x - base;
-            const uint2 L = l1[w >> 5];
-            const int ci = (int)L.y + __popc(L.x & below(w & 31));
-            atomicOr(&cm[ci].x, (uint32_t)run.y);
-            blk[ci] = run.x;
-        });
-    } else {
-        walk_runs([&](int2 run, int) {
-            if constexpr (MODE == MODE_DIRECT) {
-                atomicOr(&dw[run.x - base].x, (uint32_t)run.y);
-            } else {
-                const int h = slot_insert(slots, TT, logT, run.x);
-                atomicOr(reinterpret_cast<unsigned int*>(&slots[h].y), (uint32_t)run.y);
-            }
-        });
-    }
-    group_sync<G>();
-    if constexpr (MODE == MODE_HASHED) {
-        // occupied blocks in ascending order: compact, then rank by count
-        for (int c = lane; c < TT; c += G) {
-            const int4 sl = slots[c];
-            if (sl.y) {
-                const int pos = atomicAdd(&ncompact[sub], 1);
-                ck[pos] = sl.x;
-                cs[pos] = c;
-            }
-        }
-        for (int e = nb + lane; e < nb4; e += G) ck[e] = 0x7fffffff;
+        stage(e0);
+    };
+    // window table of one field rebuilt for the batch starting at P0
+    auto rewin = [&](auto field, int P0) {
+        constexpr int F = decltype(field)::value;
+        constexpr int K = F == 0 ? KB : KC;
+        Win* win = F == 0 ? winb : winc;
+        int& held = F == 0 ? wb0 : wc0;
+        if (held == P0) return;
+        const int p0 = F == 0 ? ch.pb : ch.pc;
         group_sync<G>();
-        const int4* ck4 = reinterpret_cast<const int4*>(ck);
-        for (int e = lane; e < nb; e += G) {
-            const int key = ck[e];
-            int r = 0;
-            for (int f = 0; f < nb4 / 4; ++f) {
-                const int4 k4 = ck4[f];
-                r += (k4.x < key) + (k4.y < key) + (k4.z < key) + (k4.w < key);
-            }
-            ord[r] = cs[e];
-        }
+        win_clear<G, K>(win, lane);
         group_sync<G>();
-    }
-    // exclusive prefix of popcounts over occupied blocks in ascending order
-    {
-        const int chunk = (items + G - 1) / G;
-        const int beg = lane * chunk;
-        const int end = min(beg + chunk, items);
-        int local = 0;
-        for (int t = beg; t < end; ++t) {
-            if constexpr (MODE == MODE_DIRECT) local += __popc(dw[t].x);
-            else if constexpr (MODE == MODE_TWOLEVEL) local += __popc(cm[t].x);
-            else local += __popc((uint32_t)slots[ord[t]].y);
-        }
-        int total;
-        int ex = group_excl_scan<G>(local, total, red);
-        for (int t = beg; t < end; ++t) {
-            if constexpr (MODE == MODE_DIRECT) {
-                dw[t].y = (uint32_t)ex;
-                ex += __popc(dw[t].x);
-            } else if constexpr (MODE == MODE_TWOLEVEL) {
-                cm[t].y = (uint32_t)ex;
-                ex += __popc(cm[t].x);
-            } else {
-                const int cl = ord[t];
-                slots[cl].z = ex;
-                ex += __popc((uint32_t)slots[cl].y);
-            }
-        }
-    }
-    group_sync<G>();
-    // pass 2: add every product at its column's rank
+        win_mark<G, K>(win, ch.ne, p0, P0);
+        const int before = group_sum<G>(ch.ne && p0 < P0, red);
+        group_sync<G>();
+        win_scan<G, K, 0>(win, nullptr, before, 0, lane, red);
+        group_sync<G>();
+        held = P0;
+    };
+    auto load_run = [&](int q) { return a.bc[q]; };
     struct CV {
         int c;
         T y;
     };
     auto load_cv = [&](int q) { return CV{a.bci[q], bv[q]}; };
-    auto add_pass = [&](const CV& v, int e) {
-        int rank;
-        if constexpr (MODE == MODE_DIRECT) {
-            const uint2 mp = dw[(v.c >> 5) - base];
-            rank = (int)mp.y + __popc(mp.x & below(v.c & 31));
-        } else if constexpr (MODE == MODE_TWOLEVEL) {
-            const int w = (v.c >> 5) - base;
-            const uint2 L = l1[w >> 5];
-            const uint2 mp = cm[(int)L.y + __popc(L.x & below(w & 31))];
-            rank = (int)mp.y + __popc(mp.x & below(v.c & 31));
-        } else {
-            const int key = v.c >> 5;
-            int h = hash_slot(key, logT);
-            int4 sl = slots[h];
-            for (int probe = 1; sl.x != key && probe < TT; ++probe) {
-                h = (h + 1) & (TT - 1);
-                sl = slots[h];
+    auto walk_runs = [&](auto&& apply) {
+        for (int e0 = a0; e0 < a1; e0 += G) {
+            restage(e0);
+            for (int P0 = 0; P0 < ch.PC; P0 += KC * G) {
+                rewin(std::integral_constant<int, 1>{}, P0);
+                Batch<G, KC, 1, decltype(load_run)> bt;
+                bt.issue(ent, winc, P0, ch.PC, lane, wv, le, load_run);
+                bt.consume(winc, P0, ch.PC, lane, wv, le, apply);
             }
-            rank = sl.z + __popc((uint32_t)sl.y & below(v.c & 31));
         }
-        atomicAdd(&vals[rank], ast[e] * v.y);
     };
-    if (one_chunk) walk_chunk<G>(a1 - a0, lane, vec, stb, load_cv, add_pass);
-    else walk_products<G>(a0, a1, a.aci, a.brp, lane, vec, stb, [&](int e, int p) { ast[e] = av[p]; }, load_cv,
-                          add_pass);
-    // column of every rank, from the masks
-    for (int t = lane; t < items; t += G) {
-        uint32_t mk;
-        int r, b;
-        if constexpr (MODE == MODE_DIRECT) {
-            const uint2 mp = dw[t];
-            mk = mp.x, r = (int)mp.y, b = base + t;
-        } else if constexpr (MODE == MODE_TWOLEVEL) {
-            const uint2 mp = cm[t];
-            mk = mp.x, r = (int)mp.y, b = blk[t];
+    auto walk_b = [&](auto&& apply) {
+        for (int e0 = a0; e0 < a1; e0 += G) {
+            restage(e0);
+            for (int P0 = 0; P0 < ch.P; P0 += KB * G) {
+                rewin(std::integral_constant<int, 0>{}, P0);
+                Batch<G, KB, 0, decltype(load_cv)> bt;
+                bt.issue(ent, winb, P0, ch.P, lane, wv, le, load_cv);
+                bt.consume(winb, P0, ch.P, lane, wv, le, apply);
+            }
+        }
+    };
+
+    // ---- pass 1: which columns occur; prefix; pass 2: values at their ranks
+    auto finish = [&](auto&& runs, auto&& bwalk) {
+        if constexpr (MODE == MODE_TWOLEVEL) {
+            runs([&](int2 run, int) {
+                const int w = run.x - base;
+                atomicOr(&l1[w >> 5].x, 1u << (w & 31));
+            });
+            group_sync<G>();
+            // compact index of each occupied block: prefix of popcounts over l1
+            {
+                const int chunk = (w1 + G - 1) / G;
+                const int beg = lane * chunk;
+                const int end = min(beg + chunk, w1);
+                int local = 0;
+                for (int t = beg; t < end; ++t) local += __popc(l1[t].x);
+                int total;
+                int ex = group_excl_scan<G>(local, total, red);
+                for (int t = beg; t < end; ++t) {
+                    l1[t].y = (uint32_t)ex;
+                    ex += __popc(l1[t].x);
+                }
+            }
+            group_sync<G>();
+            runs([&](int2 run, int) {
+                const int w = run.x - base;
+                const uint2 L = l1[w >> 5];
+                const int ci = (int)L.y + __popc(L.x & below(w & 31));
+                atomicOr(&cm[ci].x, (uint32_t)run.y);
+                blk[ci] = run.x;
+            });
         } else {
-            const int4 sl = slots[ord[t]];
-            mk = (uint32_t)sl.y, r = sl.z, b = sl.x;
+            runs([&](int2 run, int) {
+                if constexpr (MODE == MODE_DIRECT) {
+                    atomicOr(&dw[run.x - base].x, (uint32_t)run.y);
+                } else {
+                    const int h = slot_insert(slots, TT, logT, run.x);
+                    atomicOr(reinterpret_cast<unsigned int*>(&slots[h].y), (uint32_t)run.y);
+                }
+            });
         }
-        while (mk) {
-            colbuf[r++] = (b << 5) + (__ffs(mk) - 1);
-            mk &= mk - 1;
+        group_sync<G>();
+        if constexpr (MODE == MODE_HASHED) {
+            // occupied blocks in ascending order: compact, then rank by count
+            for (int c = lane; c < TT; c += G) {
+                const int4 sl = slots[c];
+                if (sl.y) {
+                    const int pos = atomicAdd(&ncompact[sub], 1);
+                    ck[pos] = sl.x;
+                    cs[pos] = c;
+                }
+            }
+            for (int e = nb + lane; e < nb4; e += G) ck[e] = 0x7fffffff;
+            group_sync<G>();
+            const int4* ck4 = reinterpret_cast<const int4*>(ck);
+            for (int e = lane; e < nb; e += G) {
+                const int key = ck[e];
+                int r = 0;
+                for (int f = 0; f < nb4 / 4; ++f) {
+                    const int4 k4 = ck4[f];
+                    r += (k4.x < key) + (k4.y < key) + (k4.z < key) + (k4.w < key);
+                }
+                ord[r] = cs[e];
+            }
+            group_sync<G>();
         }
-    }
-    group_sync<G>();
-    T* cv = reinterpret_cast<T*>(a.cval);
-    for (int r = lane; r < n; r += G) {
-        a.ccol[off + r] = colbuf[r];
-        cv[off + r] = vals[r];
+        // exclusive prefix of popcounts over occupied blocks in ascending order
+        {
+            const int chunk = (items + G - 1) / G;
+            const int beg = lane * chunk;
+            const int end = min(beg + chunk, items);
+            int local = 0;
+            for (int t = beg; t < end; ++t) {
+                if constexpr (MODE == MODE_DIRECT) local += __popc(dw[t].x);
+                else if constexpr (MODE == MODE_TWOLEVEL) local += __popc(cm[t].x);
+                else local += __popc((uint32_t)slots[ord[t]].y);
+            }
+            int total;
+            int ex = group_excl_scan<G>(local, total, red);
+            for (int t = beg; t < end; ++t) {
+                if constexpr (MODE == MODE_DIRECT) {
+                    dw[t].y = (uint32_t)ex;
+                    ex += __popc(dw[t].x);
+                } else if constexpr (MODE == MODE_TWOLEVEL) {
+                    cm[t].y = (uint32_t)ex;
+                    ex += __popc(cm[t].x);
+                } else {
+                    const int cl = ord[t];
+                    slots[cl].z = ex;
+                    ex += __popc((uint32_t)slots[cl].y);
+                }
+            }
+        }
+        group_sync<G>();
+        bwalk([&](const CV& v, int e) {
+            int rank;
+            if constexpr (MODE == MODE_DIRECT) {
+                const uint2 mp = dw[(v.c >> 5) - base];
+                rank = (int)mp.y + __popc(mp.x & below(v.c & 31));
+            } else if constexpr (MODE == MODE_TWOLEVEL) {
+                const int w = (v.c >> 5) - base;
+                const uint2 L = l1[w >> 5];
+                const uint2 mp = cm[(int)L.y + __popc(L.x & below(w & 31))];
+                rank = (int)mp.y + __popc(mp.x & below(v.c & 31));
+            } else {
+                const int key = v.c >> 5;
+                int h = hash_slot(key, logT);
+                int4 sl = slots[h];
+                for (int probe = 1; sl.x != key && probe < TT; ++probe) {
+                    h = (h + 1) & (TT - 1);
+                    sl = slots[h];
+                }
+                rank = sl.z + __popc((uint32_t)sl.y & below(v.c & 31));
+            }
+            atomicAdd(&vals[rank], ava[e] * v.y);
+        });
+        // column of every rank, from the masks, straight to C
+        int32_t* cc = a.ccol + off;
+        for (int t = lane; t < items; t += G) {
+            uint32_t mk;
+            int r, b;
+            if constexpr (MODE == MODE_DIRECT) {
+                const uint2 mp = dw[t];
+                mk = mp.x, r = (int)mp.y, b = base + t;
+            } else if constexpr (MODE == MODE_TWOLEVEL) {
+                const uint2 mp = cm[t];
+                mk = mp.x, r = (int)mp.y, b = blk[t];
+            } else {
+                const int4 sl = slots[ord[t]];
+                mk = (uint32_t)sl.y, r = sl.z, b = sl.x;
+            }
+            while (mk) {
+                cc[r++] = (b << 5) + (__ffs(mk) - 1);
+                mk &= mk - 1;
+            }
+        }
+        group_sync<G>();
+        T* cv = reinterpret_cast<T*>(a.cval) + off;
+        for (int r = lane; r < n; r += G) cv[r] = vals[r];
+    };
+
+    stage(a0);
+    if (a1 - a0 <= G && ch.P <= KB * G && ch.PC <= KC * G) {
+        // the whole row in one batch: runs and B entries are loaded together
+        Batch<G, KC, 1, decltype(load_run)> br;
+        Batch<G, KB, 0, decltype(load_cv)> bb;
+        br.issue(ent, winc, 0, ch.PC, lane, wv, le, load_run);
+        bb.issue(ent, winb, 0, ch.P, lane, wv, le, load_cv);
+        finish([&](auto&& apply) { br.consume(winc, 0, ch.PC, lane, wv, le, apply); },
+               [&](auto&& apply) { bb.consume(winb, 0, ch.P, lane, wv, le, apply); });
+    } else {
+        finish(walk_runs, walk_b);
     }
 }
 
@@ -686,7 +968,7 @@ template <int G, int MODE>
 void sym_launch(hipStream_t s, const SymArgs& a) {
     constexpr int RPW = rows_per_wg<G>();
     const unsigned grid = (unsigned)((a.count + RPW - 1) / RPW);
-    const size_t smem = (size_t)RPW * (tier_bytes(a.tier) + G * 8);
+    const size_t smem = (size_t)RPW * (tier_bytes(a.tier) + sym_stage_bytes(G));
     hipLaunchKernelGGL((k_sym<G, MODE>), dim3(grid), dim3(G * RPW), smem, s, a);
 }
 
@@ -694,7 +976,7 @@ template <int G, int MODE, typename T>
 void num_launch(hipStream_t s, const NumArgs& a) {
     constexpr int RPW = rows_per_wg<G>();
     const unsigned grid = (unsigned)((a.count + RPW - 1) / RPW);
-    const size_t smem = (size_t)RPW * (tier_bytes(a.tier) + G * 24);
+    const size_t smem = (size_t)RPW * (tier_bytes(a.tier) + stage_bytes(G));
     hipLaunchKernelGGL((k_num<G, MODE, T>), dim3(grid), dim3(G * RPW), smem, s, a);
 }
 

@@ -63,7 +63,7 @@ struct spg_handle_s {
 
     // scratch
     DevBuf binfo, rinfo, feats, sym_cls, num_cls, perm_sym, perm_num, row_nnz, row_blocks, tile_status, cursor,
-        ovf_list, ctl, slab_sym, slab_retry, slab_num, mlp_w, bcrp, bc;
+        ovf_list, ctl, slab_sym, slab_retry, slab_num, mlp_w, bcrp, bc, bhdr;
     Control* hctl = nullptr;  // pinned host copy
 
     // symbolic result
@@ -237,6 +237,7 @@ spg_status sym_prepare(spg_handle h) {
     SPG_TRY(ensure(h, h->row_blocks, M * 4));
     SPG_TRY(ensure(h, h->tile_status, (size_t)(scan_tiles(std::max(m, h->n)) + 1) * 8));
     SPG_TRY(ensure(h, h->bcrp, ((size_t)h->n + 1) * 4));
+    SPG_TRY(ensure(h, h->bhdr, (size_t)std::max(h->n, 1) * sizeof(int4)));
     SPG_TRY(ensure(h, h->cursor, NCLS * 4));
     if (learned) SPG_TRY(ensure(h, h->ovf_list, M * 4));
     if (want_feats) SPG_TRY(ensure(h, h->feats, M * 12));
@@ -276,7 +277,7 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
     SPG_TRY(ensure(h, h->bc, (size_t)std::max<int64_t>(hc.bc_total, 1) * sizeof(int2)));
     h->vecc_used = h->vec > 0 ? h->vec : vec_for(h->n > 0 ? (double)hc.bc_total / (double)h->n : 1.0);
     launch_compress_b(s, h->n, h->brp, h->bci, h->binfo.as<int4>(), h->bcrp.as<int32_t>(), h->tile_status.as<uint64_t>(),
-                      &ctl->tile_counter_b, h->bc.as<int2>());
+                      &ctl->tile_counter_b, h->bc.as<int2>(), h->bhdr.as<int4>());
     launch_fill_i32(s, h->cursor.as<int32_t>(), 0, NCLS);
     launch_scatter(s, m, h->sym_cls.as<uint8_t>(), ctl->sym_hist, h->cursor.as<int32_t>(), h->perm_sym.as<int32_t>());
     int off[NCLS];
@@ -303,7 +304,7 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
         a.mode = c / NTIER;
         a.vec = h->vecc_used;
         a.arp = h->arp, a.aci = h->aci, a.brp = h->brp, a.bci = h->bci;
-        a.bcrp = h->bcrp.as<int32_t>(), a.bc = h->bc.as<int2>();
+        a.bcrp = h->bcrp.as<int32_t>(), a.bc = h->bc.as<int2>(), a.bhdr = h->bhdr.as<int4>();
         a.rinfo = h->rinfo.as<RowInfo>();
         a.row_nnz = h->row_nnz.as<int32_t>();
         a.row_blocks = h->row_blocks.as<int32_t>();
@@ -328,7 +329,7 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
         a.mode = MODE_DIRECT;
         a.vec = h->vecc_used;
         a.arp = h->arp, a.aci = h->aci, a.brp = h->brp, a.bci = h->bci;
-        a.bcrp = h->bcrp.as<int32_t>(), a.bc = h->bc.as<int2>();
+        a.bcrp = h->bcrp.as<int32_t>(), a.bc = h->bc.as<int2>(), a.bhdr = h->bhdr.as<int4>();
         a.rinfo = h->rinfo.as<RowInfo>();
         a.row_nnz = h->row_nnz.as<int32_t>();
         a.row_blocks = h->row_blocks.as<int32_t>();
@@ -361,6 +362,7 @@ spg_status sym_finish(spg_handle h, int32_t* c_row_ptr) {
     const Control hc2 = *h->hctl;
     if (hc2.err & ERR_NNZ_OVERFLOW)
         return fail(h, SPG_ERR_OVERFLOW, "nnz(C) = " + std::to_string(hc2.nnz_c) + " exceeds the int32 range");
+    if (hc2.err & ERR_TABLE_OVERFLOW) return fail(h, SPG_ERR_HIP, "internal error: bounded symbolic table overflowed");
     h->nnz_c = hc2.nnz_c;
     int run = 0;
     for (int c = 0; c < NCLS; ++c) {
@@ -413,7 +415,7 @@ spg_status num_launch_all(spg_handle h, const void* a_vals, const void* b_vals, 
         a.vec = h->vec_used;
         a.arp = h->arp, a.aci = h->aci, a.av = a_vals;
         a.brp = h->brp, a.bci = h->bci, a.bv = b_vals;
-        a.bcrp = h->bcrp.as<int32_t>(), a.bc = h->bc.as<int2>();
+        a.bcrp = h->bcrp.as<int32_t>(), a.bc = h->bc.as<int2>(), a.bhdr = h->bhdr.as<int4>();
         a.vecc = h->vecc_used;
         a.crp = h->crp;
         a.rinfo = h->rinfo.as<RowInfo>();
@@ -483,7 +485,7 @@ spg_status spg_destroy(spg_handle h) {
     if (h->stream || true) (void)hipStreamSynchronize(h->stream);
     DevBuf* bufs[] = {&h->binfo, &h->rinfo, &h->feats, &h->sym_cls, &h->num_cls, &h->perm_sym, &h->perm_num,
                       &h->row_nnz, &h->row_blocks, &h->tile_status, &h->cursor, &h->ovf_list, &h->ctl,
-                      &h->slab_sym, &h->slab_retry, &h->slab_num, &h->mlp_w, &h->bcrp, &h->bc};
+                      &h->slab_sym, &h->slab_retry, &h->slab_num, &h->mlp_w, &h->bcrp, &h->bc, &h->bhdr};
     for (DevBuf* b : bufs) release(*b);
     if (h->hctl) (void)hipHostFree(h->hctl);
     if (h->ev_made)

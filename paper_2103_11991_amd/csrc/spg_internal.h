@@ -43,6 +43,7 @@ constexpr int ERR_A_COL = 2;
 constexpr int ERR_B_ROWPTR = 4;
 constexpr int ERR_B_COL = 8;
 constexpr int ERR_NNZ_OVERFLOW = 16;
+constexpr int ERR_TABLE_OVERFLOW = 32;  // a bounded table overflowed (internal error)
 
 // Per-tier geometry: LDS bytes per row, threads per row, rows per workgroup.
 __host__ __device__ inline int tier_bytes(int t) { return 256 << t; }
@@ -54,10 +55,25 @@ __host__ __device__ inline int tier_rows(int t) {
     int g = tier_threads(t);
     return g <= 64 ? 256 / g : 1;
 }
-// dynamic LDS of one workgroup of tier t: the rows' tables plus 24 bytes of
-// staged A entries per lane (numeric; 8 in symbolic)
+// Flat product mapping of the row kernels: a batch gives every lane K slots,
+// products (or compressed-B runs) lane + G*k of the staged A chunk.
+constexpr int FLAT_KC = 8;       // compressed-B runs per lane and batch (symbolic; table size)
+constexpr int FLAT_KC_F64 = 5;   // numeric, FP64: runs and B entries of a row are in flight
+constexpr int FLAT_KC_F32 = 6;   // together, so fewer run slots keep the registers in check
+constexpr int FLAT_KB_F64 = 12;  // B entries per lane and batch, FP64 values
+constexpr int FLAT_KB_F32 = 16;  // B entries per lane and batch, FP32 values
+__host__ __device__ inline int group_waves(int g) { return g > 64 ? g / 64 : 1; }
+// staging of one row: per staged A entry 16 bytes of B/compressed-B offsets
+// and 8 of A's value, then the two window tables (16 bytes per window and
+// wavefront) of the batch in flight
+__host__ __device__ inline int stage_bytes(int g) {
+    return g * 24 + (FLAT_KB_F32 + FLAT_KC) * group_waves(g) * 16;
+}
+// the symbolic phase stages no values and walks compressed B only
+__host__ __device__ inline int sym_stage_bytes(int g) { return g * 16 + FLAT_KC * group_waves(g) * 16; }
+// dynamic LDS of one workgroup of tier t: the rows' tables plus staging
 __host__ __device__ inline int64_t tier_smem_bytes(int t) {
-    return (int64_t)tier_rows(t) * (tier_bytes(t) + 24 * tier_threads(t));
+    return (int64_t)tier_rows(t) * (tier_bytes(t) + stage_bytes(tier_threads(t)));
 }
 
 __host__ __device__ inline int64_t pow2ceil64(int64_t x) {
@@ -85,28 +101,32 @@ using RowInfo = int4;
 __host__ __device__ inline int64_t row_words(int32_t cmin, int32_t cmax) {
     return (int64_t)(cmax >> 5) - (int64_t)(cmin >> 5) + 1;
 }
-__host__ __device__ inline int64_t sym_hash_slots(int64_t est_blocks) {
-    return pow2ceil64(est_blocks * 2 > 16 ? est_blocks * 2 : 16);
+// Slots of a symbolic hashed table.  The table overflows (the row is retried
+// on the global path) above three-quarter occupancy: a learned estimate gets
+// 2x slots, a guaranteed upper bound 4/3x, enough never to reach that mark.
+__host__ __device__ inline int64_t sym_hash_slots(int64_t est_blocks, bool bound = false) {
+    const int64_t need = bound ? (est_blocks * 4 + 2) / 3 : est_blocks * 2;
+    return pow2ceil64(need > 16 ? need : 16);
 }
 __host__ __device__ inline int64_t num_hash_slots(int64_t blocks) {
     return pow2ceil64(blocks * 2 > 16 ? blocks * 2 : 16);
 }
 __host__ __device__ inline int64_t align8(int64_t b) { return (b + 7) & ~(int64_t)7; }
 __host__ __device__ inline int64_t num_direct_bytes(int64_t words, int64_t n, int eb) {
-    return align8(words * 8) + n * (eb + 4);
+    return align8(words * 8) + n * eb;
 }
 // hashed numeric table: 16-byte slots {block, mask, prefix, -}, the occupied
 // block ids compacted (padded to a multiple of 4) with their slots, and the
 // slots in ascending block order
 __host__ __device__ inline int64_t num_hashed_bytes(int64_t blocks, int64_t n, int eb) {
-    return align8(num_hash_slots(blocks) * 16 + ((blocks + 3) / 4) * 16 + blocks * 8) + n * (eb + 4);
+    return align8(num_hash_slots(blocks) * 16 + ((blocks + 3) / 4) * 16 + blocks * 8) + n * eb;
 }
 // two-level numeric table: a {bits, prefix} pair per 32 words of the row's
 // block range (which blocks are occupied, and their compact index), then per
 // occupied block {mask, prefix} and its block id
 __host__ __device__ inline int64_t twolevel_words(int64_t words) { return (words + 31) / 32; }
 __host__ __device__ inline int64_t num_twolevel_bytes(int64_t words, int64_t blocks, int64_t n, int eb) {
-    return align8(twolevel_words(words) * 8 + blocks * 12) + n * (eb + 4);
+    return align8(twolevel_words(words) * 8 + blocks * 12) + n * eb;
 }
 
 // Smallest LDS tier that holds `bytes`, raised until its thread group gives
@@ -123,14 +143,15 @@ __host__ __device__ inline int pick_tier(int64_t bytes, int64_t work, const Clas
 }
 
 // Symbolic class of a row from its products, column range and an estimate
-// of its occupied blocks (an upper bound, or the learned prediction).
+// of its occupied blocks (an upper bound: the compressed-B runs its products
+// read; or the learned prediction).
 __host__ __device__ inline int sym_class(int64_t ub, int32_t cmin, int32_t cmax, int64_t est_blocks,
-                                         const ClassCfg& c) {
+                                         const ClassCfg& c, bool bound = false) {
     if (ub <= 0) return CLS_EMPTY;
     int64_t words = row_words(cmin, cmax);
     int64_t est = est_blocks < words ? est_blocks : words;
     if (est < 1) est = 1;
-    int64_t bd = words * 4, bh = sym_hash_slots(est) * 8;
+    int64_t bd = words * 4, bh = sym_hash_slots(est, bound) * 8;
     if (c.force_class >= 0) {
         int fm = c.force_class / NTIER, ft = c.force_class % NTIER;
         if (ft == TIER_GLOBAL) return MODE_DIRECT * NTIER + TIER_GLOBAL;
@@ -200,9 +221,10 @@ void launch_b_rowinfo(hipStream_t s, int32_t n, int32_t k, const int32_t* brp, c
 // compressed B (section 2.2.1): per B row, runs of consecutive entries in one
 // 32-column block become one {block, OR of the column bits} entry.  binfo.w
 // holds each row's run count; bcrp gets their exclusive scan (n+1 entries,
-// tile status scratch of scan_tiles(n)+1 words), bc the runs.
+// tile status scratch of scan_tiles(n)+1 words), bc the runs, and bhdr per B
+// row {first entry, length, first run, run count}.
 void launch_compress_b(hipStream_t s, int32_t n, const int32_t* brp, const int32_t* bci, const int4* binfo,
-                       int32_t* bcrp, uint64_t* tile_status, int32_t* tile_counter, int2* bc);
+                       int32_t* bcrp, uint64_t* tile_status, int32_t* tile_counter, int2* bc, int4* bhdr);
 void launch_a_rowinfo(hipStream_t s, int32_t m, int32_t n, const int32_t* arp, const int32_t* aci, int64_t annz,
                       const int4* binfo, RowInfo* rinfo, float* feats, ClassCfg cfg, int learned,
                       uint8_t* sym_cls, int32_t* row_nnz, int32_t* row_blocks, Control* ctl);
@@ -234,6 +256,7 @@ struct SymArgs {
     const int32_t* bci;
     const int32_t* bcrp;          // compressed B: row pointer and {block, mask} runs
     const int2* bc;
+    const int4* bhdr;             // per B row {start, length, run start, run count}
     const RowInfo* rinfo;
     int32_t* row_nnz;
     int32_t* row_blocks;
@@ -259,6 +282,7 @@ struct NumArgs {
     const void* bv;
     const int32_t* bcrp;
     const int2* bc;
+    const int4* bhdr;             // per B row {start, length, run start, run count}
     int32_t vecc;                 // lanes sharing one compressed-B row
     const int32_t* crp;
     const RowInfo* rinfo;

@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
     // grid-stride: few workgroups, one flush of the counters each
     for (int64_t rb = blockIdx.x * rows_per_block; rb < m; rb += (int64_t)gridDim.x * rows_per_block) {
         const int64_t row = rb + threadIdx.x / ROW_LANES;
-        int64_t ub = 0;
+        int64_t ub = 0, rs = 0;  // products; compressed-B runs (a bound on occupied blocks)
         int mx = 0, cmin = INT_MAX, cmax = -1, bad = 0, len = 0;
         if (row < m) {
             int32_t s = arp[row], e = arp[row + 1];
@@ -140,6 +140,7 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
     #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         ub += bb[u].x;
+                        rs += bb[u].w;
                         mx = max(mx, bb[u].x);
                         cmin = min(cmin, bb[u].y);
                         cmax = max(cmax, bb[u].z);
@@ -148,6 +149,7 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
             }
         }
         ub = xor_reduce_sum(ub);
+        rs = xor_reduce_sum(rs);
         mx = xor_reduce_max(mx);
         cmin = xor_reduce_min(cmin);
         cmax = xor_reduce_max(cmax);
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
                 atomicMax(&wmax_all, (unsigned long long)words);
                 atomicAdd(&prod_sum, (unsigned long long)ub);
                 if (!learned) {
-                    cls = sym_class(ub, cmin, cmax, ub, cfg);
+                    cls = sym_class(ub, cmin, cmax, rs, cfg, true);
                     sym_cls[row] = (uint8_t)cls;
                     atomicAdd(&hist[cls], 1);
                     if (cls % NTIER == TIER_GLOBAL) atomicMax(&wmax_glob, (unsigned long long)words);
@@ -502,25 +504,56 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_runs(int32_t n, const int
     if (tile == 0 && threadIdx.x == 0) bcrp[0] = 0;
 }
 
-// Writes each B row's runs: {block id, OR of the bits of its columns}.
+// Writes each B row's runs {block id, OR of the bits of its columns} and its
+// header {first entry, length, first run, run count}.  ROW_LANES lanes per row
+// read the row in coalesced chunks: an entry starts a run when its block
+// differs from the previous entry's, a segmented OR across the chunk gathers
+// each run's bits, and the lane holding a run's last entry writes it at the
+// run's index (runs begun before it in the row).
 __global__ __launch_bounds__(256) void k_compress_b(int32_t n, const int32_t* __restrict__ brp,
                                                     const int32_t* __restrict__ bci, const int32_t* __restrict__ bcrp,
-                                                    int2* __restrict__ bc) {
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+                                                    int2* __restrict__ bc, int4* __restrict__ bhdr) {
+    constexpr int L = ROW_LANES;
+    const int sl = threadIdx.x % L;
+    const int shift = (threadIdx.x & 63) & ~(L - 1);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x / L;
+    for (int64_t j = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / L; j < n; j += stride) {
         const int32_t s = brp[j], e = brp[j + 1];
-        int32_t o = bcrp[j];
-        int cur = -1;
-        uint32_t mask = 0;
-        for (int32_t q = s; q < e; ++q) {
-            const int c = bci[q];
-            if ((c >> 5) != cur) {
-                if (cur >= 0) bc[o++] = make_int2(cur, (int)mask);
-                cur = c >> 5;
-                mask = 0;
+        const int32_t o = bcrp[j];
+        if (sl == 0) bhdr[j] = make_int4(s, e - s, o, bcrp[j + 1] - o);
+        int done = 0;          // runs begun in earlier chunks
+        uint32_t carry = 0;    // bits of the run still open at the end of the last chunk
+        int last_blk = -1;     // block of the last chunk's final entry
+        for (int32_t q0 = s; q0 < e; q0 += L) {
+            const int32_t q = q0 + sl;
+            const bool v = q < e;
+            const int c = v ? bci[q] : 0;
+            const int blk = v ? c >> 5 : -1;
+            int prev = __shfl_up(blk, 1, L);
+            if (sl == 0) prev = last_blk;
+            int next = __shfl_down(blk, 1, L);
+            if (sl == L - 1) next = q + 1 < e ? bci[q + 1] >> 5 : -1;
+            const int start = v && blk != prev;
+            const bool last = v && (q + 1 >= e || next != blk);
+            // segmented inclusive OR of the column bits, segments begin at run starts
+            uint32_t m = v ? 1u << (c & 31) : 0u;
+            int f = start;
+            for (int d = 1; d < L; d <<= 1) {
+                const uint32_t mu = __shfl_up(m, d, L);
+                const int fu = __shfl_up(f, d, L);
+                if (sl >= d && !f) {
+                    m |= mu;
+                    f = fu;
+                }
             }
-            mask |= 1u << (c & 31);
+            if (!f) m |= carry;
+            const uint64_t starts = (__ballot(start) >> shift) & ((1ull << L) - 1);
+            const int idx = done + __popcll(starts & ((2ull << sl) - 1)) - 1;
+            if (last) bc[o + idx] = make_int2(blk, (int)m);
+            done += __popcll(starts);
+            carry = __shfl(m, L - 1, L);
+            last_blk = __shfl(blk, L - 1, L);
         }
-        if (cur >= 0) bc[o] = make_int2(cur, (int)mask);
     }
 }
 
@@ -562,7 +595,7 @@ void launch_b_rowinfo(hipStream_t s, int32_t n, int32_t k, const int32_t* brp, c
 }
 
 void launch_compress_b(hipStream_t s, int32_t n, const int32_t* brp, const int32_t* bci, const int4* binfo,
-                       int32_t* bcrp, uint64_t* tile_status, int32_t* tile_counter, int2* bc) {
+                       int32_t* bcrp, uint64_t* tile_status, int32_t* tile_counter, int2* bc, int4* bhdr) {
     if (n <= 0) {
         launch_fill_i32(s, bcrp, 0, 1);
         return;
@@ -570,7 +603,8 @@ void launch_compress_b(hipStream_t s, int32_t n, const int32_t* brp, const int32
     launch_fill_u8(s, tile_status, 0, (scan_tiles(n) + 1) * 8);
     hipLaunchKernelGGL(k_scan_runs, dim3((unsigned)scan_tiles(n)), dim3(SCAN_THREADS), 0, s, n, binfo, bcrp,
                        tile_status, tile_counter);
-    hipLaunchKernelGGL(k_compress_b, dim3(std::min(grid_for(n, 256), 4096u)), dim3(256), 0, s, n, brp, bci, bcrp, bc);
+    hipLaunchKernelGGL(k_compress_b, dim3(std::min(grid_for((int64_t)n * ROW_LANES, 256), 4096u)), dim3(256), 0, s, n,
+                       brp, bci, bcrp, bc, bhdr);
 }
 
 void launch_a_rowinfo(hipStream_t s, int32_t m, int32_t n, const int32_t* arp, const int32_t* aci, int64_t annz,
