@@ -316,39 +316,63 @@ __device__ inline void win_clear(Win* win, int lane) {
     for (int t = lane; t < NW; t += G) win[t] = Win{0ull, 0, 0};
 }
 
-// Staged entry index of the lane's product in window k of the batch.
-template <int G>
-__device__ inline int win_entry(const Win* win, int k, int wv, unsigned long long le) {
-    const Win w = win[k * waves_of<G>() + wv];
-    return w.cum + __popcll(w.mask & le) - 1;
-}
-
-// One batch: issue the K loads of the lane (slot k holds product
-// P0 + lane + G*k when below P), then hand each to apply(value, entry).
-// FIELD 0 takes the B offset of the entry (ent.x), 1 the run offset (ent.y).
-template <int G, int K, int FIELD, typename Load>
-struct Batch {
-    using V = decltype(std::declval<Load>()(0));
-    V v[K];
-    __device__ inline void issue(const int4* ent, const Win* win, int P0, int P, int lane, int wv,
-                                 unsigned long long le, Load& load) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int p = P0 + k * G + lane;
-            if (p < P) {
-                const int4 en = ent[win_entry<G>(win, k, wv, le)];
-                v[k] = load((FIELD == 0 ? en.x : en.y) + p);
+// Staged entry of the lane's product in window k of the batch.  Groups of
+// 64 lanes or more read a batch's window words once (lane t of a wavefront
+// holds window t of its column) and broadcast them with readlane, so a slot
+// costs no LDS access; smaller groups read the word from LDS.
+template <int G, int K>
+struct WinView {
+    unsigned long long m;
+    int c;
+    const Win* win;
+    __device__ inline void load(const Win* w, int wv) {
+        win = w;
+        if constexpr (G >= 64) {
+            const int t = threadIdx.x & 63;
+            m = 0, c = 0;
+            if (t < K) {
+                const Win x = w[t * waves_of<G>() + wv];
+                m = x.mask, c = x.cum;
             }
         }
     }
-    // the entry is looked up again here rather than held in a register
-    // across the wait (the window table is unchanged until then)
+    __device__ inline int entry(int k, int wv, unsigned long long le) const {
+        if constexpr (G >= 64) {
+            const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)m, k);
+            const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(m >> 32), k);
+            const int cum = __builtin_amdgcn_readlane(c, k);
+            return cum + __popcll((((unsigned long long)hi << 32) | lo) & le) - 1;
+        } else {
+            const Win w = win[k];
+            return w.cum + __popcll(w.mask & le) - 1;
+        }
+    }
+};
+
+// One batch: issue the K loads of the lane (slot k holds product
+// P0 + lane + G*k when below P; off[e] turns it into an index into B or
+// compressed B), then hand each to apply(value, entry).
+template <int G, int K, typename Load>
+struct Batch {
+    using V = decltype(std::declval<Load>()(0));
+    V v[K];
+    WinView<G, K> view;
+    __device__ inline void issue(const int32_t* off, const Win* win, int P0, int P, int lane, int wv,
+                                 unsigned long long le, Load& load) {
+        view.load(win, wv);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int p = P0 + k * G + lane;
+            if (p < P) v[k] = load(off[view.entry(k, wv, le)] + p);
+        }
+    }
+    // the entry is found again here rather than held in a register across the
+    // wait (the window table is unchanged until then)
     template <typename Apply>
-    __device__ inline void consume(const Win* win, int P0, int P, int lane, int wv, unsigned long long le,
-                                   Apply& apply) {
+    __device__ inline void consume(int P0, int P, int lane, int wv, unsigned long long le, Apply& apply) {
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            if (P0 + k * G + lane < P) apply(v[k], win_entry<G>(win, k, wv, le));
+            if (P0 + k * G + lane < P) apply(v[k], view.entry(k, wv, le));
     }
 };
 
@@ -386,8 +410,8 @@ void k_sym(SymArgs a) {
     const int a0 = a.arp[i], a1 = a.arp[i + 1];
     uint8_t* row_lds = reinterpret_cast<uint8_t*>(smem) + (size_t)sub * per_row;
     uint32_t* tab = reinterpret_cast<uint32_t*>(row_lds);
-    int4* ent = reinterpret_cast<int4*>(row_lds + bytes);
-    Win* win = reinterpret_cast<Win*>(row_lds + bytes + 16 * G);
+    int32_t* cq = reinterpret_cast<int32_t*>(row_lds + bytes);   // staged run offsets
+    Win* win = reinterpret_cast<Win*>(row_lds + bytes + 4 * G);
     int base = 0, ncell, T = 0, logT = 0;
     int32_t* keys = reinterpret_cast<int32_t*>(tab);
     uint32_t* masks = tab;
@@ -447,7 +471,7 @@ void k_sym(SymArgs a) {
         const bool ne = h.w > 0;
         int3 tot;
         const int3 ex = group_excl_scan3<G>(make_int3(ne, h.w, 0), tot, red);
-        if (ne) ent[ex.x] = make_int4(0, h.z - ex.y, 0, ex.y);
+        if (ne) cq[ex.x] = h.z - ex.y;
         win_mark<G, KC>(win, ne, ex.y, 0);
         group_sync<G>();
         win_scan<G, KC, 0>(win, nullptr, 0, 0, lane, red);
@@ -463,9 +487,9 @@ void k_sym(SymArgs a) {
                 win_scan<G, KC, 0>(win, nullptr, before, 0, lane, red);
                 group_sync<G>();
             }
-            Batch<G, KC, 1, decltype(load_run)> bt;
-            bt.issue(ent, win, P0, tot.y, lane, wv, le, load_run);
-            bt.consume(win, P0, tot.y, lane, wv, le, apply);
+            Batch<G, KC, decltype(load_run)> bt;
+            bt.issue(cq, win, P0, tot.y, lane, wv, le, load_run);
+            bt.consume(P0, tot.y, lane, wv, le, apply);
         }
     }
     cnt = group_sum<G>(cnt, red);
@@ -598,9 +622,10 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     const int w1 = (words + 31) >> 5;
     uint8_t* row_lds = reinterpret_cast<uint8_t*>(smem) + (size_t)sub * per_row;
     uint8_t* tab = row_lds;
-    int4* ent = reinterpret_cast<int4*>(row_lds + bytes);           // staged entries
-    T* ava = reinterpret_cast<T*>(row_lds + bytes + G * 16);         // their A values
-    Win* winb = reinterpret_cast<Win*>(row_lds + bytes + G * 24);    // product windows
+    int32_t* bq = reinterpret_cast<int32_t*>(row_lds + bytes);        // staged B offsets
+    int32_t* cq = bq + G;                                             // staged run offsets
+    T* ava = reinterpret_cast<T*>(row_lds + bytes + G * 8);           // their A values
+    Win* winb = reinterpret_cast<Win*>(row_lds + bytes + G * 16);     // product windows
     Win* winc = winb + FLAT_KB_F32 * W;                              // run windows
     // direct: {mask, prefix} per word.  two-level: l1 {bits, prefix} per 32
     // blocks, cm {mask, prefix} and blk per occupied block.  hashed: slots,
@@ -662,7 +687,8 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
         const int3 ex = group_excl_scan3<G>(make_int3(ch.ne, h.y, h.w), tot, red);
         ch.pb = ex.y, ch.pc = ex.z, ch.nr = tot.x, ch.P = tot.y, ch.PC = tot.z;
         if (ch.ne) {
-            ent[ex.x] = make_int4(h.x - ex.y, h.z - ex.z, ex.y, ex.z);
+            bq[ex.x] = h.x - ex.y;
+            cq[ex.x] = h.z - ex.z;
             ava[ex.x] = v;
         }
         win_mark<G, KB>(winb, ch.ne, ch.pb, 0);
@@ -709,9 +735,9 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
             restage(e0);
             for (int P0 = 0; P0 < ch.PC; P0 += KC * G) {
                 rewin(std::integral_constant<int, 1>{}, P0);
-                Batch<G, KC, 1, decltype(load_run)> bt;
-                bt.issue(ent, winc, P0, ch.PC, lane, wv, le, load_run);
-                bt.consume(winc, P0, ch.PC, lane, wv, le, apply);
+                Batch<G, KC, decltype(load_run)> bt;
+                bt.issue(cq, winc, P0, ch.PC, lane, wv, le, load_run);
+                bt.consume(P0, ch.PC, lane, wv, le, apply);
             }
         }
     };
@@ -720,9 +746,9 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
             restage(e0);
             for (int P0 = 0; P0 < ch.P; P0 += KB * G) {
                 rewin(std::integral_constant<int, 0>{}, P0);
-                Batch<G, KB, 0, decltype(load_cv)> bt;
-                bt.issue(ent, winb, P0, ch.P, lane, wv, le, load_cv);
-                bt.consume(winb, P0, ch.P, lane, wv, le, apply);
+                Batch<G, KB, decltype(load_cv)> bt;
+                bt.issue(bq, winb, P0, ch.P, lane, wv, le, load_cv);
+                bt.consume(P0, ch.P, lane, wv, le, apply);
             }
         }
     };
@@ -870,12 +896,12 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     stage(a0);
     if (a1 - a0 <= G && ch.P <= KB * G && ch.PC <= KC * G) {
         // the whole row in one batch: runs and B entries are loaded together
-        Batch<G, KC, 1, decltype(load_run)> br;
-        Batch<G, KB, 0, decltype(load_cv)> bb;
-        br.issue(ent, winc, 0, ch.PC, lane, wv, le, load_run);
-        bb.issue(ent, winb, 0, ch.P, lane, wv, le, load_cv);
-        finish([&](auto&& apply) { br.consume(winc, 0, ch.PC, lane, wv, le, apply); },
-               [&](auto&& apply) { bb.consume(winb, 0, ch.P, lane, wv, le, apply); });
+        Batch<G, KC, decltype(load_run)> br;
+        Batch<G, KB, decltype(load_cv)> bb;
+        br.issue(cq, winc, 0, ch.PC, lane, wv, le, load_run);
+        bb.issue(bq, winb, 0, ch.P, lane, wv, le, load_cv);
+        finish([&](auto&& apply) { br.consume(0, ch.PC, lane, wv, le, apply); },
+               [&](auto&& apply) { bb.consume(0, ch.P, lane, wv, le, apply); });
     } else {
         finish(walk_runs, walk_b);
     }

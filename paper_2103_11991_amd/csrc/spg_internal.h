@@ -63,14 +63,14 @@ constexpr int FLAT_KC_F32 = 6;   // together, so fewer run slots keep the regist
 constexpr int FLAT_KB_F64 = 12;  // B entries per lane and batch, FP64 values
 constexpr int FLAT_KB_F32 = 16;  // B entries per lane and batch, FP32 values
 __host__ __device__ inline int group_waves(int g) { return g > 64 ? g / 64 : 1; }
-// staging of one row: per staged A entry 16 bytes of B/compressed-B offsets
-// and 8 of A's value, then the two window tables (16 bytes per window and
-// wavefront) of the batch in flight
+// staging of one row: per staged A entry its B and compressed-B offsets (4
+// bytes each) and A's value (8), then the two window tables (16 bytes per
+// window and wavefront) of the batch in flight
 __host__ __device__ inline int stage_bytes(int g) {
-    return g * 24 + (FLAT_KB_F32 + FLAT_KC) * group_waves(g) * 16;
+    return g * 16 + (FLAT_KB_F32 + FLAT_KC) * group_waves(g) * 16;
 }
 // the symbolic phase stages no values and walks compressed B only
-__host__ __device__ inline int sym_stage_bytes(int g) { return g * 16 + FLAT_KC * group_waves(g) * 16; }
+__host__ __device__ inline int sym_stage_bytes(int g) { return g * 4 + FLAT_KC * group_waves(g) * 16; }
 // dynamic LDS of one workgroup of tier t: the rows' tables plus staging
 __host__ __device__ inline int64_t tier_smem_bytes(int t) {
     return (int64_t)tier_rows(t) * (tier_bytes(t) + stage_bytes(tier_threads(t)));
