@@ -406,8 +406,8 @@ void k_sym(SymArgs a) {
     const unsigned long long le = (2ull << (lane & 63)) - 1;
     const int slot = xcd_block(blockIdx.x, gridDim.x) * RPW + sub;
     if (slot >= a.count) return;  // uniform in the group (in the workgroup when G >= 128)
-    const int i = a.perm[slot];
-    const int a0 = a.arp[i], a1 = a.arp[i + 1];
+    const int4 d = a.desc[slot];
+    const int i = d.x, a0 = d.y, a1 = d.z;
     uint8_t* row_lds = reinterpret_cast<uint8_t*>(smem) + (size_t)sub * per_row;
     uint32_t* tab = reinterpret_cast<uint32_t*>(row_lds);
     int32_t* cq = reinterpret_cast<int32_t*>(row_lds + bytes);   // staged run offsets
@@ -610,12 +610,11 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     const unsigned long long le = (2ull << (lane & 63)) - 1;
     const int slot = xcd_block(blockIdx.x, gridDim.x) * RPW + sub;
     if (slot >= a.count) return;
-    const int i = a.perm[slot];
-    const int off = a.crp[i];
+    const int4 d = a.desc[slot];
+    const int i = d.x, a0 = d.y, a1 = d.z, off = d.w;
     const int n = a.crp[i + 1] - off;
     const RowInfo ri = a.rinfo[i];
     const int nb = a.row_blocks[i];
-    const int a0 = a.arp[i], a1 = a.arp[i + 1];
     const int base = ri.x >> 5;
     const int words = (ri.y >> 5) - base + 1;
     const int nb4 = (nb + 3) & ~3;

@@ -62,7 +62,8 @@ struct spg_handle_s {
     bool have_mlp = false;
 
     // scratch
-    DevBuf binfo, rinfo, feats, sym_cls, num_cls, perm_sym, perm_num, row_nnz, row_blocks, tile_status, cursor,
+    DevBuf binfo, rinfo, feats, sym_cls, num_cls, perm_sym, perm_num, desc_sym, desc_num, row_nnz, row_blocks,
+        tile_status, cursor,
         ovf_list, ctl, slab_sym, slab_retry, slab_num, mlp_w, bcrp, bc, bhdr;
     Control* hctl = nullptr;  // pinned host copy
 
@@ -233,6 +234,8 @@ spg_status sym_prepare(spg_handle h) {
     SPG_TRY(ensure(h, h->num_cls, M));
     SPG_TRY(ensure(h, h->perm_sym, M * 4));
     SPG_TRY(ensure(h, h->perm_num, M * 4));
+    SPG_TRY(ensure(h, h->desc_sym, M * sizeof(int4)));
+    SPG_TRY(ensure(h, h->desc_num, M * sizeof(int4)));
     SPG_TRY(ensure(h, h->row_nnz, M * 4));
     SPG_TRY(ensure(h, h->row_blocks, M * 4));
     SPG_TRY(ensure(h, h->tile_status, (size_t)(scan_tiles(std::max(m, h->n)) + 1) * 8));
@@ -279,7 +282,8 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
     launch_compress_b(s, h->n, h->brp, h->bci, h->binfo.as<int4>(), h->bcrp.as<int32_t>(), h->tile_status.as<uint64_t>(),
                       &ctl->tile_counter_b, h->bc.as<int2>(), h->bhdr.as<int4>());
     launch_fill_i32(s, h->cursor.as<int32_t>(), 0, NCLS);
-    launch_scatter(s, m, h->sym_cls.as<uint8_t>(), ctl->sym_hist, h->cursor.as<int32_t>(), h->perm_sym.as<int32_t>());
+    launch_scatter(s, m, h->sym_cls.as<uint8_t>(), ctl->sym_hist, h->cursor.as<int32_t>(), h->perm_sym.as<int32_t>(),
+                   h->arp, nullptr, h->desc_sym.as<int4>());
     int off[NCLS];
     {
         int run = 0;
@@ -299,6 +303,7 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
         if (!hc.sym_hist[c]) continue;
         SymArgs a{};
         a.perm = h->perm_sym.as<int32_t>() + off[c];
+        a.desc = h->desc_sym.as<int4>() + off[c];
         a.count = hc.sym_hist[c];
         a.tier = c % NTIER;
         a.mode = c / NTIER;
@@ -351,7 +356,8 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
                 ctl);
     rec(h, EV_SCAN1);
     launch_fill_i32(s, h->cursor.as<int32_t>(), 0, NCLS);
-    launch_scatter(s, m, h->num_cls.as<uint8_t>(), ctl->num_hist, h->cursor.as<int32_t>(), h->perm_num.as<int32_t>());
+    launch_scatter(s, m, h->num_cls.as<uint8_t>(), ctl->num_hist, h->cursor.as<int32_t>(), h->perm_num.as<int32_t>(),
+                   h->arp, c_row_ptr, h->desc_num.as<int4>());
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "symbolic launch");
     return SPG_OK;
@@ -409,6 +415,7 @@ spg_status num_launch_all(spg_handle h, const void* a_vals, const void* b_vals, 
         if (!h->num_hist[c]) continue;
         NumArgs a{};
         a.perm = h->perm_num.as<int32_t>() + h->num_off[c];
+        a.desc = h->desc_num.as<int4>() + h->num_off[c];
         a.count = h->num_hist[c];
         a.tier = c % NTIER;
         a.mode = c / NTIER;
@@ -484,6 +491,7 @@ spg_status spg_destroy(spg_handle h) {
     if (!h) return SPG_OK;
     if (h->stream || true) (void)hipStreamSynchronize(h->stream);
     DevBuf* bufs[] = {&h->binfo, &h->rinfo, &h->feats, &h->sym_cls, &h->num_cls, &h->perm_sym, &h->perm_num,
+                      &h->desc_sym, &h->desc_num,
                       &h->row_nnz, &h->row_blocks, &h->tile_status, &h->cursor, &h->ovf_list, &h->ctl,
                       &h->slab_sym, &h->slab_retry, &h->slab_num, &h->mlp_w, &h->bcrp, &h->bc, &h->bhdr};
     for (DevBuf* b : bufs) release(*b);

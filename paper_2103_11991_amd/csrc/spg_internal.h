@@ -230,8 +230,10 @@ void launch_a_rowinfo(hipStream_t s, int32_t m, int32_t n, const int32_t* arp, c
                       uint8_t* sym_cls, int32_t* row_nnz, int32_t* row_blocks, Control* ctl);
 void launch_mlp_classify(hipStream_t s, int32_t m, const float* feats, const float* w, const RowInfo* rinfo,
                          ClassCfg cfg, float margin, uint8_t* sym_cls, Control* ctl);
-// groups rows by class; offsets come from the class histogram in device memory
-void launch_scatter(hipStream_t s, int32_t m, const uint8_t* cls, const int32_t* hist, int32_t* cursor, int32_t* perm);
+// groups rows by class; offsets come from the class histogram in device memory.
+// perm gets the row ids, desc {row, arp[row], arp[row+1], crp ? crp[row] : 0}
+void launch_scatter(hipStream_t s, int32_t m, const uint8_t* cls, const int32_t* hist, int32_t* cursor, int32_t* perm,
+                    const int32_t* arp, const int32_t* crp, int4* desc);
 void launch_scan(hipStream_t s, int32_t m, const int32_t* row_nnz, const int32_t* row_blocks, const RowInfo* rinfo,
                  const int32_t* arp, const uint8_t* sym_cls, int32_t* c_row_ptr, uint64_t* tile_status,
                  ClassCfg cfg, uint8_t* num_cls, Control* ctl);
@@ -246,6 +248,7 @@ void launch_pack(hipStream_t s, int32_t count, const int64_t* desc, const int32_
 // ---- accumulator kernels (spg_accum.hip) ----
 struct SymArgs {
     const int32_t* perm;
+    const int4* desc;             // per slot {row, A start, A end, -} (row kernels)
     int32_t count;
     int32_t tier;
     int32_t mode;
@@ -270,6 +273,7 @@ struct SymArgs {
 
 struct NumArgs {
     const int32_t* perm;
+    const int4* desc;             // per slot {row, A start, A end, C start} (row kernels)
     int32_t count;
     int32_t tier;
     int32_t mode;

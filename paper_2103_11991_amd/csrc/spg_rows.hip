@@ -247,11 +247,13 @@ __global__ __launch_bounds__(256) void k_mlp_classify(int32_t m, const float* __
 
 // Groups rows by class: a workgroup takes chunks of 4096 consecutive rows,
 // ranks each row inside its class with LDS atomics, reserves one range per
-// class and chunk with a single global atomic, and writes the row ids there.
+// class and chunk with a single global atomic, and writes the row ids there,
+// with each row's descriptor {row, A start, A end, C start (or 0)} beside it.
 constexpr int SCATTER_ITEMS = 16;
 __global__ __launch_bounds__(256) void k_scatter(int32_t m, const uint8_t* __restrict__ cls,
                                                  const int32_t* __restrict__ hist, int32_t* __restrict__ cursor,
-                                                 int32_t* __restrict__ perm) {
+                                                 int32_t* __restrict__ perm, const int32_t* __restrict__ arp,
+                                                 const int32_t* __restrict__ crp, int4* __restrict__ desc) {
     __shared__ int32_t cnt[NCLS];
     __shared__ int32_t base[NCLS];
     __shared__ int32_t off[NCLS];
@@ -274,8 +276,13 @@ __global__ __launch_bounds__(256) void k_scatter(int32_t m, const uint8_t* __res
         if (threadIdx.x < NCLS && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
         __syncthreads();
 #pragma unroll
-        for (int t = 0; t < SCATTER_ITEMS; ++t)
-            if (c[t] != CLS_EMPTY) perm[off[c[t]] + base[c[t]] + local[t]] = (int32_t)(r0 + t * 256 + threadIdx.x);
+        for (int t = 0; t < SCATTER_ITEMS; ++t) {
+            if (c[t] == CLS_EMPTY) continue;
+            const int32_t row = (int32_t)(r0 + t * 256 + threadIdx.x);
+            const int32_t pos = off[c[t]] + base[c[t]] + local[t];
+            perm[pos] = row;
+            desc[pos] = make_int4(row, arp[row], arp[row + 1], crp ? crp[row] : 0);
+        }
         __syncthreads();
     }
 }
@@ -625,10 +632,10 @@ void launch_mlp_classify(hipStream_t s, int32_t m, const float* feats, const flo
 }
 
 void launch_scatter(hipStream_t s, int32_t m, const uint8_t* cls, const int32_t* hist, int32_t* cursor,
-                    int32_t* perm) {
+                    int32_t* perm, const int32_t* arp, const int32_t* crp, int4* desc) {
     if (m <= 0) return;
     hipLaunchKernelGGL(k_scatter, dim3(std::min(grid_for(m, 256 * SCATTER_ITEMS), 1024u)), dim3(256), 0, s, m, cls, hist,
-                       cursor, perm);
+                       cursor, perm, arp, crp, desc);
 }
 
 void launch_scan(hipStream_t s, int32_t m, const int32_t* row_nnz, const int32_t* row_blocks, const RowInfo* rinfo,

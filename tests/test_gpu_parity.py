@@ -39,7 +39,7 @@ def test_random_shapes(seed, dtype):
     compare(A, B, rp, c, v)
 
 
-@pytest.mark.parametrize("cls", list(range(20)))
+@pytest.mark.parametrize("cls", list(range(29)))
 def test_every_accumulator_class(cls):
     """All rows forced through one (mode, tier) class; rows that cannot fit fall back."""
     A = gen.random_csr(400, 300, 0, 12, seed=cls, empty_frac=0.1)
@@ -49,6 +49,20 @@ def test_every_accumulator_class(cls):
     S = gen.stencil27(9, seed=3)
     rp, c, v, op = run_gpu(S, S, force_class=cls)
     compare(S, S, rp, c, v)
+
+
+@pytest.mark.parametrize("cls", [3, 4, 5, 6, 7, 8, 13, 14, 15, 16, 23, 24, 25, 26, 27, 28])
+def test_many_batches_and_chunks(cls):
+    """Rows of ~150 A entries and ~3000 products (onto at most 200 columns),
+    forced into groups of 64 to 1024 lanes: several chunks of A per row and
+    several batches of products and runs per chunk, with empty B rows among
+    the staged entries."""
+    A = gen.random_csr(96, 800, 100, 200, seed=40 + cls, empty_frac=0.05)
+    B = gen.random_csr(800, 200, 0, 40, seed=41 + cls, empty_frac=0.2)
+    rp, c, v, op = run_gpu(A, B, force_class=cls)
+    st = op.stats()
+    assert st["num_rows"][cls] > 0
+    compare(A, B, rp, c, v)
 
 
 def test_global_path_with_global_slabs():
