@@ -106,12 +106,25 @@ def time_full_products(op, steps):
 
 
 def learned_vs_plain(dA, steps, plain):
-    """The same product with the learned row-size predictor sizing the symbolic
-    tables (committed model), against upper-bound binning."""
+    """The same product with the symbolic tables sized three ways: the upper
+    bound from each row's products, the default upper bound from the
+    compressed-B runs it reads (the headline run, ``plain``), and the learned
+    row-size predictor (committed model)."""
     from paper_2103_11991_amd import learned
     from paper_2103_11991_amd.spgemm import SpGEMM
+    out = {"t_sym_runs_bound_ms": round(plain["sym"], 4), "t_full_runs_bound_ms": round(plain["wall"], 4)}
+    op = SpGEMM(dA, dA, timing=1, binning=0)
+    for _ in range(2):
+        op.symbolic()
+        op.numeric()
+    sym0, _, wall0, st0 = time_full_products(op, steps)
+    rows = st0["m"] - st0["empty_rows"]
+    out.update({"t_sym_products_bound_ms": round(sym0, 4), "t_full_products_bound_ms": round(wall0, 4),
+                "products_bound_mispredict_rate": round(st0["mispredicted_rows"] / max(rows, 1), 5),
+                "runs_bound_mispredict_rate": round(plain["mispredicted"] / max(rows, 1), 5)})
+    del op
     if not os.path.exists(learned.DEFAULT_MODEL):
-        return None
+        return out
     w, margin, meta = learned.load()
     op = SpGEMM(dA, dA, timing=1, binning=1, mlp_margin_milli=int(round(margin * 1000)))
     op.set_mlp(w)
@@ -119,15 +132,16 @@ def learned_vs_plain(dA, steps, plain):
         op.symbolic()
         op.numeric()
     sym, num, wall, st = time_full_products(op, steps)
-    rows = st["m"] - st["empty_rows"]
-    return {"t_sym_plain_ms": round(plain["sym"], 4), "t_sym_learned_ms": round(sym, 4),
-            "t_full_plain_ms": round(plain["wall"], 4), "t_full_learned_ms": round(wall, 4),
-            "speedup_sym": round(plain["sym"] / sym, 3), "speedup_full": round(plain["wall"] / wall, 3),
-            "retry_rate": round(st["retried_rows"] / max(rows, 1), 5),
-            "mispredict_rate": round(st["mispredicted_rows"] / max(rows, 1), 5),
-            "plain_overestimate_rate": round(plain["mispredicted"] / max(rows, 1), 5),
-            "mlp_ms": round(st["mlp_ms"], 4), "model_rows": meta.get("rows"),
-            "model_quantile": meta.get("quantile"), "margin_log2": round(margin, 3)}
+    out.update({"t_sym_learned_ms": round(sym, 4), "t_full_learned_ms": round(wall, 4),
+                "speedup_sym_vs_products_bound": round(sym0 / sym, 3),
+                "speedup_full_vs_products_bound": round(wall0 / wall, 3),
+                "speedup_sym_vs_runs_bound": round(plain["sym"] / sym, 3),
+                "speedup_full_vs_runs_bound": round(plain["wall"] / wall, 3),
+                "retry_rate": round(st["retried_rows"] / max(rows, 1), 5),
+                "mispredict_rate": round(st["mispredicted_rows"] / max(rows, 1), 5),
+                "mlp_ms": round(st["mlp_ms"], 4), "model_rows": meta.get("rows"),
+                "model_quantile": meta.get("quantile"), "margin_log2": round(margin, 3)})
+    return out
 
 
 def _learned_opts():
@@ -139,7 +153,8 @@ def _learned_opts():
 
 
 def rmat_learned_vs_plain(steps, scale=18, seed=1):
-    """R-MAT scale 18 (FP32) A*A with upper-bound and with learned binning."""
+    """R-MAT scale 18 (FP32) A*A with the products bound, the compressed-run
+    bound and learned binning."""
     import torch
     from paper_2103_11991_amd import gen
     from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
@@ -148,12 +163,12 @@ def rmat_learned_vs_plain(steps, scale=18, seed=1):
     out = {"workload": f"C=A*A, A = R-MAT scale {scale} edge factor 16 (a=0.57, b=c=0.19), seed {seed}, FP32",
            "rows": A.m, "nnz_a": A.nnz}
     w, lopts = _learned_opts()
-    for label, opts in (("plain", {}), ("learned", lopts)):
+    for label, opts in (("products_bound", {"binning": 0}), ("runs_bound", {"binning": 2}), ("learned", lopts)):
         if opts is None:
             out[label] = None
             continue
         op = SpGEMM(dA, dA, timing=1, **opts)
-        if w is not None and opts:
+        if opts.get("binning") == 1:
             op.set_mlp(w)
         for _ in range(2):
             op.symbolic()
@@ -169,17 +184,18 @@ def rmat_learned_vs_plain(steps, scale=18, seed=1):
         out["nnz_c"] = int(st["nnz_c"])
         del op
         torch.cuda.synchronize()
-    if out.get("plain") and out.get("learned"):
-        out["speedup_full"] = round(out["plain"]["t_full_ms"] / out["learned"]["t_full_ms"], 3)
-        out["speedup_sym"] = round(out["plain"]["t_sym_ms"] / out["learned"]["t_sym_ms"], 3)
+    if out.get("learned"):
+        for ref in ("products_bound", "runs_bound"):
+            out[f"learned_speedup_full_vs_{ref}"] = round(out[ref]["t_full_ms"] / out["learned"]["t_full_ms"], 3)
+            out[f"learned_speedup_sym_vs_{ref}"] = round(out[ref]["t_sym_ms"] / out["learned"]["t_sym_ms"], 3)
     return out
 
 
 def galerkin_chain(sweeps=10, n0=128, levels=5):
     """R*(A*P) over 5 aggregation levels from a 7-point Laplacian on 128^3:
     the whole chain with both phases, then `sweeps` numeric-only passes with
-    changed fine-level values (symbolic reused), for upper-bound and learned
-    binning."""
+    changed fine-level values (symbolic reused), for the products bound, the
+    compressed-run bound and learned binning."""
     import torch
     from paper_2103_11991_amd import gen
     from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
@@ -189,7 +205,7 @@ def galerkin_chain(sweeps=10, n0=128, levels=5):
     out = {"workload": f"Galerkin R*(A*P), 7-point Laplacian {n0}^3, 2x2x2 aggregation, {levels} levels, FP64, "
                        f"{sweeps} changed-value numeric sweeps"}
     w, lopts = _learned_opts()
-    for label, opts in (("plain", {}), ("learned", lopts)):
+    for label, opts in (("products_bound", {"binning": 0}), ("runs_bound", {"binning": 2}), ("learned", lopts)):
         if opts is None:
             out[label] = None
             continue
@@ -203,7 +219,7 @@ def galerkin_chain(sweeps=10, n0=128, levels=5):
                 for X, Y in ((None, dP), (dR, None)):
                     left, right = (cur, Y) if X is None else (X, cur)
                     op = SpGEMM(left, right, **opts)
-                    if opts:
+                    if opts.get("binning") == 1:
                         op.set_mlp(w)
                     rp, nnz = op.symbolic()
                     col, val = op.numeric()
@@ -228,8 +244,10 @@ def galerkin_chain(sweeps=10, n0=128, levels=5):
         out["multiply_adds"] = int(products)
         del ops
         torch.cuda.synchronize()
-    if out.get("plain") and out.get("learned"):
-        out["learned_speedup_chain"] = round(out["plain"]["t_chain_full_ms"] / out["learned"]["t_chain_full_ms"], 3)
+    if out.get("learned"):
+        for ref in ("products_bound", "runs_bound"):
+            out[f"learned_speedup_chain_vs_{ref}"] = round(
+                out[ref]["t_chain_full_ms"] / out["learned"]["t_chain_full_ms"], 3)
     return out
 
 
@@ -406,7 +424,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"C=A*A, A = 3D 27-point stencil on {N}^3 (FP64 U[-1,1], diagonal 27), "
-                               "plain two-phase (upper-bound binning)",
+                               "plain two-phase (upper-bound binning from compressed-B runs)",
                    "rows": A.m, "nnz_a": nnz_a, "nnz_c": int(nnz), "multiply_adds": products,
                    **({"options": opts} if opts else {})},
         "c_nnz_per_s": round(nnz / (ms_step * 1e-3), 1),

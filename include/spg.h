@@ -60,9 +60,11 @@ typedef enum { SPG_F32 = 0, SPG_F64 = 1 } spg_dtype;
 
 /* Options for spg_set_option. */
 typedef enum {
-    /* how symbolic sizes each row's accumulator: 0 = exact upper bound from
-       the row's products and column range (default), 1 = learned predictor
-       set by spg_set_mlp, with overflow detection and an exact retry */
+    /* how symbolic sizes each row's accumulator (its occupied 32-column
+       blocks): 0 = upper bound from the row's products, 1 = learned predictor
+       set by spg_set_mlp, with overflow detection and an exact retry, 2 =
+       upper bound from the compressed-B runs the row reads (tighter than 0,
+       default); all three are capped by the row's column range */
     SPG_OPT_BINNING = 0,
     /* record HIP events around every launch (default 0); read with spg_get_stats */
     SPG_OPT_TIMING = 1,

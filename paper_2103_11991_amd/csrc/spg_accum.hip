@@ -349,21 +349,103 @@ struct WinView {
     }
 };
 
-// One batch: issue the K loads of the lane (slot k holds product
-// P0 + lane + G*k when below P; off[e] turns it into an index into B or
-// compressed B), then hand each to apply(value, entry).
-template <int G, int K, typename Load>
+// Groups: V consecutive entries of one B row (or runs of one compressed-B
+// row) from index q, the first n = min(V, end - q) of them valid, read with
+// one 16-byte load per array (dword-aligned: 16-byte loads need only that on
+// this target) unless the group would reach past the array's end.
+struct __attribute__((packed, aligned(4))) U4 {
+    int x, y, z, w;
+};
+struct __attribute__((packed, aligned(8))) D2 {
+    double x, y;
+};
+struct __attribute__((packed, aligned(4))) F4 {
+    float x, y, z, w;
+};
+
+template <typename T>
+struct ColVal {
+    int c;
+    T y;
+};
+
+template <int V>
+struct RunGroup {  // V = 1 or 2
+    int2 r[V];
+    int n;
+    __device__ inline int2 at(int j) const { return r[j]; }
+};
+
+template <typename T>
+struct BGroup {  // FLAT_VB == 4
+    int c[4];
+    T y[4];
+    int n;
+    __device__ inline ColVal<T> at(int j) const { return ColVal<T>{c[j], y[j]}; }
+};
+
+template <int V>
+__device__ inline RunGroup<V> load_runs(const int2* __restrict__ bc, int64_t total, int q, int end) {
+    RunGroup<V> g;
+    g.n = min(V, end - q);
+    if constexpr (V == 1) {
+        g.r[0] = bc[q];
+    } else if (q + 2 <= total) {
+        const U4 v = *reinterpret_cast<const U4*>(bc + q);
+        g.r[0] = make_int2(v.x, v.y);
+        g.r[1] = make_int2(v.z, v.w);
+    } else {  // the array's last run: n == 1
+        g.r[0] = bc[q];
+        g.r[1] = make_int2(0, 0);
+    }
+    return g;
+}
+
+template <typename T>
+__device__ inline BGroup<T> load_b(const int32_t* __restrict__ bci, const T* __restrict__ bv, int64_t total, int q,
+                                   int end) {
+    BGroup<T> g;
+    g.n = min(4, end - q);
+    if (q + 4 <= total) {
+        const U4 c = *reinterpret_cast<const U4*>(bci + q);
+        g.c[0] = c.x, g.c[1] = c.y, g.c[2] = c.z, g.c[3] = c.w;
+        if constexpr (sizeof(T) == 8) {
+            const D2 v0 = *reinterpret_cast<const D2*>(bv + q);
+            const D2 v1 = *reinterpret_cast<const D2*>(bv + q + 2);
+            g.y[0] = v0.x, g.y[1] = v0.y, g.y[2] = v1.x, g.y[3] = v1.y;
+        } else {
+            const F4 v = *reinterpret_cast<const F4*>(bv + q);
+            g.y[0] = v.x, g.y[1] = v.y, g.y[2] = v.z, g.y[3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            g.c[j] = 0, g.y[j] = T(0);
+            if (j < g.n) g.c[j] = bci[q + j], g.y[j] = bv[q + j];
+        }
+    }
+    return g;
+}
+
+// One batch: issue the K group loads of the lane (slot k holds group
+// P0 + lane + G*k when below P; off[e] = {start - V * first group, end} of
+// staged entry e turns it into an index), then hand every valid element to
+// apply(element, entry).
+template <int G, int K, int V, typename Load>
 struct Batch {
-    using V = decltype(std::declval<Load>()(0));
-    V v[K];
+    using R = decltype(std::declval<Load>()(0, 0));
+    R v[K];
     WinView<G, K> view;
-    __device__ inline void issue(const int32_t* off, const Win* win, int P0, int P, int lane, int wv,
+    __device__ inline void issue(const int2* off, const Win* win, int P0, int P, int lane, int wv,
                                  unsigned long long le, Load& load) {
         view.load(win, wv);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const int p = P0 + k * G + lane;
-            if (p < P) v[k] = load(off[view.entry(k, wv, le)] + p);
+            const int g = P0 + k * G + lane;
+            if (g < P) {
+                const int2 o = off[view.entry(k, wv, le)];
+                v[k] = load(o.x + V * g, o.y);
+            }
         }
     }
     // the entry is found again here rather than held in a register across the
@@ -372,15 +454,20 @@ struct Batch {
     __device__ inline void consume(int P0, int P, int lane, int wv, unsigned long long le, Apply& apply) {
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            if (P0 + k * G + lane < P) apply(v[k], view.entry(k, wv, le));
+            if (P0 + k * G + lane < P) {
+                const int e = view.entry(k, wv, le);
+#pragma unroll
+                for (int j = 0; j < V; ++j)
+                    if (j < v[k].n) apply(v[k].at(j), e);
+            }
     }
 };
 
 // Staged chunk of A's row, kept in the lanes' registers while it is in use.
 struct Chunk {
-    int pb, pc;      // first product / first run of the lane's entry
+    int pb, pc;      // first B group / first run group of the lane's entry
     bool ne;         // the entry's B row is nonempty
-    int nr, P, PC;   // nonempty entries, products and runs of the chunk
+    int nr, P, PC;   // nonempty entries, B groups and run groups of the chunk
 };
 
 // ------------------------------------------------------------------ symbolic
@@ -410,8 +497,8 @@ void k_sym(SymArgs a) {
     const int i = d.x, a0 = d.y, a1 = d.z;
     uint8_t* row_lds = reinterpret_cast<uint8_t*>(smem) + (size_t)sub * per_row;
     uint32_t* tab = reinterpret_cast<uint32_t*>(row_lds);
-    int32_t* cq = reinterpret_cast<int32_t*>(row_lds + bytes);   // staged run offsets
-    Win* win = reinterpret_cast<Win*>(row_lds + bytes + 4 * G);
+    int2* cq = reinterpret_cast<int2*>(row_lds + bytes);   // staged run {offset, end}
+    Win* win = reinterpret_cast<Win*>(row_lds + bytes + 8 * G);
     int base = 0, ncell, T = 0, logT = 0;
     int32_t* keys = reinterpret_cast<int32_t*>(tab);
     uint32_t* masks = tab;
@@ -439,7 +526,7 @@ void k_sym(SymArgs a) {
     group_sync<G>();
     int cnt = 0, nb = 0;
     const int occ_max = (T * 3) / 4;
-    auto load_run = [&](int q) { return a.bc[q]; };
+    auto load_run = [&](int q, int end) { return load_runs<FLAT_VC_SYM>(a.bc, a.bc_total, q, end); };
     auto apply = [&](int2 run, int) {
         const uint32_t bits = (uint32_t)run.y;
         int cell;
@@ -465,13 +552,13 @@ void k_sym(SymArgs a) {
             win_clear<G, KC>(win, lane);
             group_sync<G>();
         }
-        // stage: the chunk's nonempty entries in order, numbered runs
+        // stage: the chunk's nonempty entries in order, numbered run groups
         int4 h = make_int4(0, 0, 0, 0);
         if (lane < a1 - e0) h = a.bhdr[a.aci[e0 + lane]];
         const bool ne = h.w > 0;
         int3 tot;
-        const int3 ex = group_excl_scan3<G>(make_int3(ne, h.w, 0), tot, red);
-        if (ne) cq[ex.x] = h.z - ex.y;
+        const int3 ex = group_excl_scan3<G>(make_int3(ne, (h.w + FLAT_VC_SYM - 1) / FLAT_VC_SYM, 0), tot, red);
+        if (ne) cq[ex.x] = make_int2(h.z - FLAT_VC_SYM * ex.y, h.z + h.w);
         win_mark<G, KC>(win, ne, ex.y, 0);
         group_sync<G>();
         win_scan<G, KC, 0>(win, nullptr, 0, 0, lane, red);
@@ -487,7 +574,7 @@ void k_sym(SymArgs a) {
                 win_scan<G, KC, 0>(win, nullptr, before, 0, lane, red);
                 group_sync<G>();
             }
-            Batch<G, KC, decltype(load_run)> bt;
+            Batch<G, KC, FLAT_VC_SYM, decltype(load_run)> bt;
             bt.issue(cq, win, P0, tot.y, lane, wv, le, load_run);
             bt.consume(P0, tot.y, lane, wv, le, apply);
         }
@@ -598,7 +685,7 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     constexpr int RPW = rows_per_wg<G>();
     constexpr int W = waves_of<G>();
     constexpr int KB = sizeof(T) == 8 ? FLAT_KB_F64 : FLAT_KB_F32;
-    constexpr int KC = sizeof(T) == 8 ? FLAT_KC_F64 : FLAT_KC_F32;
+    constexpr int KC = FLAT_KC_NUM;
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int red[48];
     __shared__ int ncompact[RPW];
@@ -621,10 +708,10 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     const int w1 = (words + 31) >> 5;
     uint8_t* row_lds = reinterpret_cast<uint8_t*>(smem) + (size_t)sub * per_row;
     uint8_t* tab = row_lds;
-    int32_t* bq = reinterpret_cast<int32_t*>(row_lds + bytes);        // staged B offsets
-    int32_t* cq = bq + G;                                             // staged run offsets
-    T* ava = reinterpret_cast<T*>(row_lds + bytes + G * 8);           // their A values
-    Win* winb = reinterpret_cast<Win*>(row_lds + bytes + G * 16);     // product windows
+    int2* bq = reinterpret_cast<int2*>(row_lds + bytes);              // staged B {offset, end}
+    int2* cq = bq + G;                                                // staged run {offset, end}
+    T* ava = reinterpret_cast<T*>(row_lds + bytes + G * 16);          // their A values
+    Win* winb = reinterpret_cast<Win*>(row_lds + bytes + G * 24);     // B group windows
     Win* winc = winb + FLAT_KB_F32 * W;                              // run windows
     // direct: {mask, prefix} per word.  two-level: l1 {bits, prefix} per 32
     // blocks, cm {mask, prefix} and blk per occupied block.  hashed: slots,
@@ -683,11 +770,12 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
         }
         ch.ne = h.y > 0;
         int3 tot;
-        const int3 ex = group_excl_scan3<G>(make_int3(ch.ne, h.y, h.w), tot, red);
+        const int3 ex = group_excl_scan3<G>(
+            make_int3(ch.ne, (h.y + FLAT_VB - 1) / FLAT_VB, (h.w + FLAT_VC - 1) / FLAT_VC), tot, red);
         ch.pb = ex.y, ch.pc = ex.z, ch.nr = tot.x, ch.P = tot.y, ch.PC = tot.z;
         if (ch.ne) {
-            bq[ex.x] = h.x - ex.y;
-            cq[ex.x] = h.z - ex.z;
+            bq[ex.x] = make_int2(h.x - FLAT_VB * ex.y, h.x + h.y);
+            cq[ex.x] = make_int2(h.z - FLAT_VC * ex.z, h.z + h.w);
             ava[ex.x] = v;
         }
         win_mark<G, KB>(winb, ch.ne, ch.pb, 0);
@@ -723,18 +811,14 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
         group_sync<G>();
         held = P0;
     };
-    auto load_run = [&](int q) { return a.bc[q]; };
-    struct CV {
-        int c;
-        T y;
-    };
-    auto load_cv = [&](int q) { return CV{a.bci[q], bv[q]}; };
+    auto load_run = [&](int q, int end) { return load_runs<FLAT_VC>(a.bc, a.bc_total, q, end); };
+    auto load_cv = [&](int q, int end) { return load_b<T>(a.bci, bv, a.bnnz, q, end); };
     auto walk_runs = [&](auto&& apply) {
         for (int e0 = a0; e0 < a1; e0 += G) {
             restage(e0);
             for (int P0 = 0; P0 < ch.PC; P0 += KC * G) {
                 rewin(std::integral_constant<int, 1>{}, P0);
-                Batch<G, KC, decltype(load_run)> bt;
+                Batch<G, KC, FLAT_VC, decltype(load_run)> bt;
                 bt.issue(cq, winc, P0, ch.PC, lane, wv, le, load_run);
                 bt.consume(P0, ch.PC, lane, wv, le, apply);
             }
@@ -745,7 +829,7 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
             restage(e0);
             for (int P0 = 0; P0 < ch.P; P0 += KB * G) {
                 rewin(std::integral_constant<int, 0>{}, P0);
-                Batch<G, KB, decltype(load_cv)> bt;
+                Batch<G, KB, FLAT_VB, decltype(load_cv)> bt;
                 bt.issue(bq, winb, P0, ch.P, lane, wv, le, load_cv);
                 bt.consume(P0, ch.P, lane, wv, le, apply);
             }
@@ -845,7 +929,7 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
             }
         }
         group_sync<G>();
-        bwalk([&](const CV& v, int e) {
+        bwalk([&](const ColVal<T>& v, int e) {
             int rank;
             if constexpr (MODE == MODE_DIRECT) {
                 const uint2 mp = dw[(v.c >> 5) - base];
@@ -895,8 +979,8 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     stage(a0);
     if (a1 - a0 <= G && ch.P <= KB * G && ch.PC <= KC * G) {
         // the whole row in one batch: runs and B entries are loaded together
-        Batch<G, KC, decltype(load_run)> br;
-        Batch<G, KB, decltype(load_cv)> bb;
+        Batch<G, KC, FLAT_VC, decltype(load_run)> br;
+        Batch<G, KB, FLAT_VB, decltype(load_cv)> bb;
         br.issue(cq, winc, 0, ch.PC, lane, wv, le, load_run);
         bb.issue(bq, winb, 0, ch.P, lane, wv, le, load_cv);
         finish([&](auto&& apply) { br.consume(0, ch.PC, lane, wv, le, apply); },

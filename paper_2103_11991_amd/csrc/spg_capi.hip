@@ -50,7 +50,7 @@ struct spg_handle_s {
     int64_t annz = 0, bnnz = 0;
 
     // options
-    int binning = 0;
+    int binning = 2;
     int timing = 0;
     int force_class = -1;
     int work_per_lane = 16;
@@ -258,7 +258,7 @@ void sym_stage_analysis(spg_handle h) {
     if (h->m == 0) return;
     launch_b_rowinfo(s, h->n, h->k, h->brp, h->bci, h->bnnz, h->binfo.as<int4>(), ctl);
     launch_a_rowinfo(s, h->m, h->n, h->arp, h->aci, h->annz, h->binfo.as<int4>(), h->rinfo.as<RowInfo>(),
-                     want_feats ? h->feats.as<float>() : nullptr, h->cfg, learned ? 1 : 0, h->sym_cls.as<uint8_t>(),
+                     want_feats ? h->feats.as<float>() : nullptr, h->cfg, h->binning, h->sym_cls.as<uint8_t>(),
                      h->row_nnz.as<int32_t>(), h->row_blocks.as<int32_t>(), ctl);
     rec(h, EV_ANA1);
     if (learned) {
@@ -310,6 +310,7 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
         a.vec = h->vecc_used;
         a.arp = h->arp, a.aci = h->aci, a.brp = h->brp, a.bci = h->bci;
         a.bcrp = h->bcrp.as<int32_t>(), a.bc = h->bc.as<int2>(), a.bhdr = h->bhdr.as<int4>();
+        a.bc_total = h->geom.bc_total;
         a.rinfo = h->rinfo.as<RowInfo>();
         a.row_nnz = h->row_nnz.as<int32_t>();
         a.row_blocks = h->row_blocks.as<int32_t>();
@@ -335,6 +336,7 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
         a.vec = h->vecc_used;
         a.arp = h->arp, a.aci = h->aci, a.brp = h->brp, a.bci = h->bci;
         a.bcrp = h->bcrp.as<int32_t>(), a.bc = h->bc.as<int2>(), a.bhdr = h->bhdr.as<int4>();
+        a.bc_total = h->geom.bc_total;
         a.rinfo = h->rinfo.as<RowInfo>();
         a.row_nnz = h->row_nnz.as<int32_t>();
         a.row_blocks = h->row_blocks.as<int32_t>();
@@ -423,6 +425,8 @@ spg_status num_launch_all(spg_handle h, const void* a_vals, const void* b_vals, 
         a.arp = h->arp, a.aci = h->aci, a.av = a_vals;
         a.brp = h->brp, a.bci = h->bci, a.bv = b_vals;
         a.bcrp = h->bcrp.as<int32_t>(), a.bc = h->bc.as<int2>(), a.bhdr = h->bhdr.as<int4>();
+        a.bc_total = h->geom.bc_total;
+        a.bnnz = h->bnnz;
         a.vecc = h->vecc_used;
         a.crp = h->crp;
         a.rinfo = h->rinfo.as<RowInfo>();
@@ -599,7 +603,7 @@ spg_status spg_set_option(spg_handle h, int32_t opt, int64_t val) {
     if (!h) return SPG_ERR_ARG;
     switch (opt) {
         case SPG_OPT_BINNING:
-            if (val != 0 && val != 1) return fail(h, SPG_ERR_ARG, "binning must be 0 or 1");
+            if (val < 0 || val > 2) return fail(h, SPG_ERR_ARG, "binning must be 0, 1 or 2");
             h->binning = (int)val;
             break;
         case SPG_OPT_TIMING: h->timing = val != 0; break;

@@ -55,22 +55,26 @@ __host__ __device__ inline int tier_rows(int t) {
     int g = tier_threads(t);
     return g <= 64 ? 256 / g : 1;
 }
-// Flat product mapping of the row kernels: a batch gives every lane K slots,
-// products (or compressed-B runs) lane + G*k of the staged A chunk.
-constexpr int FLAT_KC = 8;       // compressed-B runs per lane and batch (symbolic; table size)
-constexpr int FLAT_KC_F64 = 5;   // numeric, FP64: runs and B entries of a row are in flight
-constexpr int FLAT_KC_F32 = 6;   // together, so fewer run slots keep the registers in check
-constexpr int FLAT_KB_F64 = 12;  // B entries per lane and batch, FP64 values
-constexpr int FLAT_KB_F32 = 16;  // B entries per lane and batch, FP32 values
+// Flat product mapping of the row kernels: an A entry's B row is cut into
+// groups of FLAT_VB consecutive entries (its compressed-B row into groups of
+// FLAT_VC runs), each read with 16-byte loads; a batch gives every lane K
+// slots, groups lane + G*k of the staged A chunk.
+constexpr int FLAT_VB = 4;       // B entries per group
+constexpr int FLAT_VC = 2;       // compressed-B runs per group (numeric)
+constexpr int FLAT_VC_SYM = 1;   // compressed-B runs per group (symbolic)
+constexpr int FLAT_KC = 5;       // run groups per lane and batch (symbolic; window table size)
+constexpr int FLAT_KC_NUM = 3;   // numeric: runs and B groups of a row are in flight together
+constexpr int FLAT_KB_F64 = 3;   // B groups per lane and batch, FP64 values
+constexpr int FLAT_KB_F32 = 4;   // B groups per lane and batch, FP32 values (window table size)
 __host__ __device__ inline int group_waves(int g) { return g > 64 ? g / 64 : 1; }
-// staging of one row: per staged A entry its B and compressed-B offsets (4
-// bytes each) and A's value (8), then the two window tables (16 bytes per
-// window and wavefront) of the batch in flight
+// staging of one row: per staged A entry its B and compressed-B {offset,
+// end} pairs (8 bytes each) and A's value (8), then the two window tables
+// (16 bytes per window and wavefront) of the batch in flight
 __host__ __device__ inline int stage_bytes(int g) {
-    return g * 16 + (FLAT_KB_F32 + FLAT_KC) * group_waves(g) * 16;
+    return g * 24 + (FLAT_KB_F32 + FLAT_KC) * group_waves(g) * 16;
 }
 // the symbolic phase stages no values and walks compressed B only
-__host__ __device__ inline int sym_stage_bytes(int g) { return g * 4 + FLAT_KC * group_waves(g) * 16; }
+__host__ __device__ inline int sym_stage_bytes(int g) { return g * 8 + FLAT_KC * group_waves(g) * 16; }
 // dynamic LDS of one workgroup of tier t: the rows' tables plus staging
 __host__ __device__ inline int64_t tier_smem_bytes(int t) {
     return (int64_t)tier_rows(t) * (tier_bytes(t) + stage_bytes(tier_threads(t)));
@@ -226,7 +230,7 @@ void launch_b_rowinfo(hipStream_t s, int32_t n, int32_t k, const int32_t* brp, c
 void launch_compress_b(hipStream_t s, int32_t n, const int32_t* brp, const int32_t* bci, const int4* binfo,
                        int32_t* bcrp, uint64_t* tile_status, int32_t* tile_counter, int2* bc, int4* bhdr);
 void launch_a_rowinfo(hipStream_t s, int32_t m, int32_t n, const int32_t* arp, const int32_t* aci, int64_t annz,
-                      const int4* binfo, RowInfo* rinfo, float* feats, ClassCfg cfg, int learned,
+                      const int4* binfo, RowInfo* rinfo, float* feats, ClassCfg cfg, int binning,
                       uint8_t* sym_cls, int32_t* row_nnz, int32_t* row_blocks, Control* ctl);
 void launch_mlp_classify(hipStream_t s, int32_t m, const float* feats, const float* w, const RowInfo* rinfo,
                          ClassCfg cfg, float margin, uint8_t* sym_cls, Control* ctl);
@@ -260,6 +264,7 @@ struct SymArgs {
     const int32_t* bcrp;          // compressed B: row pointer and {block, mask} runs
     const int2* bc;
     const int4* bhdr;             // per B row {start, length, run start, run count}
+    int64_t bc_total;             // runs of compressed B (bound of the group loads)
     const RowInfo* rinfo;
     int32_t* row_nnz;
     int32_t* row_blocks;
@@ -287,6 +292,8 @@ struct NumArgs {
     const int32_t* bcrp;
     const int2* bc;
     const int4* bhdr;             // per B row {start, length, run start, run count}
+    int64_t bnnz;                 // entries of B and of compressed B (bounds of the
+    int64_t bc_total;             // group loads near the arrays' ends)
     int32_t vecc;                 // lanes sharing one compressed-B row
     const int32_t* crp;
     const RowInfo* rinfo;

@@ -98,12 +98,14 @@ __global__ __launch_bounds__(256) void k_b_rowinfo(int32_t n, int32_t k, const i
 
 __device__ inline float log2p1(int64_t v) { return log2f(1.0f + (float)v); }
 
-// A rows: products, column range, largest B row; symbolic class (upper-bound
-// binning) or features only (learned binning, classified by k_mlp_classify).
+// A rows: products, column range, largest B row; symbolic class from an upper
+// bound on the row's occupied blocks (binning 0: its products, 2: the
+// compressed-B runs it reads) or features only (binning 1, learned: classified
+// by k_mlp_classify).
 __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const int32_t* __restrict__ arp,
                                                    const int32_t* __restrict__ aci, int64_t annz,
                                                    const int4* __restrict__ binfo, RowInfo* __restrict__ rinfo,
-                                                   float* __restrict__ feats, ClassCfg cfg, int learned,
+                                                   float* __restrict__ feats, ClassCfg cfg, int binning,
                                                    uint8_t* __restrict__ sym_cls, int32_t* __restrict__ row_nnz,
                                                    int32_t* __restrict__ row_blocks, Control* ctl) {
     __shared__ int32_t hist[NCLS];
@@ -175,8 +177,8 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
                 int64_t words = row_words(cmin, cmax);
                 atomicMax(&wmax_all, (unsigned long long)words);
                 atomicAdd(&prod_sum, (unsigned long long)ub);
-                if (!learned) {
-                    cls = sym_class(ub, cmin, cmax, rs, cfg, true);
+                if (binning != 1) {
+                    cls = sym_class(ub, cmin, cmax, binning == 2 ? rs : ub, cfg, true);
                     sym_cls[row] = (uint8_t)cls;
                     atomicAdd(&hist[cls], 1);
                     if (cls % NTIER == TIER_GLOBAL) atomicMax(&wmax_glob, (unsigned long long)words);
@@ -615,12 +617,12 @@ void launch_compress_b(hipStream_t s, int32_t n, const int32_t* brp, const int32
 }
 
 void launch_a_rowinfo(hipStream_t s, int32_t m, int32_t n, const int32_t* arp, const int32_t* aci, int64_t annz,
-                      const int4* binfo, RowInfo* rinfo, float* feats, ClassCfg cfg, int learned,
+                      const int4* binfo, RowInfo* rinfo, float* feats, ClassCfg cfg, int binning,
                       uint8_t* sym_cls, int32_t* row_nnz, int32_t* row_blocks, Control* ctl) {
     if (m <= 0) return;
     hipLaunchKernelGGL(k_a_rowinfo, dim3(std::min(grid_for((int64_t)m * ROW_LANES, 256), 1024u)), dim3(256), 0, s, m, n,
                        arp, aci,
-                       annz, binfo, rinfo, feats, cfg, learned, sym_cls, row_nnz, row_blocks, ctl);
+                       annz, binfo, rinfo, feats, cfg, binning, sym_cls, row_nnz, row_blocks, ctl);
 }
 
 void launch_mlp_classify(hipStream_t s, int32_t m, const float* feats, const float* w, const RowInfo* rinfo,

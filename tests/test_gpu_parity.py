@@ -26,16 +26,17 @@ def test_laplace2d_squared_is_bit_exact():
     compare(A, A, rp, c, v, exact=True)
 
 
+@pytest.mark.parametrize("binning", [2, 0])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("seed", range(6))
-def test_random_shapes(seed, dtype):
+def test_random_shapes(seed, dtype, binning):
     rng = np.random.default_rng(seed)
     m, n, k = (int(x) for x in rng.integers(1, 700, size=3))
     A = gen.random_csr(m, n, 0, int(rng.integers(1, 40)), seed=seed, dtype=dtype, empty_frac=0.15,
                        duplicates=seed % 3 == 0, sorted_rows=seed % 2 == 0)
     B = gen.random_csr(n, k, 0, int(rng.integers(1, 60)), seed=seed + 77, dtype=dtype, empty_frac=0.1,
                        duplicates=seed % 4 == 1, sorted_rows=seed % 3 != 1)
-    rp, c, v, _ = run_gpu(A, B)
+    rp, c, v, _ = run_gpu(A, B, binning=binning)
     compare(A, B, rp, c, v)
 
 
