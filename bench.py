@@ -55,6 +55,54 @@ def stored_traffic(kernel: str):
         return None
 
 
+def _pmc_rows(d: str):
+    import csv
+    import glob
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            yield from csv.DictReader(fh)
+
+
+def summarize_counters(fetch_dir, write_dir, cfetch_dir, cwrite_dir, cls: int, command: str) -> dict:
+    """HBM bytes per launch of the dominant numeric kernel from rocprofv3
+    FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch), each scaled by what the
+    same counter reads for the plain 1 GiB copy of --copy-calibration; writes
+    profiles/traffic.json keyed by the class, with the kernel source hash."""
+    def per_dispatch(d, counter, want):
+        vals = {}
+        for r in _pmc_rows(d):
+            if r["Counter_Name"] == counter and want(r["Kernel_Name"]):
+                vals.setdefault((int(r["Grid_Size"]), r["Dispatch_Id"]), 0.0)
+                vals[(int(r["Grid_Size"]), r["Dispatch_Id"])] += float(r["Counter_Value"])
+        return vals
+
+    is_num = lambda k: "k_num<" in k
+    is_copy = lambda k: "copyBuffer" in k
+    out = {}
+    for counter, d, cd in (("FETCH_SIZE", fetch_dir, cfetch_dir), ("WRITE_SIZE", write_dir, cwrite_dir)):
+        v = per_dispatch(d, counter, is_num)
+        grid = max(g for g, _ in v)   # the dominant class launches the largest grid
+        kib = [x for (g, _), x in v.items() if g == grid]
+        c = [x for (g, _), x in per_dispatch(cd, counter, is_copy).items() if g == max(g2 for g2, _ in per_dispatch(cd, counter, is_copy))]
+        factor = (1 << 30) / (1024.0 * float(np.mean(c)))   # true KiB per counted KiB
+        out[counter] = {"kib_per_launch": float(np.mean(kib)), "launches": len(kib), "grid": grid,
+                        "copy_kib_per_gib": float(np.mean(c)), "scale": round(factor, 4),
+                        "bytes_per_launch": float(np.mean(kib)) * 1024.0 * factor}
+    ent = {"source_sha": kernel_source_sha(), "hbm_bytes_per_launch":
+           out["FETCH_SIZE"]["bytes_per_launch"] + out["WRITE_SIZE"]["bytes_per_launch"],
+           "fetch": out["FETCH_SIZE"], "write": out["WRITE_SIZE"], "command": command}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    d = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            d = json.load(fh)
+    d[f"num_class_{cls}"] = ent
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as fh:
+        json.dump(d, fh, indent=1)
+    return ent
+
+
 def cpu_baseline(A, target_s: float = 12.0):
     """The oracle (symbolic + numeric) on the same product, timed on the host
     cores: whole-product passes repeated until about target_s seconds (or a
@@ -339,11 +387,20 @@ def main():
                     help="library option for the timed product (e.g. work_per_lane=32); repeatable")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (HBM counter calibration) and exit")
+    ap.add_argument("--counters", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="rocprofv3 output folders of FETCH_SIZE and WRITE_SIZE runs of this bench and of "
+                         "--copy-calibration: write profiles/traffic.json for --counters-class and exit (no GPU)")
+    ap.add_argument("--counters-class", type=int, default=23)
+    ap.add_argument("--counters-command", default="", help="the rocprofv3 command recorded beside the figures")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(1)
+    if args.counters:
+        ent = summarize_counters(*args.counters, cls=args.counters_class, command=args.counters_command)
+        print(json.dumps(ent), flush=True)
+        return
 
     import torch
     from paper_2103_11991_amd import gen
