@@ -88,44 +88,75 @@ __device__ inline void group_sync() {
     }
 }
 
+// Inclusive sum over each aligned group of min(G, 64) lanes of a wavefront:
+// DPP row shifts inside rows of 16 lanes, then broadcasts of lanes 15 and 31
+// into the following rows.  No LDS traffic.
+template <int G>
+__device__ inline int wave_incl_scan(int x) {
+    constexpr int S = G < 64 ? G : 64;
+    const int l = threadIdx.x & (S - 1);
+    if constexpr (S >= 2) {
+        const int y = __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+        x += (S >= 16 || l >= 1) ? y : 0;
+    }
+    if constexpr (S >= 4) {
+        const int y = __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+        x += (S >= 16 || l >= 2) ? y : 0;
+    }
+    if constexpr (S >= 8) {
+        const int y = __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+        x += (S >= 16 || l >= 4) ? y : 0;
+    }
+    if constexpr (S >= 16) x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    if constexpr (S >= 32) x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    if constexpr (S >= 64) x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return x;
+}
+
+// Value held by the last lane of the lane's group of G <= 64 lanes.
+template <int G>
+__device__ inline int group_last(int x) {
+    if constexpr (G >= 64) {
+        return __builtin_amdgcn_readlane(x, 63);
+    } else {
+        const int g = (threadIdx.x & 63) / G;
+        int r = 0;
+#pragma unroll
+        for (int t = 0; t < 64 / G; ++t) {
+            const int v = __builtin_amdgcn_readlane(x, t * G + G - 1);
+            r = g == t ? v : r;
+        }
+        return r;
+    }
+}
+
 template <int G>
 __device__ inline int group_sum(int v, int* red) {
     if constexpr (G <= 64) {
-        for (int d = G / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, G);
-        return v;
+        return group_last<G>(wave_incl_scan<G>(v));
     } else {
         constexpr int W = G / 64;
         const int wl = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+        const int t = __builtin_amdgcn_readlane(wave_incl_scan<64>(v), 63);
         __syncthreads();
-        if (wl == 0) red[wv] = v;
+        if (wl == 0) red[wv] = t;
         __syncthreads();
-        int t = 0;
-        for (int u = 0; u < W; ++u) t += red[u];
-        return t;
+        int s = 0;
+        for (int u = 0; u < W; ++u) s += red[u];
+        return s;
     }
 }
 
 // Exclusive prefix sum over the G lanes of a group; total gets the sum.
 template <int G>
 __device__ inline int group_excl_scan(int v, int& total, int* red) {
+    const int x = wave_incl_scan<G>(v);
     if constexpr (G <= 64) {
-        const int lane = threadIdx.x % G;
-        int x = v;
-        for (int d = 1; d < G; d <<= 1) {
-            int y = __shfl_up(x, d, G);
-            if (lane >= d) x += y;
-        }
-        total = __shfl(x, G - 1, G);
+        total = group_last<G>(x);
         return x - v;
     } else {
         constexpr int W = G / 64;
         const int wl = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        int x = v;
-        for (int d = 1; d < 64; d <<= 1) {
-            int y = __shfl_up(x, d, 64);
-            if (wl >= d) x += y;
-        }
         __syncthreads();
         if (wl == 63) red[wv] = x;
         __syncthreads();
@@ -235,23 +266,13 @@ __device__ inline int xcd_block(int b, int nblk) {
 
 template <int G>
 __device__ inline int3 group_excl_scan3(int3 v, int3& total, int* red) {
+    const int3 x = make_int3(wave_incl_scan<G>(v.x), wave_incl_scan<G>(v.y), wave_incl_scan<G>(v.z));
     if constexpr (G <= 64) {
-        const int lane = threadIdx.x % G;
-        int3 x = v;
-        for (int d = 1; d < G; d <<= 1) {
-            const int yx = __shfl_up(x.x, d, G), yy = __shfl_up(x.y, d, G), yz = __shfl_up(x.z, d, G);
-            if (lane >= d) x.x += yx, x.y += yy, x.z += yz;
-        }
-        total = make_int3(__shfl(x.x, G - 1, G), __shfl(x.y, G - 1, G), __shfl(x.z, G - 1, G));
+        total = make_int3(group_last<G>(x.x), group_last<G>(x.y), group_last<G>(x.z));
         return make_int3(x.x - v.x, x.y - v.y, x.z - v.z);
     } else {
         constexpr int W = G / 64;
         const int wl = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        int3 x = v;
-        for (int d = 1; d < 64; d <<= 1) {
-            const int yx = __shfl_up(x.x, d, 64), yy = __shfl_up(x.y, d, 64), yz = __shfl_up(x.z, d, 64);
-            if (wl >= d) x.x += yx, x.y += yy, x.z += yz;
-        }
         __syncthreads();
         if (wl == 63) red[3 * wv] = x.x, red[3 * wv + 1] = x.y, red[3 * wv + 2] = x.z;
         __syncthreads();
@@ -369,8 +390,9 @@ struct ColVal {
     T y;
 };
 
-template <int V>
+template <int V_>
 struct RunGroup {  // V = 1 or 2
+    static constexpr int V = V_;
     int2 r[V];
     int n;
     __device__ inline int2 at(int j) const { return r[j]; }
@@ -378,6 +400,7 @@ struct RunGroup {  // V = 1 or 2
 
 template <typename T>
 struct BGroup {  // FLAT_VB == 4
+    static constexpr int V = 4;
     int c[4];
     T y[4];
     int n;
@@ -429,8 +452,8 @@ __device__ inline BGroup<T> load_b(const int32_t* __restrict__ bci, const T* __r
 
 // One batch: issue the K group loads of the lane (slot k holds group
 // P0 + lane + G*k when below P; off[e] = {start - V * first group, end} of
-// staged entry e turns it into an index), then hand every valid element to
-// apply(element, entry).
+// staged entry e turns it into an index), then hand each group to
+// apply(group, entry).
 template <int G, int K, int V, typename Load>
 struct Batch {
     using R = decltype(std::declval<Load>()(0, 0));
@@ -451,17 +474,22 @@ struct Batch {
     // the entry is found again here rather than held in a register across the
     // wait (the window table is unchanged until then)
     template <typename Apply>
-    __device__ inline void consume(int P0, int P, int lane, int wv, unsigned long long le, Apply& apply) {
+    __device__ inline void consume(int P0, int P, int lane, int wv, unsigned long long le, Apply&& apply) {
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            if (P0 + k * G + lane < P) {
-                const int e = view.entry(k, wv, le);
-#pragma unroll
-                for (int j = 0; j < V; ++j)
-                    if (j < v[k].n) apply(v[k].at(j), e);
-            }
+            if (P0 + k * G + lane < P) apply(v[k], view.entry(k, wv, le));
     }
 };
+
+// Turns apply(element, entry) into apply(group, entry) over the valid elements.
+template <typename F>
+__device__ inline auto each(F& f) {
+    return [&f](const auto& g, int e) {
+#pragma unroll
+        for (int j = 0; j < std::decay_t<decltype(g)>::V; ++j)
+            if (j < g.n) f(g.at(j), e);
+    };
+}
 
 // Staged chunk of A's row, kept in the lanes' registers while it is in use.
 struct Chunk {
@@ -576,7 +604,7 @@ void k_sym(SymArgs a) {
             }
             Batch<G, KC, FLAT_VC_SYM, decltype(load_run)> bt;
             bt.issue(cq, win, P0, tot.y, lane, wv, le, load_run);
-            bt.consume(P0, tot.y, lane, wv, le, apply);
+            bt.consume(P0, tot.y, lane, wv, le, each(apply));
         }
     }
     cnt = group_sum<G>(cnt, red);
@@ -839,10 +867,11 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     // ---- pass 1: which columns occur; prefix; pass 2: values at their ranks
     auto finish = [&](auto&& runs, auto&& bwalk) {
         if constexpr (MODE == MODE_TWOLEVEL) {
-            runs([&](int2 run, int) {
+            auto mark_l1 = [&](int2 run, int) {
                 const int w = run.x - base;
                 atomicOr(&l1[w >> 5].x, 1u << (w & 31));
-            });
+            };
+            runs(each(mark_l1));
             group_sync<G>();
             // compact index of each occupied block: prefix of popcounts over l1
             {
@@ -859,22 +888,24 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
                 }
             }
             group_sync<G>();
-            runs([&](int2 run, int) {
+            auto or_cm = [&](int2 run, int) {
                 const int w = run.x - base;
                 const uint2 L = l1[w >> 5];
                 const int ci = (int)L.y + __popc(L.x & below(w & 31));
                 atomicOr(&cm[ci].x, (uint32_t)run.y);
                 blk[ci] = run.x;
-            });
+            };
+            runs(each(or_cm));
         } else {
-            runs([&](int2 run, int) {
+            auto or_tab = [&](int2 run, int) {
                 if constexpr (MODE == MODE_DIRECT) {
                     atomicOr(&dw[run.x - base].x, (uint32_t)run.y);
                 } else {
                     const int h = slot_insert(slots, TT, logT, run.x);
                     atomicOr(reinterpret_cast<unsigned int*>(&slots[h].y), (uint32_t)run.y);
                 }
-            });
+            };
+            runs(each(or_tab));
         }
         group_sync<G>();
         if constexpr (MODE == MODE_HASHED) {
@@ -929,27 +960,36 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
             }
         }
         group_sync<G>();
-        bwalk([&](const ColVal<T>& v, int e) {
-            int rank;
+        auto rank_of = [&](int c) {
             if constexpr (MODE == MODE_DIRECT) {
-                const uint2 mp = dw[(v.c >> 5) - base];
-                rank = (int)mp.y + __popc(mp.x & below(v.c & 31));
+                const uint2 mp = dw[(c >> 5) - base];
+                return (int)mp.y + __popc(mp.x & below(c & 31));
             } else if constexpr (MODE == MODE_TWOLEVEL) {
-                const int w = (v.c >> 5) - base;
+                const int w = (c >> 5) - base;
                 const uint2 L = l1[w >> 5];
                 const uint2 mp = cm[(int)L.y + __popc(L.x & below(w & 31))];
-                rank = (int)mp.y + __popc(mp.x & below(v.c & 31));
+                return (int)mp.y + __popc(mp.x & below(c & 31));
             } else {
-                const int key = v.c >> 5;
+                const int key = c >> 5;
                 int h = hash_slot(key, logT);
                 int4 sl = slots[h];
                 for (int probe = 1; sl.x != key && probe < TT; ++probe) {
                     h = (h + 1) & (TT - 1);
                     sl = slots[h];
                 }
-                rank = sl.z + __popc((uint32_t)sl.y & below(v.c & 31));
+                return sl.z + __popc((uint32_t)sl.y & below(c & 31));
             }
-            atomicAdd(&vals[rank], ava[e] * v.y);
+        };
+        // a group's ranks are looked up together (elements past the group's
+        // end repeat its first column), then its valid products are added
+        bwalk([&](const BGroup<T>& g, int e) {
+            const T av = ava[e];
+            int rk[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) rk[j] = rank_of(j < g.n ? g.c[j] : g.c[0]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (j < g.n) atomicAdd(&vals[rk[j]], av * g.y[j]);
         });
         // column of every rank, from the masks, straight to C
         int32_t* cc = a.ccol + off;
