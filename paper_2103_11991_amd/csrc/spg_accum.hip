@@ -71,6 +71,9 @@ __device__ inline int hash_find(const int32_t* keys, int T, int logT, int key) {
     return -1;
 }
 
+// bits below bit b of a 32-bit mask
+__device__ inline uint32_t below(int b) { return (1u << b) - 1u; }
+
 template <int G>
 constexpr int rows_per_wg() {
     return G <= 64 ? 256 / G : 1;
@@ -509,6 +512,7 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) __attribute__((amdgpu_waves_p
 void k_sym(SymArgs a) {
     constexpr int RPW = rows_per_wg<G>();
     constexpr int KC = FLAT_KC;
+    constexpr int VC = FLAT_VC_SYM;
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int red[48];
     __shared__ int occ[RPW];
@@ -527,91 +531,171 @@ void k_sym(SymArgs a) {
     uint32_t* tab = reinterpret_cast<uint32_t*>(row_lds);
     int2* cq = reinterpret_cast<int2*>(row_lds + bytes);   // staged run {offset, end}
     Win* win = reinterpret_cast<Win*>(row_lds + bytes + 8 * G);
-    int base = 0, ncell, T = 0, logT = 0;
+    // direct: a mask per word of the row's range.  hashed: keys, then masks.
+    // two-level: {bits, prefix} per 32 words, then a mask per occupied block.
+    int base = 0, ncell = 0, T = 0, logT = 0, w1 = 0, cap = 0;
     int32_t* keys = reinterpret_cast<int32_t*>(tab);
     uint32_t* masks = tab;
-    if constexpr (MODE == MODE_DIRECT) {
+    uint2* l1 = reinterpret_cast<uint2*>(tab);
+    uint32_t* cm = tab;
+    if constexpr (MODE != MODE_HASHED) {
         const RowInfo ri = a.rinfo[i];
         base = ri.x >> 5;
         ncell = (ri.y >> 5) - base + 1;
-    } else {
+    }
+    if constexpr (MODE == MODE_HASHED) {
         T = 1 << (31 - __clz(bytes / 8));
         logT = 31 - __clz(T);
         masks = tab + T;
         ncell = T;
+    } else if constexpr (MODE == MODE_TWOLEVEL) {
+        w1 = (ncell + 31) >> 5;
+        cm = reinterpret_cast<uint32_t*>(l1 + w1);
+        cap = (bytes - w1 * 8) / 4;
     }
     // 16-byte clears (tables start 256-byte aligned and tiers are multiples of 16 bytes)
     if constexpr (MODE == MODE_DIRECT) {
         for (int c = 4 * lane; c < ncell; c += 4 * G) *reinterpret_cast<uint4*>(&masks[c]) = make_uint4(0, 0, 0, 0);
-    } else {
+    } else if constexpr (MODE == MODE_HASHED) {
         for (int c = 4 * lane; c < ncell; c += 4 * G) {
             *reinterpret_cast<int4*>(&keys[c]) = make_int4(-1, -1, -1, -1);
             *reinterpret_cast<uint4*>(&masks[c]) = make_uint4(0, 0, 0, 0);
         }
+    } else {
+        for (int c = lane; c < w1; c += G) l1[c] = make_uint2(0u, 0u);
     }
     win_clear<G, KC>(win, lane);
     if (lane == 0) occ[sub] = 0, ovf[sub] = 0;
     group_sync<G>();
-    int cnt = 0, nb = 0;
-    const int occ_max = (T * 3) / 4;
-    auto load_run = [&](int q, int end) { return load_runs<FLAT_VC_SYM>(a.bc, a.bc_total, q, end); };
-    auto apply = [&](int2 run, int) {
-        const uint32_t bits = (uint32_t)run.y;
-        int cell;
-        if constexpr (MODE == MODE_DIRECT) {
-            cell = run.x - base;
-        } else {
-            if (*(volatile int*)&ovf[sub]) return;
-            bool ins;
-            cell = hash_insert(keys, T, logT, run.x, ins);
-            if (cell < 0) {
-                ovf[sub] = 1;
-                return;
-            }
-            if (ins && atomicAdd(&occ[sub], 1) >= occ_max) ovf[sub] = 1;
-        }
-        const uint32_t old = atomicOr(&masks[cell], bits);
-        cnt += __popc(bits & ~old);
-        nb += old == 0;
-    };
-    for (int e0 = a0; e0 < a1; e0 += G) {
-        if (e0 > a0) {
-            group_sync<G>();
-            win_clear<G, KC>(win, lane);
-            group_sync<G>();
-        }
-        // stage: the chunk's nonempty entries in order, numbered run groups
+
+    // ---- staging: chunks of G entries of A's row, one window table of run groups
+    int pc = 0, PC = 0;
+    bool ne = false;
+    int staged = -1, wc0 = 0;
+    auto stage = [&](int e0) {  // window table cleared and synchronised by the caller
         int4 h = make_int4(0, 0, 0, 0);
         if (lane < a1 - e0) h = a.bhdr[a.aci[e0 + lane]];
-        const bool ne = h.w > 0;
+        ne = h.w > 0;
         int3 tot;
-        const int3 ex = group_excl_scan3<G>(make_int3(ne, (h.w + FLAT_VC_SYM - 1) / FLAT_VC_SYM, 0), tot, red);
-        if (ne) cq[ex.x] = make_int2(h.z - FLAT_VC_SYM * ex.y, h.z + h.w);
-        win_mark<G, KC>(win, ne, ex.y, 0);
+        const int3 ex = group_excl_scan3<G>(make_int3(ne, (h.w + VC - 1) / VC, 0), tot, red);
+        pc = ex.y, PC = tot.y;
+        if (ne) cq[ex.x] = make_int2(h.z - VC * ex.y, h.z + h.w);
+        win_mark<G, KC>(win, ne, pc, 0);
         group_sync<G>();
         win_scan<G, KC, 0>(win, nullptr, 0, 0, lane, red);
         group_sync<G>();
-        for (int P0 = 0; P0 < tot.y; P0 += KC * G) {
-            if (P0 > 0) {
-                group_sync<G>();
-                win_clear<G, KC>(win, lane);
-                group_sync<G>();
-                win_mark<G, KC>(win, ne, ex.y, P0);
-                const int before = group_sum<G>(ne && ex.y < P0, red);
-                group_sync<G>();
-                win_scan<G, KC, 0>(win, nullptr, before, 0, lane, red);
-                group_sync<G>();
+        staged = e0, wc0 = 0;
+    };
+    auto restage = [&](int e0) {
+        if (staged == e0) return;
+        group_sync<G>();
+        win_clear<G, KC>(win, lane);
+        group_sync<G>();
+        stage(e0);
+    };
+    auto rewin = [&](int P0) {
+        if (wc0 == P0) return;
+        group_sync<G>();
+        win_clear<G, KC>(win, lane);
+        group_sync<G>();
+        win_mark<G, KC>(win, ne, pc, P0);
+        const int before = group_sum<G>(ne && pc < P0, red);
+        group_sync<G>();
+        win_scan<G, KC, 0>(win, nullptr, before, 0, lane, red);
+        group_sync<G>();
+        wc0 = P0;
+    };
+    auto load_run = [&](int q, int end) { return load_runs<VC>(a.bc, a.bc_total, q, end); };
+    auto walk_runs = [&](auto&& apply) {
+        for (int e0 = a0; e0 < a1; e0 += G) {
+            restage(e0);
+            for (int P0 = 0; P0 < PC; P0 += KC * G) {
+                rewin(P0);
+                Batch<G, KC, VC, decltype(load_run)> bt;
+                bt.issue(cq, win, P0, PC, lane, wv, le, load_run);
+                bt.consume(P0, PC, lane, wv, le, apply);
             }
-            Batch<G, KC, FLAT_VC_SYM, decltype(load_run)> bt;
-            bt.issue(cq, win, P0, tot.y, lane, wv, le, load_run);
-            bt.consume(P0, tot.y, lane, wv, le, each(apply));
         }
+    };
+
+    int cnt = 0, nb = 0;
+    auto finish = [&](auto&& runs) {
+        if constexpr (MODE == MODE_TWOLEVEL) {
+            // pass A: occupied blocks; their count and compact indices from a
+            // prefix of popcounts; pass B: masks OR-ed in at the compact index
+            auto mark = [&](int2 run, int) {
+                const int w = run.x - base;
+                atomicOr(&l1[w >> 5].x, 1u << (w & 31));
+            };
+            runs(each(mark));
+            group_sync<G>();
+            {
+                const int chunk = (w1 + G - 1) / G;
+                const int beg = lane * chunk;
+                const int end = min(beg + chunk, w1);
+                int local = 0;
+                for (int t = beg; t < end; ++t) local += __popc(l1[t].x);
+                int total;
+                int ex = group_excl_scan<G>(local, total, red);
+                for (int t = beg; t < end; ++t) {
+                    l1[t].y = (uint32_t)ex;
+                    ex += __popc(l1[t].x);
+                }
+                nb = total;
+            }
+            if (nb > cap) {  // (only under a learned estimate) the row is retried exactly
+                if (lane == 0) ovf[sub] = 1;
+                return;
+            }
+            for (int c = lane; c < nb; c += G) cm[c] = 0u;
+            group_sync<G>();
+            auto orc = [&](int2 run, int) {
+                const int w = run.x - base;
+                const uint2 L = l1[w >> 5];
+                const uint32_t bits = (uint32_t)run.y;
+                const uint32_t old = atomicOr(&cm[(int)L.y + __popc(L.x & below(w & 31))], bits);
+                cnt += __popc(bits & ~old);
+            };
+            runs(each(orc));
+        } else {
+            const int occ_max = (T * 3) / 4;
+            auto apply = [&](int2 run, int) {
+                const uint32_t bits = (uint32_t)run.y;
+                int cell;
+                if constexpr (MODE == MODE_DIRECT) {
+                    cell = run.x - base;
+                } else {
+                    if (*(volatile int*)&ovf[sub]) return;
+                    bool ins;
+                    cell = hash_insert(keys, T, logT, run.x, ins);
+                    if (cell < 0) {
+                        ovf[sub] = 1;
+                        return;
+                    }
+                    if (ins && atomicAdd(&occ[sub], 1) >= occ_max) ovf[sub] = 1;
+                }
+                const uint32_t old = atomicOr(&masks[cell], bits);
+                cnt += __popc(bits & ~old);
+                nb += old == 0;
+            };
+            runs(each(apply));
+        }
+    };
+
+    stage(a0);
+    if (a1 - a0 <= G && PC <= KC * G) {
+        // the whole row in one batch: its runs stay in registers for every pass
+        Batch<G, KC, VC, decltype(load_run)> br;
+        br.issue(cq, win, 0, PC, lane, wv, le, load_run);
+        finish([&](auto&& apply) { br.consume(0, PC, lane, wv, le, apply); });
+    } else {
+        finish(walk_runs);
     }
     cnt = group_sum<G>(cnt, red);
-    nb = group_sum<G>(nb, red);
+    if constexpr (MODE != MODE_TWOLEVEL) nb = group_sum<G>(nb, red);
     group_sync<G>();
     if (lane == 0) {
-        if (MODE == MODE_HASHED && ovf[sub]) {
+        if (MODE != MODE_DIRECT && ovf[sub]) {
             // queued for the exact retry; a table sized from an upper bound
             // (no retry list) cannot overflow, so that would be an internal error
             if (a.ovf_list) {
@@ -706,7 +790,6 @@ __device__ inline int slot_insert(int4* slots, int T, int logT, int key) {
     return -1;
 }
 
-__device__ inline uint32_t below(int b) { return (1u << b) - 1u; }
 
 template <int G, int MODE, typename T>
 __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
@@ -1170,7 +1253,8 @@ int launch_sym_class(hipStream_t s, const SymArgs& a, int grid_cap) {
     }
     if (a.count <= 0) return 0;
     if (a.mode == MODE_DIRECT) sym_dispatch<MODE_DIRECT>(s, a);
-    else sym_dispatch<MODE_HASHED>(s, a);
+    else if (a.mode == MODE_HASHED) sym_dispatch<MODE_HASHED>(s, a);
+    else sym_dispatch<MODE_TWOLEVEL>(s, a);
     return 1;
 }
 

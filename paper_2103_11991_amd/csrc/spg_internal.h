@@ -33,7 +33,7 @@ constexpr int NCLS = SPG_NCLASS;     // class = mode * NTIER + tier
 constexpr int TIER_GLOBAL = 9;
 constexpr int MODE_DIRECT = 0;
 constexpr int MODE_HASHED = 1;
-constexpr int MODE_TWOLEVEL = 2;  // numeric only
+constexpr int MODE_TWOLEVEL = 2;
 constexpr uint8_t CLS_EMPTY = 255;
 constexpr int WIDE_THREADS = 1024;   // threads per row on the global path
 
@@ -155,15 +155,21 @@ __host__ __device__ inline int sym_class(int64_t ub, int32_t cmin, int32_t cmax,
     int64_t words = row_words(cmin, cmax);
     int64_t est = est_blocks < words ? est_blocks : words;
     if (est < 1) est = 1;
+    // direct: a mask per word; hashed: keys and masks; two-level: {bits,
+    // prefix} per 32 words and a mask per (estimated) occupied block
     int64_t bd = words * 4, bh = sym_hash_slots(est, bound) * 8;
+    int64_t b2 = align8(twolevel_words(words) * 8) + est * 4;
     if (c.force_class >= 0) {
         int fm = c.force_class / NTIER, ft = c.force_class % NTIER;
         if (ft == TIER_GLOBAL) return MODE_DIRECT * NTIER + TIER_GLOBAL;
-        int64_t need = fm == MODE_DIRECT ? bd : bh;
+        int64_t need = fm == MODE_DIRECT ? bd : fm == MODE_HASHED ? bh : b2;
         if (need <= tier_bytes(ft) && tier_bytes(ft) <= c.lds_limit) return c.force_class;
     }
-    int mode = bd <= bh ? MODE_DIRECT : MODE_HASHED;
-    int t = pick_tier(bd <= bh ? bd : bh, ub, c);
+    int mode = MODE_DIRECT;
+    int64_t bytes = bd;
+    if (b2 < bytes) mode = MODE_TWOLEVEL, bytes = b2;
+    if (bh < bytes) mode = MODE_HASHED, bytes = bh;
+    int t = pick_tier(bytes, ub, c);
     if (t == TIER_GLOBAL) mode = MODE_DIRECT;
     return mode * NTIER + t;
 }

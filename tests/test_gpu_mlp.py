@@ -143,21 +143,27 @@ def test_learned_binning_gives_the_same_product(which):
         compare(A, A, rp0, col.cpu().numpy(), val.cpu().numpy())
 
 
-def test_constant_tiny_prediction_forces_retries():
-    """A predictor whose output is log2(2): every hashed table is sized for one
-    block, so rows with more blocks overflow and are redone exactly."""
+@pytest.mark.parametrize("k, table", [(400000, 10), (12000, 20)])
+def test_constant_tiny_prediction_forces_retries(k, table):
+    """A predictor whose output is log2(2): every table is sized for one block.
+    Rows of at most 128 products stay in the smallest tier (8 lanes, 256 B),
+    so rows with more blocks than that tier holds overflow and are redone
+    exactly.  With B 400000 columns wide the rows get hashed tables (class
+    10), with 12000 columns two-level ones (class 20)."""
     import torch
     from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
-    A = gen.random_csr(2000, 2000, 5, 40, seed=12)
-    dA = DeviceCsr.from_host(A)
-    op = SpGEMM(dA, dA, binning=1, mlp_margin_milli=0)
+    A = gen.random_csr(2000, 2000, 3, 4, seed=12)
+    B = gen.random_csr(2000, k, 20, 32, seed=13)
+    dA, dB = DeviceCsr.from_host(A), DeviceCsr.from_host(B)
+    op = SpGEMM(dA, dB, binning=1, mlp_margin_milli=0)
     op.set_mlp(_constant_predictor(1.0))
     rp, nnz = op.symbolic()
     col, val = op.numeric()
     torch.cuda.synchronize()
     st = op.stats()
+    assert st["sym_rows"][table] > 0
     assert st["retried_rows"] > 0
-    compare(A, A, rp.cpu().numpy().astype(np.int64), col.cpu().numpy(), val.cpu().numpy())
+    compare(A, B, rp.cpu().numpy().astype(np.int64), col.cpu().numpy(), val.cpu().numpy())
 
 
 def test_export_rows_targets_match_oracle_blocks():
