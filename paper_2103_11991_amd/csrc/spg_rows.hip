@@ -36,17 +36,30 @@ __global__ void k_fill_u8(uint8_t* p, uint8_t v, int64_t n) {
         p[i] = v;
 }
 
-template <typename T>
-__device__ inline T xor_reduce_sum(T v) {
-    for (int d = ROW_LANES / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, ROW_LANES);
+// Reductions over aligned groups of ROW_LANES = 8 lanes with DPP: swaps of
+// neighbours and pairs inside quads, then a mirror of each half row (8
+// lanes), after which every lane of the group holds the result.  No LDS.
+template <typename Op>
+__device__ inline int row8_reduce(int v, Op op) {
+    v = op(v, __builtin_amdgcn_mov_dpp(v, 0xb1, 0xf, 0xf, false));   // quad_perm [1,0,3,2]
+    v = op(v, __builtin_amdgcn_mov_dpp(v, 0x4e, 0xf, 0xf, false));   // quad_perm [2,3,0,1]
+    v = op(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xf, 0xf, false));  // row_half_mirror
     return v;
 }
-__device__ inline int xor_reduce_min(int v) {
-    for (int d = ROW_LANES / 2; d > 0; d >>= 1) v = min(v, __shfl_xor(v, d, ROW_LANES));
-    return v;
+__device__ inline int row8_sum(int v) { return row8_reduce(v, [](int x, int y) { return x + y; }); }
+__device__ inline int row8_min(int v) { return row8_reduce(v, [](int x, int y) { return min(x, y); }); }
+__device__ inline int row8_max(int v) { return row8_reduce(v, [](int x, int y) { return max(x, y); }); }
+__device__ inline int row8_or(int v) { return row8_reduce(v, [](int x, int y) { return x | y; }); }
+template <int CTRL>
+__device__ inline int64_t dpp64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, CTRL, 0xf, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)((uint64_t)v >> 32), CTRL, 0xf, 0xf, false);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
 }
-__device__ inline int xor_reduce_max(int v) {
-    for (int d = ROW_LANES / 2; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, ROW_LANES));
+__device__ inline int64_t row8_sum64(int64_t v) {
+    v += dpp64<0xb1>(v);
+    v += dpp64<0x4e>(v);
+    v += dpp64<0x141>(v);
     return v;
 }
 
@@ -81,10 +94,10 @@ __global__ __launch_bounds__(256) void k_b_rowinfo(int32_t n, int32_t k, const i
                 }
             }
         }
-        mn = xor_reduce_min(mn);
-        mx = xor_reduce_max(mx);
-        runs = xor_reduce_sum(runs);
-        int anybad = xor_reduce_sum(bad);
+        mn = row8_min(mn);
+        mx = row8_max(mx);
+        runs = row8_sum(runs);
+        int anybad = row8_or(bad);
         if (row < n && lane == 0) {
             if (anybad) len = 0, mn = INT_MAX, mx = -1, runs = 0;
             binfo[row] = make_int4(len, mn, mx, runs);
@@ -150,12 +163,12 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
                 }
             }
         }
-        ub = xor_reduce_sum(ub);
-        rs = xor_reduce_sum(rs);
-        mx = xor_reduce_max(mx);
-        cmin = xor_reduce_min(cmin);
-        cmax = xor_reduce_max(cmax);
-        int anybad = xor_reduce_sum(bad);
+        ub = row8_sum64(ub);
+        rs = row8_sum64(rs);
+        mx = row8_max(mx);
+        cmin = row8_min(cmin);
+        cmax = row8_max(cmax);
+        int anybad = row8_or(bad);
         if (bad) atomicOr(&ctl->err, bad);
         if (row < m && lane == 0) {
             if (anybad) ub = 0;
