@@ -612,7 +612,7 @@ void launch_fill_u8(hipStream_t s, void* p, uint8_t v, int64_t bytes) {
 void launch_b_rowinfo(hipStream_t s, int32_t n, int32_t k, const int32_t* brp, const int32_t* bci, int64_t bnnz,
                       int4* binfo, Control* ctl) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_b_rowinfo, dim3(std::min(grid_for((int64_t)n * ROW_LANES, 256), 1024u)), dim3(256), 0, s, n,
+    hipLaunchKernelGGL(k_b_rowinfo, dim3(std::min(grid_for((int64_t)n * ROW_LANES, 256), 4096u)), dim3(256), 0, s, n,
                        k, brp, bci, bnnz, binfo, ctl);
 }
 
@@ -633,7 +633,7 @@ void launch_a_rowinfo(hipStream_t s, int32_t m, int32_t n, const int32_t* arp, c
                       const int4* binfo, RowInfo* rinfo, float* feats, ClassCfg cfg, int binning,
                       uint8_t* sym_cls, int32_t* row_nnz, int32_t* row_blocks, Control* ctl) {
     if (m <= 0) return;
-    hipLaunchKernelGGL(k_a_rowinfo, dim3(std::min(grid_for((int64_t)m * ROW_LANES, 256), 1024u)), dim3(256), 0, s, m, n,
+    hipLaunchKernelGGL(k_a_rowinfo, dim3(std::min(grid_for((int64_t)m * ROW_LANES, 256), 4096u)), dim3(256), 0, s, m, n,
                        arp, aci,
                        annz, binfo, rinfo, feats, cfg, binning, sym_cls, row_nnz, row_blocks, ctl);
 }
