@@ -366,7 +366,7 @@ def batched_vs_loop(count, steps):
             "batched_latency_ms": round(t_batch, 3),
             "batched_latency_note": "all products complete with the single graph launch: each product's "
                                     "latency from launch is the batch time",
-            "autotuned": {"work_per_lane": chosen[0], "vector_width": chosen[1], "hash_max_blocks": chosen[2],
+            "autotuned": {"work_per_lane": chosen[0], "binning": chosen[1], "hash_max_blocks": chosen[2],
                           "best_full_run_ms": round(tuned_ms, 3)},
             "generation_s": round(gen_s, 1)}
 

@@ -77,8 +77,6 @@ typedef enum {
     SPG_OPT_WORK_PER_LANE = 3,
     /* log2 safety margin added to the predictor's output, times 1000 (default 500) */
     SPG_OPT_MLP_MARGIN_MILLI = 4,
-    /* lanes that read one B row together, 0 = from B's mean row length (default) */
-    SPG_OPT_VECTOR_WIDTH = 5,
     /* largest number of occupied column blocks for which numeric uses a
        hashed block table with an explicit sort (default 64) */
     SPG_OPT_HASH_MAX_BLOCKS = 6,
@@ -256,10 +254,11 @@ spg_status spg_batch_run(spg_batch b, const void* a_val_pool, const void* b_val_
                          int32_t numeric_only);
 
 /* Autotuner: times every combination of products per lane {8,16,32},
-   vector width {auto,4,8,16} and hashed-table block limit {32,64,128} on
-   full runs of the batch (into the given output pools), keeps the fastest
-   and re-plans.  chosen (host int32[3], may be NULL) receives the three
-   settings, best_ms (host, may be NULL) the best run time. */
+   symbolic size bound (SPG_OPT_BINNING 2 or 0; a learned model is kept) and
+   hashed-table block limit {32,64,128} on full runs of the batch (into the
+   given output pools), keeps the fastest and re-plans.  chosen (host
+   int32[3], may be NULL) receives the three settings in that order, best_ms
+   (host, may be NULL) the best run time. */
 spg_status spg_batch_tune(spg_batch b, const void* a_val_pool, const void* b_val_pool,
                           int32_t* c_row_ptr, int32_t* c_col, void* c_val, int64_t capacity,
                           int32_t* chosen, float* best_ms);

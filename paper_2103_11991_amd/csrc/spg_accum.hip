@@ -2,28 +2,30 @@
 //
 // One group of G lanes owns one row of C.  Groups of up to 64 lanes live
 // inside one wavefront (several rows per 256-lane workgroup, no workgroup
-// barriers); groups of 128 and more lanes own a whole workgroup.
+// barriers); groups of 128 and more lanes own a whole workgroup; the global
+// path gives a row 1024 lanes.
 //
-// Work distribution follows the paper's vector-parallel inner loop (section
-// 2.2.1): a chunk of up to G nonzeros of A's row is staged in LDS (their B
-// rows' start and length), sub-groups of `vec` lanes take staged entries in
-// turn and the lanes of a sub-group read consecutive entries of that B row,
-// so B is read in coalesced runs and the dependent index chain A -> B row
-// pointer -> B column is broken by the staging.  Four entries are handled
-// per step with their loads issued together.
+// Work distribution (the flat product mapping, below): a chunk of up to G
+// nonzeros of A's row is staged in LDS; their B rows are cut into groups of
+// consecutive entries (their compressed-B rows into groups of runs) that
+// are numbered in A order, and lane l takes groups l, l + G, ...: every lane
+// busy, B read in coalesced 16-byte loads, all loads of a batch in flight
+// together.  This is the paper's vector-parallel inner loop over a B row
+// (section 2.2.1) flattened across the row's B rows.
 //
-// Tables (spg_internal.h): 32-column block masks, direct or hashed.
-//   symbolic: OR each product's column bit in; the value returned by the
-//             atomic OR says whether the bit (and the block) is new, so the
-//             row size and its occupied blocks are counted on the fly;
+// Tables (spg_internal.h): 32-column block masks, direct, hashed or two-level.
+//   symbolic: OR each compressed-B run into the row's table; the value the
+//             atomic OR returns says whether bits (and the block) are new, so
+//             the row size and its occupied blocks are counted on the fly
+//             (two-level: blocks are marked first, masks OR-ed in a second pass);
 //   numeric:  OR pass, then an exclusive prefix sum of popcounts in
 //             ascending block order (hashed tables rank their occupied
 //             blocks by key first), then every product is added with an LDS
 //             atomic at its column's rank; the row leaves sorted, with
 //             coalesced stores.
-// Long rows use the global path: 1024 lanes per row, the table in LDS when
-// it fits else in a per-workgroup global slab, values added with global
-// atomics straight into C's value array.
+// Long rows use the global path: 1024 lanes per row, the mask table in LDS
+// when it fits else in a per-workgroup global slab, values summed in LDS
+// segments (or, for the longest rows, with global atomics straight into C).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -34,8 +36,6 @@
 namespace spg {
 
 namespace {
-
-constexpr int UNROLL = 4;
 
 __device__ inline int hash_slot(int key, int logT) {
     return (int)(((uint32_t)key * 2654435761u) >> (32 - logT));
@@ -171,66 +171,6 @@ __device__ inline int group_excl_scan(int v, int& total, int* red) {
         }
         total = tot;
         return pre + x - v;
-    }
-}
-
-// Visits every product (A(i,p), B(j,q)) of the row whose nonzeros are
-// [a0, a1).  A chunk of up to G nonzeros of A is staged in LDS (B-row start
-// and length of each, plus stage(e, p) for anything else the caller keeps per
-// entry); then sub-groups of S lanes take staged entries in turn, and the S
-// lanes of a sub-group read consecutive entries of that B row (coalesced).
-// UNROLL entries are handled per step with their loads issued together;
-// B rows longer than S finish in a tail loop.  load(q) fetches what a product
-// needs from B, apply(v, e) consumes it.
-// Stages A entries [cb, cb + cnt): B-row start and length per entry, plus
-// stage(e, p) for anything else the caller keeps per entry.
-template <int G, typename Stage>
-__device__ inline void stage_chunk(int cb, int cnt, const int32_t* __restrict__ aci, const int32_t* __restrict__ brp,
-                                   int lane, int2* st, Stage stage) {
-    if (lane < cnt) {
-        const int j = aci[cb + lane];
-        const int b0 = brp[j];
-        st[lane] = make_int2(b0, brp[j + 1] - b0);
-        stage(lane, cb + lane);
-    }
-}
-
-// Products of a staged chunk of cnt entries, sub-groups of S lanes per entry.
-template <int G, typename Load, typename Apply>
-__device__ inline void walk_chunk(int cnt, int lane, int S, const int2* st, Load load, Apply apply) {
-    const int nsub = G / S, sg = lane / S, vl = lane % S;
-    for (int e0 = sg; e0 < cnt; e0 += nsub * UNROLL) {
-        int2 sb[UNROLL];
-        bool ok[UNROLL];
-#pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-            const int e = e0 + u * nsub;
-            sb[u] = e < cnt ? st[e] : make_int2(0, 0);
-            ok[u] = vl < sb[u].y;
-        }
-        decltype(load(0)) v[UNROLL];
-#pragma unroll
-        for (int u = 0; u < UNROLL; ++u)
-            if (ok[u]) v[u] = load(sb[u].x + vl);
-#pragma unroll
-        for (int u = 0; u < UNROLL; ++u)
-            if (ok[u]) apply(v[u], e0 + u * nsub);
-#pragma unroll
-        for (int u = 0; u < UNROLL; ++u)
-            for (int q = sb[u].x + vl + S; q < sb[u].x + sb[u].y; q += S) apply(load(q), e0 + u * nsub);
-    }
-}
-
-template <int G, typename Stage, typename Load, typename Apply>
-__device__ inline void walk_products(int a0, int a1, const int32_t* __restrict__ aci,
-                                     const int32_t* __restrict__ brp, int lane, int S, int2* st, Stage stage,
-                                     Load load, Apply apply) {
-    for (int cb = a0; cb < a1; cb += G) {
-        const int cnt = min(G, a1 - cb);
-        stage_chunk<G>(cb, cnt, aci, brp, lane, st, stage);
-        group_sync<G>();
-        walk_chunk<G>(cnt, lane, S, st, load, apply);
-        group_sync<G>();
     }
 }
 
@@ -501,6 +441,54 @@ struct Chunk {
     int nr, P, PC;   // nonempty entries, B groups and run groups of the chunk
 };
 
+// Walks the B groups (RUNS false) or compressed-B run groups (RUNS true) of
+// A's row [a0, a1) in the flat mapping, for any row length: chunks of G staged
+// entries (off[e] = {start - V * first group, end}, and A's value in ava when
+// walking B), batches of K groups per lane.  apply(group, entry) sees every
+// group once.  Used by the global path, whose rows are long.
+template <int G, int K, int V, bool RUNS, typename T, typename Load, typename Apply>
+__device__ void flat_walk(const int32_t* __restrict__ aci, const int4* __restrict__ bhdr, const T* __restrict__ av,
+                          int a0, int a1, int2* off, T* ava, Win* win, int* red, Load& load, Apply&& apply) {
+    const int lane = threadIdx.x % G, wv = lane >> 6;
+    const unsigned long long le = (2ull << (lane & 63)) - 1;
+    for (int e0 = a0; e0 < a1; e0 += G) {
+        group_sync<G>();  // the previous chunk's readers are done
+        win_clear<G, K>(win, lane);
+        int4 h = make_int4(0, 0, 0, 0);
+        T v = T(0);
+        if (lane < a1 - e0) {
+            h = bhdr[aci[e0 + lane]];
+            if constexpr (!RUNS) v = av[e0 + lane];
+        }
+        const int start = RUNS ? h.z : h.x, len = RUNS ? h.w : h.y;
+        const bool ne = len > 0;
+        int3 tot;
+        const int3 ex = group_excl_scan3<G>(make_int3(ne, (len + V - 1) / V, 0), tot, red);
+        const int P = tot.y;
+        if (ne) {
+            off[ex.x] = make_int2(start - V * ex.y, start + len);
+            if constexpr (!RUNS) ava[ex.x] = v;
+        }
+        group_sync<G>();
+        for (int P0 = 0; P0 < P; P0 += K * G) {
+            if (P0 > 0) {
+                group_sync<G>();
+                win_clear<G, K>(win, lane);
+                group_sync<G>();
+            }
+            win_mark<G, K>(win, ne, ex.y, P0);
+            const int before = P0 > 0 ? group_sum<G>(ne && ex.y < P0, red) : 0;
+            group_sync<G>();
+            win_scan<G, K, 0>(win, nullptr, before, 0, lane, red);
+            group_sync<G>();
+            Batch<G, K, V, Load> bt;
+            bt.issue(off, win, P0, P, lane, wv, le, load);
+            bt.consume(P0, P, lane, wv, le, apply);
+        }
+    }
+    group_sync<G>();
+}
+
 // ------------------------------------------------------------------ symbolic
 // Every entry of compressed B is a {block, mask} run: the row's table gets
 // the mask OR-ed in, and the bits that were not yet set (and blocks that were
@@ -718,10 +706,9 @@ __device__ inline uint32_t ld_tab(const uint32_t* p) {
 }
 
 template <bool IN_LDS>
-__device__ void wide_sym_row(const SymArgs& a, int i, uint32_t* masks, int2* st, int* red) {
+__device__ void wide_sym_row(const SymArgs& a, int i, uint32_t* masks, int2* off, Win* win, int* red) {
     constexpr int G = WIDE_THREADS;
     const int tid = threadIdx.x;
-    const int vec = a.vec < G ? a.vec : G;
     const RowInfo ri = a.rinfo[i];
     const int base = ri.x >> 5;
     const int words = (ri.y >> 5) - base + 1;
@@ -729,13 +716,14 @@ __device__ void wide_sym_row(const SymArgs& a, int i, uint32_t* masks, int2* st,
     if (!IN_LDS) __threadfence();
     __syncthreads();
     int cnt = 0, nb = 0;
-    walk_products<G>(
-        a.arp[i], a.arp[i + 1], a.aci, a.bcrp, tid, vec, st, [](int, int) {}, [&](int q) { return a.bc[q]; },
-        [&](int2 run, int) {
-            const uint32_t old = atomicOr(&masks[run.x - base], (uint32_t)run.y);
-            cnt += __popc((uint32_t)run.y & ~old);
-            nb += old == 0;
-        });
+    auto load_run = [&](int q, int end) { return load_runs<FLAT_VC_SYM>(a.bc, a.bc_total, q, end); };
+    auto orb = [&](int2 run, int) {
+        const uint32_t old = atomicOr(&masks[run.x - base], (uint32_t)run.y);
+        cnt += __popc((uint32_t)run.y & ~old);
+        nb += old == 0;
+    };
+    flat_walk<G, FLAT_KC, FLAT_VC_SYM, true, int>(a.aci, a.bhdr, nullptr, a.arp[i], a.arp[i + 1], off, nullptr, win,
+                                                  red, load_run, each(orb));
     cnt = group_sum<G>(cnt, red);
     nb = group_sum<G>(nb, red);
     if (tid == 0) {
@@ -750,16 +738,18 @@ __device__ void wide_sym_row(const SymArgs& a, int i, uint32_t* masks, int2* st,
 // row list with stride gridDim.x (the count may be read on the device).
 __global__ __launch_bounds__(WIDE_THREADS) void k_sym_wide(SymArgs a) {
     extern __shared__ __align__(16) uint32_t smem[];
-    __shared__ int red[16];
+    __shared__ int red[48];
     const int count = a.count_dev ? *a.count_dev : a.count;
     uint32_t* slab = a.slab ? a.slab + (int64_t)blockIdx.x * a.slab_words : nullptr;
-    int2* st = reinterpret_cast<int2*>(reinterpret_cast<uint8_t*>(smem) + a.wide_lds);
+    uint8_t* stage = reinterpret_cast<uint8_t*>(smem) + a.wide_lds;
+    int2* off = reinterpret_cast<int2*>(stage);
+    Win* win = reinterpret_cast<Win*>(stage + WIDE_THREADS * 16);
     for (int r = blockIdx.x; r < count; r += gridDim.x) {
         const int i = a.perm[r];
         const RowInfo ri = a.rinfo[i];
         const int64_t words = row_words(ri.x, ri.y);
-        if (words * 4 <= a.wide_lds) wide_sym_row<true>(a, i, smem, st, red);
-        else wide_sym_row<false>(a, i, slab, st, red);
+        if (words * 4 <= a.wide_lds) wide_sym_row<true>(a, i, smem, off, win, red);
+        else wide_sym_row<false>(a, i, slab, off, win, red);
     }
 }
 
@@ -1113,28 +1103,38 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     }
 }
 
+// Global path of the numeric phase.  Values are summed in LDS, one segment
+// of `wide_vals` ranks at a time (every segment walks the row's products and
+// keeps those whose rank falls in it), then copied out coalesced; a row with
+// more than four segments instead adds straight into C with global atomics.
 template <typename T, bool IN_LDS>
-__device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int2* st, T* ast, int* red) {
+__device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int2* off, T* ava, Win* win, T* lv,
+                             int* red) {
     constexpr int G = WIDE_THREADS;
+    constexpr int KB = 2;  // B groups per lane and batch (1024 lanes: 8192 products per batch)
     const int tid = threadIdx.x;
-    const int vec = a.vec < G ? a.vec : G;
-    const int off = a.crp[i];
-    const int n = a.crp[i + 1] - off;
+    const int coff = a.crp[i];
+    const int n = a.crp[i + 1] - coff;
     const RowInfo ri = a.rinfo[i];
     const int base = ri.x >> 5;
     const int words = (ri.y >> 5) - base + 1;
+    const int seg = a.wide_vals;
+    const bool in_lds = seg > 0 && n <= 4 * seg;
     int32_t* pref = reinterpret_cast<int32_t*>(masks + words);
-    T* cv = reinterpret_cast<T*>(a.cval) + off;
-    int32_t* cc = a.ccol + off;
+    T* cv = reinterpret_cast<T*>(a.cval) + coff;
+    int32_t* cc = a.ccol + coff;
     for (int c = tid; c < words; c += G) masks[c] = 0;
-    for (int r = tid; r < n; r += G) cv[r] = T(0);
+    if (!in_lds)
+        for (int r = tid; r < n; r += G) cv[r] = T(0);
     __threadfence();
     __syncthreads();
     const int a0 = a.arp[i], a1 = a.arp[i + 1];
-    const int vecc = a.vecc < G ? a.vecc : G;
-    walk_products<G>(
-        a0, a1, a.aci, a.bcrp, tid, vecc, st, [](int, int) {}, [&](int q) { return a.bc[q]; },
-        [&](int2 run, int) { atomicOr(&masks[run.x - base], (uint32_t)run.y); });
+    const T* av = reinterpret_cast<const T*>(a.av);
+    const T* bv = reinterpret_cast<const T*>(a.bv);
+    auto load_run = [&](int q, int end) { return load_runs<FLAT_VC>(a.bc, a.bc_total, q, end); };
+    auto load_cv = [&](int q, int end) { return load_b<T>(a.bci, bv, a.bnnz, q, end); };
+    auto orb = [&](int2 run, int) { atomicOr(&masks[run.x - base], (uint32_t)run.y); };
+    flat_walk<G, FLAT_KC_NUM, FLAT_VC, true, T>(a.aci, a.bhdr, av, a0, a1, off, ava, win, red, load_run, each(orb));
     if (!IN_LDS) __threadfence();
     __syncthreads();
     {
@@ -1152,21 +1152,47 @@ __device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int2* st,
     }
     if (!IN_LDS) __threadfence();
     __syncthreads();
-    const T* av = reinterpret_cast<const T*>(a.av);
-    const T* bv = reinterpret_cast<const T*>(a.bv);
-    struct CV {
-        int c;
-        T y;
+    auto rank_of = [&](int c) {
+        const int w = (c >> 5) - base;
+        const uint32_t mk = ld_tab<IN_LDS>(&masks[w]);
+        return (int)ld_tab<IN_LDS>(reinterpret_cast<uint32_t*>(&pref[w])) + __popc(mk & below(c & 31));
     };
-    walk_products<G>(
-        a0, a1, a.aci, a.brp, tid, vec, st, [&](int e, int p) { ast[e] = av[p]; },
-        [&](int q) { return CV{a.bci[q], bv[q]}; },
-        [&](const CV& v, int e) {
-            const int w = (v.c >> 5) - base;
-            const uint32_t mk = ld_tab<IN_LDS>(&masks[w]);
-            const int rank = (int)ld_tab<IN_LDS>(reinterpret_cast<uint32_t*>(&pref[w])) + __popc(mk & below(v.c & 31));
-            atomicAdd(&cv[rank], ast[e] * v.y);
-        });
+    // a group's ranks are looked up together (elements past its end repeat its first column)
+    auto ranks = [&](const BGroup<T>& g, int* rk) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) rk[j] = rank_of(j < g.n ? g.c[j] : g.c[0]);
+    };
+    if (in_lds) {
+        for (int s0 = 0; s0 < n; s0 += seg) {
+            const int len = min(seg, n - s0);
+            for (int r = tid; r < len; r += G) lv[r] = T(0);
+            __syncthreads();
+            flat_walk<G, KB, FLAT_VB, false, T>(a.aci, a.bhdr, av, a0, a1, off, ava, win, red, load_cv,
+                                                [&](const BGroup<T>& g, int e) {
+                                                    const T x = ava[e];
+                                                    int rk[4];
+                                                    ranks(g, rk);
+#pragma unroll
+                                                    for (int j = 0; j < 4; ++j) {
+                                                        const int r = rk[j] - s0;
+                                                        if (j < g.n && (unsigned)r < (unsigned)len)
+                                                            atomicAdd(&lv[r], x * g.y[j]);
+                                                    }
+                                                });
+            for (int r = tid; r < len; r += G) cv[s0 + r] = lv[r];
+            __syncthreads();
+        }
+    } else {
+        flat_walk<G, KB, FLAT_VB, false, T>(a.aci, a.bhdr, av, a0, a1, off, ava, win, red, load_cv,
+                                            [&](const BGroup<T>& g, int e) {
+                                                const T x = ava[e];
+                                                int rk[4];
+                                                ranks(g, rk);
+#pragma unroll
+                                                for (int j = 0; j < 4; ++j)
+                                                    if (j < g.n) atomicAdd(&cv[rk[j]], x * g.y[j]);
+                                            });
+    }
     for (int t = tid; t < words; t += G) {
         uint32_t mk = ld_tab<IN_LDS>(&masks[t]);
         int r = (int)ld_tab<IN_LDS>(reinterpret_cast<uint32_t*>(&pref[t]));
@@ -1183,16 +1209,19 @@ __device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int2* st,
 template <typename T>
 __global__ __launch_bounds__(WIDE_THREADS) void k_num_wide(NumArgs a) {
     extern __shared__ __align__(16) uint32_t smem[];
-    __shared__ int red[16];
+    __shared__ int red[48];
     uint32_t* slab = a.slab ? a.slab + (int64_t)blockIdx.x * a.slab_words : nullptr;
-    int2* st = reinterpret_cast<int2*>(reinterpret_cast<uint8_t*>(smem) + a.wide_lds);
-    T* ast = reinterpret_cast<T*>(reinterpret_cast<uint8_t*>(smem) + a.wide_lds + WIDE_THREADS * 8);
+    uint8_t* stage = reinterpret_cast<uint8_t*>(smem) + a.wide_lds;
+    int2* off = reinterpret_cast<int2*>(stage);
+    T* ava = reinterpret_cast<T*>(stage + WIDE_THREADS * 8);
+    Win* win = reinterpret_cast<Win*>(stage + WIDE_THREADS * 16);
+    T* lv = reinterpret_cast<T*>(stage + WIDE_THREADS * 16 + WIDE_WIN_BYTES);
     for (int r = blockIdx.x; r < a.count; r += gridDim.x) {
         const int i = a.perm[r];
         const RowInfo ri = a.rinfo[i];
         const int64_t words = row_words(ri.x, ri.y);
-        if (words * 8 <= a.wide_lds) wide_num_row<T, true>(a, i, smem, st, ast, red);
-        else wide_num_row<T, false>(a, i, slab, st, ast, red);
+        if (words * 8 <= a.wide_lds) wide_num_row<T, true>(a, i, smem, off, ava, win, lv, red);
+        else wide_num_row<T, false>(a, i, slab, off, ava, win, lv, red);
     }
 }
 
@@ -1242,13 +1271,15 @@ void num_dispatch(hipStream_t s, const NumArgs& a) {
 
 }  // namespace
 
-size_t wide_smem_bytes(int wide_lds, int phase) { return (size_t)wide_lds + WIDE_THREADS * (phase ? 16 : 8); }
+size_t wide_smem_bytes(int wide_lds, int phase, int vals_bytes) {
+    return (size_t)wide_lds + WIDE_THREADS * 16 + WIDE_WIN_BYTES + (phase ? vals_bytes : 0);
+}
 
 int launch_sym_class(hipStream_t s, const SymArgs& a, int grid_cap) {
     if (a.tier == TIER_GLOBAL) {
         int grid = a.count_dev ? grid_cap : (a.count < grid_cap ? a.count : grid_cap);
         if (grid < 1) return 0;
-        hipLaunchKernelGGL(k_sym_wide, dim3(grid), dim3(WIDE_THREADS), wide_smem_bytes(a.wide_lds, 0), s, a);
+        hipLaunchKernelGGL(k_sym_wide, dim3(grid), dim3(WIDE_THREADS), wide_smem_bytes(a.wide_lds, 0, 0), s, a);
         return grid;
     }
     if (a.count <= 0) return 0;
@@ -1262,7 +1293,7 @@ int launch_num_class(hipStream_t s, const NumArgs& a, int elem_bytes, int grid_c
     if (a.count <= 0) return 0;
     if (a.tier == TIER_GLOBAL) {
         int grid = a.count < grid_cap ? a.count : grid_cap;
-        const size_t smem = wide_smem_bytes(a.wide_lds, 1);
+        const size_t smem = wide_smem_bytes(a.wide_lds, 1, a.wide_vals * elem_bytes);
         if (elem_bytes == 8) hipLaunchKernelGGL(k_num_wide<double>, dim3(grid), dim3(WIDE_THREADS), smem, s, a);
         else hipLaunchKernelGGL(k_num_wide<float>, dim3(grid), dim3(WIDE_THREADS), smem, s, a);
         return grid;

@@ -54,7 +54,6 @@ struct spg_handle_s {
     int timing = 0;
     int force_class = -1;
     int work_per_lane = 16;
-    int vec = 0;
     int hash_max_blocks = 64;
     int lds_limit = 65536;
     int mlp_margin_milli = 500;
@@ -76,8 +75,6 @@ struct spg_handle_s {
     int32_t num_off[NCLS] = {};
     int64_t slab_num_words = 0;
     int nslab_num = 0;
-    int vec_used = 1;
-    int vecc_used = 1;
     ClassCfg cfg{};
     Control geom{};  // control block after the analysis of the last symbolic run
 
@@ -155,18 +152,6 @@ float elapsed(spg_handle h, int a, int b) {
     return ms;
 }
 
-// lanes that read one row together: the largest power of two up to 1.5x
-// the mean row length (of B for values, of compressed B for the OR passes)
-int vec_for(double mean) {
-    int v = 1;
-    while (v < 64 && 2.0 * v <= mean * 1.5) v *= 2;
-    return v;
-}
-
-int pick_vec(spg_handle h) {
-    if (h->vec > 0) return h->vec;
-    return vec_for(h->n > 0 ? (double)h->bnnz / (double)h->n : 1.0);
-}
 
 ClassCfg make_cfg(spg_handle h) {
     ClassCfg c{};
@@ -182,8 +167,15 @@ int wide_lds(spg_handle h) {
     // table LDS of a global-path workgroup: 64 KB, less if the device cannot
     // give it together with the 16 KB of staged A entries
     int v = 65536;
-    while (v > 4096 && v + WIDE_THREADS * 24 + 1024 > h->max_lds) v >>= 1;
+    while (v > 4096 && v + WIDE_THREADS * 16 + WIDE_WIN_BYTES + 1024 > h->max_lds) v >>= 1;
     return v;
+}
+
+// values per LDS segment of a global-path numeric workgroup: what the device
+// leaves beside the mask table and the staged entries, 0 if under 4 KB
+int wide_vals(spg_handle h, int eb) {
+    const int64_t left = (int64_t)h->max_lds - wide_lds(h) - WIDE_THREADS * 16 - WIDE_WIN_BYTES - 1024;
+    return left >= 4096 ? (int)((left & ~(int64_t)255) / eb) : 0;
 }
 
 int clamp_lds_limit(spg_handle h, int v) {
@@ -245,7 +237,6 @@ spg_status sym_prepare(spg_handle h) {
     if (learned) SPG_TRY(ensure(h, h->ovf_list, M * 4));
     if (want_feats) SPG_TRY(ensure(h, h->feats, M * 12));
     h->cfg = make_cfg(h);
-    h->vec_used = pick_vec(h);
     return SPG_OK;
 }
 
@@ -278,7 +269,6 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
     const int wl = wide_lds(h);
     // compressed B, read by both phases
     SPG_TRY(ensure(h, h->bc, (size_t)std::max<int64_t>(hc.bc_total, 1) * sizeof(int2)));
-    h->vecc_used = h->vec > 0 ? h->vec : vec_for(h->n > 0 ? (double)hc.bc_total / (double)h->n : 1.0);
     launch_compress_b(s, h->n, h->brp, h->bci, h->binfo.as<int4>(), h->bcrp.as<int32_t>(), h->tile_status.as<uint64_t>(),
                       &ctl->tile_counter_b, h->bc.as<int2>(), h->bhdr.as<int4>());
     launch_fill_i32(s, h->cursor.as<int32_t>(), 0, NCLS);
@@ -307,7 +297,6 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
         a.count = hc.sym_hist[c];
         a.tier = c % NTIER;
         a.mode = c / NTIER;
-        a.vec = h->vecc_used;
         a.arp = h->arp, a.aci = h->aci, a.brp = h->brp, a.bci = h->bci;
         a.bcrp = h->bcrp.as<int32_t>(), a.bc = h->bc.as<int2>(), a.bhdr = h->bhdr.as<int4>();
         a.bc_total = h->geom.bc_total;
@@ -333,7 +322,6 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
         a.count_dev = &ctl->overflow_rows;
         a.tier = TIER_GLOBAL;
         a.mode = MODE_DIRECT;
-        a.vec = h->vecc_used;
         a.arp = h->arp, a.aci = h->aci, a.brp = h->brp, a.bci = h->bci;
         a.bcrp = h->bcrp.as<int32_t>(), a.bc = h->bc.as<int2>(), a.bhdr = h->bhdr.as<int4>();
         a.bc_total = h->geom.bc_total;
@@ -421,13 +409,11 @@ spg_status num_launch_all(spg_handle h, const void* a_vals, const void* b_vals, 
         a.count = h->num_hist[c];
         a.tier = c % NTIER;
         a.mode = c / NTIER;
-        a.vec = h->vec_used;
         a.arp = h->arp, a.aci = h->aci, a.av = a_vals;
         a.brp = h->brp, a.bci = h->bci, a.bv = b_vals;
         a.bcrp = h->bcrp.as<int32_t>(), a.bc = h->bc.as<int2>(), a.bhdr = h->bhdr.as<int4>();
         a.bc_total = h->geom.bc_total;
         a.bnnz = h->bnnz;
-        a.vecc = h->vecc_used;
         a.crp = h->crp;
         a.rinfo = h->rinfo.as<RowInfo>();
         a.row_blocks = h->row_blocks.as<int32_t>();
@@ -436,6 +422,7 @@ spg_status num_launch_all(spg_handle h, const void* a_vals, const void* b_vals, 
         a.slab = h->slab_num_words ? h->slab_num.as<uint32_t>() : nullptr;
         a.slab_words = h->slab_num_words;
         a.wide_lds = wide_lds(h);
+        a.wide_vals = wide_vals(h, eb);
         rec(h, EV_NUMCLS + 2 * c);
         launch_num_class(s, a, eb, std::max(h->nslab_num, 1));
         rec(h, EV_NUMCLS + 2 * c + 1);
@@ -618,11 +605,6 @@ spg_status spg_set_option(spg_handle h, int32_t opt, int64_t val) {
         case SPG_OPT_MLP_MARGIN_MILLI:
             if (val < -20000 || val > 20000) return fail(h, SPG_ERR_ARG, "margin out of range");
             h->mlp_margin_milli = (int)val;
-            break;
-        case SPG_OPT_VECTOR_WIDTH:
-            if (val != 0 && (val < 1 || val > 64 || (val & (val - 1))))
-                return fail(h, SPG_ERR_ARG, "vector width must be 0 or a power of two up to 64");
-            h->vec = (int)val;
             break;
         case SPG_OPT_HASH_MAX_BLOCKS:
             if (val < 0 || val > 4096) return fail(h, SPG_ERR_ARG, "hash block limit out of range");
@@ -971,14 +953,16 @@ spg_status spg_batch_tune(spg_batch b, const void* a_val_pool, const void* b_val
         HIP_TRY(h, hipEventCreate(&e0));
         HIP_TRY(h, hipEventCreate(&e1));
         const int wpl[] = {8, 16, 32};
-        const int vecs[] = {0, 4, 8, 16};
+        const int bins[] = {2, 0};
         const int hmax[] = {32, 64, 128};
         float best = 1e30f;
-        int bw = h->work_per_lane, bv = h->vec, bh = h->hash_max_blocks;
+        int bw = h->work_per_lane, bv = h->binning, bh = h->hash_max_blocks;
+        const int learned = h->binning == 1;
         for (int w : wpl)
-            for (int v : vecs)
+            for (int v : bins)
                 for (int hb : hmax) {
-                    h->work_per_lane = w, h->vec = v, h->hash_max_blocks = hb;
+                    if (learned && v != 2) continue;  // a learned model stays in charge of the sizing
+                    h->work_per_lane = w, h->binning = learned ? 1 : v, h->hash_max_blocks = hb;
                     float t = 1e30f;
                     for (int it = 0; it < 2; ++it) {
                         int64_t nnz = 0;
@@ -996,11 +980,11 @@ spg_status spg_batch_tune(spg_batch b, const void* a_val_pool, const void* b_val
                         HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
                         t = std::min(t, ms);
                     }
-                    if (t < best) best = t, bw = w, bv = v, bh = hb;
+                    if (t < best) best = t, bw = w, bv = h->binning, bh = hb;
                 }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        h->work_per_lane = bw, h->vec = bv, h->hash_max_blocks = bh;
+        h->work_per_lane = bw, h->binning = bv, h->hash_max_blocks = bh;
         if (chosen) chosen[0] = bw, chosen[1] = bv, chosen[2] = bh;
         if (best_ms) *best_ms = best;
         return batch_replan(b);

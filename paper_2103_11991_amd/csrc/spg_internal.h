@@ -36,6 +36,7 @@ constexpr int MODE_HASHED = 1;
 constexpr int MODE_TWOLEVEL = 2;
 constexpr uint8_t CLS_EMPTY = 255;
 constexpr int WIDE_THREADS = 1024;   // threads per row on the global path
+constexpr int WIDE_WIN_BYTES = 2048;  // window table of the global path (K <= 8 windows x 16 waves)
 
 // error flags in Control::err
 constexpr int ERR_A_ROWPTR = 1;
@@ -262,7 +263,6 @@ struct SymArgs {
     int32_t count;
     int32_t tier;
     int32_t mode;
-    int32_t vec;                  // lanes sharing one compressed-B row (power of two)
     const int32_t* arp;
     const int32_t* aci;
     const int32_t* brp;
@@ -288,7 +288,6 @@ struct NumArgs {
     int32_t count;
     int32_t tier;
     int32_t mode;
-    int32_t vec;
     const int32_t* arp;
     const int32_t* aci;
     const void* av;
@@ -300,7 +299,6 @@ struct NumArgs {
     const int4* bhdr;             // per B row {start, length, run start, run count}
     int64_t bnnz;                 // entries of B and of compressed B (bounds of the
     int64_t bc_total;             // group loads near the arrays' ends)
-    int32_t vecc;                 // lanes sharing one compressed-B row
     const int32_t* crp;
     const RowInfo* rinfo;
     const int32_t* row_blocks;
@@ -309,6 +307,7 @@ struct NumArgs {
     uint32_t* slab;               // global path: masks and prefixes per workgroup
     int64_t slab_words;
     int32_t wide_lds;
+    int32_t wide_vals;            // global path: values per LDS segment (0 = global atomics only)
 };
 
 // Launches one symbolic class; returns the grid size used.

@@ -88,6 +88,18 @@ def test_long_rows_accumulate_in_output():
     compare(A, B, rp, c, v)
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_long_rows_in_lds_segments_and_global_atomics(dtype):
+    """Global-path rows: ~20k-entry rows summed in a few LDS segments, and
+    ~100k-entry rows (more than four segments) with global atomics."""
+    for k, lo, hi in ((30000, 100, 300), (400000, 300, 400)):
+        A = gen.random_csr(12, 600, lo, hi, seed=k, dtype=dtype)
+        B = gen.random_csr(600, k, 300, 500, seed=k + 1, dtype=dtype)
+        rp, c, v, op = run_gpu(A, B)
+        assert op.stats()["num_rows"][9] > 0
+        compare(A, B, rp, c, v)
+
+
 @pytest.mark.parametrize("seed", range(3))
 def test_identity_products(seed):
     A = gen.random_csr(500, 400, 0, 30, seed=seed, empty_frac=0.2)
