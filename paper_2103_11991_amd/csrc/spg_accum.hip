@@ -1106,7 +1106,7 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
 // Global path of the numeric phase.  Values are summed in LDS, one segment
 // of `wide_vals` ranks at a time (every segment walks the row's products and
 // keeps those whose rank falls in it), then copied out coalesced; a row with
-// more than four segments instead adds straight into C with global atomics.
+// more than eight segments instead adds straight into C with global atomics.
 template <typename T, bool IN_LDS>
 __device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int2* off, T* ava, Win* win, T* lv,
                              int* red) {
@@ -1119,7 +1119,7 @@ __device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int2* off
     const int base = ri.x >> 5;
     const int words = (ri.y >> 5) - base + 1;
     const int seg = a.wide_vals;
-    const bool in_lds = seg > 0 && n <= 4 * seg;
+    const bool in_lds = seg > 0 && n <= 8 * seg;
     int32_t* pref = reinterpret_cast<int32_t*>(masks + words);
     T* cv = reinterpret_cast<T*>(a.cval) + coff;
     int32_t* cc = a.ccol + coff;

@@ -171,7 +171,8 @@ __host__ __device__ inline int sym_class(int64_t ub, int32_t cmin, int32_t cmax,
     if (b2 < bytes) mode = MODE_TWOLEVEL, bytes = b2;
     if (bh < bytes) mode = MODE_HASHED, bytes = bh;
     int t = pick_tier(bytes, ub, c);
-    if (t == TIER_GLOBAL) mode = MODE_DIRECT;
+    // a tier raised for the row's work may hold the direct table (one pass, no probing)
+    if (t == TIER_GLOBAL || bd <= tier_bytes(t)) mode = MODE_DIRECT;
     return mode * NTIER + t;
 }
 
@@ -198,7 +199,8 @@ __host__ __device__ inline int num_class(int64_t ub, int32_t cmin, int32_t cmax,
     else if (blocks <= c.hash_max_blocks && bh * 8 < b2) mode = MODE_HASHED, bytes = bh;
     else mode = MODE_TWOLEVEL, bytes = b2;
     int t = pick_tier(bytes, ub, c);
-    if (t == TIER_GLOBAL) mode = MODE_DIRECT;
+    // a tier raised for the row's work may hold the direct table (one lookup per product)
+    if (t == TIER_GLOBAL || bd <= tier_bytes(t)) mode = MODE_DIRECT;
     return mode * NTIER + t;
 }
 

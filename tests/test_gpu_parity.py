@@ -90,9 +90,10 @@ def test_long_rows_accumulate_in_output():
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_long_rows_in_lds_segments_and_global_atomics(dtype):
-    """Global-path rows: ~20k-entry rows summed in a few LDS segments, and
-    ~100k-entry rows (more than four segments) with global atomics."""
-    for k, lo, hi in ((30000, 100, 300), (400000, 300, 400)):
+    """Global-path rows: ~25k-entry rows summed in a few LDS segments,
+    ~100k-entry rows in up to eight (FP64) or five (FP32), and ~250k-entry
+    rows (more than eight segments) with global atomics."""
+    for k, lo, hi in ((30000, 100, 300), (400000, 300, 400), (4000000, 600, 700)):
         A = gen.random_csr(12, 600, lo, hi, seed=k, dtype=dtype)
         B = gen.random_csr(600, k, 300, 500, seed=k + 1, dtype=dtype)
         rp, c, v, op = run_gpu(A, B)
