@@ -70,22 +70,29 @@ typedef enum {
     SPG_OPT_TIMING = 1,
     /* force every row of both phases into one accumulator class (-1 = off);
        class = mode * 10 + tier with mode 0 direct, 1 hashed, 2 two-level
-       (numeric only) and tier 0..8 LDS, 9 global memory.  Rows that do not
-       fit the forced class are placed in the class they would get anyway. */
+       and tier 0..8 LDS, 9 global memory.  Rows that do not fit the forced
+       class are placed in the class they would get anyway. */
     SPG_OPT_FORCE_CLASS = 2,
     /* products per lane used to size the thread group of a row (default 16) */
     SPG_OPT_WORK_PER_LANE = 3,
     /* log2 safety margin added to the predictor's output, times 1000 (default 500) */
     SPG_OPT_MLP_MARGIN_MILLI = 4,
-    /* largest number of occupied column blocks for which numeric uses a
-       hashed block table with an explicit sort (default 64) */
+    /* largest number of occupied column blocks for which numeric may use a
+       hashed block table (default 64) */
     SPG_OPT_HASH_MAX_BLOCKS = 6,
     /* LDS bytes per row at which the global-memory path takes over (power of
        two, 1024..65536, default 65536) */
     SPG_OPT_LDS_LIMIT = 7,
     /* keep each row's predictor features after symbolic even with upper-bound
        binning, so spg_export_rows can return them (default 0) */
-    SPG_OPT_KEEP_FEATURES = 8
+    SPG_OPT_KEEP_FEATURES = 8,
+    /* device memory, in MiB, for the rows' block lists that symbolic leaves
+       for numeric (1..16383, default 8192).  Each row reserves 8 bytes per
+       block it may occupy (the smaller of its compressed-B run count and
+       its column range in 32-column blocks); rows past the limit, and rows
+       of the symbolic global path, are computed by numeric on its global
+       path instead. */
+    SPG_OPT_LIST_LIMIT_MB = 9
 } spg_option;
 
 #define SPG_NTIER 10
@@ -113,6 +120,7 @@ typedef struct {
     float analysis_ms;                  /* row analysis and binning (timing on) */
     float scan_ms;                      /* row-pointer scan (timing on) */
     float mlp_ms;                       /* predictor inference (timing on) */
+    int64_t list_pairs;                 /* {block, mask} pairs reserved for the rows' lists */
 } spg_stats;
 
 /* Human-readable name of a status code (static string). */
@@ -142,8 +150,13 @@ spg_status spg_set_matrices(spg_handle h, spg_dtype dt, int32_t m, int32_t n, in
 /* Symbolic phase (section 2.2.1): writes C's row pointer into the caller's
    device array c_row_ptr[m+1] (c_row_ptr[0] = 0) and nnz(C) into *nnz_c
    (host).  Waits for the stream.  c_row_ptr is borrowed by the handle and
-   must stay valid and unchanged until the last spg_numeric.  Returns
-   SPG_ERR_INDEX for a malformed input and SPG_ERR_OVERFLOW if nnz(C) >= 2^31. */
+   must stay valid and unchanged until the last spg_numeric.  The handle
+   also keeps C's structure in compressed form (each row's occupied
+   32-column blocks with their column bits, section 2.2.1's compressed
+   representation), which every later spg_numeric reads instead of
+   recomputing it (SPG_OPT_LIST_LIMIT_MB bounds its memory).  Returns
+   SPG_ERR_INDEX for a malformed input, SPG_ERR_OVERFLOW if nnz(C) >= 2^31 and
+   SPG_ERR_ALLOC if a device buffer cannot be allocated. */
 spg_status spg_symbolic(spg_handle h, int32_t* c_row_ptr, int64_t* nnz_c);
 
 /* Numeric phase (section 2.2.1): fills the caller's device arrays

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_PKG, "libspg.so")
 SPG_F32, SPG_F64 = 0, 1
 OPT = {
     "binning": 0, "timing": 1, "force_class": 2, "work_per_lane": 3, "mlp_margin_milli": 4,
-    "hash_max_blocks": 6, "lds_limit": 7, "keep_features": 8,
+    "hash_max_blocks": 6, "lds_limit": 7, "keep_features": 8, "list_limit_mb": 9,
 }
 NTIER, NCLASS = 10, 30
 STATUS = ["SPG_OK", "SPG_ERR_ARG", "SPG_ERR_SHAPE", "SPG_ERR_STATE", "SPG_ERR_INDEX", "SPG_ERR_OVERFLOW",
@@ -46,6 +46,7 @@ class spg_stats(ctypes.Structure):
         ("binning", ctypes.c_int32), ("sym_ms", ctypes.c_float), ("num_ms", ctypes.c_float),
         ("sym_class_ms", ctypes.c_float * NCLASS), ("num_class_ms", ctypes.c_float * NCLASS),
         ("analysis_ms", ctypes.c_float), ("scan_ms", ctypes.c_float), ("mlp_ms", ctypes.c_float),
+        ("list_pairs", ctypes.c_int64),
     ]
 
 

@@ -17,12 +17,14 @@
 //   symbolic: OR each compressed-B run into the row's table; the value the
 //             atomic OR returns says whether bits (and the block) are new, so
 //             the row size and its occupied blocks are counted on the fly
-//             (two-level: blocks are marked first, masks OR-ed in a second pass);
-//   numeric:  OR pass, then an exclusive prefix sum of popcounts in
-//             ascending block order (hashed tables rank their occupied
-//             blocks by key first), then every product is added with an LDS
-//             atomic at its column's rank; the row leaves sorted, with
-//             coalesced stores.
+//             (two-level: blocks are marked first, masks OR-ed in a second
+//             pass); the occupied blocks then go out in ascending order as
+//             the row's {block, mask} list;
+//   numeric:  the list is read back, an exclusive prefix sum of its
+//             popcounts places every block with its prefix (and writes the
+//             row's columns), then every product is added with an LDS atomic
+//             at its column's rank; the row leaves sorted, with coalesced
+//             stores.
 // Long rows use the global path: 1024 lanes per row, the mask table in LDS
 // when it fits else in a per-workgroup global slab, values summed in LDS
 // segments (or, for the longest rows, with global atomics straight into C).
@@ -230,6 +232,29 @@ __device__ inline int3 group_excl_scan3(int3 v, int3& total, int* red) {
     }
 }
 
+template <int G>
+__device__ inline int2 group_excl_scan2(int2 v, int2& total, int* red) {
+    const int2 x = make_int2(wave_incl_scan<G>(v.x), wave_incl_scan<G>(v.y));
+    if constexpr (G <= 64) {
+        total = make_int2(group_last<G>(x.x), group_last<G>(x.y));
+        return make_int2(x.x - v.x, x.y - v.y);
+    } else {
+        constexpr int W = G / 64;
+        const int wl = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        __syncthreads();
+        if (wl == 63) red[2 * wv] = x.x, red[2 * wv + 1] = x.y;
+        __syncthreads();
+        int2 pre = make_int2(0, 0), tot = make_int2(0, 0);
+        for (int u = 0; u < W; ++u) {
+            const int2 t = make_int2(red[2 * u], red[2 * u + 1]);
+            if (u < wv) pre.x += t.x, pre.y += t.y;
+            tot.x += t.x, tot.y += t.y;
+        }
+        total = tot;
+        return make_int2(pre.x + x.x - v.x, pre.y + x.y - v.y);
+    }
+}
+
 // Sets the start bit of a staged entry whose first product p0 falls in the
 // batch [P0, P0 + K*G).
 template <int G, int K>
@@ -433,13 +458,6 @@ __device__ inline auto each(F& f) {
             if (j < g.n) f(g.at(j), e);
     };
 }
-
-// Staged chunk of A's row, kept in the lanes' registers while it is in use.
-struct Chunk {
-    int pb, pc;      // first B group / first run group of the lane's entry
-    bool ne;         // the entry's B row is nonempty
-    int nr, P, PC;   // nonempty entries, B groups and run groups of the chunk
-};
 
 // Walks the B groups (RUNS false) or compressed-B run groups (RUNS true) of
 // A's row [a0, a1) in the flat mapping, for any row length: chunks of G staged
@@ -682,6 +700,55 @@ void k_sym(SymArgs a) {
     cnt = group_sum<G>(cnt, red);
     if constexpr (MODE != MODE_TWOLEVEL) nb = group_sum<G>(nb, red);
     group_sync<G>();
+    // the row's list: its occupied blocks in ascending order with their masks
+    const int lo = d.w;
+    const bool overflowed = MODE != MODE_DIRECT && ovf[sub];
+    if (lo >= 0 && !overflowed) {
+        int2* out = a.lists + lo;
+        if constexpr (MODE == MODE_TWOLEVEL) {
+            // a set bit of l1 word t is block base + 32 t + bit, at compact index prefix + rank
+            const int chunk = (w1 + G - 1) / G;
+            const int beg = lane * chunk;
+            const int end = min(beg + chunk, w1);
+            for (int t = beg; t < end; ++t) {
+                const uint2 L = l1[t];
+                uint32_t bits = L.x;
+                int ci = (int)L.y;
+                while (bits) {
+                    out[ci] = make_int2(base + 32 * t + __ffs(bits) - 1, (int)cm[ci]);
+                    ++ci;
+                    bits &= bits - 1;
+                }
+            }
+        } else if constexpr (MODE == MODE_DIRECT) {
+            const int chunk = (ncell + G - 1) / G;
+            const int beg = min(lane * chunk, ncell);
+            const int end = min(beg + chunk, ncell);
+            int local = 0;
+            for (int t = beg; t < end; ++t) local += masks[t] != 0;
+            int total;
+            int pos = group_excl_scan<G>(local, total, red);
+            for (int t = beg; t < end; ++t) {
+                const uint32_t mk = masks[t];
+                if (mk) out[pos++] = make_int2(base + t, (int)mk);
+            }
+        } else {
+            // position of an occupied slot = occupied slots with a smaller block
+            // id (empty slots hold -1, the largest unsigned key)
+            const int4* k4 = reinterpret_cast<const int4*>(keys);
+            for (int c = lane; c < T; c += G) {
+                const int key = keys[c];
+                if (key < 0) continue;
+                int r = 0;
+                for (int f = 0; f < T / 4; ++f) {
+                    const int4 q = k4[f];
+                    r += ((uint32_t)q.x < (uint32_t)key) + ((uint32_t)q.y < (uint32_t)key) +
+                         ((uint32_t)q.z < (uint32_t)key) + ((uint32_t)q.w < (uint32_t)key);
+                }
+                out[r] = make_int2(key, (int)masks[c]);
+            }
+        }
+    }
     if (lane == 0) {
         if (MODE != MODE_DIRECT && ovf[sub]) {
             // queued for the exact retry; a table sized from an upper bound
@@ -730,6 +797,23 @@ __device__ void wide_sym_row(const SymArgs& a, int i, uint32_t* masks, int2* off
         a.row_nnz[i] = cnt;
         a.row_blocks[i] = nb;
     }
+    const int lo = a.lofs[i];
+    if (lo >= 0) {  // the row's list, from the masks in word order
+        if (!IN_LDS) __threadfence();
+        __syncthreads();
+        int2* out = a.lists + lo;
+        const int chunk = (words + G - 1) / G;
+        const int beg = min(tid * chunk, words);
+        const int end = min(beg + chunk, words);
+        int local = 0;
+        for (int t = beg; t < end; ++t) local += ld_tab<IN_LDS>(&masks[t]) != 0;
+        int total;
+        int pos = group_excl_scan<G>(local, total, red);
+        for (int t = beg; t < end; ++t) {
+            const uint32_t mk = ld_tab<IN_LDS>(&masks[t]);
+            if (mk) out[pos++] = make_int2(base + t, (int)mk);
+        }
+    }
     __syncthreads();
 }
 
@@ -754,15 +838,14 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_sym_wide(SymArgs a) {
 }
 
 // ------------------------------------------------------------------- numeric
-// Pass 1 finds the occupied columns from compressed B; a prefix sum of
-// popcounts in ascending block order turns them into ranks; pass 2 walks B
-// itself and adds each product at its column's rank.
+// The row's list (its occupied blocks in ascending order, from the symbolic
+// phase) and a prefix sum of its popcounts give every column its rank; the
+// walk over B adds each product at its column's rank.
 //   direct:    one {mask, prefix} pair per 32-column word of the row's range;
-//   two-level: a {bits, prefix} pair per 32 blocks marks occupied blocks, so
-//              a block's compact index (already in block order) is a popcount;
-//              per occupied block {mask, prefix} and its id.  Pass 1 is split
-//              in two walks of compressed B: blocks first, then masks;
-//   hashed:    {block, mask, prefix} slots, occupied blocks ranked by count.
+//   two-level: a {bits, first} pair per 32 blocks marks occupied blocks and
+//              holds the list index of the first of them, so a block's list
+//              index is first + a popcount; per listed block {mask, prefix};
+//   hashed:    {block, mask, prefix} slots keyed by block id.
 
 // Hashed numeric slot {block id, mask, prefix, -}: insert-or-find by block id.
 __device__ inline int slot_insert(int4* slots, int T, int logT, int key) {
@@ -782,14 +865,13 @@ __device__ inline int slot_insert(int4* slots, int T, int logT, int key) {
 
 
 template <int G, int MODE, typename T>
-__global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
+// (one row per wavefront: 72 VGPRs give 7 waves per SIMD without spilling)
+__global__ __launch_bounds__(G * rows_per_wg<G>()) __attribute__((amdgpu_waves_per_eu(G == 64 ? 7 : 4)))
+void k_num(NumArgs a) {
     constexpr int RPW = rows_per_wg<G>();
-    constexpr int W = waves_of<G>();
     constexpr int KB = sizeof(T) == 8 ? FLAT_KB_F64 : FLAT_KB_F32;
-    constexpr int KC = FLAT_KC_NUM;
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int red[48];
-    __shared__ int ncompact[RPW];
     const int bytes = tier_bytes(a.tier);
     const int per_row = bytes + stage_bytes(G);
     // a group of 64 or more lanes owns whole wavefronts: its row is wave-uniform
@@ -803,304 +885,184 @@ __global__ __launch_bounds__(G * rows_per_wg<G>()) void k_num(NumArgs a) {
     const int n = a.crp[i + 1] - off;
     const RowInfo ri = a.rinfo[i];
     const int nb = a.row_blocks[i];
+    const int2* lst = a.lists + a.lofs[i];  // rows of these classes always have a list
     const int base = ri.x >> 5;
     const int words = (ri.y >> 5) - base + 1;
-    const int nb4 = (nb + 3) & ~3;
     const int w1 = (words + 31) >> 5;
     uint8_t* row_lds = reinterpret_cast<uint8_t*>(smem) + (size_t)sub * per_row;
     uint8_t* tab = row_lds;
     int2* bq = reinterpret_cast<int2*>(row_lds + bytes);              // staged B {offset, end}
-    int2* cq = bq + G;                                                // staged run {offset, end}
-    T* ava = reinterpret_cast<T*>(row_lds + bytes + G * 16);          // their A values
-    Win* winb = reinterpret_cast<Win*>(row_lds + bytes + G * 24);     // B group windows
-    Win* winc = winb + FLAT_KB_F32 * W;                              // run windows
-    // direct: {mask, prefix} per word.  two-level: l1 {bits, prefix} per 32
-    // blocks, cm {mask, prefix} and blk per occupied block.  hashed: slots,
-    // compact keys (padded), their slots, slots in block order.
+    T* ava = reinterpret_cast<T*>(row_lds + bytes + G * 8);           // their A values
+    Win* winb = reinterpret_cast<Win*>(row_lds + bytes + G * 16);     // B group windows
+    // direct: {mask, prefix} per word.  two-level: l1 {bits, first list index}
+    // per 32 blocks, then {mask, prefix} per occupied block.  hashed: slots.
     uint2* dw = reinterpret_cast<uint2*>(tab);
     uint2* l1 = reinterpret_cast<uint2*>(tab);
     uint2* cm = l1 + w1;
-    int32_t* blk = reinterpret_cast<int32_t*>(cm + nb);
     int4* slots = reinterpret_cast<int4*>(tab);
-    int32_t* ck = nullptr;
-    int32_t* cs = nullptr;
-    int32_t* ord = nullptr;
     T* vals;
-    int items, TT = 0, logT = 0;
+    int TT = 0, logT = 0;
     if constexpr (MODE == MODE_DIRECT) {
         vals = reinterpret_cast<T*>(tab + align8((int64_t)words * 8));
-        items = words;
     } else if constexpr (MODE == MODE_TWOLEVEL) {
-        vals = reinterpret_cast<T*>(tab + align8((int64_t)w1 * 8 + (int64_t)nb * 12));
-        items = nb;
+        vals = reinterpret_cast<T*>(tab + align8((int64_t)w1 * 8 + (int64_t)nb * 8));
     } else {
         TT = (int)num_hash_slots(nb);
         logT = 31 - __clz(TT);
-        ck = reinterpret_cast<int32_t*>(slots + TT);
-        cs = ck + nb4;
-        ord = cs + nb;
-        vals = reinterpret_cast<T*>(tab + align8((int64_t)TT * 16 + (int64_t)nb4 * 4 + (int64_t)nb * 8));
-        items = nb;
+        vals = reinterpret_cast<T*>(tab + (int64_t)TT * 16);
     }
     if constexpr (MODE == MODE_DIRECT) {
         // pairs of words per 16-byte store; an odd last word spills 8 bytes into vals, cleared below
         for (int c = 2 * lane; c < words; c += 2 * G) *reinterpret_cast<uint4*>(&dw[c]) = make_uint4(0, 0, 0, 0);
     } else if constexpr (MODE == MODE_TWOLEVEL) {
-        for (int c = lane; c < w1 + nb; c += G) l1[c] = make_uint2(0u, 0u);
+        for (int c = lane; c < w1; c += G) l1[c] = make_uint2(0u, ~0u);
     } else {
         for (int c = lane; c < TT; c += G) slots[c] = make_int4(-1, 0, 0, 0);
     }
     for (int r = lane; r < n; r += G) vals[r] = T(0);
     win_clear<G, KB>(winb, lane);
-    win_clear<G, KC>(winc, lane);
-    if (lane == 0) ncompact[sub] = 0;
     group_sync<G>();
 
     const T* av = reinterpret_cast<const T*>(a.av);
     const T* bv = reinterpret_cast<const T*>(a.bv);
-    // ---- staging (chunks of G entries of A's row; window tables of one batch each)
-    Chunk ch;
-    int staged = -1;         // first A entry of the staged chunk
-    int wb0 = 0, wc0 = 0;    // batch held by each window table
-    auto stage = [&](int e0) {  // window tables cleared and synchronised by the caller
+    // ---- staging (chunks of G entries of A's row; a window table of one batch)
+    bool ne = false;
+    int pb = 0, P = 0;
+    int staged = -1, wb0 = 0;
+    auto stage = [&](int e0) {  // window table cleared and synchronised by the caller
         int4 h = make_int4(0, 0, 0, 0);
         T v = T(0);
         if (lane < a1 - e0) {
             h = a.bhdr[a.aci[e0 + lane]];
             v = av[e0 + lane];
         }
-        ch.ne = h.y > 0;
-        int3 tot;
-        const int3 ex = group_excl_scan3<G>(
-            make_int3(ch.ne, (h.y + FLAT_VB - 1) / FLAT_VB, (h.w + FLAT_VC - 1) / FLAT_VC), tot, red);
-        ch.pb = ex.y, ch.pc = ex.z, ch.nr = tot.x, ch.P = tot.y, ch.PC = tot.z;
-        if (ch.ne) {
+        ne = h.y > 0;
+        int2 tot;
+        const int2 ex = group_excl_scan2<G>(make_int2(ne, (h.y + FLAT_VB - 1) / FLAT_VB), tot, red);
+        pb = ex.y, P = tot.y;
+        if (ne) {
             bq[ex.x] = make_int2(h.x - FLAT_VB * ex.y, h.x + h.y);
-            cq[ex.x] = make_int2(h.z - FLAT_VC * ex.z, h.z + h.w);
             ava[ex.x] = v;
         }
-        win_mark<G, KB>(winb, ch.ne, ch.pb, 0);
-        win_mark<G, KC>(winc, ch.ne, ch.pc, 0);
+        win_mark<G, KB>(winb, ne, pb, 0);
         group_sync<G>();
-        win_scan<G, KB, KC>(winb, winc, 0, 0, lane, red);
+        win_scan<G, KB, 0>(winb, nullptr, 0, 0, lane, red);
         group_sync<G>();
-        staged = e0, wb0 = 0, wc0 = 0;
+        staged = e0, wb0 = 0;
     };
     auto restage = [&](int e0) {
         if (staged == e0) return;
         group_sync<G>();
         win_clear<G, KB>(winb, lane);
-        win_clear<G, KC>(winc, lane);
         group_sync<G>();
         stage(e0);
     };
-    // window table of one field rebuilt for the batch starting at P0
-    auto rewin = [&](auto field, int P0) {
-        constexpr int F = decltype(field)::value;
-        constexpr int K = F == 0 ? KB : KC;
-        Win* win = F == 0 ? winb : winc;
-        int& held = F == 0 ? wb0 : wc0;
-        if (held == P0) return;
-        const int p0 = F == 0 ? ch.pb : ch.pc;
+    // window table rebuilt for the batch starting at P0
+    auto rewin = [&](int P0) {
+        if (wb0 == P0) return;
         group_sync<G>();
-        win_clear<G, K>(win, lane);
+        win_clear<G, KB>(winb, lane);
         group_sync<G>();
-        win_mark<G, K>(win, ch.ne, p0, P0);
-        const int before = group_sum<G>(ch.ne && p0 < P0, red);
+        win_mark<G, KB>(winb, ne, pb, P0);
+        const int before = group_sum<G>(ne && pb < P0, red);
         group_sync<G>();
-        win_scan<G, K, 0>(win, nullptr, before, 0, lane, red);
+        win_scan<G, KB, 0>(winb, nullptr, before, 0, lane, red);
         group_sync<G>();
-        held = P0;
+        wb0 = P0;
     };
-    auto load_run = [&](int q, int end) { return load_runs<FLAT_VC>(a.bc, a.bc_total, q, end); };
     auto load_cv = [&](int q, int end) { return load_b<T>(a.bci, bv, a.bnnz, q, end); };
-    auto walk_runs = [&](auto&& apply) {
-        for (int e0 = a0; e0 < a1; e0 += G) {
-            restage(e0);
-            for (int P0 = 0; P0 < ch.PC; P0 += KC * G) {
-                rewin(std::integral_constant<int, 1>{}, P0);
-                Batch<G, KC, FLAT_VC, decltype(load_run)> bt;
-                bt.issue(cq, winc, P0, ch.PC, lane, wv, le, load_run);
-                bt.consume(P0, ch.PC, lane, wv, le, apply);
-            }
-        }
-    };
-    auto walk_b = [&](auto&& apply) {
-        for (int e0 = a0; e0 < a1; e0 += G) {
-            restage(e0);
-            for (int P0 = 0; P0 < ch.P; P0 += KB * G) {
-                rewin(std::integral_constant<int, 0>{}, P0);
-                Batch<G, KB, FLAT_VB, decltype(load_cv)> bt;
-                bt.issue(bq, winb, P0, ch.P, lane, wv, le, load_cv);
-                bt.consume(P0, ch.P, lane, wv, le, apply);
-            }
-        }
-    };
 
-    // ---- pass 1: which columns occur; prefix; pass 2: values at their ranks
-    auto finish = [&](auto&& runs, auto&& bwalk) {
-        if constexpr (MODE == MODE_TWOLEVEL) {
-            auto mark_l1 = [&](int2 run, int) {
-                const int w = run.x - base;
-                atomicOr(&l1[w >> 5].x, 1u << (w & 31));
-            };
-            runs(each(mark_l1));
-            group_sync<G>();
-            // compact index of each occupied block: prefix of popcounts over l1
-            {
-                const int chunk = (w1 + G - 1) / G;
-                const int beg = lane * chunk;
-                const int end = min(beg + chunk, w1);
-                int local = 0;
-                for (int t = beg; t < end; ++t) local += __popc(l1[t].x);
-                int total;
-                int ex = group_excl_scan<G>(local, total, red);
-                for (int t = beg; t < end; ++t) {
-                    l1[t].y = (uint32_t)ex;
-                    ex += __popc(l1[t].x);
-                }
-            }
-            group_sync<G>();
-            auto or_cm = [&](int2 run, int) {
-                const int w = run.x - base;
-                const uint2 L = l1[w >> 5];
-                const int ci = (int)L.y + __popc(L.x & below(w & 31));
-                atomicOr(&cm[ci].x, (uint32_t)run.y);
-                blk[ci] = run.x;
-            };
-            runs(each(or_cm));
-        } else {
-            auto or_tab = [&](int2 run, int) {
+    // ---- the table from the row's list: prefix of popcounts in list order
+    // (ascending blocks), every block placed with its prefix, and its columns
+    // written straight to C
+    int32_t* cc = a.ccol + off;
+    auto build = [&]() {
+        int carry = 0;
+        for (int t0 = 0; t0 < nb; t0 += G) {
+            const int t = t0 + lane;
+            int2 e = make_int2(0, 0);
+            if (t < nb) e = lst[t];
+            int tot;
+            const int ex = carry + group_excl_scan<G>(__popc((uint32_t)e.y), tot, red);
+            carry += tot;
+            if (t < nb) {
+                const int b = e.x;
+                uint32_t mk = (uint32_t)e.y;
                 if constexpr (MODE == MODE_DIRECT) {
-                    atomicOr(&dw[run.x - base].x, (uint32_t)run.y);
-                } else {
-                    const int h = slot_insert(slots, TT, logT, run.x);
-                    atomicOr(reinterpret_cast<unsigned int*>(&slots[h].y), (uint32_t)run.y);
-                }
-            };
-            runs(each(or_tab));
-        }
-        group_sync<G>();
-        if constexpr (MODE == MODE_HASHED) {
-            // occupied blocks in ascending order: compact, then rank by count
-            for (int c = lane; c < TT; c += G) {
-                const int4 sl = slots[c];
-                if (sl.y) {
-                    const int pos = atomicAdd(&ncompact[sub], 1);
-                    ck[pos] = sl.x;
-                    cs[pos] = c;
-                }
-            }
-            for (int e = nb + lane; e < nb4; e += G) ck[e] = 0x7fffffff;
-            group_sync<G>();
-            const int4* ck4 = reinterpret_cast<const int4*>(ck);
-            for (int e = lane; e < nb; e += G) {
-                const int key = ck[e];
-                int r = 0;
-                for (int f = 0; f < nb4 / 4; ++f) {
-                    const int4 k4 = ck4[f];
-                    r += (k4.x < key) + (k4.y < key) + (k4.z < key) + (k4.w < key);
-                }
-                ord[r] = cs[e];
-            }
-            group_sync<G>();
-        }
-        // exclusive prefix of popcounts over occupied blocks in ascending order
-        {
-            const int chunk = (items + G - 1) / G;
-            const int beg = lane * chunk;
-            const int end = min(beg + chunk, items);
-            int local = 0;
-            for (int t = beg; t < end; ++t) {
-                if constexpr (MODE == MODE_DIRECT) local += __popc(dw[t].x);
-                else if constexpr (MODE == MODE_TWOLEVEL) local += __popc(cm[t].x);
-                else local += __popc((uint32_t)slots[ord[t]].y);
-            }
-            int total;
-            int ex = group_excl_scan<G>(local, total, red);
-            for (int t = beg; t < end; ++t) {
-                if constexpr (MODE == MODE_DIRECT) {
-                    dw[t].y = (uint32_t)ex;
-                    ex += __popc(dw[t].x);
+                    dw[b - base] = make_uint2(mk, (uint32_t)ex);
                 } else if constexpr (MODE == MODE_TWOLEVEL) {
-                    cm[t].y = (uint32_t)ex;
-                    ex += __popc(cm[t].x);
+                    cm[t] = make_uint2(mk, (uint32_t)ex);
+                    const int w = b - base;
+                    atomicOr(&l1[w >> 5].x, 1u << (w & 31));
+                    atomicMin(&l1[w >> 5].y, (uint32_t)t);
                 } else {
-                    const int cl = ord[t];
-                    slots[cl].z = ex;
-                    ex += __popc((uint32_t)slots[cl].y);
+                    const int h = slot_insert(slots, TT, logT, b);
+                    slots[h].y = (int)mk;
+                    slots[h].z = ex;
+                }
+                int r = ex;
+                while (mk) {
+                    cc[r++] = (b << 5) + (__ffs(mk) - 1);
+                    mk &= mk - 1;
                 }
             }
         }
         group_sync<G>();
-        auto rank_of = [&](int c) {
-            if constexpr (MODE == MODE_DIRECT) {
-                const uint2 mp = dw[(c >> 5) - base];
-                return (int)mp.y + __popc(mp.x & below(c & 31));
-            } else if constexpr (MODE == MODE_TWOLEVEL) {
-                const int w = (c >> 5) - base;
-                const uint2 L = l1[w >> 5];
-                const uint2 mp = cm[(int)L.y + __popc(L.x & below(w & 31))];
-                return (int)mp.y + __popc(mp.x & below(c & 31));
-            } else {
-                const int key = c >> 5;
-                int h = hash_slot(key, logT);
-                int4 sl = slots[h];
-                for (int probe = 1; sl.x != key && probe < TT; ++probe) {
-                    h = (h + 1) & (TT - 1);
-                    sl = slots[h];
-                }
-                return sl.z + __popc((uint32_t)sl.y & below(c & 31));
+    };
+    auto rank_of = [&](int c) {
+        if constexpr (MODE == MODE_DIRECT) {
+            const uint2 mp = dw[(c >> 5) - base];
+            return (int)mp.y + __popc(mp.x & below(c & 31));
+        } else if constexpr (MODE == MODE_TWOLEVEL) {
+            const int w = (c >> 5) - base;
+            const uint2 L = l1[w >> 5];
+            const uint2 mp = cm[(int)L.y + __popc(L.x & below(w & 31))];
+            return (int)mp.y + __popc(mp.x & below(c & 31));
+        } else {
+            const int key = c >> 5;
+            int h = hash_slot(key, logT);
+            int4 sl = slots[h];
+            for (int probe = 1; sl.x != key && probe < TT; ++probe) {
+                h = (h + 1) & (TT - 1);
+                sl = slots[h];
             }
-        };
-        // a group's ranks are looked up together (elements past the group's
-        // end repeat its first column), then its valid products are added
-        bwalk([&](const BGroup<T>& g, int e) {
-            const T av = ava[e];
-            int rk[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) rk[j] = rank_of(j < g.n ? g.c[j] : g.c[0]);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (j < g.n) atomicAdd(&vals[rk[j]], av * g.y[j]);
-        });
-        // column of every rank, from the masks, straight to C
-        int32_t* cc = a.ccol + off;
-        for (int t = lane; t < items; t += G) {
-            uint32_t mk;
-            int r, b;
-            if constexpr (MODE == MODE_DIRECT) {
-                const uint2 mp = dw[t];
-                mk = mp.x, r = (int)mp.y, b = base + t;
-            } else if constexpr (MODE == MODE_TWOLEVEL) {
-                const uint2 mp = cm[t];
-                mk = mp.x, r = (int)mp.y, b = blk[t];
-            } else {
-                const int4 sl = slots[ord[t]];
-                mk = (uint32_t)sl.y, r = sl.z, b = sl.x;
-            }
-            while (mk) {
-                cc[r++] = (b << 5) + (__ffs(mk) - 1);
-                mk &= mk - 1;
-            }
+            return sl.z + __popc((uint32_t)sl.y & below(c & 31));
         }
-        group_sync<G>();
-        T* cv = reinterpret_cast<T*>(a.cval) + off;
-        for (int r = lane; r < n; r += G) cv[r] = vals[r];
+    };
+    // a group's ranks are looked up together (elements past the group's end
+    // repeat its first column), then its valid products are added
+    auto add = [&](const BGroup<T>& g, int e) {
+        const T x = ava[e];
+        int rk[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) rk[j] = rank_of(j < g.n ? g.c[j] : g.c[0]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j < g.n) atomicAdd(&vals[rk[j]], x * g.y[j]);
     };
 
     stage(a0);
-    if (a1 - a0 <= G && ch.P <= KB * G && ch.PC <= KC * G) {
-        // the whole row in one batch: runs and B entries are loaded together
-        Batch<G, KC, FLAT_VC, decltype(load_run)> br;
+    if (a1 - a0 <= G && P <= KB * G) {
+        // the whole row in one batch: its B loads are in flight while the table is built
         Batch<G, KB, FLAT_VB, decltype(load_cv)> bb;
-        br.issue(cq, winc, 0, ch.PC, lane, wv, le, load_run);
-        bb.issue(bq, winb, 0, ch.P, lane, wv, le, load_cv);
-        finish([&](auto&& apply) { br.consume(0, ch.PC, lane, wv, le, apply); },
-               [&](auto&& apply) { bb.consume(0, ch.P, lane, wv, le, apply); });
+        bb.issue(bq, winb, 0, P, lane, wv, le, load_cv);
+        build();
+        bb.consume(0, P, lane, wv, le, add);
     } else {
-        finish(walk_runs, walk_b);
+        build();
+        for (int e0 = a0; e0 < a1; e0 += G) {
+            restage(e0);
+            for (int P0 = 0; P0 < P; P0 += KB * G) {
+                rewin(P0);
+                Batch<G, KB, FLAT_VB, decltype(load_cv)> bt;
+                bt.issue(bq, winb, P0, P, lane, wv, le, load_cv);
+                bt.consume(P0, P, lane, wv, le, add);
+            }
+        }
     }
+    group_sync<G>();
+    T* cv = reinterpret_cast<T*>(a.cval) + off;
+    for (int r = lane; r < n; r += G) cv[r] = vals[r];
 }
 
 // Global path of the numeric phase.  Values are summed in LDS, one segment
@@ -1134,7 +1096,19 @@ __device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int2* off
     auto load_run = [&](int q, int end) { return load_runs<FLAT_VC>(a.bc, a.bc_total, q, end); };
     auto load_cv = [&](int q, int end) { return load_b<T>(a.bci, bv, a.bnnz, q, end); };
     auto orb = [&](int2 run, int) { atomicOr(&masks[run.x - base], (uint32_t)run.y); };
-    flat_walk<G, FLAT_KC_NUM, FLAT_VC, true, T>(a.aci, a.bhdr, av, a0, a1, off, ava, win, red, load_run, each(orb));
+    const int lo = a.lofs[i];
+    if (lo >= 0) {  // masks from the row's list, else from compressed B
+        if (!IN_LDS) __threadfence();
+        __syncthreads();
+        const int nbk = a.row_blocks[i];
+        for (int t = tid; t < nbk; t += G) {
+            const int2 e = a.lists[lo + t];
+            masks[e.x - base] = (uint32_t)e.y;
+        }
+    } else {
+        flat_walk<G, FLAT_KC_NUM, FLAT_VC, true, T>(a.aci, a.bhdr, av, a0, a1, off, ava, win, red, load_run,
+                                                    each(orb));
+    }
     if (!IN_LDS) __threadfence();
     __syncthreads();
     {

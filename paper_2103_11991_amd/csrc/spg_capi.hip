@@ -58,12 +58,13 @@ struct spg_handle_s {
     int lds_limit = 65536;
     int mlp_margin_milli = 500;
     int keep_features = 0;
+    int64_t list_limit_mb = 8192;
     bool have_mlp = false;
 
     // scratch
     DevBuf binfo, rinfo, feats, sym_cls, num_cls, perm_sym, perm_num, desc_sym, desc_num, row_nnz, row_blocks,
         tile_status, cursor,
-        ovf_list, ctl, slab_sym, slab_retry, slab_num, mlp_w, bcrp, bc, bhdr;
+        ovf_list, ctl, slab_sym, slab_retry, slab_num, mlp_w, bcrp, bc, bhdr, lofs, lists;
     Control* hctl = nullptr;  // pinned host copy
 
     // symbolic result
@@ -178,6 +179,9 @@ int wide_vals(spg_handle h, int eb) {
     return left >= 4096 ? (int)((left & ~(int64_t)255) / eb) : 0;
 }
 
+// list pairs the list memory may hold (8 bytes each; offsets stay in int32)
+int64_t list_limit_pairs(spg_handle h) { return h->list_limit_mb * (1 << 20) / 8; }
+
 int clamp_lds_limit(spg_handle h, int v) {
     // largest tier whose workgroup (tables + staging) fits the device's LDS
     while (v > 1024) {
@@ -207,8 +211,9 @@ spg_status check_input_errors(spg_handle h) {
 
 // ---- stages of the symbolic phase ----------------------------------------
 // sym_prepare      buffers for the current matrices (may allocate)
-// sym_stage_analysis  launches: control reset, B and A row analysis, learned classes
-// sym_stage_rows   launches: grouping by class, accumulators, retry, scan, numeric grouping;
+// sym_stage_analysis  launches: control reset, B and A row analysis, learned classes,
+//                  grouping by symbolic class with the rows' list offsets
+// sym_stage_rows   launches: compressed B, accumulators, retry, scan, numeric grouping;
 //                  launch geometry from h->geom (the control block read back after analysis)
 // sym_finish       host bookkeeping from the control block read back after the scan
 // A batch replays analysis + rows + numeric from a captured graph with the
@@ -234,6 +239,7 @@ spg_status sym_prepare(spg_handle h) {
     SPG_TRY(ensure(h, h->bcrp, ((size_t)h->n + 1) * 4));
     SPG_TRY(ensure(h, h->bhdr, (size_t)std::max(h->n, 1) * sizeof(int4)));
     SPG_TRY(ensure(h, h->cursor, NCLS * 4));
+    SPG_TRY(ensure(h, h->lofs, M * 4));
     if (learned) SPG_TRY(ensure(h, h->ovf_list, M * 4));
     if (want_feats) SPG_TRY(ensure(h, h->feats, M * 12));
     h->cfg = make_cfg(h);
@@ -250,14 +256,18 @@ void sym_stage_analysis(spg_handle h) {
     launch_b_rowinfo(s, h->n, h->k, h->brp, h->bci, h->bnnz, h->binfo.as<int4>(), ctl);
     launch_a_rowinfo(s, h->m, h->n, h->arp, h->aci, h->annz, h->binfo.as<int4>(), h->rinfo.as<RowInfo>(),
                      want_feats ? h->feats.as<float>() : nullptr, h->cfg, h->binning, h->sym_cls.as<uint8_t>(),
-                     h->row_nnz.as<int32_t>(), h->row_blocks.as<int32_t>(), ctl);
-    rec(h, EV_ANA1);
+                     h->row_nnz.as<int32_t>(), h->row_blocks.as<int32_t>(), h->lofs.as<int32_t>(), ctl);
     if (learned) {
         rec(h, EV_MLP0);
         launch_mlp_classify(s, h->m, h->feats.as<float>(), h->mlp_w.as<float>(), h->rinfo.as<RowInfo>(), h->cfg,
                             h->mlp_margin_milli / 1000.0f, h->sym_cls.as<uint8_t>(), ctl);
         rec(h, EV_MLP1);
     }
+    // rows grouped by symbolic class; each row's list placed (the total is read back)
+    launch_fill_i32(s, h->cursor.as<int32_t>(), 0, NCLS);
+    launch_scatter(s, h->m, h->sym_cls.as<uint8_t>(), ctl->sym_hist, h->cursor.as<int32_t>(), h->perm_sym.as<int32_t>(),
+                   h->arp, nullptr, h->desc_sym.as<int4>(), h->lofs.as<int32_t>(), ctl, list_limit_pairs(h));
+    rec(h, EV_ANA1);
 }
 
 spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
@@ -271,9 +281,7 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
     SPG_TRY(ensure(h, h->bc, (size_t)std::max<int64_t>(hc.bc_total, 1) * sizeof(int2)));
     launch_compress_b(s, h->n, h->brp, h->bci, h->binfo.as<int4>(), h->bcrp.as<int32_t>(), h->tile_status.as<uint64_t>(),
                       &ctl->tile_counter_b, h->bc.as<int2>(), h->bhdr.as<int4>());
-    launch_fill_i32(s, h->cursor.as<int32_t>(), 0, NCLS);
-    launch_scatter(s, m, h->sym_cls.as<uint8_t>(), ctl->sym_hist, h->cursor.as<int32_t>(), h->perm_sym.as<int32_t>(),
-                   h->arp, nullptr, h->desc_sym.as<int4>());
+    SPG_TRY(ensure(h, h->lists, (size_t)std::max<int64_t>(std::min(hc.list_total, list_limit_pairs(h)), 1) * 8));
     int off[NCLS];
     {
         int run = 0;
@@ -309,6 +317,8 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
         a.slab_words = slab_words;
         a.count_dev = nullptr;
         a.wide_lds = wl;
+        a.lofs = h->lofs.as<int32_t>();
+        a.lists = h->lists.as<int2>();
         rec(h, EV_SYMCLS + 2 * c);
         launch_sym_class(s, a, grid_cap);
         rec(h, EV_SYMCLS + 2 * c + 1);
@@ -330,6 +340,8 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
         a.row_blocks = h->row_blocks.as<int32_t>();
         a.ctl = ctl;
         a.wide_lds = wl;
+        a.lofs = h->lofs.as<int32_t>();
+        a.lists = h->lists.as<int2>();
         const int retry_grid = std::min(grid_cap, 64);
         if (hc.max_words_all * 4 > wl) {
             a.slab_words = (hc.max_words_all + 63) & ~(int64_t)63;
@@ -342,8 +354,8 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
     rec(h, EV_SCAN0);
     launch_fill_u8(s, h->tile_status.p, 0, (scan_tiles(m) + 1) * 8);
     launch_scan(s, m, h->row_nnz.as<int32_t>(), h->row_blocks.as<int32_t>(), h->rinfo.as<RowInfo>(), h->arp,
-                h->sym_cls.as<uint8_t>(), c_row_ptr, h->tile_status.as<uint64_t>(), h->cfg, h->num_cls.as<uint8_t>(),
-                ctl);
+                h->sym_cls.as<uint8_t>(), h->lofs.as<int32_t>(), c_row_ptr, h->tile_status.as<uint64_t>(), h->cfg,
+                h->num_cls.as<uint8_t>(), ctl);
     rec(h, EV_SCAN1);
     launch_fill_i32(s, h->cursor.as<int32_t>(), 0, NCLS);
     launch_scatter(s, m, h->num_cls.as<uint8_t>(), ctl->num_hist, h->cursor.as<int32_t>(), h->perm_num.as<int32_t>(),
@@ -391,6 +403,7 @@ spg_status sym_finish(spg_handle h, int32_t* c_row_ptr) {
     st.retried_rows = hc2.overflow_rows;
     st.mispredicted_rows = hc2.mispredicted;
     st.binning = h->binning;
+    st.list_pairs = std::min(hc.list_total, list_limit_pairs(h));
     h->crp = c_row_ptr;
     h->have_sym = true;
     h->have_feats = h->binning == 1 || h->keep_features;
@@ -423,6 +436,8 @@ spg_status num_launch_all(spg_handle h, const void* a_vals, const void* b_vals, 
         a.slab_words = h->slab_num_words;
         a.wide_lds = wide_lds(h);
         a.wide_vals = wide_vals(h, eb);
+        a.lofs = h->lofs.as<int32_t>();
+        a.lists = h->lists.as<int2>();
         rec(h, EV_NUMCLS + 2 * c);
         launch_num_class(s, a, eb, std::max(h->nslab_num, 1));
         rec(h, EV_NUMCLS + 2 * c + 1);
@@ -484,7 +499,8 @@ spg_status spg_destroy(spg_handle h) {
     DevBuf* bufs[] = {&h->binfo, &h->rinfo, &h->feats, &h->sym_cls, &h->num_cls, &h->perm_sym, &h->perm_num,
                       &h->desc_sym, &h->desc_num,
                       &h->row_nnz, &h->row_blocks, &h->tile_status, &h->cursor, &h->ovf_list, &h->ctl,
-                      &h->slab_sym, &h->slab_retry, &h->slab_num, &h->mlp_w, &h->bcrp, &h->bc, &h->bhdr};
+                      &h->slab_sym, &h->slab_retry, &h->slab_num, &h->mlp_w, &h->bcrp, &h->bc, &h->bhdr,
+                      &h->lofs, &h->lists};
     for (DevBuf* b : bufs) release(*b);
     if (h->hctl) (void)hipHostFree(h->hctl);
     if (h->ev_made)
@@ -617,6 +633,10 @@ spg_status spg_set_option(spg_handle h, int32_t opt, int64_t val) {
             break;
         }
         case SPG_OPT_KEEP_FEATURES: h->keep_features = val != 0; break;
+        case SPG_OPT_LIST_LIMIT_MB:
+            if (val < 1 || val > 16383) return fail(h, SPG_ERR_ARG, "list memory limit must be 1..16383 MiB");
+            h->list_limit_mb = val;
+            break;
         default: return fail(h, SPG_ERR_ARG, "unknown option " + std::to_string(opt));
     }
     // options change how rows are binned: the symbolic result must be redone

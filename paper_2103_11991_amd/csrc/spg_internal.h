@@ -5,11 +5,17 @@
 // so far.  The symbolic phase ORs masks in, as the paper's compressed
 // accumulator does (section 2.2.1: columns represented by bits, bitwise OR as
 // the accumulate operation); nnz(C(i,:)) is the sum of the masks' popcounts.
-// The numeric phase builds the same masks, turns them into ranks with a
-// prefix sum of popcounts taken in ascending block order, and then adds every
-// product into a compact value array at
+// It also stores each row's occupied blocks in ascending order as
+// {block, mask} pairs (the row's list, C's structure in compressed form).
+// The numeric phase reads the list back, turns it into ranks with a prefix
+// sum of popcounts, and adds every product into a compact value array at
 //     rank(c) = prefix[block(c)] + popcount(mask[block(c)] & ((1 << (c & 31)) - 1)),
 // so the output comes out sorted without a sort of the columns themselves.
+// A row's list has room for min(compressed-B runs its products read, words
+// of its column range) pairs, a bound on its occupied blocks known before
+// the symbolic phase; rows that the list memory cannot hold (and rows of the
+// symbolic global path) take the numeric global path, which finds the masks
+// from compressed B itself.
 //
 // The table is either *direct* (indexed by block - first block of the row:
 // the paper's dense accumulator restricted to the row's column range) or
@@ -64,16 +70,14 @@ constexpr int FLAT_VB = 4;       // B entries per group
 constexpr int FLAT_VC = 2;       // compressed-B runs per group (numeric)
 constexpr int FLAT_VC_SYM = 1;   // compressed-B runs per group (symbolic)
 constexpr int FLAT_KC = 5;       // run groups per lane and batch (symbolic; window table size)
-constexpr int FLAT_KC_NUM = 3;   // numeric: runs and B groups of a row are in flight together
+constexpr int FLAT_KC_NUM = 3;   // numeric global path: run groups per lane and batch
 constexpr int FLAT_KB_F64 = 3;   // B groups per lane and batch, FP64 values
 constexpr int FLAT_KB_F32 = 4;   // B groups per lane and batch, FP32 values (window table size)
 __host__ __device__ inline int group_waves(int g) { return g > 64 ? g / 64 : 1; }
-// staging of one row: per staged A entry its B and compressed-B {offset,
-// end} pairs (8 bytes each) and A's value (8), then the two window tables
-// (16 bytes per window and wavefront) of the batch in flight
-__host__ __device__ inline int stage_bytes(int g) {
-    return g * 24 + (FLAT_KB_F32 + FLAT_KC) * group_waves(g) * 16;
-}
+// numeric staging of one row: per staged A entry its B {offset, end} pair
+// and A's value (8 bytes each), then the window table (16 bytes per window
+// and wavefront) of the batch in flight
+__host__ __device__ inline int stage_bytes(int g) { return g * 16 + FLAT_KB_F32 * group_waves(g) * 16; }
 // the symbolic phase stages no values and walks compressed B only
 __host__ __device__ inline int sym_stage_bytes(int g) { return g * 8 + FLAT_KC * group_waves(g) * 16; }
 // dynamic LDS of one workgroup of tier t: the rows' tables plus staging
@@ -120,18 +124,22 @@ __host__ __device__ inline int64_t align8(int64_t b) { return (b + 7) & ~(int64_
 __host__ __device__ inline int64_t num_direct_bytes(int64_t words, int64_t n, int eb) {
     return align8(words * 8) + n * eb;
 }
-// hashed numeric table: 16-byte slots {block, mask, prefix, -}, the occupied
-// block ids compacted (padded to a multiple of 4) with their slots, and the
-// slots in ascending block order
+// hashed numeric table: 16-byte slots {block, mask, prefix, -}
 __host__ __device__ inline int64_t num_hashed_bytes(int64_t blocks, int64_t n, int eb) {
-    return align8(num_hash_slots(blocks) * 16 + ((blocks + 3) / 4) * 16 + blocks * 8) + n * eb;
+    return num_hash_slots(blocks) * 16 + n * eb;
 }
-// two-level numeric table: a {bits, prefix} pair per 32 words of the row's
-// block range (which blocks are occupied, and their compact index), then per
-// occupied block {mask, prefix} and its block id
+// two-level numeric table: a {bits, first index} pair per 32 words of the
+// row's block range (which blocks are occupied, and the list index of the
+// first of them), then {mask, prefix} per occupied block
 __host__ __device__ inline int64_t twolevel_words(int64_t words) { return (words + 31) / 32; }
 __host__ __device__ inline int64_t num_twolevel_bytes(int64_t words, int64_t blocks, int64_t n, int eb) {
-    return align8(twolevel_words(words) * 8 + blocks * 12) + n * eb;
+    return align8(twolevel_words(words) * 8 + blocks * 8) + n * eb;
+}
+// A row's list capacity: its compressed-B run count bounds its occupied
+// blocks, and so does the width of its column range in words.
+__host__ __device__ inline int32_t list_capacity(int64_t runs, int64_t words) {
+    const int64_t c = runs < words ? runs : words;
+    return c > INT32_MAX ? INT32_MAX : (int32_t)c;
 }
 
 // Smallest LDS tier that holds `bytes`, raised until its thread group gives
@@ -178,8 +186,8 @@ __host__ __device__ inline int sym_class(int64_t ub, int32_t cmin, int32_t cmax,
 
 // Numeric class of a row from its exact size n and occupied blocks: the
 // direct table when the row's block range is about as small as its block
-// count, else the two-level table; the hashed table only for very wide, very
-// sparse rows (its block ranking costs blocks^2 / G).
+// count, else the two-level table; the hashed table for very wide, sparse
+// rows with few blocks, when it is the smaller.
 __host__ __device__ inline int num_class(int64_t ub, int32_t cmin, int32_t cmax, int64_t n, int64_t blocks,
                                          const ClassCfg& c) {
     if (n <= 0) return CLS_EMPTY;
@@ -196,7 +204,7 @@ __host__ __device__ inline int num_class(int64_t ub, int32_t cmin, int32_t cmax,
     int mode;
     int64_t bytes;
     if (words <= 2 * blocks + 8) mode = MODE_DIRECT, bytes = bd;
-    else if (blocks <= c.hash_max_blocks && bh * 8 < b2) mode = MODE_HASHED, bytes = bh;
+    else if (blocks <= c.hash_max_blocks && bh < b2) mode = MODE_HASHED, bytes = bh;
     else mode = MODE_TWOLEVEL, bytes = b2;
     int t = pick_tier(bytes, ub, c);
     // a tier raised for the row's work may hold the direct table (one lookup per product)
@@ -224,6 +232,7 @@ struct Control {
     int32_t tile_counter;         // dynamic tile id of the row-pointer scan
     int32_t tile_counter_b;       // dynamic tile id of the compressed-B scan
     int64_t bc_total;             // runs of compressed B
+    int64_t list_total;           // list pairs reserved by the grouping of the symbolic rows
 };
 
 // ---- launch wrappers (spg_rows.hip) ----
@@ -240,16 +249,21 @@ void launch_compress_b(hipStream_t s, int32_t n, const int32_t* brp, const int32
                        int32_t* bcrp, uint64_t* tile_status, int32_t* tile_counter, int2* bc, int4* bhdr);
 void launch_a_rowinfo(hipStream_t s, int32_t m, int32_t n, const int32_t* arp, const int32_t* aci, int64_t annz,
                       const int4* binfo, RowInfo* rinfo, float* feats, ClassCfg cfg, int binning,
-                      uint8_t* sym_cls, int32_t* row_nnz, int32_t* row_blocks, Control* ctl);
+                      uint8_t* sym_cls, int32_t* row_nnz, int32_t* row_blocks, int32_t* lofs, Control* ctl);
 void launch_mlp_classify(hipStream_t s, int32_t m, const float* feats, const float* w, const RowInfo* rinfo,
                          ClassCfg cfg, float margin, uint8_t* sym_cls, Control* ctl);
 // groups rows by class; offsets come from the class histogram in device memory.
-// perm gets the row ids, desc {row, arp[row], arp[row+1], crp ? crp[row] : 0}
+// perm gets the row ids, desc {row, arp[row], arp[row+1], crp ? crp[row] : 0}.
+// With lofs (grouping of the symbolic rows): lofs holds each row's list
+// capacity on entry and its list offset on exit (-1 for rows of the global
+// path and rows past list_limit pairs), reserved from ctl->list_total; desc.w
+// gets the same offset.
 void launch_scatter(hipStream_t s, int32_t m, const uint8_t* cls, const int32_t* hist, int32_t* cursor, int32_t* perm,
-                    const int32_t* arp, const int32_t* crp, int4* desc);
+                    const int32_t* arp, const int32_t* crp, int4* desc, int32_t* lofs = nullptr,
+                    Control* ctl = nullptr, int64_t list_limit = 0);
 void launch_scan(hipStream_t s, int32_t m, const int32_t* row_nnz, const int32_t* row_blocks, const RowInfo* rinfo,
-                 const int32_t* arp, const uint8_t* sym_cls, int32_t* c_row_ptr, uint64_t* tile_status,
-                 ClassCfg cfg, uint8_t* num_cls, Control* ctl);
+                 const int32_t* arp, const uint8_t* sym_cls, const int32_t* lofs, int32_t* c_row_ptr,
+                 uint64_t* tile_status, ClassCfg cfg, uint8_t* num_cls, Control* ctl);
 void launch_export_rows(hipStream_t s, int32_t m, const float* feats, const int32_t* row_blocks,
                         const int32_t* row_nnz_in, float* x, float* y, int32_t* row_nnz_out);
 int64_t scan_tiles(int32_t m);
@@ -261,7 +275,7 @@ void launch_pack(hipStream_t s, int32_t count, const int64_t* desc, const int32_
 // ---- accumulator kernels (spg_accum.hip) ----
 struct SymArgs {
     const int32_t* perm;
-    const int4* desc;             // per slot {row, A start, A end, -} (row kernels)
+    const int4* desc;             // per slot {row, A start, A end, list offset} (row kernels)
     int32_t count;
     int32_t tier;
     int32_t mode;
@@ -282,6 +296,8 @@ struct SymArgs {
     int64_t slab_words;
     const int32_t* count_dev;     // global path: device-side row count (or null)
     int32_t wide_lds;             // global path: LDS bytes per workgroup
+    const int32_t* lofs;          // per row: first pair of its list, -1 if it has none
+    int2* lists;                  // {block, mask} pairs of the rows' occupied blocks
 };
 
 struct NumArgs {
@@ -310,6 +326,8 @@ struct NumArgs {
     int64_t slab_words;
     int32_t wide_lds;
     int32_t wide_vals;            // global path: values per LDS segment (0 = global atomics only)
+    const int32_t* lofs;          // per row: first pair of its list, -1 if it has none
+    const int2* lists;            // {block, mask} pairs in ascending block order
 };
 
 // Launches one symbolic class; returns the grid size used.

@@ -120,7 +120,8 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
                                                    const int4* __restrict__ binfo, RowInfo* __restrict__ rinfo,
                                                    float* __restrict__ feats, ClassCfg cfg, int binning,
                                                    uint8_t* __restrict__ sym_cls, int32_t* __restrict__ row_nnz,
-                                                   int32_t* __restrict__ row_blocks, Control* ctl) {
+                                                   int32_t* __restrict__ row_blocks, int32_t* __restrict__ lofs,
+                                                   Control* ctl) {
     __shared__ int32_t hist[NCLS];
     __shared__ int32_t empties;
     __shared__ unsigned long long prod_sum, wmax_all, wmax_glob;
@@ -188,6 +189,7 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
                 sym_cls[row] = CLS_EMPTY;
             } else {
                 int64_t words = row_words(cmin, cmax);
+                lofs[row] = list_capacity(rs, words);
                 atomicMax(&wmax_all, (unsigned long long)words);
                 atomicAdd(&prod_sum, (unsigned long long)ub);
                 if (binning != 1) {
@@ -263,15 +265,20 @@ __global__ __launch_bounds__(256) void k_mlp_classify(int32_t m, const float* __
 // Groups rows by class: a workgroup takes chunks of 4096 consecutive rows,
 // ranks each row inside its class with LDS atomics, reserves one range per
 // class and chunk with a single global atomic, and writes the row ids there,
-// with each row's descriptor {row, A start, A end, C start (or 0)} beside it.
+// with each row's descriptor {row, A start, A end, C start (or list offset)}
+// beside it.  For the symbolic rows it also places the rows' lists: a scan
+// of the chunk's capacities and one global atomic for the chunk's range.
 constexpr int SCATTER_ITEMS = 16;
 __global__ __launch_bounds__(256) void k_scatter(int32_t m, const uint8_t* __restrict__ cls,
                                                  const int32_t* __restrict__ hist, int32_t* __restrict__ cursor,
                                                  int32_t* __restrict__ perm, const int32_t* __restrict__ arp,
-                                                 const int32_t* __restrict__ crp, int4* __restrict__ desc) {
+                                                 const int32_t* __restrict__ crp, int4* __restrict__ desc,
+                                                 int32_t* __restrict__ lofs, Control* ctl, int64_t list_limit) {
     __shared__ int32_t cnt[NCLS];
     __shared__ int32_t base[NCLS];
     __shared__ int32_t off[NCLS];
+    __shared__ int64_t wsum[4];
+    __shared__ int64_t lbase;
     if (threadIdx.x == 0) {
         int32_t run = 0;
         for (int c = 0; c < NCLS; ++c) off[c] = run, run += hist[c];
@@ -287,16 +294,52 @@ __global__ __launch_bounds__(256) void k_scatter(int32_t m, const uint8_t* __res
             c[t] = row < m ? cls[row] : CLS_EMPTY;
             local[t] = c[t] != CLS_EMPTY ? atomicAdd(&cnt[c[t]], 1) : 0;
         }
+        // list capacities of the chunk (rows of the global path get none)
+        int32_t cap[SCATTER_ITEMS];
+        int64_t lsum = 0;
+#pragma unroll
+        for (int t = 0; t < SCATTER_ITEMS; ++t) {
+            cap[t] = 0;
+            if (lofs && c[t] != CLS_EMPTY && c[t] % NTIER != TIER_GLOBAL) cap[t] = lofs[r0 + t * 256 + threadIdx.x];
+            lsum += cap[t];
+        }
+        int64_t lex = 0;
+        if (lofs) {
+            const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+            int64_t x = lsum;
+            for (int d = 1; d < 64; d <<= 1) {
+                const int64_t y = __shfl_up(x, d, 64);
+                if (lane >= d) x += y;
+            }
+            if (lane == 63) wsum[wv] = x;
+            __syncthreads();
+            int64_t pre = 0, tot = 0;
+            for (int u = 0; u < 4; ++u) {
+                if (u < wv) pre += wsum[u];
+                tot += wsum[u];
+            }
+            lex = pre + x - lsum;
+            if (threadIdx.x == 0) lbase = tot ? (int64_t)atomicAdd((unsigned long long*)&ctl->list_total,
+                                                                   (unsigned long long)tot)
+                                              : 0;
+        }
         __syncthreads();
         if (threadIdx.x < NCLS && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
         __syncthreads();
+        int64_t lpos = lofs ? lbase + lex : 0;
 #pragma unroll
         for (int t = 0; t < SCATTER_ITEMS; ++t) {
             if (c[t] == CLS_EMPTY) continue;
             const int32_t row = (int32_t)(r0 + t * 256 + threadIdx.x);
             const int32_t pos = off[c[t]] + base[c[t]] + local[t];
+            int32_t w = crp ? crp[row] : 0;
+            if (lofs) {
+                w = cap[t] > 0 && lpos + cap[t] <= list_limit ? (int32_t)lpos : -1;
+                lofs[row] = w;
+                lpos += cap[t];
+            }
             perm[pos] = row;
-            desc[pos] = make_int4(row, arp[row], arp[row + 1], crp ? crp[row] : 0);
+            desc[pos] = make_int4(row, arp[row], arp[row + 1], w);
         }
         __syncthreads();
     }
@@ -309,13 +352,15 @@ constexpr uint64_t ST_VAL = (1ull << 62) - 1;
 
 // Row pointer = exclusive prefix sum of row_nnz, in 64-bit, single pass with
 // decoupled look-back over tiles taken in launch order.  Also assigns each
-// row's numeric class (its exact size is now known) and counts rows whose
-// symbolic class differed from the class their true size asks for.
+// row's numeric class (its exact size is now known; rows without a list take
+// the global path) and counts rows whose symbolic class differed from the
+// class their true size asks for.
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan(int32_t m, const int32_t* __restrict__ row_nnz,
                                                        const int32_t* __restrict__ row_blocks,
                                                        const RowInfo* __restrict__ rinfo,
                                                        const int32_t* __restrict__ arp,
                                                        const uint8_t* __restrict__ sym_cls,
+                                                       const int32_t* __restrict__ lofs,
                                                        int32_t* __restrict__ c_row_ptr, uint64_t* tile_status,
                                                        ClassCfg cfg, uint8_t* __restrict__ num_cls, Control* ctl) {
     __shared__ int32_t tile_sh;
@@ -342,6 +387,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(int32_t m, const int32_t*
             RowInfo ri = rinfo[r];
             int blocks = row_blocks[r];
             int nc = num_class(ri.z, ri.x, ri.y, c, blocks, cfg);
+            // a row kernel builds its table from the row's list: without one, the global path
+            if (nc != CLS_EMPTY && nc % NTIER != TIER_GLOBAL && lofs[r] < 0) nc = MODE_DIRECT * NTIER + TIER_GLOBAL;
             num_cls[r] = (uint8_t)nc;
             if (nc != CLS_EMPTY) {
                 atomicAdd(&hist[nc], 1);
@@ -631,11 +678,10 @@ void launch_compress_b(hipStream_t s, int32_t n, const int32_t* brp, const int32
 
 void launch_a_rowinfo(hipStream_t s, int32_t m, int32_t n, const int32_t* arp, const int32_t* aci, int64_t annz,
                       const int4* binfo, RowInfo* rinfo, float* feats, ClassCfg cfg, int binning,
-                      uint8_t* sym_cls, int32_t* row_nnz, int32_t* row_blocks, Control* ctl) {
+                      uint8_t* sym_cls, int32_t* row_nnz, int32_t* row_blocks, int32_t* lofs, Control* ctl) {
     if (m <= 0) return;
     hipLaunchKernelGGL(k_a_rowinfo, dim3(std::min(grid_for((int64_t)m * ROW_LANES, 256), 4096u)), dim3(256), 0, s, m, n,
-                       arp, aci,
-                       annz, binfo, rinfo, feats, cfg, binning, sym_cls, row_nnz, row_blocks, ctl);
+                       arp, aci, annz, binfo, rinfo, feats, cfg, binning, sym_cls, row_nnz, row_blocks, lofs, ctl);
 }
 
 void launch_mlp_classify(hipStream_t s, int32_t m, const float* feats, const float* w, const RowInfo* rinfo,
@@ -647,18 +693,19 @@ void launch_mlp_classify(hipStream_t s, int32_t m, const float* feats, const flo
 }
 
 void launch_scatter(hipStream_t s, int32_t m, const uint8_t* cls, const int32_t* hist, int32_t* cursor,
-                    int32_t* perm, const int32_t* arp, const int32_t* crp, int4* desc) {
+                    int32_t* perm, const int32_t* arp, const int32_t* crp, int4* desc, int32_t* lofs, Control* ctl,
+                    int64_t list_limit) {
     if (m <= 0) return;
     hipLaunchKernelGGL(k_scatter, dim3(std::min(grid_for(m, 256 * SCATTER_ITEMS), 1024u)), dim3(256), 0, s, m, cls, hist,
-                       cursor, perm, arp, crp, desc);
+                       cursor, perm, arp, crp, desc, lofs, ctl, list_limit);
 }
 
 void launch_scan(hipStream_t s, int32_t m, const int32_t* row_nnz, const int32_t* row_blocks, const RowInfo* rinfo,
-                 const int32_t* arp, const uint8_t* sym_cls, int32_t* c_row_ptr, uint64_t* tile_status,
-                 ClassCfg cfg, uint8_t* num_cls, Control* ctl) {
+                 const int32_t* arp, const uint8_t* sym_cls, const int32_t* lofs, int32_t* c_row_ptr,
+                 uint64_t* tile_status, ClassCfg cfg, uint8_t* num_cls, Control* ctl) {
     if (m <= 0) return;
     hipLaunchKernelGGL(k_scan, dim3((unsigned)scan_tiles(m)), dim3(SCAN_THREADS), 0, s, m, row_nnz, row_blocks,
-                       rinfo, arp, sym_cls, c_row_ptr, tile_status, cfg, num_cls, ctl);
+                       rinfo, arp, sym_cls, lofs, c_row_ptr, tile_status, cfg, num_cls, ctl);
 }
 
 void launch_export_rows(hipStream_t s, int32_t m, const float* feats, const int32_t* row_blocks,

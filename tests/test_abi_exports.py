@@ -33,6 +33,9 @@ def test_status_strings_and_argument_errors_without_gpu():
 
 
 def test_stats_struct_layout_matches_header():
-    # 4 ints, 2 int64, 2x30 int32, 3x30 int64, 4 int32, 2 floats, 2x30 floats, 3 floats
+    # 4 ints, 2 int64, 2x30 int32, 3x30 int64, 4 int32, 2 floats, 2x30 floats, 3 floats, then an
+    # int64 on an 8-byte boundary
     expect = 16 + 16 + 240 + 720 + 16 + 8 + 240 + 12
-    assert ctypes.sizeof(_lib.spg_stats) == expect + (-expect % 8)
+    expect += -expect % 8
+    assert _lib.spg_stats.list_pairs.offset == expect
+    assert ctypes.sizeof(_lib.spg_stats) == expect + 8

@@ -140,6 +140,44 @@ def test_galerkin_exact():
     np.testing.assert_array_equal(v2, ref.values)
 
 
+def test_rows_past_the_list_limit_take_the_global_path():
+    """With 1 MiB of list memory (131072 pairs) only some rows of a 27-point
+    stencil on 30^3 get a list (each reserves 100-250 pairs): the others are
+    computed by the numeric global path from compressed B.  The product is
+    unchanged, also when numeric is run again with new values."""
+    import torch
+    A = gen.stencil27(30, seed=4)
+    rp, c, v, op = run_gpu(A, A, list_limit_mb=1)
+    st = op.stats()
+    assert 0 < st["list_pairs"] <= (1 << 20) // 8
+    assert st["num_rows"][9] > 0 and sum(st["num_rows"][:9]) + sum(st["num_rows"][10:]) > 0
+    compare(A, A, rp, c, v)
+    A2 = A.with_values(gen.sweep_values(A, 2))
+    col, val = op.numeric(a_vals=torch.from_numpy(A2.values).cuda())
+    torch.cuda.synchronize()
+    compare(A2, A, rp, col.cpu().numpy(), val.cpu().numpy())
+
+
+def test_list_memory_is_the_run_bound():
+    """Each row reserves min(compressed-B runs of its products, words of its
+    column range) list pairs."""
+    A = gen.random_csr(500, 3000, 0, 30, seed=8, empty_frac=0.1)
+    B = gen.random_csr(3000, 9000, 0, 25, seed=9)
+    rp, c, v, op = run_gpu(A, B)
+    compare(A, B, rp, c, v)
+    def runs_of_row(j):  # maximal runs of consecutive stored entries in one 32-column block
+        blk = B.col_idx[B.row_ptr[j]:B.row_ptr[j + 1]] >> 5
+        return int(len(blk) > 0) + int(np.count_nonzero(blk[1:] != blk[:-1]))
+    runs = np.array([runs_of_row(j) for j in range(B.m)])
+    want = 0
+    for i in range(A.m):
+        js = A.col_idx[A.row_ptr[i]:A.row_ptr[i + 1]]
+        cols = np.concatenate([B.col_idx[B.row_ptr[j]:B.row_ptr[j + 1]] for j in js]) if len(js) else []
+        if len(cols):
+            want += min(int(runs[js].sum()), int((cols.max() >> 5) - (cols.min() >> 5) + 1))
+    assert op.stats()["list_pairs"] == want
+
+
 def test_symbolic_reuse_with_new_values():
     import torch
     from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
