@@ -533,6 +533,9 @@ void k_sym(SymArgs a) {
     if (slot >= a.count) return;  // uniform in the group (in the workgroup when G >= 128)
     const int4 d = a.desc[slot];
     const int i = d.x, a0 = d.y, a1 = d.z;
+    // the first chunk's B headers are gathered before the table is cleared
+    int4 h0 = make_int4(0, 0, 0, 0);
+    if (lane < a1 - a0) h0 = a.bhdr[a.aci[a0 + lane]];
     uint8_t* row_lds = reinterpret_cast<uint8_t*>(smem) + (size_t)sub * per_row;
     uint32_t* tab = reinterpret_cast<uint32_t*>(row_lds);
     int2* cq = reinterpret_cast<int2*>(row_lds + bytes);   // staged run {offset, end}
@@ -578,9 +581,9 @@ void k_sym(SymArgs a) {
     int pc = 0, PC = 0;
     bool ne = false;
     int staged = -1, wc0 = 0;
-    auto stage = [&](int e0) {  // window table cleared and synchronised by the caller
-        int4 h = make_int4(0, 0, 0, 0);
-        if (lane < a1 - e0) h = a.bhdr[a.aci[e0 + lane]];
+    // h: the lane's B header in chunk e0 (window table cleared and
+    // synchronised by the caller)
+    auto stage = [&](int e0, int4 h) {
         ne = h.w > 0;
         int3 tot;
         const int3 ex = group_excl_scan3<G>(make_int3(ne, (h.w + VC - 1) / VC, 0), tot, red);
@@ -594,10 +597,12 @@ void k_sym(SymArgs a) {
     };
     auto restage = [&](int e0) {
         if (staged == e0) return;
+        int4 h = make_int4(0, 0, 0, 0);
+        if (lane < a1 - e0) h = a.bhdr[a.aci[e0 + lane]];
         group_sync<G>();
         win_clear<G, KC>(win, lane);
         group_sync<G>();
-        stage(e0);
+        stage(e0, h);
     };
     auto rewin = [&](int P0) {
         if (wc0 == P0) return;
@@ -688,7 +693,7 @@ void k_sym(SymArgs a) {
         }
     };
 
-    stage(a0);
+    stage(a0, h0);
     if (a1 - a0 <= G && PC <= KC * G) {
         // the whole row in one batch: its runs stay in registers for every pass
         Batch<G, KC, VC, decltype(load_run)> br;
@@ -882,10 +887,26 @@ void k_num(NumArgs a) {
     if (slot >= a.count) return;
     const int4 d = a.desc[slot];
     const int i = d.x, a0 = d.y, a1 = d.z, off = d.w;
+    const T* av = reinterpret_cast<const T*>(a.av);
+    const T* bv = reinterpret_cast<const T*>(a.bv);
+    // Loads are issued in the order their data is needed (vector memory
+    // returns in order): the first chunk's A entries and values, the row's
+    // list, then the B headers of the chunk; all of them before the table is
+    // cleared, so their latencies overlap each other and the clear.
+    int aj = -1;
+    T v0 = T(0);
+    if (lane < a1 - a0) {
+        aj = a.aci[a0 + lane];
+        v0 = av[a0 + lane];
+    }
     const int n = a.crp[i + 1] - off;
     const RowInfo ri = a.rinfo[i];
     const int nb = a.row_blocks[i];
     const int2* lst = a.lists + a.lofs[i];  // rows of these classes always have a list
+    int2 e_first = make_int2(0, 0);         // the lane's entry of the list's first round
+    if (lane < nb) e_first = lst[lane];
+    int4 h0 = make_int4(0, 0, 0, 0);        // B headers of the first chunk
+    if (aj >= 0) h0 = a.bhdr[aj];
     const int base = ri.x >> 5;
     const int words = (ri.y >> 5) - base + 1;
     const int w1 = (words + 31) >> 5;
@@ -923,19 +944,13 @@ void k_num(NumArgs a) {
     win_clear<G, KB>(winb, lane);
     group_sync<G>();
 
-    const T* av = reinterpret_cast<const T*>(a.av);
-    const T* bv = reinterpret_cast<const T*>(a.bv);
     // ---- staging (chunks of G entries of A's row; a window table of one batch)
     bool ne = false;
     int pb = 0, P = 0;
     int staged = -1, wb0 = 0;
-    auto stage = [&](int e0) {  // window table cleared and synchronised by the caller
-        int4 h = make_int4(0, 0, 0, 0);
-        T v = T(0);
-        if (lane < a1 - e0) {
-            h = a.bhdr[a.aci[e0 + lane]];
-            v = av[e0 + lane];
-        }
+    // h, v: the lane's B header and A value in chunk e0 (window table
+    // cleared and synchronised by the caller)
+    auto stage = [&](int e0, int4 h, T v) {
         ne = h.y > 0;
         int2 tot;
         const int2 ex = group_excl_scan2<G>(make_int2(ne, (h.y + FLAT_VB - 1) / FLAT_VB), tot, red);
@@ -952,10 +967,16 @@ void k_num(NumArgs a) {
     };
     auto restage = [&](int e0) {
         if (staged == e0) return;
+        int4 h = make_int4(0, 0, 0, 0);
+        T v = T(0);
+        if (lane < a1 - e0) {
+            h = a.bhdr[a.aci[e0 + lane]];
+            v = av[e0 + lane];
+        }
         group_sync<G>();
         win_clear<G, KB>(winb, lane);
         group_sync<G>();
-        stage(e0);
+        stage(e0, h, v);
     };
     // window table rebuilt for the batch starting at P0
     auto rewin = [&](int P0) {
@@ -980,8 +1001,11 @@ void k_num(NumArgs a) {
         int carry = 0;
         for (int t0 = 0; t0 < nb; t0 += G) {
             const int t = t0 + lane;
-            int2 e = make_int2(0, 0);
-            if (t < nb) e = lst[t];
+            int2 e = e_first;
+            if (t0 > 0) {
+                e = make_int2(0, 0);
+                if (t < nb) e = lst[t];
+            }
             int tot;
             const int ex = carry + group_excl_scan<G>(__popc((uint32_t)e.y), tot, red);
             carry += tot;
@@ -1041,7 +1065,7 @@ void k_num(NumArgs a) {
             if (j < g.n) atomicAdd(&vals[rk[j]], x * g.y[j]);
     };
 
-    stage(a0);
+    stage(a0, h0, v0);
     if (a1 - a0 <= G && P <= KB * G) {
         // the whole row in one batch: its B loads are in flight while the table is built
         Batch<G, KB, FLAT_VB, decltype(load_cv)> bb;
