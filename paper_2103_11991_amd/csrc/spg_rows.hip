@@ -85,12 +85,28 @@ __global__ __launch_bounds__(256) void k_b_rowinfo(int32_t n, int32_t k, const i
                 bad = ERR_B_ROWPTR;
             } else {
                 len = e - s;
-                for (int32_t q = s + lane; q < e; q += ROW_LANES) {
-                    int c = bci[q];
-                    if (c < 0 || c >= k) { bad = ERR_B_COL; continue; }
-                    mn = min(mn, c);
-                    mx = max(mx, c);
-                    runs += q == s || (bci[q - 1] >> 5) != (c >> 5);
+                // four independent entry loads per lane (with each entry's
+                // predecessor), then their checks
+                for (int32_t p0 = s + lane; p0 < e; p0 += 4 * ROW_LANES) {
+                    int c[4], cp[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int32_t q = p0 + u * ROW_LANES;
+                        c[u] = q < e ? bci[q] : 0;
+                        cp[u] = q < e && q > s ? bci[q - 1] : 0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int32_t q = p0 + u * ROW_LANES;
+                        if (q >= e) continue;
+                        if (c[u] < 0 || c[u] >= k) {
+                            bad = ERR_B_COL;
+                            continue;
+                        }
+                        mn = min(mn, c[u]);
+                        mx = max(mx, c[u]);
+                        runs += q == s || (cp[u] >> 5) != (c[u] >> 5);
+                    }
                 }
             }
         }
@@ -593,15 +609,27 @@ __global__ __launch_bounds__(256) void k_compress_b(int32_t n, const int32_t* __
         int done = 0;          // runs begun in earlier chunks
         uint32_t carry = 0;    // bits of the run still open at the end of the last chunk
         int last_blk = -1;     // block of the last chunk's final entry
-        for (int32_t q0 = s; q0 < e; q0 += L) {
+        // four chunks' entries (and the entry after each chunk) are loaded at once
+        for (int32_t Q0 = s; Q0 < e; Q0 += 4 * L) {
+            int cc[4], nx[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int32_t q = Q0 + u * L + sl;
+                cc[u] = q < e ? bci[q] : 0;
+                nx[u] = sl == L - 1 && q + 1 < e ? bci[q + 1] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+            const int32_t q0 = Q0 + u * L;
+            if (q0 >= e) break;  // uniform in the row's lanes
             const int32_t q = q0 + sl;
             const bool v = q < e;
-            const int c = v ? bci[q] : 0;
+            const int c = cc[u];
             const int blk = v ? c >> 5 : -1;
             int prev = __shfl_up(blk, 1, L);
             if (sl == 0) prev = last_blk;
             int next = __shfl_down(blk, 1, L);
-            if (sl == L - 1) next = q + 1 < e ? bci[q + 1] >> 5 : -1;
+            if (sl == L - 1) next = q + 1 < e ? nx[u] >> 5 : -1;
             const int start = v && blk != prev;
             const bool last = v && (q + 1 >= e || next != blk);
             // segmented inclusive OR of the column bits, segments begin at run starts
@@ -622,6 +650,7 @@ __global__ __launch_bounds__(256) void k_compress_b(int32_t n, const int32_t* __
             done += __popcll(starts);
             carry = __shfl(m, L - 1, L);
             last_blk = __shfl(blk, L - 1, L);
+            }
         }
     }
 }
