@@ -284,7 +284,7 @@ __global__ __launch_bounds__(256) void k_mlp_classify(int32_t m, const float* __
 // with each row's descriptor {row, A start, A end, C start (or list offset)}
 // beside it.  For the symbolic rows it also places the rows' lists: a scan
 // of the chunk's capacities and one global atomic for the chunk's range.
-constexpr int SCATTER_ITEMS = 16;
+constexpr int SCATTER_ITEMS = 8;
 __global__ __launch_bounds__(256) void k_scatter(int32_t m, const uint8_t* __restrict__ cls,
                                                  const int32_t* __restrict__ hist, int32_t* __restrict__ cursor,
                                                  int32_t* __restrict__ perm, const int32_t* __restrict__ arp,
