@@ -92,7 +92,13 @@ typedef enum {
        its column range in 32-column blocks); rows past the limit, and rows
        of the symbolic global path, are computed by numeric on its global
        path instead. */
-    SPG_OPT_LIST_LIMIT_MB = 9
+    SPG_OPT_LIST_LIMIT_MB = 9,
+    /* run the rows of a class that has few rows in the next populated class
+       of the same table mode with a larger tier (at most 4x the lanes per row,
+       at least 8x the rows), saving a short launch (1 = default, 0 = off;
+       off under SPG_OPT_FORCE_CLASS).  sym_rows / num_rows in spg_stats count
+       rows by the class they ran in. */
+    SPG_OPT_MERGE_CLASSES = 10
 } spg_option;
 
 #define SPG_NTIER 10

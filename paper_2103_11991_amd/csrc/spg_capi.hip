@@ -59,6 +59,7 @@ struct spg_handle_s {
     int mlp_margin_milli = 500;
     int keep_features = 0;
     int64_t list_limit_mb = 8192;
+    int merge_classes = 1;
     bool have_mlp = false;
 
     // scratch
@@ -179,6 +180,9 @@ int wide_vals(spg_handle h, int eb) {
     return left >= 4096 ? (int)((left & ~(int64_t)255) / eb) : 0;
 }
 
+// small classes run in larger ones unless a class is forced
+int merging(spg_handle h) { return h->merge_classes && h->force_class < 0; }
+
 // list pairs the list memory may hold (8 bytes each; offsets stay in int32)
 int64_t list_limit_pairs(spg_handle h) { return h->list_limit_mb * (1 << 20) / 8; }
 
@@ -263,10 +267,12 @@ void sym_stage_analysis(spg_handle h) {
                             h->mlp_margin_milli / 1000.0f, h->sym_cls.as<uint8_t>(), ctl);
         rec(h, EV_MLP1);
     }
-    // rows grouped by symbolic class; each row's list placed (the total is read back)
+    // rows grouped by symbolic launch class (small classes merged); each
+    // row's list placed (the total is read back)
     launch_fill_i32(s, h->cursor.as<int32_t>(), 0, NCLS);
-    launch_scatter(s, h->m, h->sym_cls.as<uint8_t>(), ctl->sym_hist, h->cursor.as<int32_t>(), h->perm_sym.as<int32_t>(),
-                   h->arp, nullptr, h->desc_sym.as<int4>(), h->lofs.as<int32_t>(), ctl, list_limit_pairs(h));
+    launch_scatter(s, h->m, h->sym_cls.as<uint8_t>(), merging(h), ctl->sym_hist, h->cursor.as<int32_t>(),
+                   h->perm_sym.as<int32_t>(), h->arp, nullptr, h->desc_sym.as<int4>(), h->lofs.as<int32_t>(), ctl,
+                   list_limit_pairs(h));
     rec(h, EV_ANA1);
 }
 
@@ -277,6 +283,9 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
     const Control& hc = h->geom;
     Control* ctl = h->ctl.as<Control>();
     const int wl = wide_lds(h);
+    int32_t sym_hist[NCLS];  // rows per launch class
+    uint8_t sym_remap[NCLS];
+    merge_classes(hc.sym_hist, sym_remap, sym_hist, merging(h) != 0);
     // compressed B, read by both phases
     SPG_TRY(ensure(h, h->bc, (size_t)std::max<int64_t>(hc.bc_total, 1) * sizeof(int2)));
     launch_compress_b(s, h->n, h->brp, h->bci, h->binfo.as<int4>(), h->bcrp.as<int32_t>(), h->tile_status.as<uint64_t>(),
@@ -285,24 +294,24 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
     int off[NCLS];
     {
         int run = 0;
-        for (int c = 0; c < NCLS; ++c) off[c] = run, run += hc.sym_hist[c];
+        for (int c = 0; c < NCLS; ++c) off[c] = run, run += sym_hist[c];
     }
     const int grid_cap = 2 * h->n_cu;
     uint32_t* slab = nullptr;
     int64_t slab_words = 0;
     const int gcls = MODE_DIRECT * NTIER + TIER_GLOBAL;
-    if (hc.sym_hist[gcls] > 0 && hc.max_words_sym_global * 4 > wl) {
+    if (sym_hist[gcls] > 0 && hc.max_words_sym_global * 4 > wl) {
         slab_words = (hc.max_words_sym_global + 63) & ~(int64_t)63;
-        int ns = std::min(hc.sym_hist[gcls], grid_cap);
+        int ns = std::min(sym_hist[gcls], grid_cap);
         SPG_TRY(ensure(h, h->slab_sym, (size_t)ns * slab_words * 4));
         slab = h->slab_sym.as<uint32_t>();
     }
     for (int c = 0; c < NCLS; ++c) {
-        if (!hc.sym_hist[c]) continue;
+        if (!sym_hist[c]) continue;
         SymArgs a{};
         a.perm = h->perm_sym.as<int32_t>() + off[c];
         a.desc = h->desc_sym.as<int4>() + off[c];
-        a.count = hc.sym_hist[c];
+        a.count = sym_hist[c];
         a.tier = c % NTIER;
         a.mode = c / NTIER;
         a.arp = h->arp, a.aci = h->aci, a.brp = h->brp, a.bci = h->bci;
@@ -358,8 +367,8 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
                 h->num_cls.as<uint8_t>(), ctl);
     rec(h, EV_SCAN1);
     launch_fill_i32(s, h->cursor.as<int32_t>(), 0, NCLS);
-    launch_scatter(s, m, h->num_cls.as<uint8_t>(), ctl->num_hist, h->cursor.as<int32_t>(), h->perm_num.as<int32_t>(),
-                   h->arp, c_row_ptr, h->desc_num.as<int4>());
+    launch_scatter(s, m, h->num_cls.as<uint8_t>(), merging(h), ctl->num_hist, h->cursor.as<int32_t>(),
+                   h->perm_num.as<int32_t>(), h->arp, c_row_ptr, h->desc_num.as<int4>());
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "symbolic launch");
     return SPG_OK;
@@ -372,18 +381,22 @@ spg_status sym_finish(spg_handle h, int32_t* c_row_ptr) {
         return fail(h, SPG_ERR_OVERFLOW, "nnz(C) = " + std::to_string(hc2.nnz_c) + " exceeds the int32 range");
     if (hc2.err & ERR_TABLE_OVERFLOW) return fail(h, SPG_ERR_HIP, "internal error: bounded symbolic table overflowed");
     h->nnz_c = hc2.nnz_c;
+    uint8_t num_remap[NCLS];
+    merge_classes(hc2.num_hist, num_remap, h->num_hist, merging(h) != 0);
+    int32_t sym_hist[NCLS];
+    uint8_t sym_remap[NCLS];
+    merge_classes(hc.sym_hist, sym_remap, sym_hist, merging(h) != 0);
     int run = 0;
     for (int c = 0; c < NCLS; ++c) {
-        h->num_hist[c] = hc2.num_hist[c];
         h->num_off[c] = run;
-        run += hc2.num_hist[c];
+        run += h->num_hist[c];
     }
     // global-path slabs for the numeric phase are sized now, not inside numeric
     const int gcls = MODE_DIRECT * NTIER + TIER_GLOBAL;
     const int grid_cap = 2 * h->n_cu;
     h->slab_num_words = 0;
-    h->nslab_num = std::min(std::max(hc2.num_hist[gcls], 0), grid_cap);
-    if (hc2.num_hist[gcls] > 0 && hc2.max_words_num_global * 8 > wide_lds(h)) {
+    h->nslab_num = std::min(std::max(h->num_hist[gcls], 0), grid_cap);
+    if (h->num_hist[gcls] > 0 && hc2.max_words_num_global * 8 > wide_lds(h)) {
         h->slab_num_words = 2 * ((hc2.max_words_num_global + 63) & ~(int64_t)63);
         SPG_TRY(ensure(h, h->slab_num, (size_t)h->nslab_num * h->slab_num_words * 4));
     }
@@ -392,12 +405,16 @@ spg_status sym_finish(spg_handle h, int32_t* c_row_ptr) {
     st.m = h->m, st.n = h->n, st.k = h->k;
     st.products = hc2.products;
     st.nnz_c = hc2.nnz_c;
+    // statistics per launch class
     for (int c = 0; c < NCLS; ++c) {
-        st.sym_rows[c] = hc.sym_hist[c];
-        st.num_rows[c] = hc2.num_hist[c];
-        st.num_a_nnz[c] = hc2.num_a_nnz[c];
-        st.num_c_nnz[c] = hc2.num_c_nnz[c];
-        st.num_products[c] = hc2.num_products[c];
+        st.sym_rows[c] = sym_hist[c];
+        st.num_rows[c] = h->num_hist[c];
+        st.num_a_nnz[c] = st.num_c_nnz[c] = st.num_products[c] = 0;
+    }
+    for (int c = 0; c < NCLS; ++c) {
+        st.num_a_nnz[num_remap[c]] += hc2.num_a_nnz[c];
+        st.num_c_nnz[num_remap[c]] += hc2.num_c_nnz[c];
+        st.num_products[num_remap[c]] += hc2.num_products[c];
     }
     st.empty_rows = hc2.empty_rows;
     st.retried_rows = hc2.overflow_rows;
@@ -633,6 +650,7 @@ spg_status spg_set_option(spg_handle h, int32_t opt, int64_t val) {
             break;
         }
         case SPG_OPT_KEEP_FEATURES: h->keep_features = val != 0; break;
+        case SPG_OPT_MERGE_CLASSES: h->merge_classes = val != 0; break;
         case SPG_OPT_LIST_LIMIT_MB:
             if (val < 1 || val > 16383) return fail(h, SPG_ERR_ARG, "list memory limit must be 1..16383 MiB");
             h->list_limit_mb = val;

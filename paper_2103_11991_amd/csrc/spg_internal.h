@@ -212,6 +212,33 @@ __host__ __device__ inline int num_class(int64_t ub, int32_t cmin, int32_t cmax,
     return mode * NTIER + t;
 }
 
+// Launch classes: a class with few rows runs in the next populated class of
+// the same mode and a larger LDS tier (up to 4x the lanes per row) when that
+// class has at least 8x the rows.  The larger tier holds every table of the
+// smaller one, so rows only change the launch they run in, and a short launch
+// with its tail is saved.  Merges chain upwards.  remap gets the launch class
+// of every class and merged the row counts per launch class.  The host and
+// the grouping kernel both evaluate it on the same histogram.
+__host__ __device__ inline void merge_classes(const int32_t* hist, uint8_t* remap, int32_t* merged, bool enable) {
+    for (int c = 0; c < NCLS; ++c) remap[c] = (uint8_t)c, merged[c] = hist[c];
+    if (!enable) return;
+    for (int mode = 0; mode < 3; ++mode) {
+        for (int t = 0; t < TIER_GLOBAL; ++t) {
+            const int c = mode * NTIER + t;
+            if (merged[c] == 0) continue;
+            int u = t + 1;
+            while (u < TIER_GLOBAL && merged[mode * NTIER + u] == 0) ++u;
+            if (u >= TIER_GLOBAL || tier_threads(u) > 4 * tier_threads(t)) continue;
+            const int d = mode * NTIER + u;
+            if ((int64_t)merged[c] * 8 > merged[d]) continue;
+            merged[d] += merged[c];
+            merged[c] = 0;
+            for (int e = 0; e < NCLS; ++e)
+                if (remap[e] == c) remap[e] = (uint8_t)d;
+        }
+    }
+}
+
 // Device-side control block: counters and histograms the host reads back
 // in one copy at each of symbolic's two synchronisation points.
 struct Control {
@@ -258,8 +285,9 @@ void launch_mlp_classify(hipStream_t s, int32_t m, const float* feats, const flo
 // capacity on entry and its list offset on exit (-1 for rows of the global
 // path and rows past list_limit pairs), reserved from ctl->list_total; desc.w
 // gets the same offset.
-void launch_scatter(hipStream_t s, int32_t m, const uint8_t* cls, const int32_t* hist, int32_t* cursor, int32_t* perm,
-                    const int32_t* arp, const int32_t* crp, int4* desc, int32_t* lofs = nullptr,
+// With merge, rows are grouped by their launch class (merge_classes).
+void launch_scatter(hipStream_t s, int32_t m, const uint8_t* cls, int merge, const int32_t* hist, int32_t* cursor,
+                    int32_t* perm, const int32_t* arp, const int32_t* crp, int4* desc, int32_t* lofs = nullptr,
                     Control* ctl = nullptr, int64_t list_limit = 0);
 void launch_scan(hipStream_t s, int32_t m, const int32_t* row_nnz, const int32_t* row_blocks, const RowInfo* rinfo,
                  const int32_t* arp, const uint8_t* sym_cls, const int32_t* lofs, int32_t* c_row_ptr,

@@ -285,7 +285,7 @@ __global__ __launch_bounds__(256) void k_mlp_classify(int32_t m, const float* __
 // beside it.  For the symbolic rows it also places the rows' lists: a scan
 // of the chunk's capacities and one global atomic for the chunk's range.
 constexpr int SCATTER_ITEMS = 8;
-__global__ __launch_bounds__(256) void k_scatter(int32_t m, const uint8_t* __restrict__ cls,
+__global__ __launch_bounds__(256) void k_scatter(int32_t m, const uint8_t* __restrict__ cls, int merge,
                                                  const int32_t* __restrict__ hist, int32_t* __restrict__ cursor,
                                                  int32_t* __restrict__ perm, const int32_t* __restrict__ arp,
                                                  const int32_t* __restrict__ crp, int4* __restrict__ desc,
@@ -295,9 +295,13 @@ __global__ __launch_bounds__(256) void k_scatter(int32_t m, const uint8_t* __res
     __shared__ int32_t off[NCLS];
     __shared__ int64_t wsum[4];
     __shared__ int64_t lbase;
+    __shared__ uint8_t remap[NCLS];
     if (threadIdx.x == 0) {
+        int32_t h[NCLS], merged[NCLS];
+        for (int c = 0; c < NCLS; ++c) h[c] = hist[c];
+        merge_classes(h, remap, merged, merge != 0);
         int32_t run = 0;
-        for (int c = 0; c < NCLS; ++c) off[c] = run, run += hist[c];
+        for (int c = 0; c < NCLS; ++c) off[c] = run, run += merged[c];
     }
     const int64_t chunk = 256 * SCATTER_ITEMS;
     for (int64_t r0 = blockIdx.x * chunk; r0 < m; r0 += (int64_t)gridDim.x * chunk) {
@@ -308,6 +312,7 @@ __global__ __launch_bounds__(256) void k_scatter(int32_t m, const uint8_t* __res
         for (int t = 0; t < SCATTER_ITEMS; ++t) {
             const int64_t row = r0 + t * 256 + threadIdx.x;
             c[t] = row < m ? cls[row] : CLS_EMPTY;
+            if (c[t] != CLS_EMPTY) c[t] = remap[c[t]];
             local[t] = c[t] != CLS_EMPTY ? atomicAdd(&cnt[c[t]], 1) : 0;
         }
         // list capacities of the chunk (rows of the global path get none)
@@ -721,12 +726,12 @@ void launch_mlp_classify(hipStream_t s, int32_t m, const float* feats, const flo
                        sym_cls, ctl);
 }
 
-void launch_scatter(hipStream_t s, int32_t m, const uint8_t* cls, const int32_t* hist, int32_t* cursor,
+void launch_scatter(hipStream_t s, int32_t m, const uint8_t* cls, int merge, const int32_t* hist, int32_t* cursor,
                     int32_t* perm, const int32_t* arp, const int32_t* crp, int4* desc, int32_t* lofs, Control* ctl,
                     int64_t list_limit) {
     if (m <= 0) return;
-    hipLaunchKernelGGL(k_scatter, dim3(std::min(grid_for(m, 256 * SCATTER_ITEMS), 1024u)), dim3(256), 0, s, m, cls, hist,
-                       cursor, perm, arp, crp, desc, lofs, ctl, list_limit);
+    hipLaunchKernelGGL(k_scatter, dim3(std::min(grid_for(m, 256 * SCATTER_ITEMS), 1024u)), dim3(256), 0, s, m, cls,
+                       merge, hist, cursor, perm, arp, crp, desc, lofs, ctl, list_limit);
 }
 
 void launch_scan(hipStream_t s, int32_t m, const int32_t* row_nnz, const int32_t* row_blocks, const RowInfo* rinfo,

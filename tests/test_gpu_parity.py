@@ -158,6 +158,26 @@ def test_rows_past_the_list_limit_take_the_global_path():
     compare(A2, A, rp, col.cpu().numpy(), val.cpu().numpy())
 
 
+def test_small_classes_merge_into_larger_tiers():
+    """The boundary rows of a stencil form small classes beside the interior
+    class; merged, they run in the larger tier of the same mode.  The product
+    is the same either way, and rows only move to larger tiers of their mode."""
+    A = gen.stencil27(40, seed=6)
+    rp1, c1, v1, op1 = run_gpu(A, A, merge_classes=0)
+    rp2, c2, v2, op2 = run_gpu(A, A)
+    compare(A, A, rp2, c2, v2)
+    np.testing.assert_array_equal(rp1, rp2)
+    np.testing.assert_array_equal(c1, c2)
+    for key in ("sym_rows", "num_rows"):
+        off, on = np.array(op1.stats()[key]), np.array(op2.stats()[key])
+        assert off.sum() == on.sum()
+        assert np.count_nonzero(on) < np.count_nonzero(off)
+        for mode in range(3):
+            a, b = off[mode * 10:mode * 10 + 9], on[mode * 10:mode * 10 + 9]
+            # merged counts are suffix sums' worth: no rows move to a smaller tier
+            assert all(b[t:].sum() >= a[t:].sum() for t in range(9))
+
+
 def test_list_memory_is_the_run_bound():
     """Each row reserves min(compressed-B runs of its products, words of its
     column range) list pairs."""
