@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -24,6 +25,7 @@ namespace {
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
+    bool pooled = false;  // from the library's stream-ordered pool
     template <typename T>
     T* as() const { return static_cast<T*>(p); }
 };
@@ -105,29 +107,58 @@ spg_status hip_fail(spg_handle h, hipError_t e, const char* what) {
         if (e_ != hipSuccess) return hip_fail(h, e_, #call); \
     } while (0)
 
+// Device memory of every handle comes from one stream-ordered pool per device
+// that keeps up to 2 GiB of freed memory for reuse, so a handle created per
+// product (a chain of small products) allocates without driver calls.  Null
+// if the device has no pool support: plain hipMalloc then.
+hipMemPool_t lib_pool(int device) {
+    static std::mutex mu;
+    static hipMemPool_t pools[64] = {};
+    static bool tried[64] = {};
+    std::lock_guard<std::mutex> lock(mu);
+    if (device < 0 || device >= 64) return nullptr;
+    if (!tried[device]) {
+        tried[device] = true;
+        hipMemPoolProps props{};
+        props.allocType = hipMemAllocationTypePinned;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = device;
+        if (hipMemPoolCreate(&pools[device], &props) != hipSuccess) {
+            pools[device] = nullptr;
+            (void)hipGetLastError();
+        } else {
+            uint64_t keep = 2ull << 30;
+            (void)hipMemPoolSetAttribute(pools[device], hipMemPoolAttrReleaseThreshold, &keep);
+        }
+    }
+    return pools[device];
+}
+
+void release(DevBuf& b, hipStream_t s) {
+    if (b.p) {
+        if (b.pooled) (void)hipFreeAsync(b.p, s);
+        else (void)hipFree(b.p);
+    }
+    b.p = nullptr;
+    b.cap = 0;
+    b.pooled = false;
+}
+
+// Grows b to at least `bytes` on the handle's stream (contents not kept).
 spg_status ensure(spg_handle h, DevBuf& b, size_t bytes) {
     if (bytes <= b.cap && b.p) return SPG_OK;
-    if (b.p) {
-        hipError_t e = hipFree(b.p);
-        b.p = nullptr;
-        b.cap = 0;
-        if (e != hipSuccess) return hip_fail(h, e, "hipFree");
-    }
+    release(b, h->stream);
     size_t want = std::max<size_t>(bytes, 256);
-    hipError_t e = hipMalloc(&b.p, want);
+    hipMemPool_t pool = lib_pool(h->device);
+    hipError_t e = pool ? hipMallocFromPoolAsync(&b.p, want, pool, h->stream) : hipMalloc(&b.p, want);
     if (e != hipSuccess) {
         b.p = nullptr;
         (void)hipGetLastError();
         return fail(h, SPG_ERR_ALLOC, "device allocation of " + std::to_string(want) + " bytes failed");
     }
     b.cap = want;
+    b.pooled = pool != nullptr;
     return SPG_OK;
-}
-
-void release(DevBuf& b) {
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-    b.cap = 0;
 }
 
 #define SPG_TRY(call)                 \
@@ -518,7 +549,7 @@ spg_status spg_destroy(spg_handle h) {
                       &h->row_nnz, &h->row_blocks, &h->tile_status, &h->cursor, &h->ovf_list, &h->ctl,
                       &h->slab_sym, &h->slab_retry, &h->slab_num, &h->mlp_w, &h->bcrp, &h->bc, &h->bhdr,
                       &h->lofs, &h->lists};
-    for (DevBuf* b : bufs) release(*b);
+    for (DevBuf* b : bufs) release(*b, h->stream);
     if (h->hctl) (void)hipHostFree(h->hctl);
     if (h->ev_made)
         for (auto& e : h->ev) (void)hipEventDestroy(e);
@@ -528,6 +559,8 @@ spg_status spg_destroy(spg_handle h) {
 
 spg_status spg_set_stream(spg_handle h, void* stream) {
     if (!h) return SPG_ERR_ARG;
+    // the handle's buffers are allocated in the old stream's order: let it finish
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return hip_fail(h, hipGetLastError(), "hipStreamSynchronize");
     h->stream = static_cast<hipStream_t>(stream);
     return SPG_OK;
 }
@@ -882,7 +915,7 @@ spg_status spg_batch_destroy(spg_batch b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     drop_graph(b);
     DevBuf* bufs[] = {&b->arp, &b->aci, &b->brp, &b->desc, &b->err, &b->crp_plan};
-    for (DevBuf* x : bufs) release(*x);
+    for (DevBuf* x : bufs) release(*x, b->stream);
     if (b->h) spg_destroy(b->h);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
