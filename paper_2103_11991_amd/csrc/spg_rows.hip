@@ -278,7 +278,7 @@ __global__ __launch_bounds__(256) void k_mlp_classify(int32_t m, const float* __
     if (threadIdx.x == 0 && wmax_glob) atomicMax((unsigned long long*)&ctl->max_words_sym_global, wmax_glob);
 }
 
-// Groups rows by class: a workgroup takes chunks of 4096 consecutive rows,
+// Groups rows by class: a workgroup takes chunks of 2048 consecutive rows,
 // ranks each row inside its class with LDS atomics, reserves one range per
 // class and chunk with a single global atomic, and writes the row ids there,
 // with each row's descriptor {row, A start, A end, C start (or list offset)}
