@@ -21,7 +21,9 @@ namespace spg {
 
 namespace {
 
-constexpr int ROW_LANES = 8;        // lanes per row in the analysis passes
+constexpr int ROW_LANES = 8;        // lanes per B row when compressing B
+constexpr int AN_LANES = 4;         // lanes per row in the row analysis passes
+constexpr int AN_LOADS = 8;         // independent entry loads per lane and round trip there
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
@@ -36,30 +38,29 @@ __global__ void k_fill_u8(uint8_t* p, uint8_t v, int64_t n) {
         p[i] = v;
 }
 
-// Reductions over aligned groups of ROW_LANES = 8 lanes with DPP: swaps of
-// neighbours and pairs inside quads, then a mirror of each half row (8
-// lanes), after which every lane of the group holds the result.  No LDS.
+// Reductions over aligned groups of AN_LANES = 4 lanes with DPP: swaps of
+// neighbours and of pairs inside each quad, after which every lane of the
+// group holds the result.  No LDS.
+static_assert(AN_LANES == 4, "the row reductions below cover one quad");
 template <typename Op>
-__device__ inline int row8_reduce(int v, Op op) {
+__device__ inline int rowq_reduce(int v, Op op) {
     v = op(v, __builtin_amdgcn_mov_dpp(v, 0xb1, 0xf, 0xf, false));   // quad_perm [1,0,3,2]
     v = op(v, __builtin_amdgcn_mov_dpp(v, 0x4e, 0xf, 0xf, false));   // quad_perm [2,3,0,1]
-    v = op(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xf, 0xf, false));  // row_half_mirror
     return v;
 }
-__device__ inline int row8_sum(int v) { return row8_reduce(v, [](int x, int y) { return x + y; }); }
-__device__ inline int row8_min(int v) { return row8_reduce(v, [](int x, int y) { return min(x, y); }); }
-__device__ inline int row8_max(int v) { return row8_reduce(v, [](int x, int y) { return max(x, y); }); }
-__device__ inline int row8_or(int v) { return row8_reduce(v, [](int x, int y) { return x | y; }); }
+__device__ inline int rowq_sum(int v) { return rowq_reduce(v, [](int x, int y) { return x + y; }); }
+__device__ inline int rowq_min(int v) { return rowq_reduce(v, [](int x, int y) { return min(x, y); }); }
+__device__ inline int rowq_max(int v) { return rowq_reduce(v, [](int x, int y) { return max(x, y); }); }
+__device__ inline int rowq_or(int v) { return rowq_reduce(v, [](int x, int y) { return x | y; }); }
 template <int CTRL>
 __device__ inline int64_t dpp64(int64_t v) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, CTRL, 0xf, 0xf, false);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)((uint64_t)v >> 32), CTRL, 0xf, 0xf, false);
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
-__device__ inline int64_t row8_sum64(int64_t v) {
+__device__ inline int64_t rowq_sum64(int64_t v) {
     v += dpp64<0xb1>(v);
     v += dpp64<0x4e>(v);
-    v += dpp64<0x141>(v);
     return v;
 }
 
@@ -73,10 +74,10 @@ __global__ __launch_bounds__(256) void k_b_rowinfo(int32_t n, int32_t k, const i
     __shared__ unsigned long long runs_sum;
     if (threadIdx.x == 0) runs_sum = 0;
     __syncthreads();
-    const int lane = (int)(threadIdx.x % ROW_LANES);
-    const int64_t rows_per_block = blockDim.x / ROW_LANES;
+    const int lane = (int)(threadIdx.x % AN_LANES);
+    const int64_t rows_per_block = blockDim.x / AN_LANES;
     for (int64_t rb = blockIdx.x * rows_per_block; rb < n; rb += (int64_t)gridDim.x * rows_per_block) {
-        const int64_t row = rb + threadIdx.x / ROW_LANES;
+        const int64_t row = rb + threadIdx.x / AN_LANES;
         int len = 0, mn = INT_MAX, mx = -1, bad = 0, runs = 0;
         if (row < n) {
             int32_t s = brp[row], e = brp[row + 1];
@@ -85,19 +86,19 @@ __global__ __launch_bounds__(256) void k_b_rowinfo(int32_t n, int32_t k, const i
                 bad = ERR_B_ROWPTR;
             } else {
                 len = e - s;
-                // four independent entry loads per lane (with each entry's
+                // independent entry loads per lane (with each entry's
                 // predecessor), then their checks
-                for (int32_t p0 = s + lane; p0 < e; p0 += 4 * ROW_LANES) {
-                    int c[4], cp[4];
+                for (int32_t p0 = s + lane; p0 < e; p0 += AN_LOADS * AN_LANES) {
+                    int c[AN_LOADS], cp[AN_LOADS];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int32_t q = p0 + u * ROW_LANES;
+                    for (int u = 0; u < AN_LOADS; ++u) {
+                        const int32_t q = p0 + u * AN_LANES;
                         c[u] = q < e ? bci[q] : 0;
                         cp[u] = q < e && q > s ? bci[q - 1] : 0;
                     }
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int32_t q = p0 + u * ROW_LANES;
+                    for (int u = 0; u < AN_LOADS; ++u) {
+                        const int32_t q = p0 + u * AN_LANES;
                         if (q >= e) continue;
                         if (c[u] < 0 || c[u] >= k) {
                             bad = ERR_B_COL;
@@ -110,10 +111,10 @@ __global__ __launch_bounds__(256) void k_b_rowinfo(int32_t n, int32_t k, const i
                 }
             }
         }
-        mn = row8_min(mn);
-        mx = row8_max(mx);
-        runs = row8_sum(runs);
-        int anybad = row8_or(bad);
+        mn = rowq_min(mn);
+        mx = rowq_max(mx);
+        runs = rowq_sum(runs);
+        int anybad = rowq_or(bad);
         if (row < n && lane == 0) {
             if (anybad) len = 0, mn = INT_MAX, mx = -1, runs = 0;
             binfo[row] = make_int4(len, mn, mx, runs);
@@ -144,11 +145,11 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
     if (threadIdx.x < NCLS) hist[threadIdx.x] = 0;
     if (threadIdx.x == 0) empties = 0, prod_sum = 0, wmax_all = 0, wmax_glob = 0;
     __syncthreads();
-    const int lane = (int)(threadIdx.x % ROW_LANES);
-    const int64_t rows_per_block = blockDim.x / ROW_LANES;
+    const int lane = (int)(threadIdx.x % AN_LANES);
+    const int64_t rows_per_block = blockDim.x / AN_LANES;
     // grid-stride: few workgroups, one flush of the counters each
     for (int64_t rb = blockIdx.x * rows_per_block; rb < m; rb += (int64_t)gridDim.x * rows_per_block) {
-        const int64_t row = rb + threadIdx.x / ROW_LANES;
+        const int64_t row = rb + threadIdx.x / AN_LANES;
         int64_t ub = 0, rs = 0;  // products; compressed-B runs (a bound on occupied blocks)
         int mx = 0, cmin = INT_MAX, cmax = -1, bad = 0, len = 0;
         if (row < m) {
@@ -157,20 +158,20 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
                 bad = ERR_A_ROWPTR;
             } else {
                 len = e - s;
-                // four independent index loads, then their four gathers
-                for (int32_t p0 = s + lane; p0 < e; p0 += 4 * ROW_LANES) {
-                    int jj[4];
+                // independent index loads, then their gathers
+                for (int32_t p0 = s + lane; p0 < e; p0 += AN_LOADS * AN_LANES) {
+                    int jj[AN_LOADS];
     #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int32_t p = p0 + u * ROW_LANES;
+                    for (int u = 0; u < AN_LOADS; ++u) {
+                        const int32_t p = p0 + u * AN_LANES;
                         jj[u] = p < e ? aci[p] : -1;
                         if (p < e && (jj[u] < 0 || jj[u] >= n)) bad = ERR_A_COL, jj[u] = -1;
                     }
-                    int4 bb[4];
+                    int4 bb[AN_LOADS];
     #pragma unroll
-                    for (int u = 0; u < 4; ++u) bb[u] = jj[u] >= 0 ? binfo[jj[u]] : make_int4(0, INT_MAX, -1, 0);
+                    for (int u = 0; u < AN_LOADS; ++u) bb[u] = jj[u] >= 0 ? binfo[jj[u]] : make_int4(0, INT_MAX, -1, 0);
     #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
+                    for (int u = 0; u < AN_LOADS; ++u) {
                         ub += bb[u].x;
                         rs += bb[u].w;
                         mx = max(mx, bb[u].x);
@@ -180,12 +181,12 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
                 }
             }
         }
-        ub = row8_sum64(ub);
-        rs = row8_sum64(rs);
-        mx = row8_max(mx);
-        cmin = row8_min(cmin);
-        cmax = row8_max(cmax);
-        int anybad = row8_or(bad);
+        ub = rowq_sum64(ub);
+        rs = rowq_sum64(rs);
+        mx = rowq_max(mx);
+        cmin = rowq_min(cmin);
+        cmax = rowq_max(cmax);
+        int anybad = rowq_or(bad);
         if (bad) atomicOr(&ctl->err, bad);
         if (row < m && lane == 0) {
             if (anybad) ub = 0;
@@ -693,7 +694,7 @@ void launch_fill_u8(hipStream_t s, void* p, uint8_t v, int64_t bytes) {
 void launch_b_rowinfo(hipStream_t s, int32_t n, int32_t k, const int32_t* brp, const int32_t* bci, int64_t bnnz,
                       int4* binfo, Control* ctl) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_b_rowinfo, dim3(std::min(grid_for((int64_t)n * ROW_LANES, 256), 4096u)), dim3(256), 0, s, n,
+    hipLaunchKernelGGL(k_b_rowinfo, dim3(std::min(grid_for((int64_t)n * AN_LANES, 256), 4096u)), dim3(256), 0, s, n,
                        k, brp, bci, bnnz, binfo, ctl);
 }
 
@@ -714,7 +715,7 @@ void launch_a_rowinfo(hipStream_t s, int32_t m, int32_t n, const int32_t* arp, c
                       const int4* binfo, RowInfo* rinfo, float* feats, ClassCfg cfg, int binning,
                       uint8_t* sym_cls, int32_t* row_nnz, int32_t* row_blocks, int32_t* lofs, Control* ctl) {
     if (m <= 0) return;
-    hipLaunchKernelGGL(k_a_rowinfo, dim3(std::min(grid_for((int64_t)m * ROW_LANES, 256), 4096u)), dim3(256), 0, s, m, n,
+    hipLaunchKernelGGL(k_a_rowinfo, dim3(std::min(grid_for((int64_t)m * AN_LANES, 256), 4096u)), dim3(256), 0, s, m, n,
                        arp, aci, annz, binfo, rinfo, feats, cfg, binning, sym_cls, row_nnz, row_blocks, lofs, ctl);
 }
 
