@@ -136,21 +136,36 @@ def cpu_baseline(A, target_s: float = 12.0):
             "c_nnz_per_s": round(int(rp[-1]) / dt, 1)}
 
 
-def time_full_products(op, steps):
-    """Median GPU time of symbolic+numeric (events recorded by the library) and
-    the wall time per full product."""
+def time_full_products(op, steps, warmup=0):
+    """Wall time per full product over `steps` back-to-back products, during
+    which the library times only the numeric class launches (HIP events on its
+    stream, summed per class: st_timed), then the medians of the symbolic and
+    numeric GPU times over three more products with every stage timed (st).
+    Returns (sym_ms, num_ms, wall_ms, st_timed, st)."""
     import torch
-    sym, num = [], []
+    op.set_option("timing", 2)
+    for _ in range(warmup):
+        op.symbolic()
+        op.numeric()
+    torch.cuda.synchronize()
+    op.set_option("timing", 2)  # the sums cover the timed products only
     t0 = time.perf_counter()
     for _ in range(steps):
+        op.symbolic()
+        op.numeric()
+    torch.cuda.synchronize()
+    wall = 1e3 * (time.perf_counter() - t0) / steps
+    st_timed = op.stats()
+    op.set_option("timing", 1)
+    sym, num = [], []
+    for _ in range(3):
         op.symbolic()
         op.numeric()
         st = op.stats()
         sym.append(st["sym_ms"])
         num.append(st["num_ms"])
-    torch.cuda.synchronize()
-    wall = 1e3 * (time.perf_counter() - t0) / steps
-    return float(np.median(sym)), float(np.median(num)), wall, st
+    op.set_option("timing", 0)
+    return float(np.median(sym)), float(np.median(num)), wall, st_timed, st
 
 
 def learned_vs_plain(dA, steps, plain):
@@ -165,7 +180,7 @@ def learned_vs_plain(dA, steps, plain):
     for _ in range(2):
         op.symbolic()
         op.numeric()
-    sym0, _, wall0, st0 = time_full_products(op, steps)
+    sym0, _, wall0, _, st0 = time_full_products(op, steps)
     rows = st0["m"] - st0["empty_rows"]
     out.update({"t_sym_products_bound_ms": round(sym0, 4), "t_full_products_bound_ms": round(wall0, 4),
                 "products_bound_mispredict_rate": round(st0["mispredicted_rows"] / max(rows, 1), 5),
@@ -179,7 +194,7 @@ def learned_vs_plain(dA, steps, plain):
     for _ in range(2):
         op.symbolic()
         op.numeric()
-    sym, num, wall, st = time_full_products(op, steps)
+    sym, num, wall, _, st = time_full_products(op, steps)
     out.update({"t_sym_learned_ms": round(sym, 4), "t_full_learned_ms": round(wall, 4),
                 "speedup_sym_vs_products_bound": round(sym0 / sym, 3),
                 "speedup_full_vs_products_bound": round(wall0 / wall, 3),
@@ -221,7 +236,7 @@ def rmat_learned_vs_plain(steps, scale=18, seed=1):
         for _ in range(2):
             op.symbolic()
             op.numeric()
-        sym, num, wall, st = time_full_products(op, steps)
+        sym, num, wall, _, st = time_full_products(op, steps)
         rows = st["m"] - st["empty_rows"]
         out[label] = {"t_sym_ms": round(sym, 3), "t_num_ms": round(num, 3), "t_full_ms": round(wall, 3),
                       "gflops": round(2.0 * st["products"] / (wall * 1e-3) / 1e9, 2),
@@ -421,31 +436,14 @@ def main():
     products = int(gen.products_per_row(A, A).sum())
     dA = DeviceCsr.from_host(A)
     opts = dict(kv.split("=", 1) for kv in args.opt)
-    op = SpGEMM(dA, dA, timing=1, **{k: int(v) for k, v in opts.items()})
-    stream = op.stream
-
-    def step():
-        rp, nnz = op.symbolic()
-        col, val = op.numeric()
-        return nnz
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
-    sym_ms, num_ms, dom = [], [], {}
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        nnz = step()
-        st = op.stats()  # waits for this step's events
-        sym_ms.append(st["sym_ms"])
-        num_ms.append(st["num_ms"])
-        for c, ms in enumerate(st["num_class_ms"]):
-            if st["num_rows"][c]:
-                dom.setdefault(c, []).append(ms)
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t0
-    ms_step = 1e3 * t_total / args.steps
+    op = SpGEMM(dA, dA, **{k: int(v) for k, v in opts.items()})
+    # the timed region: args.steps back-to-back products (symbolic, then
+    # numeric), bracketed by device synchronisation; the numeric class
+    # launches carry HIP events on the library's stream throughout
+    sym_med, num_med, ms_step, st_t, st = time_full_products(op, args.steps, args.warmup)
+    nnz = op.nnz
+    dom = {c: st_t["num_class_ms_total"][c] / st_t["num_class_launches"][c]
+           for c in range(len(st_t["num_class_launches"])) if st_t["num_class_launches"][c]}
 
     # numeric alone (symbolic reused), the repeated-product path
     col, val = op.numeric()
@@ -464,8 +462,8 @@ def main():
     comp = (nnz_a * (4 + eb)) * 2 + nnz * (4 + eb) + (A.m + 1) * 4 * 3 + A.m * 4 * 4
     gflops = 2.0 * products / (ms_step * 1e-3) / 1e9
 
-    dcls = max(dom, key=lambda c: np.mean(dom[c]))
-    dom_ms = float(np.mean(dom[dcls]))
+    dcls = max(dom, key=lambda c: dom[c])
+    dom_ms = float(dom[dcls])
     rows_c = st["num_rows"][dcls]
     frac_prod = st["num_products"][dcls] / max(st["products"], 1)
     alg_bytes = (st["num_a_nnz"][dcls] * (4 + eb) + st["num_c_nnz"][dcls] * (4 + eb)
@@ -474,7 +472,8 @@ def main():
     kname = f"numeric class {dcls} (mode {('direct', 'hashed', 'two-level')[dcls // 10]}, tier {dcls % 10})"
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(f"num_class_{dcls}"),
-            "kernel": kname, "launch_ms": round(dom_ms, 4), "algorithmic_bytes": int(alg_bytes)}
+            "kernel": kname, "launch_ms": round(dom_ms, 4), "launches_averaged": int(st_t["num_class_launches"][dcls]),
+            "algorithmic_bytes": int(alg_bytes)}
 
     out = {
         "metric": METRIC, "value": round(gflops, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
@@ -486,7 +485,7 @@ def main():
                    **({"options": opts} if opts else {})},
         "c_nnz_per_s": round(nnz / (ms_step * 1e-3), 1),
         "hbm_frac_compulsory": round(comp / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "t_sym_ms": round(float(np.median(sym_ms)), 4), "t_num_ms": round(float(np.median(num_ms)), 4),
+        "t_sym_ms": round(sym_med, 4), "t_num_ms": round(num_med, 4),
         "t_num_reuse_ms": round(ms_num_only, 4),
         "gflops_numeric_reuse": round(2.0 * products / (ms_num_only * 1e-3) / 1e9, 2),
         "roofline": roof,

@@ -66,7 +66,10 @@ typedef enum {
        upper bound from the compressed-B runs the row reads (tighter than 0,
        default); all three are capped by the row's column range */
     SPG_OPT_BINNING = 0,
-    /* record HIP events around every launch (default 0); read with spg_get_stats */
+    /* HIP events on the handle's stream, read with spg_get_stats: 0 = none
+       (default), 1 = around both phases, their stages and every class launch,
+       2 = around the numeric class launches only (what a timed loop of
+       products needs).  Setting it clears the summed numeric launch times. */
     SPG_OPT_TIMING = 1,
     /* force every row of both phases into one accumulator class (-1 = off);
        class = mode * 10 + tier with mode 0 direct, 1 hashed, 2 two-level
@@ -127,6 +130,9 @@ typedef struct {
     float scan_ms;                      /* row-pointer scan (timing on) */
     float mlp_ms;                       /* predictor inference (timing on) */
     int64_t list_pairs;                 /* {block, mask} pairs reserved for the rows' lists */
+    float num_class_ms_total[SPG_NCLASS];   /* timing on: summed GPU time of every numeric launch of each
+                                               class since SPG_OPT_TIMING was last set */
+    int32_t num_class_launches[SPG_NCLASS]; /* ... and the number of those launches */
 } spg_stats;
 
 /* Human-readable name of a status code (static string). */

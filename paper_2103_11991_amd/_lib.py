@@ -48,6 +48,7 @@ class spg_stats(ctypes.Structure):
         ("sym_class_ms", ctypes.c_float * NCLASS), ("num_class_ms", ctypes.c_float * NCLASS),
         ("analysis_ms", ctypes.c_float), ("scan_ms", ctypes.c_float), ("mlp_ms", ctypes.c_float),
         ("list_pairs", ctypes.c_int64),
+        ("num_class_ms_total", ctypes.c_float * NCLASS), ("num_class_launches", ctypes.c_int32 * NCLASS),
     ]
 
 

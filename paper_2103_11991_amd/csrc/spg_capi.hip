@@ -32,8 +32,8 @@ struct DevBuf {
 
 enum EvId { EV_SYM0 = 0, EV_SYM1, EV_ANA1, EV_MLP0, EV_MLP1, EV_SCAN0, EV_SCAN1, EV_NUM0, EV_NUM1, EV_FIXED };
 constexpr int EV_SYMCLS = EV_FIXED;                 // 2 per class
-constexpr int EV_NUMCLS = EV_FIXED + 2 * NCLS;      // 2 per class
-constexpr int EV_TOTAL = EV_FIXED + 4 * NCLS;
+constexpr int EV_NUMCLS = EV_FIXED + 2 * NCLS;      // 2 per class, two alternating sets
+constexpr int EV_TOTAL = EV_FIXED + 6 * NCLS;
 
 }  // namespace
 
@@ -88,6 +88,13 @@ struct spg_handle_s {
     bool ev_made = false;
     bool sym_timed = false, num_timed = false;
     bool sym_cls_timed[NCLS] = {}, num_cls_timed[NCLS] = {};
+    // numeric class launches: two event sets used in turn; a set's previous
+    // pair is read (long complete by then) when the set is reused or stats
+    // are read, and summed per class
+    int num_set = 0, num_last_set = 0;
+    bool num_pending[2][NCLS] = {};
+    double num_acc_ms[NCLS] = {};
+    int32_t num_acc_n[NCLS] = {};
 };
 
 namespace {
@@ -167,6 +174,26 @@ spg_status ensure(spg_handle h, DevBuf& b, size_t bytes) {
         if (s_ != SPG_OK) return s_;  \
     } while (0)
 
+int num_ev(int set, int c) { return EV_NUMCLS + 2 * NCLS * set + 2 * c; }
+
+float elapsed(spg_handle h, int a, int b);
+
+// adds a numeric class launch's recorded time to the class's sum
+void resolve_num(spg_handle h, int set, int c) {
+    if (!h->num_pending[set][c]) return;
+    h->num_pending[set][c] = false;
+    const float ms = elapsed(h, num_ev(set, c), num_ev(set, c) + 1);
+    if (ms >= 0.f) h->num_acc_ms[c] += ms, h->num_acc_n[c] += 1;
+}
+
+void reset_num_sums(spg_handle h) {
+    for (int c = 0; c < NCLS; ++c) {
+        h->num_pending[0][c] = h->num_pending[1][c] = false;
+        h->num_acc_ms[c] = 0.0;
+        h->num_acc_n[c] = 0;
+    }
+}
+
 spg_status make_events(spg_handle h) {
     if (h->ev_made) return SPG_OK;
     for (int i = 0; i < EV_TOTAL; ++i) HIP_TRY(h, hipEventCreate(&h->ev[i]));
@@ -174,8 +201,9 @@ spg_status make_events(spg_handle h) {
     return SPG_OK;
 }
 
+// events of the phases and of every launch (timing 1)
 void rec(spg_handle h, int id) {
-    if (h->timing) (void)hipEventRecord(h->ev[id], h->stream);
+    if (h->timing == 1) (void)hipEventRecord(h->ev[id], h->stream);
 }
 
 float elapsed(spg_handle h, int a, int b) {
@@ -362,7 +390,7 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
         rec(h, EV_SYMCLS + 2 * c);
         launch_sym_class(s, a, grid_cap);
         rec(h, EV_SYMCLS + 2 * c + 1);
-        h->sym_cls_timed[c] = h->timing != 0;
+        h->sym_cls_timed[c] = h->timing == 1;
     }
     if (learned) {
         // exact retry of overflowed rows on the global path (row count read on the device)
@@ -486,11 +514,17 @@ spg_status num_launch_all(spg_handle h, const void* a_vals, const void* b_vals, 
         a.wide_vals = wide_vals(h, eb);
         a.lofs = h->lofs.as<int32_t>();
         a.lists = h->lists.as<int2>();
-        rec(h, EV_NUMCLS + 2 * c);
+        const int set = h->num_set;
+        if (h->timing) {
+            resolve_num(h, set, c);
+            (void)hipEventRecord(h->ev[num_ev(set, c)], s);
+        }
         launch_num_class(s, a, eb, std::max(h->nslab_num, 1));
-        rec(h, EV_NUMCLS + 2 * c + 1);
+        if (h->timing) (void)hipEventRecord(h->ev[num_ev(set, c) + 1], s);
         h->num_cls_timed[c] = h->timing != 0;
+        h->num_pending[set][c] = h->timing != 0;
     }
+    if (h->timing) h->num_last_set = h->num_set, h->num_set ^= 1;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "numeric launch");
     return SPG_OK;
@@ -599,7 +633,7 @@ spg_status spg_symbolic(spg_handle h, int32_t* c_row_ptr, int64_t* nnz_c) {
         if (h->binning == 1 && !h->have_mlp) return fail(h, SPG_ERR_STATE, "learned binning needs spg_set_mlp");
         h->have_sym = false;
         if (h->timing) SPG_TRY(make_events(h));
-        h->sym_timed = h->timing != 0;
+        h->sym_timed = h->timing == 1;
         std::fill(std::begin(h->sym_cls_timed), std::end(h->sym_cls_timed), false);
         SPG_TRY(sym_prepare(h));
         rec(h, EV_SYM0);
@@ -659,7 +693,11 @@ spg_status spg_set_option(spg_handle h, int32_t opt, int64_t val) {
             if (val < 0 || val > 2) return fail(h, SPG_ERR_ARG, "binning must be 0, 1 or 2");
             h->binning = (int)val;
             break;
-        case SPG_OPT_TIMING: h->timing = val != 0; break;
+        case SPG_OPT_TIMING:
+            if (val < 0 || val > 2) return fail(h, SPG_ERR_ARG, "timing must be 0, 1 or 2");
+            h->timing = (int)val;
+            reset_num_sums(h);
+            break;
         case SPG_OPT_FORCE_CLASS:
             if (val < -1 || val >= NCLS) return fail(h, SPG_ERR_ARG, "class out of range");
             h->force_class = (int)val;
@@ -721,10 +759,17 @@ spg_status spg_get_stats(spg_handle h, spg_stats* out, int32_t size) {
                 st.sym_class_ms[c] = h->sym_cls_timed[c] ? elapsed(h, EV_SYMCLS + 2 * c, EV_SYMCLS + 2 * c + 1) : 0.f;
         }
         if (h->num_timed) {
-            st.num_ms = elapsed(h, EV_NUM0, EV_NUM1);
+            st.num_ms = h->timing == 1 ? elapsed(h, EV_NUM0, EV_NUM1) : 0.f;
             for (int c = 0; c < NCLS; ++c)
-                st.num_class_ms[c] = h->num_cls_timed[c] ? elapsed(h, EV_NUMCLS + 2 * c, EV_NUMCLS + 2 * c + 1) : 0.f;
+                st.num_class_ms[c] =
+                    h->num_cls_timed[c] ? elapsed(h, num_ev(h->num_last_set, c), num_ev(h->num_last_set, c) + 1) : 0.f;
         }
+        for (int set = 0; set < 2; ++set)
+            for (int c = 0; c < NCLS; ++c) resolve_num(h, set, c);
+    }
+    for (int c = 0; c < NCLS; ++c) {
+        st.num_class_ms_total[c] = (float)h->num_acc_ms[c];
+        st.num_class_launches[c] = h->num_acc_n[c];
     }
     *out = st;
     return SPG_OK;
