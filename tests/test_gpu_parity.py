@@ -178,6 +178,35 @@ def test_small_classes_merge_into_larger_tiers():
             assert all(b[t:].sum() >= a[t:].sum() for t in range(9))
 
 
+def test_numeric_launch_times_are_summed_without_waiting():
+    """Timing level 2 sums every numeric class launch since the option was
+    set: three products and two reused numeric calls give five launches per
+    launched class, and setting the option again starts from zero."""
+    import torch
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
+    A = gen.stencil27(20, seed=3)
+    dA = DeviceCsr.from_host(A)
+    op = SpGEMM(dA, dA, timing=2)
+    for _ in range(3):
+        op.symbolic()
+        col, val = op.numeric()
+    for _ in range(2):
+        op.numeric(out_col=col, out_val=val)
+    torch.cuda.synchronize()
+    st = op.stats()
+    launched = [c for c in range(30) if st["num_rows"][c]]
+    assert launched
+    for c in range(30):
+        assert st["num_class_launches"][c] == (5 if c in launched else 0)
+        assert (st["num_class_ms_total"][c] > 0) == (c in launched)
+        if c in launched:  # the last launch is one of the five summed
+            assert 0 < st["num_class_ms"][c] <= st["num_class_ms_total"][c]
+    assert st["sym_ms"] == 0.0  # level 2 times no symbolic stage
+    compare(A, A, op.row_ptr.cpu().numpy().astype(np.int64), col.cpu().numpy(), val.cpu().numpy())
+    op.set_option("timing", 2)
+    assert sum(op.stats()["num_class_launches"]) == 0
+
+
 def test_list_memory_is_the_run_bound():
     """Each row reserves min(compressed-B runs of its products, words of its
     column range) list pairs."""
