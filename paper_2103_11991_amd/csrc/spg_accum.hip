@@ -541,12 +541,17 @@ void k_sym(SymArgs a) {
     int2* cq = reinterpret_cast<int2*>(row_lds + bytes);   // staged run {offset, end}
     Win* win = reinterpret_cast<Win*>(row_lds + bytes + 8 * G);
     // direct: a mask per word of the row's range.  hashed: keys, then masks.
-    // two-level: {bits, prefix} per 32 words, then a mask per occupied block.
+    // two-level: {bits, prefix} per 32 words, then per occupied block a mask,
+    // then per occupied block its id (for the row's list; 16-bit offsets from
+    // the first block when the range allows).
     int base = 0, ncell = 0, T = 0, logT = 0, w1 = 0, cap = 0;
     int32_t* keys = reinterpret_cast<int32_t*>(tab);
     uint32_t* masks = tab;
     uint2* l1 = reinterpret_cast<uint2*>(tab);
     uint32_t* cm = tab;
+    int32_t* cb = nullptr;
+    uint16_t* cb16 = nullptr;
+    bool short_ids = false;
     if constexpr (MODE != MODE_HASHED) {
         const RowInfo ri = a.rinfo[i];
         base = ri.x >> 5;
@@ -560,7 +565,10 @@ void k_sym(SymArgs a) {
     } else if constexpr (MODE == MODE_TWOLEVEL) {
         w1 = (ncell + 31) >> 5;
         cm = reinterpret_cast<uint32_t*>(l1 + w1);
-        cap = (bytes - w1 * 8) / 4;
+        cap = (bytes - w1 * 8) / sym_block_bytes(ncell);
+        short_ids = sym_block_bytes(ncell) == 6;
+        cb = reinterpret_cast<int32_t*>(cm + cap);
+        cb16 = reinterpret_cast<uint16_t*>(cm + cap);
     }
     // 16-byte clears (tables start 256-byte aligned and tiers are multiples of 16 bytes)
     if constexpr (MODE == MODE_DIRECT) {
@@ -664,8 +672,12 @@ void k_sym(SymArgs a) {
                 const int w = run.x - base;
                 const uint2 L = l1[w >> 5];
                 const uint32_t bits = (uint32_t)run.y;
-                const uint32_t old = atomicOr(&cm[(int)L.y + __popc(L.x & below(w & 31))], bits);
+                const int ci = (int)L.y + __popc(L.x & below(w & 31));
+                const uint32_t old = atomicOr(&cm[ci], bits);
                 cnt += __popc(bits & ~old);
+                // every run of the block stores the same id
+                if (short_ids) cb16[ci] = (uint16_t)w;
+                else cb[ci] = run.x;
             };
             runs(each(orc));
         } else {
@@ -711,20 +723,9 @@ void k_sym(SymArgs a) {
     if (lo >= 0 && !overflowed) {
         int2* out = a.lists + lo;
         if constexpr (MODE == MODE_TWOLEVEL) {
-            // a set bit of l1 word t is block base + 32 t + bit, at compact index prefix + rank
-            const int chunk = (w1 + G - 1) / G;
-            const int beg = lane * chunk;
-            const int end = min(beg + chunk, w1);
-            for (int t = beg; t < end; ++t) {
-                const uint2 L = l1[t];
-                uint32_t bits = L.x;
-                int ci = (int)L.y;
-                while (bits) {
-                    out[ci] = make_int2(base + 32 * t + __ffs(bits) - 1, (int)cm[ci]);
-                    ++ci;
-                    bits &= bits - 1;
-                }
-            }
+            // compact indices are in block order: one coalesced store per block
+            for (int t = lane; t < nb; t += G)
+                out[t] = make_int2(short_ids ? base + (int)cb16[t] : cb[t], (int)cm[t]);
         } else if constexpr (MODE == MODE_DIRECT) {
             const int chunk = (ncell + G - 1) / G;
             const int beg = min(lane * chunk, ncell);

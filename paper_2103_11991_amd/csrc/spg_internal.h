@@ -155,6 +155,11 @@ __host__ __device__ inline int pick_tier(int64_t bytes, int64_t work, const Clas
     return t;
 }
 
+// Bytes per occupied block of the symbolic two-level table: its mask and its
+// id, kept as a 16-bit offset from the row's first block when the row's range
+// spans at most 2^16 blocks.
+__host__ __device__ inline int sym_block_bytes(int64_t words) { return words <= 65536 ? 6 : 8; }
+
 // Symbolic class of a row from its products, column range and an estimate
 // of its occupied blocks (an upper bound: the compressed-B runs its products
 // read; or the learned prediction).
@@ -165,9 +170,9 @@ __host__ __device__ inline int sym_class(int64_t ub, int32_t cmin, int32_t cmax,
     int64_t est = est_blocks < words ? est_blocks : words;
     if (est < 1) est = 1;
     // direct: a mask per word; hashed: keys and masks; two-level: {bits,
-    // prefix} per 32 words and a mask per (estimated) occupied block
+    // prefix} per 32 words, a mask and the block id per (estimated) occupied block
     int64_t bd = words * 4, bh = sym_hash_slots(est, bound) * 8;
-    int64_t b2 = align8(twolevel_words(words) * 8) + est * 4;
+    int64_t b2 = align8(twolevel_words(words) * 8) + est * sym_block_bytes(words);
     if (c.force_class >= 0) {
         int fm = c.force_class / NTIER, ft = c.force_class % NTIER;
         if (ft == TIER_GLOBAL) return MODE_DIRECT * NTIER + TIER_GLOBAL;
