@@ -605,6 +605,7 @@ __global__ __launch_bounds__(256) void k_compress_b(int32_t n, const int32_t* __
                                                     const int32_t* __restrict__ bci, const int32_t* __restrict__ bcrp,
                                                     int2* __restrict__ bc, int4* __restrict__ bhdr) {
     constexpr int L = ROW_LANES;
+    static_assert(L == 8, "the DPP shifts and swizzles below assume 8-lane groups");
     const int sl = threadIdx.x % L;
     const int shift = (threadIdx.x & 63) & ~(L - 1);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x / L;
@@ -632,30 +633,38 @@ __global__ __launch_bounds__(256) void k_compress_b(int32_t n, const int32_t* __
             const bool v = q < e;
             const int c = cc[u];
             const int blk = v ? c >> 5 : -1;
-            int prev = __shfl_up(blk, 1, L);
+            // neighbours inside the 8-lane group: DPP row shifts (a group is an
+            // aligned half of a 16-lane row; the lanes whose neighbour lies
+            // outside the group take it from elsewhere)
+            int prev = __builtin_amdgcn_mov_dpp(blk, 0x111, 0xf, 0xf, false);  // row_shr:1
             if (sl == 0) prev = last_blk;
-            int next = __shfl_down(blk, 1, L);
+            int next = __builtin_amdgcn_mov_dpp(blk, 0x101, 0xf, 0xf, false);  // row_shl:1
             if (sl == L - 1) next = q + 1 < e ? nx[u] >> 5 : -1;
             const int start = v && blk != prev;
             const bool last = v && (q + 1 >= e || next != blk);
             // segmented inclusive OR of the column bits, segments begin at run starts
             uint32_t m = v ? 1u << (c & 31) : 0u;
             int f = start;
-            for (int d = 1; d < L; d <<= 1) {
-                const uint32_t mu = __shfl_up(m, d, L);
-                const int fu = __shfl_up(f, d, L);
+            const auto seg_step = [&](uint32_t mu, int fu, int d) {
                 if (sl >= d && !f) {
                     m |= mu;
                     f = fu;
                 }
-            }
+            };
+            seg_step((uint32_t)__builtin_amdgcn_mov_dpp((int)m, 0x111, 0xf, 0xf, false),
+                     __builtin_amdgcn_mov_dpp(f, 0x111, 0xf, 0xf, false), 1);  // row_shr:1
+            seg_step((uint32_t)__builtin_amdgcn_mov_dpp((int)m, 0x112, 0xf, 0xf, false),
+                     __builtin_amdgcn_mov_dpp(f, 0x112, 0xf, 0xf, false), 2);  // row_shr:2
+            seg_step((uint32_t)__builtin_amdgcn_mov_dpp((int)m, 0x114, 0xf, 0xf, false),
+                     __builtin_amdgcn_mov_dpp(f, 0x114, 0xf, 0xf, false), 4);  // row_shr:4
             if (!f) m |= carry;
             const uint64_t starts = (__ballot(start) >> shift) & ((1ull << L) - 1);
             const int idx = done + __popcll(starts & ((2ull << sl) - 1)) - 1;
             if (last) bc[o + idx] = make_int2(blk, (int)m);
             done += __popcll(starts);
-            carry = __shfl(m, L - 1, L);
-            last_blk = __shfl(blk, L - 1, L);
+            // lane 7 of each group to the whole group: swizzle lane -> (lane & 0x18) | 7
+            carry = (uint32_t)__builtin_amdgcn_ds_swizzle((int)m, 0xF8);
+            last_blk = __builtin_amdgcn_ds_swizzle(blk, 0xF8);
             }
         }
     }
