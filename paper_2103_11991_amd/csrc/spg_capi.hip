@@ -69,6 +69,7 @@ struct spg_handle_s {
         tile_status, cursor,
         ovf_list, ctl, slab_sym, slab_retry, slab_num, mlp_w, bcrp, bc, bhdr, lofs, lists;
     Control* hctl = nullptr;  // pinned host copy
+    hipEvent_t ev_ctl = nullptr;  // marks the copy of the control block after the row-pointer scan
 
     // symbolic result
     bool have_sym = false;
@@ -335,7 +336,10 @@ void sym_stage_analysis(spg_handle h) {
     rec(h, EV_ANA1);
 }
 
-spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
+// (with read_back, the control block is copied to the host right after the
+// row-pointer scan and an event marks the copy: the host needs nothing the
+// numeric grouping after it changes, and need not wait for it)
+spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr, bool read_back = false) {
     hipStream_t s = h->stream;
     const int32_t m = h->m;
     const bool learned = h->binning == 1;
@@ -425,6 +429,11 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr) {
                 h->sym_cls.as<uint8_t>(), h->lofs.as<int32_t>(), c_row_ptr, h->tile_status.as<uint64_t>(), h->cfg,
                 h->num_cls.as<uint8_t>(), ctl);
     rec(h, EV_SCAN1);
+    if (read_back) {
+        if (!h->ev_ctl) HIP_TRY(h, hipEventCreateWithFlags(&h->ev_ctl, hipEventDisableTiming));
+        HIP_TRY(h, hipMemcpyAsync(h->hctl, h->ctl.p, sizeof(Control), hipMemcpyDeviceToHost, s));
+        HIP_TRY(h, hipEventRecord(h->ev_ctl, s));
+    }
     launch_fill_i32(s, h->cursor.as<int32_t>(), 0, NCLS);
     launch_scatter(s, m, h->num_cls.as<uint8_t>(), merging(h), ctl->num_hist, h->cursor.as<int32_t>(),
                    h->perm_num.as<int32_t>(), h->arp, c_row_ptr, h->desc_num.as<int4>());
@@ -587,6 +596,7 @@ spg_status spg_destroy(spg_handle h) {
     if (h->hctl) (void)hipHostFree(h->hctl);
     if (h->ev_made)
         for (auto& e : h->ev) (void)hipEventDestroy(e);
+    if (h->ev_ctl) (void)hipEventDestroy(h->ev_ctl);
     delete h;
     return SPG_OK;
 }
@@ -655,9 +665,11 @@ spg_status spg_symbolic(spg_handle h, int32_t* c_row_ptr, int64_t* nnz_c) {
         SPG_TRY(sync_ctl(h));  // first synchronisation: validity, class histogram, slab sizes
         SPG_TRY(check_input_errors(h));
         h->geom = *h->hctl;
-        SPG_TRY(sym_stage_rows(h, c_row_ptr));
-        SPG_TRY(sync_ctl(h));  // second synchronisation: nnz(C) for the caller's allocation
+        SPG_TRY(sym_stage_rows(h, c_row_ptr, true));
         rec(h, EV_SYM1);
+        // second synchronisation: nnz(C) for the caller's allocation (the
+        // numeric grouping may still run; numeric is ordered after it)
+        HIP_TRY(h, hipEventSynchronize(h->ev_ctl));
         SPG_TRY(sym_finish(h, c_row_ptr));
         *nnz_c = h->nnz_c;
         return SPG_OK;
