@@ -400,6 +400,17 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(int32_t m, const int32_t*
     const int64_t r0 = (int64_t)tile * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
     int64_t v[SCAN_ITEMS];
     int64_t run = 0;
+    // the thread's consecutive rows of one class are counted in registers and
+    // added to the workgroup's counters once per run of equal classes
+    int cur = CLS_EMPTY, n_cur = 0, miss = 0;
+    unsigned long long a_cur = 0, c_cur = 0, p_cur = 0;
+    auto flush = [&]() {
+        if (cur == CLS_EMPTY) return;
+        atomicAdd(&hist[cur], n_cur);
+        atomicAdd(&s_annz[cur], a_cur);
+        atomicAdd(&s_cnnz[cur], c_cur);
+        atomicAdd(&s_prod[cur], p_cur);
+    };
 #pragma unroll
     for (int t = 0; t < SCAN_ITEMS; ++t) {
         int64_t r = r0 + t;
@@ -413,18 +424,23 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(int32_t m, const int32_t*
             if (nc != CLS_EMPTY && nc % NTIER != TIER_GLOBAL && lofs[r] < 0) nc = MODE_DIRECT * NTIER + TIER_GLOBAL;
             num_cls[r] = (uint8_t)nc;
             if (nc != CLS_EMPTY) {
-                atomicAdd(&hist[nc], 1);
-                atomicAdd(&s_annz[nc], (unsigned long long)(arp[r + 1] - arp[r]));
-                atomicAdd(&s_cnnz[nc], (unsigned long long)c);
-                atomicAdd(&s_prod[nc], (unsigned long long)ri.z);
+                if (nc != cur) {
+                    flush();
+                    cur = nc, n_cur = 0, a_cur = c_cur = p_cur = 0;
+                }
+                n_cur += 1;
+                a_cur += (unsigned long long)(arp[r + 1] - arp[r]);
+                c_cur += (unsigned long long)c;
+                p_cur += (unsigned long long)ri.z;
                 if (nc % NTIER == TIER_GLOBAL) atomicMax(&wmax_glob, (unsigned long long)row_words(ri.x, ri.y));
-                int ideal = sym_class(ri.z, ri.x, ri.y, blocks, cfg);
-                if (ideal != sym_cls[r]) atomicAdd(&mispred, 1);
+                miss += sym_class(ri.z, ri.x, ri.y, blocks, cfg) != sym_cls[r];
             }
         }
         run += c;
         v[t] = run;
     }
+    flush();
+    if (miss) atomicAdd(&mispred, miss);
     // block scan of the per-thread totals
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int64_t x = run;
