@@ -145,10 +145,14 @@ const char* spg_last_error(spg_handle h);
    (a hipStream_t; NULL = the default stream).  *h receives the handle. */
 spg_status spg_create(spg_handle* h, void* hip_stream);
 
-/* Releases every buffer the handle owns. Null is accepted. */
+/* Waits for the handle's stream, then releases every buffer the handle owns
+   (back to the library's per-device memory pool, which keeps up to 2 GiB of
+   freed memory for later handles until the process ends). Null is accepted. */
 spg_status spg_destroy(spg_handle h);
 
-/* Rebinds the handle to another stream (later calls run there). */
+/* Rebinds the handle to another stream (later calls run there).  Waits for
+   the work already enqueued on the previous stream first: the handle's device
+   buffers are allocated in that stream's order. */
 spg_status spg_set_stream(spg_handle h, void* hip_stream);
 
 /* Sets A (m x n) and B (n x k) structure, borrowed device arrays:

@@ -586,7 +586,7 @@ spg_status spg_create(spg_handle* out, void* stream) {
 
 spg_status spg_destroy(spg_handle h) {
     if (!h) return SPG_OK;
-    if (h->stream || true) (void)hipStreamSynchronize(h->stream);
+    (void)hipStreamSynchronize(h->stream);  // no launch of this handle still reads its buffers
     DevBuf* bufs[] = {&h->binfo, &h->rinfo, &h->feats, &h->sym_cls, &h->num_cls, &h->perm_sym, &h->perm_num,
                       &h->desc_sym, &h->desc_num,
                       &h->row_nnz, &h->row_blocks, &h->tile_status, &h->cursor, &h->ovf_list, &h->ctl,
