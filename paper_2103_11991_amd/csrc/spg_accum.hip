@@ -673,8 +673,7 @@ void k_sym(SymArgs a) {
                 const uint2 L = l1[w >> 5];
                 const uint32_t bits = (uint32_t)run.y;
                 const int ci = (int)L.y + __popc(L.x & below(w & 31));
-                const uint32_t old = atomicOr(&cm[ci], bits);
-                cnt += __popc(bits & ~old);
+                atomicOr(&cm[ci], bits);  // the row size is counted from the final masks
                 // every run of the block stores the same id
                 if (short_ids) cb16[ci] = (uint16_t)w;
                 else cb[ci] = run.x;
@@ -714,19 +713,29 @@ void k_sym(SymArgs a) {
     } else {
         finish(walk_runs);
     }
-    cnt = group_sum<G>(cnt, red);
-    if constexpr (MODE != MODE_TWOLEVEL) nb = group_sum<G>(nb, red);
+    if constexpr (MODE != MODE_TWOLEVEL) {
+        cnt = group_sum<G>(cnt, red);
+        nb = group_sum<G>(nb, red);
+    }
     group_sync<G>();
     // the row's list: its occupied blocks in ascending order with their masks
     const int lo = d.w;
     const bool overflowed = MODE != MODE_DIRECT && ovf[sub];
-    if (lo >= 0 && !overflowed) {
+    if constexpr (MODE == MODE_TWOLEVEL) {
+        // the row size from the final masks; compact indices are in block
+        // order, so the list is one coalesced store per block
+        if (!overflowed) {
+            for (int t = lane; t < nb; t += G) {
+                const uint32_t mk = cm[t];
+                cnt += __popc(mk);
+                if (lo >= 0) a.lists[lo + t] = make_int2(short_ids ? base + (int)cb16[t] : cb[t], (int)mk);
+            }
+        }
+        cnt = group_sum<G>(cnt, red);
+    }
+    if (MODE != MODE_TWOLEVEL && lo >= 0 && !overflowed) {
         int2* out = a.lists + lo;
-        if constexpr (MODE == MODE_TWOLEVEL) {
-            // compact indices are in block order: one coalesced store per block
-            for (int t = lane; t < nb; t += G)
-                out[t] = make_int2(short_ids ? base + (int)cb16[t] : cb[t], (int)cm[t]);
-        } else if constexpr (MODE == MODE_DIRECT) {
+        if constexpr (MODE == MODE_DIRECT) {
             const int chunk = (ncell + G - 1) / G;
             const int beg = min(lane * chunk, ncell);
             const int end = min(beg + chunk, ncell);
