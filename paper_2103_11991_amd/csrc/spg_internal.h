@@ -17,14 +17,16 @@
 // symbolic global path) take the numeric global path, which finds the masks
 // from compressed B itself.
 //
-// The table is either *direct* (indexed by block - first block of the row:
-// the paper's dense accumulator restricted to the row's column range) or
-// *hashed* (the paper's HashmapAccumulator keyed by block id, open
-// addressing with linear probing), whichever is smaller.  It lives in LDS
-// for rows up to a per-row byte tier; longer rows take the global-memory path
-// (section 2.2.1: second-level accumulator in slow global memory), where the
-// mask table lives in LDS when it fits, else in a global slab, and values
-// accumulate straight into C's own storage with global atomics.
+// The table is *direct* (indexed by block - first block of the row: the
+// paper's dense accumulator restricted to the row's column range), *hashed*
+// (the paper's HashmapAccumulator keyed by block id, open addressing with
+// linear probing) or *two-level* (a bitmap of occupied blocks with running
+// counts, then per occupied block its mask), whichever suits the row.  It
+// lives in LDS for rows up to a per-row byte tier; longer rows take the
+// global-memory path (section 2.2.1: second-level accumulator in slow global
+// memory), where the mask table lives in LDS when it fits, else in a global
+// slab, and values are summed in LDS segments of the rank space or, for the
+// longest rows, straight into C's own storage with global atomics.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -67,7 +69,7 @@ __host__ __device__ inline int tier_rows(int t) {
 // FLAT_VC runs), each read with 16-byte loads; a batch gives every lane K
 // slots, groups lane + G*k of the staged A chunk.
 constexpr int FLAT_VB = 4;       // B entries per group
-constexpr int FLAT_VC = 2;       // compressed-B runs per group (numeric)
+constexpr int FLAT_VC = 2;       // compressed-B runs per group (numeric global path)
 constexpr int FLAT_VC_SYM = 1;   // compressed-B runs per group (symbolic)
 constexpr int FLAT_KC = 5;       // run groups per lane and batch (symbolic; window table size)
 constexpr int FLAT_KC_NUM = 3;   // numeric global path: run groups per lane and batch
