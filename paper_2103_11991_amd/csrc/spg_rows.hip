@@ -229,51 +229,104 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
     }
 }
 
-// Learned binning: one thread per row evaluates the 3-32-32-1 network on the
-// row's features (weights are wave-uniform, so they are read as scalars) and
-// sizes the symbolic table from 2^(y + margin) - 1 occupied blocks.
+// Learned binning: the 3-32-32-1 network on each row's features (weights are
+// wave-uniform, so they are read as scalars) sizes the symbolic table from
+// 2^(y + margin) - 1 occupied blocks.  Consecutive rows with the same
+// features (a stencil's interior) share one evaluation: per pass of 256 rows
+// the first row of every run of equal features takes a slot (a block scan of
+// the run starts, so slots follow row order), the slots are evaluated packed
+// into as few wavefronts as possible, and every row reads its run's result.
+__device__ inline float mlp_eval(const float* __restrict__ w, float x0, float x1, float x2) {
+    const float* W1 = w;
+    const float* b1 = w + 96;
+    const float* W2 = w + 128;
+    const float* b2 = w + 1152;
+    const float* w3 = w + 1184;
+    const float b3 = w[1216];
+    float h1[32];
+#pragma unroll
+    for (int o = 0; o < 32; ++o) {
+        float z = b1[o] + W1[o * 3] * x0 + W1[o * 3 + 1] * x1 + W1[o * 3 + 2] * x2;
+        h1[o] = z > 0.f ? z : 0.f;
+    }
+    float y = b3;
+#pragma unroll 4
+    for (int o = 0; o < 32; ++o) {
+        float z = b2[o];
+#pragma unroll
+        for (int i = 0; i < 32; ++i) z += W2[o * 32 + i] * h1[i];
+        y += w3[o] * (z > 0.f ? z : 0.f);
+    }
+    return y;
+}
+
 __global__ __launch_bounds__(256) void k_mlp_classify(int32_t m, const float* __restrict__ feats,
                                                       const float* __restrict__ w, const RowInfo* __restrict__ rinfo,
                                                       ClassCfg cfg, float margin, uint8_t* __restrict__ sym_cls,
                                                       Control* ctl) {
     __shared__ int32_t hist[NCLS];
     __shared__ unsigned long long wmax_glob;
+    __shared__ float xs[3][256];      // each row's features
+    __shared__ float ys[256];         // the prediction of each run (by slot)
+    __shared__ int32_t wsum[4];
     if (threadIdx.x < NCLS) hist[threadIdx.x] = 0;
     if (threadIdx.x == 0) wmax_glob = 0;
-    __syncthreads();
-    for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < m;
-         row += (int64_t)gridDim.x * blockDim.x) {
-        RowInfo ri = rinfo[row];
-        if (ri.z > 0) {
-            float x0 = feats[row * 3], x1 = feats[row * 3 + 1], x2 = feats[row * 3 + 2];
-            const float* W1 = w;
-            const float* b1 = w + 96;
-            const float* W2 = w + 128;
-            const float* b2 = w + 1152;
-            const float* w3 = w + 1184;
-            const float b3 = w[1216];
-            float h1[32];
-#pragma unroll
-            for (int o = 0; o < 32; ++o) {
-                float z = b1[o] + W1[o * 3] * x0 + W1[o * 3 + 1] * x1 + W1[o * 3 + 2] * x2;
-                h1[o] = z > 0.f ? z : 0.f;
-            }
-            float y = b3;
-#pragma unroll 4
-            for (int o = 0; o < 32; ++o) {
-                float z = b2[o];
-#pragma unroll
-                for (int i = 0; i < 32; ++i) z += W2[o * 32 + i] * h1[i];
-                y += w3[o] * (z > 0.f ? z : 0.f);
-            }
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    int cur = CLS_EMPTY, n_cur = 0;
+    unsigned long long my_wglob = 0;
+    // every thread runs the same number of passes (the barriers below)
+    for (int64_t r0 = blockIdx.x * (int64_t)blockDim.x; r0 < m; r0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = r0 + tid;
+        RowInfo ri = make_int4(0, 0, 0, 0);
+        float x0 = 0.f, x1 = 0.f, x2 = 0.f;
+        if (row < m) {
+            ri = rinfo[row];
+            x0 = feats[row * 3], x1 = feats[row * 3 + 1], x2 = feats[row * 3 + 2];
+        }
+        const bool valid = row < m && ri.z > 0;
+        __syncthreads();  // the previous pass is done with xs and ys
+        // an invalid row holds NaN, which equals nothing: the next valid row starts a run
+        xs[0][tid] = valid ? x0 : __builtin_nanf(""), xs[1][tid] = x1, xs[2][tid] = x2;
+        __syncthreads();
+        const bool start = valid && (tid == 0 || xs[0][tid - 1] != x0 || xs[1][tid - 1] != x1 ||
+                                     xs[2][tid - 1] != x2);
+        // slots of the run starts in row order: block scan of the start flags
+        int inc = start ? 1 : 0;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int up = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += up;
+        }
+        if (lane == 63) wsum[wv] = inc;
+        __syncthreads();  // every start test has read xs
+        int before = 0, nslots = 0;
+        for (int u = 0; u < 4; ++u) {
+            if (u < wv) before += wsum[u];
+            nslots += wsum[u];
+        }
+        // the run a valid row belongs to (its own start or the latest one before it)
+        const int slot = before + inc - 1;
+        if (start) xs[0][slot] = x0, xs[1][slot] = x1, xs[2][slot] = x2;  // slot <= tid
+        __syncthreads();
+        // the runs' features evaluated packed from thread 0
+        if (tid < nslots) ys[tid] = mlp_eval(w, xs[0][tid], xs[1][tid], xs[2][tid]);
+        __syncthreads();
+        if (valid) {
+            // a valid row that starts no run continues the run of a valid row before it
+            const float y = ys[slot];
             float e = exp2f(fminf(y + margin, 40.f)) - 1.f;
             int64_t est = e < 1.f ? 1 : (int64_t)ceilf(e);
             int cls = sym_class(ri.z, ri.x, ri.y, est, cfg);
             sym_cls[row] = (uint8_t)cls;
-            atomicAdd(&hist[cls], 1);
-            if (cls % NTIER == TIER_GLOBAL) atomicMax(&wmax_glob, (unsigned long long)row_words(ri.x, ri.y));
+            if (cls != cur) {
+                if (n_cur) atomicAdd(&hist[cur], n_cur);
+                cur = cls, n_cur = 0;
+            }
+            n_cur += 1;
+            if (cls % NTIER == TIER_GLOBAL) my_wglob = max(my_wglob, (unsigned long long)row_words(ri.x, ri.y));
         }
     }
+    if (n_cur) atomicAdd(&hist[cur], n_cur);
+    if (my_wglob) atomicMax(&wmax_glob, my_wglob);
     __syncthreads();
     if (threadIdx.x < NCLS && hist[threadIdx.x]) atomicAdd(&ctl->sym_hist[threadIdx.x], hist[threadIdx.x]);
     if (threadIdx.x == 0 && wmax_glob) atomicMax((unsigned long long*)&ctl->max_words_sym_global, wmax_glob);
