@@ -287,7 +287,10 @@ spg_status spg_batch_run(spg_batch b, const void* a_val_pool, const void* b_val_
    hashed-table block limit {32,64,128} on full runs of the batch (into the
    given output pools), keeps the fastest and re-plans.  chosen (host
    int32[3], may be NULL) receives the three settings in that order, best_ms
-   (host, may be NULL) the best run time. */
+   (host, may be NULL) the best run time.  The trials replace the batch's
+   plan and captured graph: if any trial fails, the call returns its status
+   with the batch's options unchanged and the batch unplanned (spg_batch_run
+   returns SPG_ERR_STATE until the next spg_batch_plan). */
 spg_status spg_batch_tune(spg_batch b, const void* a_val_pool, const void* b_val_pool,
                           int32_t* c_row_ptr, int32_t* c_col, void* c_val, int64_t capacity,
                           int32_t* chosen, float* best_ms);

@@ -1076,10 +1076,30 @@ spg_status spg_batch_tune(spg_batch b, const void* a_val_pool, const void* b_val
     try {
         if (!b->planned) return bfail(b, SPG_ERR_STATE, "spg_batch_plan must come first");
         if (capacity < b->nnz_total) return bfail(b, SPG_ERR_ARG, "C pools smaller than the planned nnz");
+        if (b->nnz_total > 0 && (!c_row_ptr || !c_col || !c_val)) return bfail(b, SPG_ERR_ARG, "null output pool");
         spg_handle h = b->h;
-        hipEvent_t e0, e1;
-        HIP_TRY(h, hipEventCreate(&e0));
-        HIP_TRY(h, hipEventCreate(&e1));
+        // the trials rewrite the handle's structure state and may grow its
+        // buffers: the captured graph and the plan are void from here on, and
+        // a failure leaves the batch unplanned with its options as they were
+        drop_graph(b);
+        b->planned = false;
+        struct Restore {
+            spg_handle h;
+            int w, v, hb;
+            bool armed = true;
+            ~Restore() {
+                if (armed) h->work_per_lane = w, h->binning = v, h->hash_max_blocks = hb, h->have_sym = false;
+            }
+        } restore{h, h->work_per_lane, h->binning, h->hash_max_blocks};
+        struct Events {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            ~Events() {
+                if (e0) (void)hipEventDestroy(e0);
+                if (e1) (void)hipEventDestroy(e1);
+            }
+        } ev;
+        HIP_TRY(h, hipEventCreate(&ev.e0));
+        HIP_TRY(h, hipEventCreate(&ev.e1));
         const int wpl[] = {8, 16, 32};
         const int bins[] = {2, 0};
         const int hmax[] = {32, 64, 128};
@@ -1094,25 +1114,20 @@ spg_status spg_batch_tune(spg_batch b, const void* a_val_pool, const void* b_val
                     float t = 1e30f;
                     for (int it = 0; it < 2; ++it) {
                         int64_t nnz = 0;
-                        HIP_TRY(h, hipEventRecord(e0, b->stream));
+                        HIP_TRY(h, hipEventRecord(ev.e0, b->stream));
                         spg_status st = spg_symbolic(h, c_row_ptr, &nnz);
                         if (st == SPG_OK) st = spg_numeric(h, a_val_pool, b_val_pool, c_col, c_val);
-                        if (st != SPG_OK) {
-                            (void)hipEventDestroy(e0);
-                            (void)hipEventDestroy(e1);
-                            return bfail(b, st, h->err);
-                        }
-                        HIP_TRY(h, hipEventRecord(e1, b->stream));
-                        HIP_TRY(h, hipEventSynchronize(e1));
+                        if (st != SPG_OK) return bfail(b, st, h->err);
+                        HIP_TRY(h, hipEventRecord(ev.e1, b->stream));
+                        HIP_TRY(h, hipEventSynchronize(ev.e1));
                         float ms = 0.f;
-                        HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
+                        HIP_TRY(h, hipEventElapsedTime(&ms, ev.e0, ev.e1));
                         t = std::min(t, ms);
                     }
                     if (t < best) best = t, bw = w, bv = h->binning, bh = hb;
                 }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
         h->work_per_lane = bw, h->binning = bv, h->hash_max_blocks = bh;
+        restore.armed = false;
         if (chosen) chosen[0] = bw, chosen[1] = bv, chosen[2] = bh;
         if (best_ms) *best_ms = best;
         return batch_replan(b);

@@ -101,3 +101,35 @@ def test_batch_rejects_bad_product():
     with pytest.raises(_lib.SpgError):
         SpGEMMBatch([DeviceCsr.from_host(A)] * 2, [DeviceCsr.from_host(B), DeviceCsr.from_host(badB)])
     torch.cuda.synchronize()
+
+
+def test_failed_tune_leaves_the_batch_unplanned_with_its_options():
+    """A tuning trial that fails (here: no A values, found by the first trial's
+    numeric after its symbolic ran with the trial options) returns the error,
+    leaves the batch unplanned (run is a state error, no stale graph is
+    replayed) and its options as they were; planning again restores it."""
+    import torch
+    from paper_2103_11991_amd import _lib
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMMBatch
+    prods = _products(6, 9)
+    batch = SpGEMMBatch([DeviceCsr.from_host(A) for A, _ in prods], [DeviceCsr.from_host(B) for _, B in prods],
+                        work_per_lane=16)
+    batch.plan()
+    batch.run()
+    torch.cuda.synchronize()
+    _check_all(batch, prods)
+    before = batch.stats()
+    ptrs = list(batch._ptrs(None, None))
+    ptrs[0] = 0  # no A values
+    with pytest.raises(_lib.SpgError):
+        _lib.spg_batch_tune(batch.b, *ptrs)
+    with pytest.raises(_lib.SpgError) as e:
+        _lib.spg_batch_run(batch.b, *batch._ptrs(None, None), 0)
+    assert e.value.status_name == "SPG_ERR_STATE"
+    batch.plan()
+    batch.run()
+    torch.cuda.synchronize()
+    after = batch.stats()
+    # same options: same classes for every row
+    assert after["sym_rows"] == before["sym_rows"] and after["num_rows"] == before["num_rows"]
+    _check_all(batch, prods)

@@ -184,3 +184,119 @@ def test_export_rows_targets_match_oracle_blocks():
     lens = A.row_lengths()
     mx = np.array([A.row_lengths()[A.col_idx[A.row_ptr[i]:A.row_ptr[i + 1]]].max(initial=0) for i in range(A.m)])
     np.testing.assert_allclose(x.cpu().numpy(), ref.features(lens, ub, mx), rtol=1e-6)
+
+
+def _runs_matrix(reps, seed=21):
+    """A (rows in runs of equal features) and B (rows of a few lengths).  Every
+    row of a run has the same length and reads B rows of one length, so the
+    predictor features (len, ub, mx) are equal inside a run while the rows'
+    columns differ.  Runs of 1..1000 rows start at varying offsets, so they
+    cross 64-row wavefront and 256-row pass boundaries; empty rows sit inside
+    some runs (splitting them) and between others."""
+    rng = np.random.default_rng(seed)
+    k = 6000
+    blens = [2, 5, 9, 17, 33]
+    per = 400
+    brows = []
+    for L in blens:
+        for _ in range(per):
+            brows.append(np.sort(rng.choice(k, L, replace=False)))
+    by_len = {L: np.arange(i * per, (i + 1) * per) for i, L in enumerate(blens)}
+    pattern = [1, 2, 63, 64, 65, 128, 255, 256, 257, 300, 511, 513, 1000, 3, 7]
+    shapes = [(a, L) for a in (1, 2, 4, 7, 12, 20) for L in blens]
+    rows = []
+    s = 0
+    for r in range(reps):
+        for j, run in enumerate(pattern):
+            a, L = shapes[(s * 7 + j) % len(shapes)]
+            s += 1
+            holes = set()
+            if run > 100 and j % 2 == 0:
+                holes = {run // 3, run // 3 + 1, (2 * run) // 3}
+            for q in range(run):
+                rows.append(np.array([], dtype=np.int64) if q in holes else rng.choice(by_len[L], a, replace=False))
+            if j % 3 == 1:
+                rows.append(np.array([], dtype=np.int64))
+    m, n = len(rows), len(brows)
+    rp = np.zeros(m + 1, dtype=np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.concatenate(rows).astype(np.int32)
+    A = gen.Csr(m, n, rp.astype(np.int32), ci, np.ones(ci.size))
+    brp = np.zeros(n + 1, dtype=np.int64)
+    brp[1:] = np.cumsum([len(r) for r in brows])
+    bci = np.concatenate(brows).astype(np.int32)
+    B = gen.Csr(n, k, brp.astype(np.int32), bci, np.ones(bci.size))
+    return A, B
+
+
+@pytest.mark.parametrize("reps", [1, 80])
+def test_learned_classes_follow_each_rows_own_prediction(reps):
+    """The classifier evaluates the network once per run of rows with equal
+    features.  Every row must still get the class of its own prediction: the
+    per-class row counts and the misprediction count of the kernel equal what
+    the network's outputs (spg_mlp_forward on the exported features) give
+    through the host port of the class function, up to rows whose estimate
+    sits within float rounding of a boundary (counted, and required rare).
+    With 80 repetitions (about 290k rows) every classifier workgroup takes
+    several 256-row passes."""
+    import torch
+    import oracle
+    from paper_2103_11991_amd import _lib, learned
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
+    import class_port as cp
+    A, B = _runs_matrix(reps)
+    import os
+    if os.path.exists(learned.DEFAULT_MODEL):
+        w, margin, _ = learned.load()
+        w = np.asarray(w, dtype=np.float32)
+    else:
+        w, margin = _w(4, 0.3), 0.5
+    dA, dB = DeviceCsr.from_host(A), DeviceCsr.from_host(B)
+    op = SpGEMM(dA, dB, binning=1, mlp_margin_milli=int(round(margin * 1000)), merge_classes=0, keep_features=1)
+    op.set_mlp(w)
+    op.symbolic()
+    x, _, _ = op.export_rows()
+    y = torch.empty(A.m, dtype=torch.float32, device="cuda")
+    dw = _dev(w)
+    _lib.spg_mlp_forward(0, dw.data_ptr(), x.data_ptr(), A.m, y.data_ptr(), 0)
+    torch.cuda.synchronize()
+    st = op.stats()
+    yh = y.cpu().numpy().astype(np.float64)
+    ub = gen.products_per_row(A, B)
+    orp, ocol, _, _ = oracle.spgemm(A, B)
+    hist_lo = np.zeros(30, dtype=np.int64)
+    hist_hi = np.zeros(30, dtype=np.int64)
+    miss_lo = miss_hi = 0
+    ambiguous = 0
+    eps = 1e-4
+    for i in range(A.m):
+        if ub[i] == 0:
+            continue
+        cols = ocol[orp[i]:orp[i + 1]]
+        cmin, cmax = int(cols[0]), int(cols[-1])
+        blocks = len(np.unique(cols >> 5))
+        cls = set()
+        for d in (-eps, 0.0, eps):
+            e = 2.0 ** min(yh[i] + margin + d, 40.0) - 1.0
+            est = 1 if e < 1.0 else int(np.ceil(e))
+            cls.add(cp.sym_class(int(ub[i]), cmin, cmax, est))
+        true_cls = cp.sym_class(int(ub[i]), cmin, cmax, blocks)
+        if len(cls) > 1:
+            ambiguous += 1
+            for c in cls:
+                hist_hi[c] += 1
+            miss_hi += any(c != true_cls for c in cls)
+            miss_lo += all(c != true_cls for c in cls)
+        else:
+            c = cls.pop()
+            hist_lo[c] += 1
+            hist_hi[c] += 1
+            miss_lo += c != true_cls
+            miss_hi += c != true_cls
+    got = np.asarray(st["sym_rows"], dtype=np.int64)
+    rows = int((ub > 0).sum())
+    assert got.sum() == rows
+    assert ambiguous <= max(2, rows // 200), ambiguous
+    assert (got >= hist_lo).all() and (got <= hist_hi).all(), (got, hist_lo, hist_hi)
+    assert miss_lo <= st["mispredicted_rows"] <= miss_hi
+    assert len(np.nonzero(got)[0]) >= 2  # the runs land in several classes

@@ -282,3 +282,40 @@ def test_numeric_before_symbolic_is_state_error():
     with pytest.raises(_lib.SpgError) as e:
         _lib.spg_numeric(op.h, A.values.data_ptr(), A.values.data_ptr(), A.col_idx.data_ptr(), A.values.data_ptr())
     assert e.value.status_name == "SPG_ERR_STATE"
+
+
+def test_nnz_beyond_int32_is_an_overflow_error():
+    """A = 46341 x 1 column of ones, B = 1 x 46341 row of ones: every row of C
+    is full, so nnz(C) = 46341^2 = 2,147,488,281 >= 2^31.  Symbolic reports
+    SPG_ERR_OVERFLOW and leaves no symbolic result (numeric is a state error).
+    The row-pointer scan runs in 64 bits and only its int32 store is
+    truncated; nothing indexes with the truncated values before the error is
+    returned.  A square of one row less fits (46340^2 < 2^31)."""
+    import torch
+    from paper_2103_11991_amd import _lib
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
+    for n, overflow in ((46341, True), (46340, False)):
+        dev = "cuda"
+        A = DeviceCsr(n, 1, torch.arange(n + 1, dtype=torch.int32, device=dev),
+                      torch.zeros(n, dtype=torch.int32, device=dev), torch.ones(n, dtype=torch.float64, device=dev))
+        B = DeviceCsr(1, n, torch.tensor([0, n], dtype=torch.int32, device=dev),
+                      torch.arange(n, dtype=torch.int32, device=dev), torch.ones(n, dtype=torch.float64, device=dev))
+        op = SpGEMM(A, B)
+        if overflow:
+            assert n * n >= 2 ** 31
+            with pytest.raises(_lib.SpgError) as e:
+                op.symbolic()
+            assert e.value.status_name == "SPG_ERR_OVERFLOW"
+            with pytest.raises(_lib.SpgError) as e:
+                _lib.spg_numeric(op.h, A.values.data_ptr(), B.values.data_ptr(), A.col_idx.data_ptr(),
+                                 A.values.data_ptr())
+            assert e.value.status_name == "SPG_ERR_STATE"
+        else:
+            rp, nnz = op.symbolic()
+            torch.cuda.synchronize()
+            assert nnz == n * n < 2 ** 31
+            rph = rp.cpu().numpy().astype(np.int64)
+            np.testing.assert_array_equal(rph, np.arange(n + 1, dtype=np.int64) * n)
+            # the symbolic phase alone: C itself would take 26 GB
+        del op
+        torch.cuda.synchronize()

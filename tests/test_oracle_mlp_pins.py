@@ -113,3 +113,21 @@ def test_pinball_gradient_and_minimiser():
     w, _ = mlp.train(X, T, w0, epochs=600, lr=0.1, batch=3000, quantile=0.9)
     assert not w[:-1].any()
     assert abs(w[-1] - np.quantile(T, 0.9)) < 0.05
+
+
+def test_features_are_log2_of_one_plus_each_count_in_order():
+    """features(len, ub, mx) per row is (log2(1+len), log2(1+ub), log2(1+mx)):
+    counts one below a power of two give exact integers, so a wrong base, a
+    missing +1 or swapped columns all change these values."""
+    got = mlp.features([0, 1, 3, 1023], [7, 15, 0, 1], [1, 0, 255, 3])
+    want = np.array([[0.0, 3.0, 1.0],
+                     [1.0, 4.0, 0.0],
+                     [2.0, 0.0, 8.0],
+                     [10.0, 1.0, 2.0]])
+    assert got.shape == (4, 3) and got.dtype == np.float64
+    np.testing.assert_array_equal(got, want)
+    # between powers of two the feature is strictly between the neighbours' integers
+    f = mlp.features([2, 4, 5], [2, 4, 5], [2, 4, 5])
+    assert (f[:, 0] == f[:, 1]).all() and (f[:, 1] == f[:, 2]).all()
+    assert 1.0 < f[0, 0] < 2.0 and 2.0 < f[1, 0] < f[2, 0] < 3.0
+    np.testing.assert_allclose(2.0 ** f[:, 0], [3.0, 5.0, 6.0], rtol=1e-15)
