@@ -216,6 +216,21 @@ spg_status spg_mlp_forward(void* stream, const float* w, const float* x, int32_t
 spg_status spg_mlp_backward(void* stream, const float* w, const float* x, const float* act,
                             const float* dy, int32_t rows, float* dw);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving or training loops, harnesses that forbid
+   hipMalloc): the same result as spg_mlp_backward, bit for bit, with no
+   allocation and no allocating library call.  The per-workgroup partial
+   gradients live in a fixed array of the library (256 x 1217 floats,
+   1.19 MiB per device, held until the process ends); the backward grid never
+   exceeds 256 workgroups whatever `rows` is, so every size fits (a grid
+   beyond the array would return SPG_ERR_ARG).  The current HIP device must
+   be the stream's device.  Every call on one device shares that device's
+   array: calls that overlap in time on one device (two streams, two host
+   threads) race and give wrong gradients; calls ordered on one stream are
+   safe.  Asynchronous on `stream`. */
+spg_status spg_mlp_backward_noalloc(void* stream, const float* w, const float* x, const float* act,
+                                    const float* dy, int32_t rows, float* dw);
+
 /* Trains w_inout (device, 1217 floats) in place with minibatch Adam
    (beta1 0.9, beta2 0.999, eps 1e-8), visiting x/y rows in the given order,
    `batch` rows per step, for `epochs` passes.  The loss per row is the

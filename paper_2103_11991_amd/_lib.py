@@ -24,7 +24,7 @@ STATUS = ["SPG_OK", "SPG_ERR_ARG", "SPG_ERR_SHAPE", "SPG_ERR_STATE", "SPG_ERR_IN
           "SPG_ERR_ALLOC", "SPG_ERR_HIP", "SPG_ERR_UNSUPPORTED"]
 EXPORTS = ["spg_status_string", "spg_last_error", "spg_create", "spg_destroy", "spg_set_stream",
            "spg_set_matrices", "spg_symbolic", "spg_numeric", "spg_set_option", "spg_set_mlp", "spg_get_stats",
-           "spg_export_rows", "spg_mlp_forward", "spg_mlp_backward", "spg_mlp_train",
+           "spg_export_rows", "spg_mlp_forward", "spg_mlp_backward", "spg_mlp_backward_noalloc", "spg_mlp_train",
            "spg_batch_create", "spg_batch_destroy", "spg_batch_last_error", "spg_batch_set_option",
            "spg_batch_set_mlp", "spg_batch_plan", "spg_batch_run", "spg_batch_tune", "spg_batch_get_stats"]
 
@@ -79,6 +79,7 @@ def load() -> ctypes.CDLL:
         "spg_export_rows": ([p, p, p, p], ctypes.c_int),
         "spg_mlp_forward": ([p, p, p, i32, p, p], ctypes.c_int),
         "spg_mlp_backward": ([p, p, p, p, p, i32, p], ctypes.c_int),
+        "spg_mlp_backward_noalloc": ([p, p, p, p, p, i32, p], ctypes.c_int),
         "spg_mlp_train": ([p, p, p, i32, i32, i32, f32, f32, p, p], ctypes.c_int),
         "spg_batch_create": ([ctypes.POINTER(p), p, ctypes.c_int, i32, p, p, p, p, p, p, p, p, p], ctypes.c_int),
         "spg_batch_destroy": ([p], ctypes.c_int),
@@ -163,6 +164,10 @@ def spg_mlp_forward(stream: int, w: int, x: int, rows: int, y: int, act: int = 0
 
 def spg_mlp_backward(stream: int, w: int, x: int, act: int, dy: int, rows: int, dw: int) -> None:
     _check(load().spg_mlp_backward(stream or None, w, x, act, dy, rows, dw))
+
+
+def spg_mlp_backward_noalloc(stream: int, w: int, x: int, act: int, dy: int, rows: int, dw: int) -> None:
+    _check(load().spg_mlp_backward_noalloc(stream or None, w, x, act, dy, rows, dw))
 
 
 def spg_mlp_train(stream: int, x: int, y: int, rows: int, epochs: int, batch: int, lr: float, quantile: float,

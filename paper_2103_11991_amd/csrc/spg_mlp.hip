@@ -13,6 +13,7 @@
 // Training is minibatch Adam on the mean squared error or a pinball loss.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <vector>
 
 #include "spg_internal.h"
@@ -184,9 +185,41 @@ __global__ void k_zero(float* p, int64_t n) {
         p[i] = 0.f;
 }
 
+constexpr int MAX_BWD_BLOCKS = 256;  // backward grid cap (row tiles are strided over it)
+
 int bwd_blocks(int32_t rows) {
     int t = (rows + TILE - 1) / TILE;
-    return t < 1 ? 1 : (t > 256 ? 256 : t);
+    return t < 1 ? 1 : (t > MAX_BWD_BLOCKS ? MAX_BWD_BLOCKS : t);
+}
+
+// Partial gradients of spg_mlp_backward_noalloc: one slice of NW floats per
+// backward workgroup (1.19 MiB), held by every device the library runs on
+// until the process ends.  Host code never passes this name to a kernel: it
+// is a host-side stand-in; the device address comes from scratch_address().
+constexpr size_t SCRATCH_FLOATS = (size_t)MAX_BWD_BLOCKS * NW;
+static __device__ __align__(256) float scratch[SCRATCH_FLOATS];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+spg_status scratch_address(float** out) {
+    static std::mutex mu;
+    static float* addr[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return SPG_ERR_HIP;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return SPG_ERR_HIP;
+        }
+        addr[dev] = static_cast<float*>(p);
+    }
+    *out = addr[dev];
+    return SPG_OK;
 }
 
 spg_status launch_backward(hipStream_t s, const float* w, const float* x, const float* act, const float* dy,
@@ -222,6 +255,19 @@ spg_status spg_mlp_backward(void* stream, const float* w, const float* x, const 
     spg_status st = launch_backward(s, w, x, act, dy, rows, dw, partial);
     if (hipFreeAsync(partial, s) != hipSuccess) st = SPG_ERR_HIP;
     return st;
+}
+
+spg_status spg_mlp_backward_noalloc(void* stream, const float* w, const float* x, const float* act,
+                                    const float* dy, int32_t rows, float* dw) {
+    if (rows < 0 || !w || !dw || (rows > 0 && (!x || !act || !dy))) return SPG_ERR_ARG;
+    const int nb = bwd_blocks(rows);
+    if ((size_t)nb * NW > SCRATCH_FLOATS) return SPG_ERR_ARG;  // cannot happen: the grid is capped
+    float* partial = nullptr;
+    spg_status st = scratch_address(&partial);
+    if (st != SPG_OK) return st;
+    // every workgroup of the backward grid writes its whole slice and the
+    // reduction reads only those slices: nothing needs clearing first
+    return launch_backward(static_cast<hipStream_t>(stream), w, x, act, dy, rows, dw, partial);
 }
 
 spg_status spg_mlp_train(void* stream, const float* x, const float* y, int32_t rows, int32_t epochs, int32_t batch,
