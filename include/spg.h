@@ -101,7 +101,16 @@ typedef enum {
        at least 8x the rows), saving a short launch (1 = default, 0 = off;
        off under SPG_OPT_FORCE_CLASS).  sym_rows / num_rows in spg_stats count
        rows by the class they ran in. */
-    SPG_OPT_MERGE_CLASSES = 10
+    SPG_OPT_MERGE_CLASSES = 10,
+    /* numeric rows of the global-memory path run tiled (1 = default): B's
+       columns are cut into tiles of 32 KB of values (8192 FP32 or 4096 FP64
+       columns), each (row, tile) pair sums its products in a dense window,
+       so each product is visited once.  Applies when C has at most 64 tiles
+       of columns; rows without a block list, and all rows when some B row's
+       entries are not grouped by tile (rows in ascending column order always
+       are), take the segment path (0 = always the segment path: the row's
+       values summed one LDS segment of its ranks at a time) */
+    SPG_OPT_TILED_GLOBAL = 11
 } spg_option;
 
 #define SPG_NTIER 10
@@ -133,6 +142,8 @@ typedef struct {
     float num_class_ms_total[SPG_NCLASS];   /* timing on: summed GPU time of every numeric launch of each
                                                class since SPG_OPT_TIMING was last set */
     int32_t num_class_launches[SPG_NCLASS]; /* ... and the number of those launches */
+    int32_t num_tiles;                  /* column tiles of the tiled global path (0: not used) */
+    int32_t tile_fallback_rows;         /* global-path rows the last numeric call left to the segment path */
 } spg_stats;
 
 /* Human-readable name of a status code (static string). */

@@ -30,6 +30,7 @@
 // segments (or, for the longest rows, with global atomics straight into C).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 #include <utility>
 
@@ -464,47 +465,71 @@ __device__ inline auto each(F& f) {
 // entries (off[e] = {start - V * first group, end}, and A's value in ava when
 // walking B), batches of K groups per lane.  apply(group, entry) sees every
 // group once.  Used by the global path, whose rows are long.
+// hdr(j) gives the {first entry, length} of the piece of B row (or
+// compressed-B row) j that the walk covers.
+// One staged chunk of the walk: the lane's entry (if `has`) covers the piece
+// {first, length} = h of a B row with A value v.  The caller has cleared the
+// window table and synchronised the group.
 template <int G, int K, int V, bool RUNS, typename T, typename Load, typename Apply>
-__device__ void flat_walk(const int32_t* __restrict__ aci, const int4* __restrict__ bhdr, const T* __restrict__ av,
-                          int a0, int a1, int2* off, T* ava, Win* win, int* red, Load& load, Apply&& apply) {
+__device__ inline void walk_chunk(int2 h, T v, int2* off, T* ava, Win* win, int* red, Load& load, Apply&& apply) {
     const int lane = threadIdx.x % G, wv = lane >> 6;
     const unsigned long long le = (2ull << (lane & 63)) - 1;
+    const int start = h.x, len = h.y;
+    const bool ne = len > 0;
+    int3 tot;
+    const int3 ex = group_excl_scan3<G>(make_int3(ne, (len + V - 1) / V, 0), tot, red);
+    const int P = tot.y;
+    if (ne) {
+        off[ex.x] = make_int2(start - V * ex.y, start + len);
+        if constexpr (!RUNS) ava[ex.x] = v;
+    }
+    group_sync<G>();
+    for (int P0 = 0; P0 < P; P0 += K * G) {
+        if (P0 > 0) {
+            group_sync<G>();
+            win_clear<G, K>(win, lane);
+            group_sync<G>();
+        }
+        win_mark<G, K>(win, ne, ex.y, P0);
+        const int before = P0 > 0 ? group_sum<G>(ne && ex.y < P0, red) : 0;
+        group_sync<G>();
+        win_scan<G, K, 0>(win, nullptr, before, 0, lane, red);
+        group_sync<G>();
+        Batch<G, K, V, Load> bt;
+        bt.issue(off, win, P0, P, lane, wv, le, load);
+        bt.consume(P0, P, lane, wv, le, apply);
+    }
+}
+
+// hdr(j) gives the {first entry, length} of the piece of B row (or
+// compressed-B row) j that the walk covers.
+template <int G, int K, int V, bool RUNS, typename T, typename Hdr, typename Load, typename Apply>
+__device__ void flat_walk_hdr(const int32_t* __restrict__ aci, Hdr&& hdr, const T* __restrict__ av, int a0, int a1,
+                              int2* off, T* ava, Win* win, int* red, Load& load, Apply&& apply) {
+    const int lane = threadIdx.x % G;
     for (int e0 = a0; e0 < a1; e0 += G) {
         group_sync<G>();  // the previous chunk's readers are done
         win_clear<G, K>(win, lane);
-        int4 h = make_int4(0, 0, 0, 0);
+        int2 h = make_int2(0, 0);
         T v = T(0);
         if (lane < a1 - e0) {
-            h = bhdr[aci[e0 + lane]];
+            h = hdr(aci[e0 + lane]);
             if constexpr (!RUNS) v = av[e0 + lane];
         }
-        const int start = RUNS ? h.z : h.x, len = RUNS ? h.w : h.y;
-        const bool ne = len > 0;
-        int3 tot;
-        const int3 ex = group_excl_scan3<G>(make_int3(ne, (len + V - 1) / V, 0), tot, red);
-        const int P = tot.y;
-        if (ne) {
-            off[ex.x] = make_int2(start - V * ex.y, start + len);
-            if constexpr (!RUNS) ava[ex.x] = v;
-        }
-        group_sync<G>();
-        for (int P0 = 0; P0 < P; P0 += K * G) {
-            if (P0 > 0) {
-                group_sync<G>();
-                win_clear<G, K>(win, lane);
-                group_sync<G>();
-            }
-            win_mark<G, K>(win, ne, ex.y, P0);
-            const int before = P0 > 0 ? group_sum<G>(ne && ex.y < P0, red) : 0;
-            group_sync<G>();
-            win_scan<G, K, 0>(win, nullptr, before, 0, lane, red);
-            group_sync<G>();
-            Batch<G, K, V, Load> bt;
-            bt.issue(off, win, P0, P, lane, wv, le, load);
-            bt.consume(P0, P, lane, wv, le, apply);
-        }
+        walk_chunk<G, K, V, RUNS, T>(h, v, off, ava, win, red, load, apply);
     }
     group_sync<G>();
+}
+
+// The walk over whole B rows (RUNS false) or compressed-B rows (RUNS true).
+template <int G, int K, int V, bool RUNS, typename T, typename Load, typename Apply>
+__device__ void flat_walk(const int32_t* __restrict__ aci, const int4* __restrict__ bhdr, const T* __restrict__ av,
+                          int a0, int a1, int2* off, T* ava, Win* win, int* red, Load& load, Apply&& apply) {
+    auto hdr = [&](int j) {
+        const int4 h = bhdr[j];
+        return RUNS ? make_int2(h.z, h.w) : make_int2(h.x, h.y);
+    };
+    flat_walk_hdr<G, K, V, RUNS, T>(aci, hdr, av, a0, a1, off, ava, win, red, load, static_cast<Apply&&>(apply));
 }
 
 // ------------------------------------------------------------------ symbolic
@@ -1224,12 +1249,253 @@ __global__ __launch_bounds__(WIDE_THREADS) void k_num_wide(NumArgs a) {
     T* ava = reinterpret_cast<T*>(stage + WIDE_THREADS * 8);
     Win* win = reinterpret_cast<Win*>(stage + WIDE_THREADS * 16);
     T* lv = reinterpret_cast<T*>(stage + WIDE_THREADS * 16 + WIDE_WIN_BYTES);
-    for (int r = blockIdx.x; r < a.count; r += gridDim.x) {
+    const int count = a.count_dev ? *a.count_dev : a.count;
+    for (int r = blockIdx.x; r < count; r += gridDim.x) {
         const int i = a.perm[r];
         const RowInfo ri = a.rinfo[i];
         const int64_t words = row_words(ri.x, ri.y);
         if (words * 8 <= a.wide_lds) wide_num_row<T, true>(a, i, smem, off, ava, win, lv, red);
         else wide_num_row<T, false>(a, i, slab, off, ava, win, lv, red);
+    }
+}
+
+// ---------------------------------------------------- tiled global path
+// Long rows of the numeric phase, cut by column tile.  B's columns are split
+// into tiles of W = TILE_BYTES / (element size) columns, and every B row
+// keeps the offsets where its entries of each tile begin (built once per
+// symbolic result; the entries of a row must be grouped by tile, which holds
+// for rows stored in ascending column order).  A work item is one (row, tile)
+// pair: its products are exactly the products of the B rows' entries in the
+// tile, summed into a dense LDS window indexed by column minus the tile's
+// first column (the paper's dense accumulator restricted to one tile), so no
+// product is walked twice and no rank is looked up per product.  The row's
+// list pairs of the tile (its occupied 32-column blocks, ascending, with the
+// rank of the first) then place every column, and the values go out
+// coalesced.  Items are numbered tile-major, so the workgroups in flight work
+// on the same tile of B and share it in L2.
+
+// Tile offsets: per B row, toff[t] = first entry whose column lies in tile t
+// or later (t = 0..T-1), toff[T] = the row's end.  Sixteen lanes per row; a
+// row whose tiles go down somewhere raises b_tile_unordered (the items then
+// all take the segment path).
+__global__ __launch_bounds__(256) void k_b_tiles(TileArgs a) {
+    const int T = a.ntiles;
+    const int64_t total = (int64_t)a.n * 16;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(g >> 4), l = (int)(g & 15);
+        const int s0 = a.brp[j], e0 = a.brp[j + 1];
+        int32_t* to = a.toff + (int64_t)j * (T + 1);
+        if (s0 == e0) {
+            for (int t = l; t <= T; t += 16) to[t] = s0;
+            continue;
+        }
+        for (int q = s0 + l; q < e0; q += 16) {
+            const int tq = a.bci[q] >> a.log_cols;
+            const int tp = q > s0 ? a.bci[q - 1] >> a.log_cols : -1;
+            if (tq < tp) {
+                a.ctl->b_tile_unordered = 1;
+                continue;
+            }
+            for (int t = tp + 1; t <= tq; ++t) to[t] = q;
+            if (q == e0 - 1)
+                for (int t = tq + 1; t <= T; ++t) to[t] = e0;
+        }
+    }
+}
+
+// Work items: one wavefront per row of the class walks the row's list once
+// and records, per tile, the list pairs that fall in it and the rank of the
+// first.  Rows without a list (or all rows, if B's rows are not grouped by
+// tile) go to the fallback list for the segment path, with empty items.
+__global__ __launch_bounds__(256) void k_tile_items(TileArgs a) {
+    __shared__ int3 tl[4][TILE_MAX];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int T = a.ntiles, R = a.rows;
+    const int log_blocks = a.log_cols - 5;
+    const bool unordered = a.ctl->b_tile_unordered != 0;
+    for (int r = blockIdx.x * 4 + w; r < R; r += gridDim.x * 4) {
+        const int i = a.perm[r];
+        const int lo = a.lofs[i];
+        if (lo < 0 || unordered) {
+            if (lane == 0) a.fallback[atomicAdd(&a.ctl->tile_fallback, 1)] = i;
+            for (int t = lane; t < T; t += 64) a.items[(int64_t)t * R + r] = make_int4(i, 0, 0, 0);
+            continue;
+        }
+        if (lane == 0) {
+            if (a.arp[i + 1] - a.arp[i] > TILE_G) a.heavy[atomicAdd(&a.ctl->tile_heavy, 1)] = r;
+            else a.light[atomicAdd(&a.ctl->tile_light, 1)] = r;
+        }
+        for (int t = lane; t < T; t += 64) tl[w][t] = make_int3(0, 0, 0);
+        __builtin_amdgcn_wave_barrier();
+        const int nbk = a.row_blocks[i];
+        const int2* L = a.lists + lo;
+        int run = 0;
+        for (int p0 = 0; p0 < nbk; p0 += 64) {
+            const int p = p0 + lane;
+            const bool ok = p < nbk;
+            const int2 e = ok ? L[p] : make_int2(0, 0);
+            const int tile = e.x >> log_blocks;
+            const int prev = ok && p > 0 ? L[p - 1].x >> log_blocks : -1;
+            const int next = ok && p + 1 < nbk ? L[p + 1].x >> log_blocks : -1;
+            const int pop = ok ? __popc((uint32_t)e.y) : 0;
+            const int incl = wave_incl_scan<64>(pop);
+            if (ok && tile != prev) tl[w][tile].x = p, tl[w][tile].z = run + incl - pop;
+            if (ok && tile != next) tl[w][tile].y = p + 1;
+            run += __builtin_amdgcn_readlane(incl, 63);
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int t = lane; t < T; t += 64) {
+            const int3 v = tl[w][t];
+            a.items[(int64_t)t * R + r] = make_int4(i, lo + v.x, lo + v.y, v.z);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Position of the k-th set bit (k from 0) of m, which has more than k bits set.
+__device__ inline int kth_bit(uint32_t m, int k) {
+    int pos = 0;
+#pragma unroll
+    for (int w = 16; w >= 1; w >>= 1) {
+        const int c = __popc(m & ((1u << w) - 1u));
+        if (k >= c) k -= c, m >>= w, pos += w;
+    }
+    return pos;
+}
+
+// Work units, strided over the grid: first one per (tile, row) of the rows
+// of more than TILE_G entries of A (their chunks are restaged per tile, and
+// the units of one row run on many workgroups), then one per other row, whose
+// tiles run in order on one workgroup with the row's entries held in
+// registers.  There each lane loads its entry's offset of the tile after next
+// while the current tile is walked (consecutive tiles share a boundary) and
+// the next tile's item is fetched early, so a tile waits only for its B
+// loads; the tile's list pairs are loaded before the walk and scanned after
+// it.
+template <typename T>
+__global__ __launch_bounds__(TILE_G) void k_num_tiled(TileArgs a) {
+    constexpr int G = TILE_G;
+    constexpr int W = TILE_BYTES / (int)sizeof(T);  // columns per tile
+    constexpr int NB = W / 32;                       // blocks per tile
+    constexpr int K = sizeof(T) == 8 ? FLAT_KB_F64 : FLAT_KB_F32;
+    __shared__ T dense[W];
+    __shared__ int2 pc[NB];
+    __shared__ int pref[NB];
+    __shared__ int2 off[G];
+    __shared__ T ava[G];
+    __shared__ Win win[K * (G / 64)];
+    __shared__ int red[48];
+    const int tid = threadIdx.x;
+    const int T_ = a.ntiles, R = a.rows;
+    const int nh = a.ctl->tile_heavy, nl = a.ctl->tile_light;
+    const int64_t units = (int64_t)nh * T_ + nl;
+    const T* av = reinterpret_cast<const T*>(a.av);
+    const T* bv = reinterpret_cast<const T*>(a.bv);
+    T* cvals = reinterpret_cast<T*>(a.cval);
+    auto load_cv = [&](int q, int end) { return load_b<T>(a.bci, bv, a.bnnz, q, end); };
+    // a tile's table before the walk: dense window cleared, window table
+    // cleared, its list pairs loaded (pr, scanned after the walk)
+    auto begin_tile = [&](int p0, int np, int2& pr) {
+        for (int c = tid; c < W; c += G) dense[c] = T(0);
+        win_clear<G, K>(win, tid);
+        pr = make_int2(0, 0);
+        if (tid < np) pr = a.lists[p0 + tid];
+    };
+    // after the walk: ranks from the pairs, then columns and values out
+    auto end_tile = [&](int i, int col0, int4 d, int np, int2 pr) {
+        int n_t;
+        const int ex = group_excl_scan<G>(tid < np ? __popc((uint32_t)pr.y) : 0, n_t, red);
+        if (tid < np) pc[tid] = pr, pref[tid] = ex;
+        __syncthreads();
+        const int64_t coff = (int64_t)a.crp[i] + d.w;
+        for (int q = tid; q < n_t; q += G) {
+            int lo = 0, hi = np - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pref[mid] <= q) lo = mid;
+                else hi = mid - 1;
+            }
+            const int2 e = pc[lo];
+            const int c = (e.x << 5) + kth_bit((uint32_t)e.y, q - pref[lo]);
+            a.ccol[coff + q] = c;
+            cvals[coff + q] = dense[c - col0];
+        }
+        __syncthreads();
+    };
+    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+        if (u < (int64_t)nh * T_) {
+            // one tile of a long row; units are numbered tile-major, so the
+            // workgroups in flight share a tile of B
+            const int r = a.heavy[u % nh];
+            const int t = (int)(u / nh);
+            const int4 d = a.items[(int64_t)t * R + r];
+            const int i = __builtin_amdgcn_readfirstlane(d.x);
+            const int p0 = __builtin_amdgcn_readfirstlane(d.y);
+            const int np = __builtin_amdgcn_readfirstlane(d.z) - p0;
+            if (np <= 0) continue;
+            const int col0 = t * W;
+            int2 pr;
+            begin_tile(p0, np, pr);
+            auto add = [&](const BGroup<T>& g, int e) {
+                const T x = ava[e];
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (j < g.n) atomicAdd(&dense[g.c[j] - col0], x * g.y[j]);
+            };
+            const int* to = a.toff + t;
+            auto hdr = [&](int j) {
+                const int64_t o = (int64_t)j * (T_ + 1);
+                const int s0 = to[o], s1 = to[o + 1];
+                return make_int2(s0, s1 - s0);
+            };
+            flat_walk_hdr<G, K, FLAT_VB, false, T>(a.aci, hdr, av, a.arp[i], a.arp[i + 1], off, ava, win, red, load_cv,
+                                                   add);
+            end_tile(i, col0, d, np, pr);
+            continue;
+        }
+        // a row of at most G entries, all its tiles
+        const int r = a.light[u - (int64_t)nh * T_];
+        int4 d = a.items[r];
+        const int i = __builtin_amdgcn_readfirstlane(d.x);
+        const int a0 = a.arp[i], a1 = a.arp[i + 1];
+        const int* tj = nullptr;
+        T v = T(0);
+        int s_cur = 0, s_nxt = 0, s_nn = 0;
+        if (tid < a1 - a0) {
+            const int j = a.aci[a0 + tid];
+            v = av[a0 + tid];
+            tj = a.toff + (int64_t)j * (T_ + 1);
+            s_cur = tj[0];
+            s_nxt = tj[1];
+            if (T_ > 1) s_nn = tj[2];
+        }
+        for (int t = 0; t < T_; ++t) {
+            const int4 dn = t + 1 < T_ ? a.items[(int64_t)(t + 1) * R + r] : make_int4(0, 0, 0, 0);
+            const int p0 = __builtin_amdgcn_readfirstlane(d.y);
+            const int np = __builtin_amdgcn_readfirstlane(d.z) - p0;
+            const int2 h = make_int2(s_cur, s_nxt - s_cur);
+            if (tj) {  // shift the offsets one tile on, fetching the next one early
+                s_cur = s_nxt;
+                s_nxt = s_nn;
+                if (t + 3 <= T_) s_nn = tj[t + 3];
+            }
+            if (np > 0) {
+                const int col0 = t * W;
+                int2 pr;
+                begin_tile(p0, np, pr);
+                auto add = [&](const BGroup<T>& g, int e) {
+                    const T x = ava[e];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (j < g.n) atomicAdd(&dense[g.c[j] - col0], x * g.y[j]);
+                };
+                group_sync<G>();
+                walk_chunk<G, K, FLAT_VB, false, T>(h, v, off, ava, win, red, load_cv, add);
+                group_sync<G>();
+                end_tile(i, col0, d, np, pr);
+            }
+            d = dn;
+        }
     }
 }
 
@@ -1298,14 +1564,16 @@ int launch_sym_class(hipStream_t s, const SymArgs& a, int grid_cap) {
 }
 
 int launch_num_class(hipStream_t s, const NumArgs& a, int elem_bytes, int grid_cap) {
-    if (a.count <= 0) return 0;
+    if (a.count <= 0 && !a.count_dev) return 0;
     if (a.tier == TIER_GLOBAL) {
-        int grid = a.count < grid_cap ? a.count : grid_cap;
+        int grid = a.count_dev ? grid_cap : (a.count < grid_cap ? a.count : grid_cap);
+        if (grid < 1) return 0;
         const size_t smem = wide_smem_bytes(a.wide_lds, 1, a.wide_vals * elem_bytes);
         if (elem_bytes == 8) hipLaunchKernelGGL(k_num_wide<double>, dim3(grid), dim3(WIDE_THREADS), smem, s, a);
         else hipLaunchKernelGGL(k_num_wide<float>, dim3(grid), dim3(WIDE_THREADS), smem, s, a);
         return grid;
     }
+    if (a.count <= 0) return 0;
     if (elem_bytes == 8) {
         if (a.mode == MODE_DIRECT) num_dispatch<MODE_DIRECT, double>(s, a);
         else if (a.mode == MODE_HASHED) num_dispatch<MODE_HASHED, double>(s, a);
@@ -1316,6 +1584,24 @@ int launch_num_class(hipStream_t s, const NumArgs& a, int elem_bytes, int grid_c
         else num_dispatch<MODE_TWOLEVEL, float>(s, a);
     }
     return 1;
+}
+
+void launch_tile_build(hipStream_t s, const TileArgs& a) {
+    const int64_t lanes = (int64_t)a.n * 16;
+    const unsigned gb = (unsigned)std::min<int64_t>((lanes + 255) / 256, 8192);
+    if (gb > 0) hipLaunchKernelGGL(k_b_tiles, dim3(gb), dim3(256), 0, s, a);
+    const unsigned gi = (unsigned)std::min<int64_t>(((int64_t)a.rows + 3) / 4, 4096);
+    if (gi > 0) hipLaunchKernelGGL(k_tile_items, dim3(gi), dim3(256), 0, s, a);
+}
+
+int launch_num_tiled(hipStream_t s, const TileArgs& a, int elem_bytes, int n_cu) {
+    if (a.ntiles <= 0 || a.rows <= 0) return 0;
+    // four 256-lane workgroups fit a compute unit's LDS (the unit counts are
+    // read on the device; workgroups beyond them exit at once)
+    const int grid = (int)std::min<int64_t>((int64_t)a.rows * a.ntiles, (int64_t)n_cu * 4);
+    if (elem_bytes == 8) hipLaunchKernelGGL(k_num_tiled<double>, dim3(grid), dim3(TILE_G), 0, s, a);
+    else hipLaunchKernelGGL(k_num_tiled<float>, dim3(grid), dim3(TILE_G), 0, s, a);
+    return grid;
 }
 
 }  // namespace spg

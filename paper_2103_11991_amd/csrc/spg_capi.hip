@@ -62,12 +62,13 @@ struct spg_handle_s {
     int keep_features = 0;
     int64_t list_limit_mb = 8192;
     int merge_classes = 1;
+    int tiled_global = 1;
     bool have_mlp = false;
 
     // scratch
     DevBuf binfo, rinfo, feats, sym_cls, num_cls, perm_sym, perm_num, desc_sym, desc_num, row_nnz, row_blocks,
         tile_status, cursor,
-        ovf_list, ctl, slab_sym, slab_retry, slab_num, mlp_w, bcrp, bc, bhdr, lofs, lists;
+        ovf_list, ctl, slab_sym, slab_retry, slab_num, mlp_w, bcrp, bc, bhdr, lofs, lists, toff, titems, tfb;
     Control* hctl = nullptr;  // pinned host copy
     hipEvent_t ev_ctl = nullptr;  // marks the copy of the control block after the row-pointer scan
 
@@ -80,6 +81,9 @@ struct spg_handle_s {
     int32_t num_off[NCLS] = {};
     int64_t slab_num_words = 0;
     int nslab_num = 0;
+    bool tiled = false;        // the numeric global class runs on the tiled path
+    bool tiled_built = false;  // its tile offsets and items exist for this symbolic result
+    int ntiles = 0;
     ClassCfg cfg{};
     Control geom{};  // control block after the analysis of the last symbolic run
 
@@ -468,6 +472,22 @@ spg_status sym_finish(spg_handle h, int32_t* c_row_ptr) {
         h->slab_num_words = 2 * ((hc2.max_words_num_global + 63) & ~(int64_t)63);
         SPG_TRY(ensure(h, h->slab_num, (size_t)h->nslab_num * h->slab_num_words * 4));
     }
+    // tiled global path: tile offsets of B and the (row, tile) items, built
+    // by the first numeric call on this symbolic result
+    h->tiled = false;
+    h->tiled_built = false;
+    if (h->tiled_global && h->num_hist[gcls] > 0) {
+        const int64_t w = tile_cols(h->dt == SPG_F64 ? 8 : 4);
+        const int64_t T = (h->k + w - 1) / w;
+        if (T >= 1 && T <= TILE_MAX) {
+            const int64_t R = h->num_hist[gcls];
+            SPG_TRY(ensure(h, h->toff, (size_t)h->n * (T + 1) * 4));
+            SPG_TRY(ensure(h, h->titems, (size_t)(T * R) * sizeof(int4)));
+            SPG_TRY(ensure(h, h->tfb, (size_t)R * 3 * 4));  // fallback rows, heavy and light slots
+            h->tiled = true;
+            h->ntiles = (int)T;
+        }
+    }
     spg_stats& st = h->stats;
     st.size = sizeof(spg_stats);
     st.m = h->m, st.n = h->n, st.k = h->k;
@@ -495,8 +515,57 @@ spg_status sym_finish(spg_handle h, int32_t* c_row_ptr) {
     return SPG_OK;
 }
 
+int ilog2(int64_t v) {
+    int l = 0;
+    while ((int64_t)1 << (l + 1) <= v) ++l;
+    return l;
+}
+
+// The numeric global class on the tiled path: tile offsets and items when
+// this symbolic result has none yet (always when `build`), the (row, tile)
+// items, then the rows left to the segment path.
+void num_launch_tiled(spg_handle h, const NumArgs& g, bool build) {
+    hipStream_t s = h->stream;
+    const int eb = h->dt == SPG_F64 ? 8 : 4;
+    Control* ctl = h->ctl.as<Control>();
+    TileArgs t{};
+    t.n = h->n;
+    t.rows = g.count;
+    t.ntiles = h->ntiles;
+    t.log_cols = ilog2(tile_cols(eb));
+    t.perm = g.perm;
+    t.arp = h->arp, t.aci = h->aci, t.av = g.av;
+    t.brp = h->brp, t.bci = h->bci, t.bv = g.bv, t.bnnz = h->bnnz;
+    t.crp = h->crp;
+    t.lofs = h->lofs.as<int32_t>();
+    t.row_blocks = h->row_blocks.as<int32_t>();
+    t.lists = h->lists.as<int2>();
+    t.toff = h->toff.as<int32_t>();
+    t.items = h->titems.as<int4>();
+    t.fallback = h->tfb.as<int32_t>();
+    t.heavy = t.fallback + g.count;
+    t.light = t.heavy + g.count;
+    t.ctl = ctl;
+    t.ccol = g.ccol;
+    t.cval = g.cval;
+    if (build || !h->tiled_built) {
+        launch_fill_u8(s, &ctl->tile_fallback, 0, 4 * sizeof(int32_t));
+        launch_tile_build(s, t);
+        h->tiled_built = true;
+    }
+    launch_num_tiled(s, t, eb, h->n_cu);
+    NumArgs f = g;
+    f.perm = h->tfb.as<int32_t>();
+    f.count = 0;
+    f.count_dev = &ctl->tile_fallback;
+    launch_num_class(s, f, eb, std::max(h->nslab_num, 1));
+}
+
 // Numeric launches for the current symbolic result (no synchronisation).
-spg_status num_launch_all(spg_handle h, const void* a_vals, const void* b_vals, int32_t* c_col_idx, void* c_vals) {
+// `build_tiles` rebuilds the tiled path's items even if they exist (a
+// captured graph must hold the build).
+spg_status num_launch_all(spg_handle h, const void* a_vals, const void* b_vals, int32_t* c_col_idx, void* c_vals,
+                          bool build_tiles = false) {
     hipStream_t s = h->stream;
     const int eb = h->dt == SPG_F64 ? 8 : 4;
     for (int c = 0; c < NCLS; ++c) {
@@ -528,7 +597,8 @@ spg_status num_launch_all(spg_handle h, const void* a_vals, const void* b_vals, 
             resolve_num(h, set, c);
             (void)hipEventRecord(h->ev[num_ev(set, c)], s);
         }
-        launch_num_class(s, a, eb, std::max(h->nslab_num, 1));
+        if (c == MODE_DIRECT * NTIER + TIER_GLOBAL && h->tiled) num_launch_tiled(h, a, build_tiles);
+        else launch_num_class(s, a, eb, std::max(h->nslab_num, 1));
         if (h->timing) (void)hipEventRecord(h->ev[num_ev(set, c) + 1], s);
         h->num_cls_timed[c] = h->timing != 0;
         h->num_pending[set][c] = h->timing != 0;
@@ -591,7 +661,7 @@ spg_status spg_destroy(spg_handle h) {
                       &h->desc_sym, &h->desc_num,
                       &h->row_nnz, &h->row_blocks, &h->tile_status, &h->cursor, &h->ovf_list, &h->ctl,
                       &h->slab_sym, &h->slab_retry, &h->slab_num, &h->mlp_w, &h->bcrp, &h->bc, &h->bhdr,
-                      &h->lofs, &h->lists};
+                      &h->lofs, &h->lists, &h->toff, &h->titems, &h->tfb};
     for (DevBuf* b : bufs) release(*b, h->stream);
     if (h->hctl) (void)hipHostFree(h->hctl);
     if (h->ev_made)
@@ -734,6 +804,7 @@ spg_status spg_set_option(spg_handle h, int32_t opt, int64_t val) {
         }
         case SPG_OPT_KEEP_FEATURES: h->keep_features = val != 0; break;
         case SPG_OPT_MERGE_CLASSES: h->merge_classes = val != 0; break;
+        case SPG_OPT_TILED_GLOBAL: h->tiled_global = val != 0; break;
         case SPG_OPT_LIST_LIMIT_MB:
             if (val < 1 || val > 16383) return fail(h, SPG_ERR_ARG, "list memory limit must be 1..16383 MiB");
             h->list_limit_mb = val;
@@ -782,6 +853,16 @@ spg_status spg_get_stats(spg_handle h, spg_stats* out, int32_t size) {
     for (int c = 0; c < NCLS; ++c) {
         st.num_class_ms_total[c] = (float)h->num_acc_ms[c];
         st.num_class_launches[c] = h->num_acc_n[c];
+    }
+    st.num_tiles = h->have_sym && h->tiled ? h->ntiles : 0;
+    st.tile_fallback_rows = 0;
+    if (st.num_tiles && h->tiled_built) {
+        // written by the last numeric call's item build, on the handle's stream
+        int32_t fb = 0;
+        HIP_TRY(h, hipMemcpyAsync(&fb, &h->ctl.as<Control>()->tile_fallback, sizeof(fb), hipMemcpyDeviceToHost,
+                                  h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        st.tile_fallback_rows = fb;
     }
     *out = st;
     return SPG_OK;
@@ -1044,7 +1125,7 @@ spg_status spg_batch_run(spg_batch b, const void* a_val_pool, const void* b_val_
                                    b->stream, b->crp_plan.as<int32_t>(), c_row_ptr, n1);
                 h->crp = b->crp_plan.as<int32_t>();
             }
-            if (st == SPG_OK) st = num_launch_all(h, a_val_pool, b_val_pool, c_col, c_val);
+            if (st == SPG_OK) st = num_launch_all(h, a_val_pool, b_val_pool, c_col, c_val, true);
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(b->stream, &g);
             h->timing = timing;

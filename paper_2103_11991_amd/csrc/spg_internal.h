@@ -267,6 +267,10 @@ struct Control {
     int32_t tile_counter_b;       // dynamic tile id of the compressed-B scan
     int64_t bc_total;             // runs of compressed B
     int64_t list_total;           // list pairs reserved by the grouping of the symbolic rows
+    int32_t tile_fallback;        // tiled global path: rows left to the segment path
+    int32_t b_tile_unordered;     // tiled global path: a B row's entries are not grouped by tile
+    int32_t tile_heavy;           // tiled global path: rows of more than TILE_G entries (one unit per tile)
+    int32_t tile_light;           // tiled global path: rows of at most TILE_G entries (one unit per row)
 };
 
 // ---- launch wrappers (spg_rows.hip) ----
@@ -363,7 +367,48 @@ struct NumArgs {
     int32_t wide_vals;            // global path: values per LDS segment (0 = global atomics only)
     const int32_t* lofs;          // per row: first pair of its list, -1 if it has none
     const int2* lists;            // {block, mask} pairs in ascending block order
+    const int32_t* count_dev;     // global path: device-side row count (or null)
 };
+
+// Tiled global path of the numeric phase (spg_accum.hip).  B's columns are
+// cut into tiles of TILE_BYTES / (element size) columns; a work item is one
+// (row, tile) pair of a long row.
+constexpr int TILE_BYTES = 32768;  // dense LDS window of one item
+constexpr int TILE_G = 256;        // lanes per row
+constexpr int TILE_MAX = 64;       // most tiles a matrix may have for this path
+__host__ __device__ inline int tile_cols(int elem_bytes) { return TILE_BYTES / elem_bytes; }
+
+struct TileArgs {
+    int32_t n;                    // rows of B
+    int32_t rows;                 // rows of the global class (R)
+    int32_t ntiles;               // T
+    int32_t log_cols;             // log2(columns per tile)
+    const int32_t* perm;          // the class's rows (R entries)
+    const int32_t* arp;
+    const int32_t* aci;
+    const void* av;
+    const int32_t* brp;
+    const int32_t* bci;
+    const void* bv;
+    int64_t bnnz;
+    const int32_t* crp;
+    const int32_t* lofs;
+    const int32_t* row_blocks;
+    const int2* lists;
+    int32_t* toff;                // per B row, T + 1 tile offsets: first entry of each tile, then the row end
+    int4* items;                  // [T][R]: {row, first list pair, end pair, rank of the first pair}
+    int32_t* fallback;            // rows for the segment path (no list, or B rows not grouped by tile)
+    int32_t* heavy;               // class slots of rows of more than TILE_G entries of A
+    int32_t* light;               // class slots of the other rows
+    Control* ctl;
+    int32_t* ccol;
+    void* cval;
+};
+
+// Tile offsets of B and the work items (once per symbolic result), then the
+// tiled numeric launch; returns the grid used.
+void launch_tile_build(hipStream_t s, const TileArgs& a);
+int launch_num_tiled(hipStream_t s, const TileArgs& a, int elem_bytes, int n_cu);
 
 // Launches one symbolic class; returns the grid size used.
 int launch_sym_class(hipStream_t s, const SymArgs& a, int grid_cap);

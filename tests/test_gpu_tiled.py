@@ -1,0 +1,108 @@
+"""The tiled numeric global path (long rows cut by column tile, one dense
+window per (row, tile) item) against the oracle, beside the segment path it
+replaces, its fallbacks (rows without a block list, B rows not grouped by
+tile) and matrices too wide for it."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2103_11991_amd import gen
+from gpu_util import compare, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def setup_module(module):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("tiled", [1, 0])
+def test_long_rows_tiled_and_segment_paths(dtype, tiled):
+    """Rows of 10k-60k entries over 3-15 tiles (both dtypes), some A rows
+    empty; the same product on the segment path."""
+    A = gen.random_csr(40, 700, 100, 400, seed=11, dtype=dtype, empty_frac=0.1)
+    B = gen.random_csr(700, 60000, 50, 300, seed=12, dtype=dtype)
+    rp, c, v, op = run_gpu(A, B, tiled_global=tiled)
+    st = op.stats()
+    assert st["num_rows"][9] > 0
+    w = 32768 // np.dtype(dtype).itemsize
+    assert st["num_tiles"] == (-(-60000 // w) if tiled else 0)
+    assert st["tile_fallback_rows"] == 0
+    compare(A, B, rp, c, v)
+
+
+def test_tiled_items_cover_ragged_tiles_and_single_block_rows():
+    """Columns on tile edges, a last tile of a few columns, rows whose
+    products all fall in one 32-column block of one tile, and products that
+    sum into one column many times (integers: exact)."""
+    k = 3 * 4096 + 7  # FP64 tiles of 4096 columns: the last has 7 columns
+    A = gen.random_csr(64, 300, 200, 300, seed=21, value_kind="int")
+    rows, cols = [], []
+    for j in range(300):
+        if j % 3 == 0:     # tile edges and the ragged last tile
+            cs = [0, 4095, 4096, 8191, 8192, 12287, 12288, k - 1]
+        elif j % 3 == 1:   # one block in the middle of tile 1
+            cs = list(range(4096 + 64, 4096 + 96))
+        else:              # every tile, about 950 columns
+            cs = list(range(j % 17, k, 13))
+        rows += [j] * len(cs)
+        cols += cs
+    vals = ((np.arange(len(cols)) % 5) - 2).astype(np.float64)
+    B = gen.csr_from_rows_cols(300, k, np.array(rows), np.array(cols), vals)
+    rp, c, v, op = run_gpu(A, B)
+    st = op.stats()
+    assert st["num_rows"][9] == A.m - st["empty_rows"] and st["num_tiles"] == 4
+    assert st["tile_fallback_rows"] == 0
+    compare(A, B, rp, c, v, exact=True)
+
+
+def test_unsorted_b_rows_fall_back_to_the_segment_path():
+    """B rows whose entries are not grouped by tile: every global row takes
+    the segment path, and the product is unchanged."""
+    A = gen.random_csr(24, 500, 100, 300, seed=31)
+    B = gen.random_csr(500, 40000, 100, 300, seed=32, sorted_rows=False)
+    rp, c, v, op = run_gpu(A, B)
+    st = op.stats()
+    assert st["num_rows"][9] > 0 and st["num_tiles"] > 0
+    assert st["tile_fallback_rows"] == st["num_rows"][9]
+    compare(A, B, rp, c, v)
+
+
+def test_repeated_b_columns_add_up_on_the_tiled_path():
+    """Sorted B rows with repeated columns are grouped by tile: they stay on
+    the tiled path, and repeats add up as in the oracle."""
+    A = gen.random_csr(24, 400, 150, 300, seed=41, value_kind="int")
+    B = gen.random_csr(400, 50000, 100, 400, seed=42, duplicates=True, value_kind="int")
+    assert (np.diff(B.col_idx) == 0).sum() > 100  # repeated columns inside rows
+    rp, c, v, op = run_gpu(A, B)
+    st = op.stats()
+    assert st["num_rows"][9] > 0 and st["tile_fallback_rows"] == 0
+    compare(A, B, rp, c, v, exact=True)
+
+
+def test_rows_without_lists_fall_back_and_numeric_reuse():
+    """With 1 MiB of list memory some global rows have no block list: they
+    take the segment path next to the tiled rows.  Numeric again with new
+    values reuses the built items."""
+    A = gen.random_csr(400, 800, 200, 400, seed=51)
+    B = gen.random_csr(800, 30000, 100, 400, seed=52)
+    rp, c, v, op = run_gpu(A, B, list_limit_mb=1)
+    st = op.stats()
+    assert st["num_tiles"] > 0 and 0 < st["tile_fallback_rows"] < st["num_rows"][9]
+    compare(A, B, rp, c, v)
+    A2 = A.with_values(gen.random_csr(400, 800, 200, 400, seed=51, value_kind="uniform").values)
+    col, val = op.numeric(a_vals=torch.from_numpy(A2.values).cuda())
+    torch.cuda.synchronize()
+    compare(A2, B, rp, col.cpu().numpy(), val.cpu().numpy())
+
+
+def test_too_many_tiles_keeps_the_segment_path():
+    """FP64 with more than 64 tiles of 4096 columns: the segment path."""
+    A = gen.random_csr(12, 600, 300, 400, seed=61)
+    B = gen.random_csr(600, 64 * 4096 + 1, 300, 500, seed=62)
+    rp, c, v, op = run_gpu(A, B)
+    st = op.stats()
+    assert st["num_rows"][9] > 0 and st["num_tiles"] == 0
+    compare(A, B, rp, c, v)
