@@ -194,6 +194,22 @@ spg_status spg_symbolic(spg_handle h, int32_t* c_row_ptr, int64_t* nnz_c);
 spg_status spg_numeric(spg_handle h, const void* a_vals, const void* b_vals,
                        int32_t* c_col_idx, void* c_vals);
 
+/* Jacobi-fused numeric phase (section 2.2.2): C = (I - omega D^-1 A) B for
+   a square A (m x m, every row storing its diagonal entry) and B (m x k),
+   on the structure of the last spg_symbolic, which is the structure of A*B
+   (A's diagonal puts B(i,:) inside it).  Row i of C is
+       C(i,:) = B(i,:) - omega * dinv[i] * E(i,:),   E(i,:) = sum_j A(i,j) B(j,:),
+   computed in one pass of the numeric kernels: E(i,:) is accumulated as in
+   spg_numeric, scaled by -omega * dinv[i] once per row, and B(i,:)'s entries
+   are added into the same accumulator before the row is written out.
+   dinv: device, m values of the handle's dtype (D^-1, usually 1 / A(i,i);
+   the caller's values are used as given).  Other arguments and ownership as
+   spg_numeric; asynchronous.  SPG_ERR_SHAPE if A is not square or some row of
+   A stores no diagonal entry (checked from the structure by spg_symbolic),
+   SPG_ERR_STATE without a symbolic result. */
+spg_status spg_numeric_jacobi(spg_handle h, double omega, const void* dinv, const void* a_vals, const void* b_vals,
+                              int32_t* c_col_idx, void* c_vals);
+
 /* Sets an spg_option (see above). */
 spg_status spg_set_option(spg_handle h, int32_t opt, int64_t val);
 

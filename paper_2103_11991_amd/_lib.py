@@ -23,7 +23,7 @@ NTIER, NCLASS = 10, 30
 STATUS = ["SPG_OK", "SPG_ERR_ARG", "SPG_ERR_SHAPE", "SPG_ERR_STATE", "SPG_ERR_INDEX", "SPG_ERR_OVERFLOW",
           "SPG_ERR_ALLOC", "SPG_ERR_HIP", "SPG_ERR_UNSUPPORTED"]
 EXPORTS = ["spg_status_string", "spg_last_error", "spg_create", "spg_destroy", "spg_set_stream",
-           "spg_set_matrices", "spg_symbolic", "spg_numeric", "spg_set_option", "spg_set_mlp", "spg_get_stats",
+           "spg_set_matrices", "spg_symbolic", "spg_numeric", "spg_numeric_jacobi", "spg_set_option", "spg_set_mlp", "spg_get_stats",
            "spg_export_rows", "spg_mlp_forward", "spg_mlp_backward", "spg_mlp_backward_noalloc", "spg_mlp_train",
            "spg_batch_create", "spg_batch_destroy", "spg_batch_last_error", "spg_batch_set_option",
            "spg_batch_set_mlp", "spg_batch_plan", "spg_batch_run", "spg_batch_tune", "spg_batch_get_stats"]
@@ -74,6 +74,7 @@ def load() -> ctypes.CDLL:
         "spg_set_matrices": ([p, ctypes.c_int, i32, i32, i32, p, p, i64, p, p, i64], ctypes.c_int),
         "spg_symbolic": ([p, p, ctypes.POINTER(i64)], ctypes.c_int),
         "spg_numeric": ([p, p, p, p, p], ctypes.c_int),
+        "spg_numeric_jacobi": ([p, ctypes.c_double, p, p, p, p, p], ctypes.c_int),
         "spg_set_option": ([p, i32, i64], ctypes.c_int),
         "spg_set_mlp": ([p, p, i32], ctypes.c_int),
         "spg_get_stats": ([p, ctypes.POINTER(spg_stats), i32], ctypes.c_int),
@@ -138,6 +139,12 @@ def spg_symbolic(h: int, c_row_ptr: int) -> int:
 
 def spg_numeric(h: int, a_vals: int, b_vals: int, c_col_idx: int, c_vals: int) -> None:
     _check(load().spg_numeric(h, a_vals or None, b_vals or None, c_col_idx or None, c_vals or None), h)
+
+
+def spg_numeric_jacobi(h: int, omega: float, dinv: int, a_vals: int, b_vals: int, c_col_idx: int,
+                       c_vals: int) -> None:
+    _check(load().spg_numeric_jacobi(h, float(omega), dinv or None, a_vals or None, b_vals or None,
+                                     c_col_idx or None, c_vals or None), h)
 
 
 def spg_set_option(h: int, opt, val: int) -> None:

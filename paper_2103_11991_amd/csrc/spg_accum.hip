@@ -1119,6 +1119,15 @@ void k_num(NumArgs a) {
             }
         }
     }
+    if (a.dinv) {
+        // Jacobi-fused product: C(i,:) = B(i,:) - omega D^-1(i) E(i,:); the
+        // row's table holds E(i,:), B(i,:) lies inside its pattern
+        group_sync<G>();
+        const T sc = -(T)a.omega * reinterpret_cast<const T*>(a.dinv)[i];
+        for (int r = lane; r < n; r += G) vals[r] *= sc;
+        group_sync<G>();
+        for (int q = a.brp[i] + lane; q < a.brp[i + 1]; q += G) atomicAdd(&vals[rank_of(a.bci[q])], bv[q]);
+    }
     group_sync<G>();
     T* cv = reinterpret_cast<T*>(a.cval) + off;
     for (int r = lane; r < n; r += G) cv[r] = vals[r];
@@ -1212,6 +1221,16 @@ __device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int2* off
                                                             atomicAdd(&lv[r], x * g.y[j]);
                                                     }
                                                 });
+            if (a.dinv) {  // Jacobi-fused: scale the segment, then add B(i,:)'s entries in it
+                const T sc = -(T)a.omega * reinterpret_cast<const T*>(a.dinv)[i];
+                for (int r = tid; r < len; r += G) lv[r] *= sc;
+                __syncthreads();
+                for (int q = a.brp[i] + tid; q < a.brp[i + 1]; q += G) {
+                    const int r = rank_of(a.bci[q]) - s0;
+                    if ((unsigned)r < (unsigned)len) atomicAdd(&lv[r], bv[q]);
+                }
+                __syncthreads();
+            }
             for (int r = tid; r < len; r += G) cv[s0 + r] = lv[r];
             __syncthreads();
         }
@@ -1225,6 +1244,15 @@ __device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int2* off
                                                 for (int j = 0; j < 4; ++j)
                                                     if (j < g.n) atomicAdd(&cv[rk[j]], x * g.y[j]);
                                             });
+        if (a.dinv) {  // Jacobi-fused, in C's own storage
+            const T sc = -(T)a.omega * reinterpret_cast<const T*>(a.dinv)[i];
+            __threadfence();
+            __syncthreads();
+            for (int r = tid; r < n; r += G) cv[r] *= sc;
+            __threadfence();
+            __syncthreads();
+            for (int q = a.brp[i] + tid; q < a.brp[i + 1]; q += G) atomicAdd(&cv[rank_of(a.bci[q])], bv[q]);
+        }
     }
     for (int t = tid; t < words; t += G) {
         uint32_t mk = ld_tab<IN_LDS>(&masks[t]);
@@ -1401,6 +1429,17 @@ __global__ __launch_bounds__(TILE_G) void k_num_tiled(TileArgs a) {
         pr = make_int2(0, 0);
         if (tid < np) pr = a.lists[p0 + tid];
     };
+    // Jacobi-fused product: the tile's window holds E(i, tile); scale it by
+    // -omega D^-1(i) and add B(i,:)'s entries of the tile (toff of row i)
+    auto jacobi_tile = [&](int i, int t, int col0) {
+        if (!a.dinv) return;
+        const T sc = -(T)a.omega * reinterpret_cast<const T*>(a.dinv)[i];
+        for (int c = tid; c < W; c += G) dense[c] *= sc;
+        __syncthreads();
+        const int* tr = a.toff + (int64_t)i * (T_ + 1);
+        for (int q = tr[t] + tid; q < tr[t + 1]; q += G) atomicAdd(&dense[a.bci[q] - col0], bv[q]);
+        __syncthreads();
+    };
     // after the walk: ranks from the pairs, then columns and values out
     auto end_tile = [&](int i, int col0, int4 d, int np, int2 pr) {
         int n_t;
@@ -1450,6 +1489,7 @@ __global__ __launch_bounds__(TILE_G) void k_num_tiled(TileArgs a) {
             };
             flat_walk_hdr<G, K, FLAT_VB, false, T>(a.aci, hdr, av, a.arp[i], a.arp[i + 1], off, ava, win, red, load_cv,
                                                    add);
+            jacobi_tile(i, t, col0);
             end_tile(i, col0, d, np, pr);
             continue;
         }
@@ -1492,6 +1532,7 @@ __global__ __launch_bounds__(TILE_G) void k_num_tiled(TileArgs a) {
                 group_sync<G>();
                 walk_chunk<G, K, FLAT_VB, false, T>(h, v, off, ava, win, red, load_cv, add);
                 group_sync<G>();
+                jacobi_tile(i, t, col0);
                 end_tile(i, col0, d, np, pr);
             }
             d = dn;

@@ -548,6 +548,8 @@ void num_launch_tiled(spg_handle h, const NumArgs& g, bool build) {
     t.ctl = ctl;
     t.ccol = g.ccol;
     t.cval = g.cval;
+    t.dinv = g.dinv;
+    t.omega = g.omega;
     if (build || !h->tiled_built) {
         launch_fill_u8(s, &ctl->tile_fallback, 0, 4 * sizeof(int32_t));
         launch_tile_build(s, t);
@@ -565,7 +567,7 @@ void num_launch_tiled(spg_handle h, const NumArgs& g, bool build) {
 // `build_tiles` rebuilds the tiled path's items even if they exist (a
 // captured graph must hold the build).
 spg_status num_launch_all(spg_handle h, const void* a_vals, const void* b_vals, int32_t* c_col_idx, void* c_vals,
-                          bool build_tiles = false) {
+                          bool build_tiles = false, const void* dinv = nullptr, double omega = 0.0) {
     hipStream_t s = h->stream;
     const int eb = h->dt == SPG_F64 ? 8 : 4;
     for (int c = 0; c < NCLS; ++c) {
@@ -592,6 +594,8 @@ spg_status num_launch_all(spg_handle h, const void* a_vals, const void* b_vals, 
         a.wide_vals = wide_vals(h, eb);
         a.lofs = h->lofs.as<int32_t>();
         a.lists = h->lists.as<int2>();
+        a.dinv = dinv;
+        a.omega = omega;
         const int set = h->num_set;
         if (h->timing) {
             resolve_num(h, set, c);
@@ -761,6 +765,30 @@ spg_status spg_numeric(spg_handle h, const void* a_vals, const void* b_vals, int
         std::fill(std::begin(h->num_cls_timed), std::end(h->num_cls_timed), false);
         rec(h, EV_NUM0);
         SPG_TRY(num_launch_all(h, a_vals, b_vals, c_col_idx, c_vals));
+        rec(h, EV_NUM1);
+        return SPG_OK;
+    } catch (...) {
+        return fail(h, SPG_ERR_HIP, "unexpected host exception");
+    }
+}
+
+spg_status spg_numeric_jacobi(spg_handle h, double omega, const void* dinv, const void* a_vals, const void* b_vals,
+                              int32_t* c_col_idx, void* c_vals) {
+    if (!h) return SPG_ERR_ARG;
+    try {
+        if (!h->have_sym) return fail(h, SPG_ERR_STATE, "spg_symbolic must come first");
+        if (h->m != h->n) return fail(h, SPG_ERR_SHAPE, "the Jacobi-fused product needs a square A");
+        if (h->geom.a_missing_diag > 0)
+            return fail(h, SPG_ERR_SHAPE, std::to_string(h->geom.a_missing_diag) +
+                                              " rows of A store no diagonal entry: C would leave the pattern of A*B");
+        if (h->m > 0 && !dinv) return fail(h, SPG_ERR_ARG, "null D^-1");
+        if ((h->annz > 0 && !a_vals) || (h->bnnz > 0 && !b_vals)) return fail(h, SPG_ERR_ARG, "null input values");
+        if (h->nnz_c > 0 && (!c_col_idx || !c_vals)) return fail(h, SPG_ERR_ARG, "null output");
+        if (h->timing) SPG_TRY(make_events(h));
+        h->num_timed = h->timing != 0;
+        std::fill(std::begin(h->num_cls_timed), std::end(h->num_cls_timed), false);
+        rec(h, EV_NUM0);
+        SPG_TRY(num_launch_all(h, a_vals, b_vals, c_col_idx, c_vals, false, dinv, omega));
         rec(h, EV_NUM1);
         return SPG_OK;
     } catch (...) {

@@ -271,6 +271,7 @@ struct Control {
     int32_t b_tile_unordered;     // tiled global path: a B row's entries are not grouped by tile
     int32_t tile_heavy;           // tiled global path: rows of more than TILE_G entries (one unit per tile)
     int32_t tile_light;           // tiled global path: rows of at most TILE_G entries (one unit per row)
+    int32_t a_missing_diag;       // square A: rows without a stored diagonal entry
 };
 
 // ---- launch wrappers (spg_rows.hip) ----
@@ -368,6 +369,8 @@ struct NumArgs {
     const int32_t* lofs;          // per row: first pair of its list, -1 if it has none
     const int2* lists;            // {block, mask} pairs in ascending block order
     const int32_t* count_dev;     // global path: device-side row count (or null)
+    const void* dinv;             // Jacobi-fused product: D^-1 (m values), else null
+    double omega;                 // Jacobi-fused product: the damping factor
 };
 
 // Tiled global path of the numeric phase (spg_accum.hip).  B's columns are
@@ -403,6 +406,8 @@ struct TileArgs {
     Control* ctl;
     int32_t* ccol;
     void* cval;
+    const void* dinv;             // Jacobi-fused product (see NumArgs)
+    double omega;
 };
 
 // Tile offsets of B and the work items (once per symbolic result), then the

@@ -140,10 +140,10 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
                                                    int32_t* __restrict__ row_blocks, int32_t* __restrict__ lofs,
                                                    Control* ctl) {
     __shared__ int32_t hist[NCLS];
-    __shared__ int32_t empties;
+    __shared__ int32_t empties, nodiag;
     __shared__ unsigned long long prod_sum, wmax_all, wmax_glob;
     if (threadIdx.x < NCLS) hist[threadIdx.x] = 0;
-    if (threadIdx.x == 0) empties = 0, prod_sum = 0, wmax_all = 0, wmax_glob = 0;
+    if (threadIdx.x == 0) empties = 0, nodiag = 0, prod_sum = 0, wmax_all = 0, wmax_glob = 0;
     __syncthreads();
     const int lane = (int)(threadIdx.x % AN_LANES);
     const int64_t rows_per_block = blockDim.x / AN_LANES;
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
     for (int64_t rb = blockIdx.x * rows_per_block; rb < m; rb += (int64_t)gridDim.x * rows_per_block) {
         const int64_t row = rb + threadIdx.x / AN_LANES;
         int64_t ub = 0, rs = 0;  // products; compressed-B runs (a bound on occupied blocks)
-        int mx = 0, cmin = INT_MAX, cmax = -1, bad = 0, len = 0;
+        int mx = 0, cmin = INT_MAX, cmax = -1, bad = 0, len = 0, diag = 0;
         if (row < m) {
             int32_t s = arp[row], e = arp[row + 1];
             if (s < 0 || e < s || (int64_t)e > annz || (row == 0 && s != 0) || (row == m - 1 && (int64_t)e != annz)) {
@@ -166,6 +166,7 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
                         const int32_t p = p0 + u * AN_LANES;
                         jj[u] = p < e ? aci[p] : -1;
                         if (p < e && (jj[u] < 0 || jj[u] >= n)) bad = ERR_A_COL, jj[u] = -1;
+                        diag |= jj[u] == row;  // a stored diagonal entry (square A)
                     }
                     int4 bb[AN_LOADS];
     #pragma unroll
@@ -187,7 +188,9 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
         cmin = rowq_min(cmin);
         cmax = rowq_max(cmax);
         int anybad = rowq_or(bad);
+        diag = rowq_or(diag);
         if (bad) atomicOr(&ctl->err, bad);
+        if (row < m && lane == 0 && m == n && !diag) atomicAdd(&nodiag, 1);
         if (row < m && lane == 0) {
             if (anybad) ub = 0;
             int32_t ubc = ub > INT_MAX ? INT_MAX : (int32_t)ub;
@@ -223,6 +226,7 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
     if (threadIdx.x < NCLS && hist[threadIdx.x]) atomicAdd(&ctl->sym_hist[threadIdx.x], hist[threadIdx.x]);
     if (threadIdx.x == 0) {
         if (empties) atomicAdd(&ctl->empty_rows, empties);
+        if (nodiag) atomicAdd(&ctl->a_missing_diag, nodiag);
         if (prod_sum) atomicAdd((unsigned long long*)&ctl->products, prod_sum);
         if (wmax_all) atomicMax((unsigned long long*)&ctl->max_words_all, wmax_all);
         if (wmax_glob) atomicMax((unsigned long long*)&ctl->max_words_sym_global, wmax_glob);

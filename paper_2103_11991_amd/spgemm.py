@@ -123,6 +123,30 @@ class SpGEMM:
         _lib.spg_numeric(self.h, a_vals.data_ptr(), b_vals.data_ptr(), out_col.data_ptr(), out_val.data_ptr())
         return out_col, out_val
 
+    def numeric_jacobi(self, omega: float, dinv: torch.Tensor, a_vals: torch.Tensor | None = None,
+                       b_vals: torch.Tensor | None = None, out_col: torch.Tensor | None = None,
+                       out_val: torch.Tensor | None = None):
+        """C = (I - omega D^-1 A) B on the symbolic result of A*B (A square, its
+        diagonal stored in every row); ``dinv``: the m entries of D^-1."""
+        if self.nnz is None:
+            raise RuntimeError("symbolic() must come first")
+        a_vals = self.A.values if a_vals is None else a_vals
+        b_vals = self.B.values if b_vals is None else b_vals
+        _check_tensor(a_vals, self.dtype, self.A.nnz, "a_vals")
+        _check_tensor(b_vals, self.dtype, self.B.nnz, "b_vals")
+        _check_tensor(dinv, self.dtype, self.A.m, "dinv")
+        dev = self.A.row_ptr.device
+        with torch.cuda.stream(self.stream):
+            if out_col is None:
+                out_col = torch.empty(self.nnz, dtype=torch.int32, device=dev)
+            if out_val is None:
+                out_val = torch.empty(self.nnz, dtype=self.dtype, device=dev)
+        _check_tensor(out_col, torch.int32, self.nnz, "out_col")
+        _check_tensor(out_val, self.dtype, self.nnz, "out_val")
+        _lib.spg_numeric_jacobi(self.h, omega, dinv.data_ptr(), a_vals.data_ptr(), b_vals.data_ptr(),
+                                out_col.data_ptr(), out_val.data_ptr())
+        return out_col, out_val
+
     def stats(self) -> dict:
         st = _lib.spg_get_stats(self.h)
         out = {}
