@@ -341,6 +341,49 @@ spg_status spg_batch_tune(spg_batch b, const void* a_val_pool, const void* b_val
    numeric launches (per-class rows, products, times when timing is on). */
 spg_status spg_batch_get_stats(spg_batch b, spg_stats* out, int32_t size);
 
+/* ---- sparse matrix addition C = alpha*A + beta*B (section 2.3) ----------
+   A and B are m x n CRS matrices; each row of C holds the union of the
+   columns of A(i,:) and B(i,:), in ascending order, with every entry of one
+   column (also repeats inside A's or B's row) added into one value; explicit
+   zeros are kept.  Two phases as for the product: symbolic finds C's row
+   pointer and, for every input entry, the position of its column in C's row
+   (the paper's Apos and Bpos, kept in the handle); numeric scatters the
+   scaled values there and may be called again with new values on the same
+   structures.  Input rows may be unsorted; when both rows are in ascending
+   column order the symbolic phase merges them (the merge network of a
+   bitonic sort), otherwise it sorts them.  A row of A and B together may hold
+   at most 16384 entries (SPG_ERR_UNSUPPORTED beyond). */
+typedef struct spg_add_s* spg_add;
+
+/* Creates an addition handle on `hip_stream` (hipStream_t; NULL = default). */
+spg_status spg_add_create(spg_add* h, void* hip_stream);
+
+/* Waits for the stream and frees the handle's device memory (null accepted). */
+spg_status spg_add_destroy(spg_add h);
+
+/* Message for the last failing call on h. */
+const char* spg_add_last_error(spg_add h);
+
+/* Symbolic phase: A and B structures (borrowed device arrays, which must stay
+   valid and unchanged until the last spg_add_numeric), C's row pointer into
+   the caller's device array c_row_ptr[m+1] (borrowed likewise), nnz(C) into
+   *nnz_c (host).  Waits for the stream once.  SPG_ERR_INDEX for malformed
+   input, SPG_ERR_OVERFLOW if nnz(C) >= 2^31, SPG_ERR_UNSUPPORTED for a row
+   pair of more than 16384 entries, SPG_ERR_ALLOC if the handle's buffers
+   (4 bytes per entry of A and B, 8 per row) cannot be allocated. */
+spg_status spg_add_symbolic(spg_add h, int32_t m, int32_t n, const int32_t* a_row_ptr, const int32_t* a_col_idx,
+                            int64_t a_nnz, const int32_t* b_row_ptr, const int32_t* b_col_idx, int64_t b_nnz,
+                            int32_t* c_row_ptr, int64_t* nnz_c);
+
+/* Numeric phase: c_col_idx[nnz(C)] and c_vals[nnz(C)] (caller's device
+   arrays) from a_vals[a_nnz] and b_vals[b_nnz] (device, type dt); alpha and
+   beta are converted to dt.  Each contribution is rounded once (alpha*a or
+   beta*b) and added at its position, A's contributions before B's; repeats
+   inside a row add in any order.  Asynchronous.  SPG_ERR_STATE without a
+   symbolic result. */
+spg_status spg_add_numeric(spg_add h, spg_dtype dt, double alpha, const void* a_vals, double beta,
+                           const void* b_vals, int32_t* c_col_idx, void* c_vals);
+
 #ifdef __cplusplus
 }
 #endif

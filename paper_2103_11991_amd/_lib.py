@@ -26,7 +26,8 @@ EXPORTS = ["spg_status_string", "spg_last_error", "spg_create", "spg_destroy", "
            "spg_set_matrices", "spg_symbolic", "spg_numeric", "spg_numeric_jacobi", "spg_set_option", "spg_set_mlp", "spg_get_stats",
            "spg_export_rows", "spg_mlp_forward", "spg_mlp_backward", "spg_mlp_backward_noalloc", "spg_mlp_train",
            "spg_batch_create", "spg_batch_destroy", "spg_batch_last_error", "spg_batch_set_option",
-           "spg_batch_set_mlp", "spg_batch_plan", "spg_batch_run", "spg_batch_tune", "spg_batch_get_stats"]
+           "spg_batch_set_mlp", "spg_batch_plan", "spg_batch_run", "spg_batch_tune", "spg_batch_get_stats",
+           "spg_add_create", "spg_add_destroy", "spg_add_last_error", "spg_add_symbolic", "spg_add_numeric"]
 
 
 class SpgError(RuntimeError):
@@ -92,6 +93,11 @@ def load() -> ctypes.CDLL:
         "spg_batch_run": ([p, p, p, p, p, p, i64, i32], ctypes.c_int),
         "spg_batch_tune": ([p, p, p, p, p, p, i64, p, p], ctypes.c_int),
         "spg_batch_get_stats": ([p, ctypes.POINTER(spg_stats), i32], ctypes.c_int),
+        "spg_add_create": ([ctypes.POINTER(p), p], ctypes.c_int),
+        "spg_add_destroy": ([p], ctypes.c_int),
+        "spg_add_last_error": ([p], ctypes.c_char_p),
+        "spg_add_symbolic": ([p, i32, i32, p, p, i64, p, p, i64, p, ctypes.POINTER(i64)], ctypes.c_int),
+        "spg_add_numeric": ([p, ctypes.c_int, ctypes.c_double, p, ctypes.c_double, p, p, p], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -238,3 +244,37 @@ def spg_batch_get_stats(b: int) -> spg_stats:
     st = spg_stats()
     _bcheck(load().spg_batch_get_stats(b, ctypes.byref(st), ctypes.sizeof(spg_stats)), b)
     return st
+
+
+def _acheck(rc: int, h=None):
+    if rc != 0:
+        msg = load().spg_add_last_error(h).decode() if h else ""
+        raise SpgError(rc, msg or (STATUS[rc] if 0 <= rc < len(STATUS) else str(rc)))
+
+
+def spg_add_create(stream: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _acheck(load().spg_add_create(ctypes.byref(h), stream or None))
+    return h.value
+
+
+def spg_add_destroy(h: int) -> None:
+    _acheck(load().spg_add_destroy(h))
+
+
+def spg_add_last_error(h: int) -> str:
+    return load().spg_add_last_error(h).decode()
+
+
+def spg_add_symbolic(h: int, m: int, n: int, a_row_ptr: int, a_col_idx: int, a_nnz: int, b_row_ptr: int,
+                     b_col_idx: int, b_nnz: int, c_row_ptr: int) -> int:
+    nnz = ctypes.c_int64(-1)
+    _acheck(load().spg_add_symbolic(h, m, n, a_row_ptr or None, a_col_idx or None, a_nnz, b_row_ptr or None,
+                                    b_col_idx or None, b_nnz, c_row_ptr or None, ctypes.byref(nnz)), h)
+    return nnz.value
+
+
+def spg_add_numeric(h: int, dtype: int, alpha: float, a_vals: int, beta: float, b_vals: int, c_col_idx: int,
+                    c_vals: int) -> None:
+    _acheck(load().spg_add_numeric(h, dtype, float(alpha), a_vals or None, float(beta), b_vals or None,
+                                   c_col_idx or None, c_vals or None), h)

@@ -166,6 +166,69 @@ class SpGEMM:
         return x, y, r
 
 
+class SpAdd:
+    """Two-phase C = alpha*A + beta*B (section 2.3) bound to one handle and one stream.
+
+        add = SpAdd(A, B)                       # A, B: DeviceCsr of one shape
+        row_ptr, nnz = add.symbolic()           # union of the row patterns
+        col, val = add.numeric(alpha, beta)     # any number of times
+    """
+
+    def __init__(self, A: DeviceCsr, B: DeviceCsr, stream: torch.cuda.Stream | None = None):
+        if (A.m, A.n) != (B.m, B.n):
+            raise ValueError(f"shapes differ: A is {A.m}x{A.n}, B is {B.m}x{B.n}")
+        if A.values.dtype != B.values.dtype:
+            raise TypeError("A and B values must have the same dtype")
+        for t, n, nm in ((A.row_ptr, A.m + 1, "A.row_ptr"), (B.row_ptr, B.m + 1, "B.row_ptr")):
+            _check_tensor(t, torch.int32, n, nm)
+        _check_tensor(A.col_idx, torch.int32, A.nnz, "A.col_idx")
+        _check_tensor(B.col_idx, torch.int32, B.nnz, "B.col_idx")
+        self.A, self.B = A, B
+        self.dtype = A.values.dtype
+        self.stream = stream or torch.cuda.current_stream()
+        self.h = _lib.spg_add_create(self.stream.cuda_stream)
+        self.row_ptr = None
+        self.nnz = None
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            try:
+                _lib.spg_add_destroy(h)
+            except Exception:
+                pass
+            self.h = None
+
+    def symbolic(self):
+        A, B = self.A, self.B
+        with torch.cuda.stream(self.stream):
+            self.row_ptr = torch.empty(A.m + 1, dtype=torch.int32, device=A.row_ptr.device)
+        self.nnz = _lib.spg_add_symbolic(self.h, A.m, A.n, A.row_ptr.data_ptr(), A.col_idx.data_ptr(), A.nnz,
+                                         B.row_ptr.data_ptr(), B.col_idx.data_ptr(), B.nnz, self.row_ptr.data_ptr())
+        return self.row_ptr, self.nnz
+
+    def numeric(self, alpha: float = 1.0, beta: float = 1.0, a_vals: torch.Tensor | None = None,
+                b_vals: torch.Tensor | None = None, out_col: torch.Tensor | None = None,
+                out_val: torch.Tensor | None = None):
+        if self.nnz is None:
+            raise RuntimeError("symbolic() must come first")
+        a_vals = self.A.values if a_vals is None else a_vals
+        b_vals = self.B.values if b_vals is None else b_vals
+        _check_tensor(a_vals, self.dtype, self.A.nnz, "a_vals")
+        _check_tensor(b_vals, self.dtype, self.B.nnz, "b_vals")
+        dev = self.A.row_ptr.device
+        with torch.cuda.stream(self.stream):
+            if out_col is None:
+                out_col = torch.empty(self.nnz, dtype=torch.int32, device=dev)
+            if out_val is None:
+                out_val = torch.empty(self.nnz, dtype=self.dtype, device=dev)
+        _check_tensor(out_col, torch.int32, self.nnz, "out_col")
+        _check_tensor(out_val, self.dtype, self.nnz, "out_val")
+        _lib.spg_add_numeric(self.h, _dtype_code(self.dtype), alpha, a_vals.data_ptr(), beta, b_vals.data_ptr(),
+                             out_col.data_ptr(), out_val.data_ptr())
+        return out_col, out_val
+
+
 def spgemm(A: DeviceCsr, B: DeviceCsr, **options) -> DeviceCsr:
     """One-shot C = A*B (symbolic, then numeric) on the current stream."""
     op = SpGEMM(A, B, **options)
