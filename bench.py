@@ -386,6 +386,115 @@ def batched_vs_loop(count, steps):
             "generation_s": round(gen_s, 1)}
 
 
+def jacobi_fused_vs_unfused(steps, n0=128, omega=2.0 / 3.0):
+    """Prolongator smoothing C = (I - omega D^-1 A) P: A the 7-point Laplacian
+    on n0^3 (FP64), P the 2x2x2 aggregation, D^-1 = 1/6.  Fused: one
+    Jacobi-fused numeric call on the symbolic result of A*P.  Unfused (the
+    three kernels of the paper's comparison): E = A*P, F = D^-1 E (row scaling
+    of E's values), C = P - omega F (sparse addition)."""
+    import torch
+    from paper_2103_11991_amd import gen
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpAdd, SpGEMM
+    A = gen.laplace3d_7pt(n0)
+    P = gen.aggregation_P(n0)
+    dA, dP = DeviceCsr.from_host(A), DeviceCsr.from_host(P)
+    dinv = torch.full((A.m,), 1.0 / 6.0, dtype=torch.float64, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            ev[0].record()
+            fn()
+            ev[1].record()
+            ev[1].synchronize()
+            t.append(ev[0].elapsed_time(ev[1]))
+        return float(np.median(t))
+
+    op = SpGEMM(dA, dP)
+    rp, nnz = op.symbolic()
+    col, val = op.numeric_jacobi(omega, dinv)
+
+    def fused_full():
+        op.symbolic()
+        op.numeric_jacobi(omega, dinv, out_col=col, out_val=val)
+
+    t_fused_num = timed(lambda: op.numeric_jacobi(omega, dinv, out_col=col, out_val=val), steps)
+    t_fused_full = timed(fused_full, steps)
+    # unfused: SpGEMM, row scaling, addition
+    opE = SpGEMM(dA, dP)
+    rpE, nnzE = opE.symbolic()
+    colE, valE = opE.numeric()
+    rowsE = torch.repeat_interleave(torch.arange(A.m, device="cuda"), torch.diff(rpE.long()))
+    F = DeviceCsr(A.m, P.n, rpE, colE, valE.clone())
+    add = SpAdd(dP, F)
+    add.symbolic()
+    colC, valC = add.numeric(1.0, -omega)
+
+    def unfused_num():
+        opE.numeric(out_col=colE, out_val=valE)
+        torch.mul(valE, dinv[rowsE], out=F.values)
+        add.numeric(1.0, -omega, out_col=colC, out_val=valC)
+
+    def unfused_full():
+        opE.symbolic()
+        opE.numeric(out_col=colE, out_val=valE)
+        torch.mul(valE, dinv[rowsE], out=F.values)
+        add.symbolic()
+        add.numeric(1.0, -omega, out_col=colC, out_val=valC)
+
+    t_unf_num = timed(unfused_num, steps)
+    t_unf_full = timed(unfused_full, steps)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(col, colC)) and float((val - valC).abs().max()) <= 1e-12 * 2
+    return {"workload": f"C = (I - {omega:.4g} D^-1 A) P, A = 7-point Laplacian {n0}^3 (FP64), P = 2x2x2 "
+                        f"aggregation ({P.n} columns), D^-1 = 1/6",
+            "rows": A.m, "nnz_c": int(nnz), "multiply_adds": int(op.stats()["products"]),
+            "fused_numeric_ms": round(t_fused_num, 4), "fused_full_ms": round(t_fused_full, 4),
+            "unfused_numeric_ms": round(t_unf_num, 4), "unfused_full_ms": round(t_unf_full, 4),
+            "speedup_numeric": round(t_unf_num / t_fused_num, 3), "speedup_full": round(t_unf_full / t_fused_full, 3),
+            "unfused_kernels": "SpGEMM (this library), row scaling (torch elementwise), SpAdd (this library)",
+            "same_result": same}
+
+
+def spadd_bench(steps, m=1 << 20, per_row=30):
+    """C = A + B for square m x m matrices with `per_row` random columns per
+    row (the paper's SpAdd input), sorted and unsorted rows, FP64: symbolic and
+    numeric times, and the numeric phase's compulsory-byte bandwidth."""
+    import torch
+    from paper_2103_11991_amd import gen
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpAdd
+    out = {"workload": f"C = A + B, {m} x {m}, {per_row} random columns per row of A and of B, FP64"}
+    for label, srt in (("sorted", True), ("unsorted", False)):
+        A = gen.random_csr(m, m, per_row, per_row, seed=21, sorted_rows=srt)
+        B = gen.random_csr(m, m, per_row, per_row, seed=22, sorted_rows=srt)
+        add = SpAdd(DeviceCsr.from_host(A), DeviceCsr.from_host(B))
+        rp, nnz = add.symbolic()
+        col, val = add.numeric(1.0, 1.0)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ts, tn = [], []
+        for _ in range(steps):
+            ev[0].record()
+            add.symbolic()
+            ev[1].record()
+            ev[1].synchronize()
+            ts.append(ev[0].elapsed_time(ev[1]))
+            ev[0].record()
+            add.numeric(1.0, 1.0, out_col=col, out_val=val)
+            ev[1].record()
+            ev[1].synchronize()
+            tn.append(ev[0].elapsed_time(ev[1]))
+        sym, num = float(np.median(ts)), float(np.median(tn))
+        # numeric compulsory bytes: A and B structure, values and positions read, C columns and values written
+        nbytes = (A.nnz + B.nnz) * (4 + 8 + 4) + 2 * (m + 1) * 4 * 2 + (m + 1) * 4 + int(nnz) * 12
+        out[label] = {"nnz_c": int(nnz), "symbolic_ms": round(sym, 4), "numeric_ms": round(num, 4),
+                      "numeric_gbs": round(nbytes / (num * 1e-3) / 1e9, 1),
+                      "numeric_hbm_frac": round(nbytes / (num * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -398,6 +507,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-binning comparison")
     ap.add_argument("--no-rmat", action="store_true", help="skip the R-MAT plain/learned comparison")
     ap.add_argument("--no-galerkin", action="store_true", help="skip the Galerkin chain")
+    ap.add_argument("--no-jacobi", action="store_true", help="skip the Jacobi-fused vs unfused comparison")
+    ap.add_argument("--no-spadd", action="store_true", help="skip the sparse-addition leg")
     ap.add_argument("--opt", action="append", default=[], metavar="NAME=VALUE",
                     help="library option for the timed product (e.g. work_per_lane=32); repeatable")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -507,6 +618,10 @@ def main():
         out["rmat_s18"] = rmat_learned_vs_plain(max(3, args.steps // 2))
     if not args.no_galerkin:
         out["galerkin"] = galerkin_chain()
+    if not args.no_jacobi:
+        out["jacobi_fused_vs_unfused"] = jacobi_fused_vs_unfused(max(3, args.steps // 2))
+    if not args.no_spadd:
+        out["spadd"] = spadd_bench(max(3, args.steps // 2))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(A)
     print(json.dumps(out), flush=True)
