@@ -495,6 +495,65 @@ def spadd_bench(steps, m=1 << 20, per_row=30):
     return out
 
 
+def paper_method_ablation(steps):
+    """The paper's design (one method for the whole matrix, two-level hash
+    maps whose global level a row uses once its LDS level fills;
+    SPG_OPT_METHOD 2 = a 16-lane group per row, 3 = a 256-lane team per row,
+    1 = picked from the products per row) against this library's per-row
+    classes (method 0) on the same products: full product (symbolic +
+    numeric) and numeric alone, median over `steps` after one warm-up (one
+    timed run for the paper's design on R-MAT, which takes seconds).  The
+    paper's numeric leaves rows in hash order; ours emits them sorted."""
+    import torch
+    from paper_2103_11991_amd import gen
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
+    cases = [("2D 5-point 64^2 A*A (FP64)", lambda: (gen.laplace2d_5pt(64),) * 2, steps),
+             ("3D 27-point 100^3 A*A (FP64)", lambda: (gen.stencil27(100, seed=2),) * 2, steps),
+             ("R-MAT scale 18 A*A (FP32, seed 1)", lambda: (gen.rmat(18, seed=1),) * 2, 1),
+             ("7-point 128^3 A*P, 2x2x2 aggregation (FP64)", lambda: (gen.laplace3d_7pt(128), gen.aggregation_P(128)),
+              steps)]
+    out = {}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for name, make, paper_steps in cases:
+        A, B = make()
+        dA = DeviceCsr.from_host(A)
+        dB = dA if B is A else DeviceCsr.from_host(B)
+        rows = int((gen.products_per_row(A, B) > 0).sum())
+        ent = {}
+        for label, method, reps in (("classes", 0, steps), ("paper_group", 2, paper_steps),
+                                    ("paper_team", 3, paper_steps)):
+            op = SpGEMM(dA, dB, method=method)
+            op.symbolic()
+            col, val = op.numeric()
+            torch.cuda.synchronize()
+            full, num = [], []
+            for _ in range(reps):
+                ev[0].record()
+                op.symbolic()
+                op.numeric(out_col=col, out_val=val)
+                ev[1].record()
+                ev[1].synchronize()
+                full.append(ev[0].elapsed_time(ev[1]))
+                ev[0].record()
+                op.numeric(out_col=col, out_val=val)
+                ev[1].record()
+                ev[1].synchronize()
+                num.append(ev[0].elapsed_time(ev[1]))
+            ent[label] = {"full_ms": round(float(np.median(full)), 4), "numeric_ms": round(float(np.median(num)), 4)}
+            if label == "classes":
+                ent["products_per_row"] = round(op.stats()["products"] / max(rows, 1), 1)
+            del op, col, val
+            torch.cuda.synchronize()
+        auto = "paper_team" if ent["products_per_row"] >= 256 else "paper_group"
+        ent["paper_auto"] = auto
+        for lab in ("paper_group", "paper_team"):
+            ent[f"{lab}_slowdown_full"] = round(ent[lab]["full_ms"] / ent["classes"]["full_ms"], 3)
+        out[name] = ent
+        del dA, dB
+        torch.cuda.synchronize()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -509,6 +568,7 @@ def main():
     ap.add_argument("--no-galerkin", action="store_true", help="skip the Galerkin chain")
     ap.add_argument("--no-jacobi", action="store_true", help="skip the Jacobi-fused vs unfused comparison")
     ap.add_argument("--no-spadd", action="store_true", help="skip the sparse-addition leg")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the paper-design ablation")
     ap.add_argument("--opt", action="append", default=[], metavar="NAME=VALUE",
                     help="library option for the timed product (e.g. work_per_lane=32); repeatable")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -622,6 +682,8 @@ def main():
         out["jacobi_fused_vs_unfused"] = jacobi_fused_vs_unfused(max(3, args.steps // 2))
     if not args.no_spadd:
         out["spadd"] = spadd_bench(max(3, args.steps // 2))
+    if not args.no_ablation:
+        out["paper_design_ablation"] = paper_method_ablation(3)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(A)
     print(json.dumps(out), flush=True)

@@ -110,7 +110,17 @@ typedef enum {
        entries are not grouped by tile (rows in ascending column order always
        are), take the segment path (0 = always the segment path: the row's
        values summed one LDS segment of its ranks at a time) */
-    SPG_OPT_TILED_GLOBAL = 11
+    SPG_OPT_TILED_GLOBAL = 11,
+    /* accumulation method of both phases: 0 = this library's per-row classes
+       (default); 1..3 = the paper's design (section 2.2.1), for comparison:
+       one parallelisation method for the whole matrix (1 = chosen from the
+       products per nonempty row: a 16-lane group per row below 256, else a
+       256-lane team per row; 2 = always the group, 3 = always the team) with a
+       two-level hash-map accumulator (LDS, then a global-memory level created
+       when a row's LDS level fills).  With 1..3 the numeric phase leaves each
+       row of C in hash order rather than ascending column order, and
+       spg_numeric_jacobi is not available (SPG_ERR_UNSUPPORTED). */
+    SPG_OPT_METHOD = 12
 } spg_option;
 
 #define SPG_NTIER 10

@@ -17,7 +17,7 @@ SPG_F32, SPG_F64 = 0, 1
 OPT = {
     "binning": 0, "timing": 1, "force_class": 2, "work_per_lane": 3, "mlp_margin_milli": 4,
     "hash_max_blocks": 6, "lds_limit": 7, "keep_features": 8, "list_limit_mb": 9,
-    "merge_classes": 10, "tiled_global": 11,
+    "merge_classes": 10, "tiled_global": 11, "method": 12,
 }
 NTIER, NCLASS = 10, 30
 STATUS = ["SPG_OK", "SPG_ERR_ARG", "SPG_ERR_SHAPE", "SPG_ERR_STATE", "SPG_ERR_INDEX", "SPG_ERR_OVERFLOW",

@@ -74,6 +74,11 @@ __device__ inline int hash_find(const int32_t* keys, int T, int logT, int key) {
     return -1;
 }
 
+// Orders a workgroup's own global-memory accesses (its slab rows, the rows
+// of C it writes): they stay within one compute unit, so workgroup scope is
+// enough, and unlike an agent-scope fence it writes nothing back from L2.
+__device__ inline void wg_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+
 // bits below bit b of a 32-bit mask
 __device__ inline uint32_t below(int b) { return (1u << b) - 1u; }
 
@@ -820,7 +825,7 @@ __device__ void wide_sym_row(const SymArgs& a, int i, uint32_t* masks, int2* off
     const int base = ri.x >> 5;
     const int words = (ri.y >> 5) - base + 1;
     for (int c = tid; c < words; c += G) masks[c] = 0;
-    if (!IN_LDS) __threadfence();
+    if (!IN_LDS) wg_fence();
     __syncthreads();
     int cnt = 0, nb = 0;
     auto load_run = [&](int q, int end) { return load_runs<FLAT_VC_SYM>(a.bc, a.bc_total, q, end); };
@@ -839,7 +844,7 @@ __device__ void wide_sym_row(const SymArgs& a, int i, uint32_t* masks, int2* off
     }
     const int lo = a.lofs[i];
     if (lo >= 0) {  // the row's list, from the masks in word order
-        if (!IN_LDS) __threadfence();
+        if (!IN_LDS) wg_fence();
         __syncthreads();
         int2* out = a.lists + lo;
         const int chunk = (words + G - 1) / G;
@@ -1156,7 +1161,7 @@ __device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int2* off
     for (int c = tid; c < words; c += G) masks[c] = 0;
     if (!in_lds)
         for (int r = tid; r < n; r += G) cv[r] = T(0);
-    __threadfence();
+    wg_fence();
     __syncthreads();
     const int a0 = a.arp[i], a1 = a.arp[i + 1];
     const T* av = reinterpret_cast<const T*>(a.av);
@@ -1166,7 +1171,7 @@ __device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int2* off
     auto orb = [&](int2 run, int) { atomicOr(&masks[run.x - base], (uint32_t)run.y); };
     const int lo = a.lofs[i];
     if (lo >= 0) {  // masks from the row's list, else from compressed B
-        if (!IN_LDS) __threadfence();
+        if (!IN_LDS) wg_fence();
         __syncthreads();
         const int nbk = a.row_blocks[i];
         for (int t = tid; t < nbk; t += G) {
@@ -1177,7 +1182,7 @@ __device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int2* off
         flat_walk<G, FLAT_KC_NUM, FLAT_VC, true, T>(a.aci, a.bhdr, av, a0, a1, off, ava, win, red, load_run,
                                                     each(orb));
     }
-    if (!IN_LDS) __threadfence();
+    if (!IN_LDS) wg_fence();
     __syncthreads();
     {
         const int chunk = (words + G - 1) / G;
@@ -1192,7 +1197,7 @@ __device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int2* off
             ex += __popc(ld_tab<IN_LDS>(&masks[t]));
         }
     }
-    if (!IN_LDS) __threadfence();
+    if (!IN_LDS) wg_fence();
     __syncthreads();
     auto rank_of = [&](int c) {
         const int w = (c >> 5) - base;
@@ -1244,12 +1249,14 @@ __device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int2* off
                                                 for (int j = 0; j < 4; ++j)
                                                     if (j < g.n) atomicAdd(&cv[rk[j]], x * g.y[j]);
                                             });
-        if (a.dinv) {  // Jacobi-fused, in C's own storage
+        if (a.dinv) {  // Jacobi-fused, in C's own storage (summed by atomics in L2: read and written there)
             const T sc = -(T)a.omega * reinterpret_cast<const T*>(a.dinv)[i];
-            __threadfence();
+            wg_fence();
             __syncthreads();
-            for (int r = tid; r < n; r += G) cv[r] *= sc;
-            __threadfence();
+            for (int r = tid; r < n; r += G)
+                __hip_atomic_store(&cv[r], __hip_atomic_load(&cv[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) * sc,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            wg_fence();
             __syncthreads();
             for (int q = a.brp[i] + tid; q < a.brp[i + 1]; q += G) atomicAdd(&cv[rank_of(a.bci[q])], bv[q]);
         }
@@ -1263,7 +1270,7 @@ __device__ void wide_num_row(const NumArgs& a, int i, uint32_t* masks, int2* off
             mk &= mk - 1;
         }
     }
-    __threadfence();
+    wg_fence();
     __syncthreads();
 }
 

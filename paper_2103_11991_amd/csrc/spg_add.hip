@@ -48,6 +48,10 @@ struct AddCtl {
     int64_t nnz_c;
 };
 
+// Orders a wavefront's own global-memory accesses (the C row it writes):
+// workgroup scope is enough and writes nothing back from L2.
+__device__ inline void wg_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -405,14 +409,14 @@ __global__ __launch_bounds__(WAVE * ROWS_PER_WG) void k_add_num(int32_t m, const
         const bool in_lds = nc <= MID_CAP;
         T* dst = in_lds ? s : cv;
         for (int r = lane; r < nc; r += WAVE) dst[r] = T(0);
-        if (!in_lds) __threadfence();
+        if (!in_lds) wg_fence();
         wave_sync();
         for (int t = as + lane; t < ae; t += WAVE) {
             const int p = apos[t];
             cc[p] = aci[t];
             atomicAdd(&dst[p], alpha * av[t]);
         }
-        if (!in_lds) __threadfence();
+        if (!in_lds) wg_fence();
         wave_sync();
         for (int t = bs + lane; t < be; t += WAVE) {
             const int p = bpos[t];

@@ -63,12 +63,13 @@ struct spg_handle_s {
     int64_t list_limit_mb = 8192;
     int merge_classes = 1;
     int tiled_global = 1;
+    int method = 0;            // 0: per-row classes; 1..3: the paper's design (auto, vector, team)
     bool have_mlp = false;
 
     // scratch
     DevBuf binfo, rinfo, feats, sym_cls, num_cls, perm_sym, perm_num, desc_sym, desc_num, row_nnz, row_blocks,
         tile_status, cursor,
-        ovf_list, ctl, slab_sym, slab_retry, slab_num, mlp_w, bcrp, bc, bhdr, lofs, lists, toff, titems, tfb;
+        ovf_list, ctl, slab_sym, slab_retry, slab_num, mlp_w, bcrp, bc, bhdr, lofs, lists, toff, titems, tfb, slab_paper;
     Control* hctl = nullptr;  // pinned host copy
     hipEvent_t ev_ctl = nullptr;  // marks the copy of the control block after the row-pointer scan
 
@@ -81,6 +82,9 @@ struct spg_handle_s {
     int32_t num_off[NCLS] = {};
     int64_t slab_num_words = 0;
     int nslab_num = 0;
+    bool paper_team = false;   // the paper's design: team method (else vector method)
+    int paper_grid = 0;
+    int64_t paper_sym_slots = 0, paper_num_slots = 0;
     bool tiled = false;        // the numeric global class runs on the tiled path
     bool tiled_built = false;  // its tile offsets and items exist for this symbolic result
     int ntiles = 0;
@@ -364,17 +368,50 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr, bool read_back = fal
         for (int c = 0; c < NCLS; ++c) off[c] = run, run += sym_hist[c];
     }
     const int grid_cap = 2 * h->n_cu;
+    if (h->method) {
+        // the paper's design: one method for the whole matrix, two-level hash maps
+        const int64_t rows = std::max<int64_t>(1, (int64_t)m - hc.empty_rows);
+        h->paper_team = h->method == 3 || (h->method == 1 && hc.products >= (int64_t)PAPER_TEAM_PRODUCTS * rows);
+        const int rpw = paper_rows_per_wg(h->paper_team);
+        // as many workgroups as the LDS of the chip holds at once (a team's
+        // maps take ~37 KB, a group workgroup's ~25-49 KB)
+        h->paper_grid = (int)std::min<int64_t>(((int64_t)m + rpw - 1) / rpw, (int64_t)h->n_cu * (h->paper_team ? 4 : 3));
+        auto slots = [](int64_t bound) {
+            int64_t s = 16;
+            while (s < 2 * bound) s <<= 1;
+            return s;
+        };
+        h->paper_sym_slots = slots(std::min<int64_t>(hc.max_products, hc.max_words_all));
+        h->paper_num_slots = slots(std::min<int64_t>(hc.max_products, 32 * hc.max_words_all));
+        // level-2 regions (symbolic: keys, masks, used; numeric: keys, used,
+        // 8-byte values), zero when allocated and left zero by every row
+        const int64_t per = std::max(3 * h->paper_sym_slots, 4 * h->paper_num_slots);
+        const size_t bytes = (size_t)h->paper_grid * rpw * per * 4;
+        const void* before = h->slab_paper.p;
+        SPG_TRY(ensure(h, h->slab_paper, bytes));
+        if (h->slab_paper.p != before) launch_fill_u8(s, h->slab_paper.p, 0, h->slab_paper.cap);
+        PaperLaunch p{};
+        p.m = m, p.team = h->paper_team, p.grid = h->paper_grid;
+        p.arp = h->arp, p.aci = h->aci, p.brp = h->brp, p.bci = h->bci;
+        p.bc = h->bc.as<int2>(), p.bhdr = h->bhdr.as<int4>(), p.rinfo = h->rinfo.as<RowInfo>();
+        p.row_nnz = h->row_nnz.as<int32_t>(), p.row_blocks = h->row_blocks.as<int32_t>();
+        p.slab = h->slab_paper.as<int32_t>(), p.slab_slots = h->paper_sym_slots;
+        rec(h, EV_SYMCLS);
+        launch_paper(s, p, false, h->dt == SPG_F64 ? 8 : 4, h->n_cu);
+        rec(h, EV_SYMCLS + 1);
+        h->sym_cls_timed[0] = h->timing == 1;
+    }
     uint32_t* slab = nullptr;
     int64_t slab_words = 0;
     const int gcls = MODE_DIRECT * NTIER + TIER_GLOBAL;
-    if (sym_hist[gcls] > 0 && hc.max_words_sym_global * 4 > wl) {
+    if (!h->method && sym_hist[gcls] > 0 && hc.max_words_sym_global * 4 > wl) {
         slab_words = (hc.max_words_sym_global + 63) & ~(int64_t)63;
         int ns = std::min(sym_hist[gcls], grid_cap);
         SPG_TRY(ensure(h, h->slab_sym, (size_t)ns * slab_words * 4));
         slab = h->slab_sym.as<uint32_t>();
     }
     for (int c = 0; c < NCLS; ++c) {
-        if (!sym_hist[c]) continue;
+        if (!sym_hist[c] || h->method) continue;
         SymArgs a{};
         a.perm = h->perm_sym.as<int32_t>() + off[c];
         a.desc = h->desc_sym.as<int4>() + off[c];
@@ -400,7 +437,7 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr, bool read_back = fal
         rec(h, EV_SYMCLS + 2 * c + 1);
         h->sym_cls_timed[c] = h->timing == 1;
     }
-    if (learned) {
+    if (learned && !h->method) {
         // exact retry of overflowed rows on the global path (row count read on the device)
         SymArgs a{};
         a.perm = h->ovf_list.as<int32_t>();
@@ -468,7 +505,7 @@ spg_status sym_finish(spg_handle h, int32_t* c_row_ptr) {
     const int grid_cap = 2 * h->n_cu;
     h->slab_num_words = 0;
     h->nslab_num = std::min(std::max(h->num_hist[gcls], 0), grid_cap);
-    if (h->num_hist[gcls] > 0 && hc2.max_words_num_global * 8 > wide_lds(h)) {
+    if (!h->method && h->num_hist[gcls] > 0 && hc2.max_words_num_global * 8 > wide_lds(h)) {
         h->slab_num_words = 2 * ((hc2.max_words_num_global + 63) & ~(int64_t)63);
         SPG_TRY(ensure(h, h->slab_num, (size_t)h->nslab_num * h->slab_num_words * 4));
     }
@@ -476,7 +513,7 @@ spg_status sym_finish(spg_handle h, int32_t* c_row_ptr) {
     // by the first numeric call on this symbolic result
     h->tiled = false;
     h->tiled_built = false;
-    if (h->tiled_global && h->num_hist[gcls] > 0) {
+    if (h->tiled_global && !h->method && h->num_hist[gcls] > 0) {
         const int64_t w = tile_cols(h->dt == SPG_F64 ? 8 : 4);
         const int64_t T = (h->k + w - 1) / w;
         if (T >= 1 && T <= TILE_MAX) {
@@ -570,6 +607,28 @@ spg_status num_launch_all(spg_handle h, const void* a_vals, const void* b_vals, 
                           bool build_tiles = false, const void* dinv = nullptr, double omega = 0.0) {
     hipStream_t s = h->stream;
     const int eb = h->dt == SPG_F64 ? 8 : 4;
+    if (h->method) {
+        if (dinv) return fail(h, SPG_ERR_UNSUPPORTED, "the Jacobi-fused product runs on the per-row classes only");
+        PaperLaunch p{};
+        p.m = h->m, p.team = h->paper_team, p.grid = h->paper_grid;
+        p.arp = h->arp, p.aci = h->aci, p.av = a_vals, p.brp = h->brp, p.bci = h->bci, p.bv = b_vals;
+        p.rinfo = h->rinfo.as<RowInfo>(), p.crp = h->crp, p.ccol = c_col_idx, p.cval = c_vals;
+        p.slab = h->slab_paper.as<int32_t>(), p.slab_slots = h->paper_num_slots;
+        const int set = h->num_set;
+        if (h->timing) {
+            resolve_num(h, set, 0);
+            (void)hipEventRecord(h->ev[num_ev(set, 0)], s);
+        }
+        launch_paper(s, p, true, eb, h->n_cu);
+        if (h->timing) {
+            (void)hipEventRecord(h->ev[num_ev(set, 0) + 1], s);
+            h->num_cls_timed[0] = true;
+            h->num_pending[set][0] = true;
+            h->num_last_set = h->num_set, h->num_set ^= 1;
+        }
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? SPG_OK : hip_fail(h, e, "numeric launch");
+    }
     for (int c = 0; c < NCLS; ++c) {
         if (!h->num_hist[c]) continue;
         NumArgs a{};
@@ -665,7 +724,7 @@ spg_status spg_destroy(spg_handle h) {
                       &h->desc_sym, &h->desc_num,
                       &h->row_nnz, &h->row_blocks, &h->tile_status, &h->cursor, &h->ovf_list, &h->ctl,
                       &h->slab_sym, &h->slab_retry, &h->slab_num, &h->mlp_w, &h->bcrp, &h->bc, &h->bhdr,
-                      &h->lofs, &h->lists, &h->toff, &h->titems, &h->tfb};
+                      &h->lofs, &h->lists, &h->toff, &h->titems, &h->tfb, &h->slab_paper};
     for (DevBuf* b : bufs) release(*b, h->stream);
     if (h->hctl) (void)hipHostFree(h->hctl);
     if (h->ev_made)
@@ -833,6 +892,10 @@ spg_status spg_set_option(spg_handle h, int32_t opt, int64_t val) {
         case SPG_OPT_KEEP_FEATURES: h->keep_features = val != 0; break;
         case SPG_OPT_MERGE_CLASSES: h->merge_classes = val != 0; break;
         case SPG_OPT_TILED_GLOBAL: h->tiled_global = val != 0; break;
+        case SPG_OPT_METHOD:
+            if (val < 0 || val > 3) return fail(h, SPG_ERR_ARG, "method must be 0..3");
+            h->method = (int)val;
+            break;
         case SPG_OPT_LIST_LIMIT_MB:
             if (val < 1 || val > 16383) return fail(h, SPG_ERR_ARG, "list memory limit must be 1..16383 MiB");
             h->list_limit_mb = val;

@@ -272,6 +272,7 @@ struct Control {
     int32_t tile_heavy;           // tiled global path: rows of more than TILE_G entries (one unit per tile)
     int32_t tile_light;           // tiled global path: rows of at most TILE_G entries (one unit per row)
     int32_t a_missing_diag;       // square A: rows without a stored diagonal entry
+    int64_t max_products;         // most products of one row
 };
 
 // ---- launch wrappers (spg_rows.hip) ----
@@ -409,6 +410,34 @@ struct TileArgs {
     const void* dinv;             // Jacobi-fused product (see NumArgs)
     double omega;
 };
+
+// The paper's design (spg_paper.hip): one method for the whole matrix (a
+// 16-lane group or a 256-lane team per row) with a two-level hash-map
+// accumulator (LDS, then global memory created when a row needs it).
+constexpr int PAPER_TEAM_PRODUCTS = 256;  // team method from this many products per nonempty row
+struct PaperLaunch {
+    int32_t m;
+    int32_t team;
+    int32_t grid;
+    const int32_t* arp;
+    const int32_t* aci;
+    const void* av;
+    const int32_t* brp;
+    const int32_t* bci;
+    const void* bv;
+    const int2* bc;
+    const int4* bhdr;
+    const RowInfo* rinfo;
+    int32_t* row_nnz;
+    int32_t* row_blocks;
+    const int32_t* crp;
+    int32_t* ccol;
+    void* cval;
+    int32_t* slab;          // level-2 tables: grid * rows per workgroup of them
+    int64_t slab_slots;     // slots of each
+};
+__host__ __device__ inline int paper_rows_per_wg(bool team) { return team ? 1 : 16; }
+int launch_paper(hipStream_t s, const PaperLaunch& p, bool numeric, int elem_bytes, int n_cu);
 
 // Tile offsets of B and the work items (once per symbolic result), then the
 // tiled numeric launch; returns the grid used.

@@ -141,9 +141,9 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
                                                    Control* ctl) {
     __shared__ int32_t hist[NCLS];
     __shared__ int32_t empties, nodiag;
-    __shared__ unsigned long long prod_sum, wmax_all, wmax_glob;
+    __shared__ unsigned long long prod_sum, wmax_all, wmax_glob, pmax;
     if (threadIdx.x < NCLS) hist[threadIdx.x] = 0;
-    if (threadIdx.x == 0) empties = 0, nodiag = 0, prod_sum = 0, wmax_all = 0, wmax_glob = 0;
+    if (threadIdx.x == 0) empties = 0, nodiag = 0, prod_sum = 0, wmax_all = 0, wmax_glob = 0, pmax = 0;
     __syncthreads();
     const int lane = (int)(threadIdx.x % AN_LANES);
     const int64_t rows_per_block = blockDim.x / AN_LANES;
@@ -212,6 +212,7 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
                 lofs[row] = list_capacity(rs, words);
                 atomicMax(&wmax_all, (unsigned long long)words);
                 atomicAdd(&prod_sum, (unsigned long long)ub);
+                atomicMax(&pmax, (unsigned long long)ub);
                 if (binning != 1) {
                     cls = sym_class(ub, cmin, cmax, binning == 2 ? rs : ub, cfg, true);
                     sym_cls[row] = (uint8_t)cls;
@@ -229,6 +230,7 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
         if (nodiag) atomicAdd(&ctl->a_missing_diag, nodiag);
         if (prod_sum) atomicAdd((unsigned long long*)&ctl->products, prod_sum);
         if (wmax_all) atomicMax((unsigned long long*)&ctl->max_words_all, wmax_all);
+        if (pmax) atomicMax((unsigned long long*)&ctl->max_products, pmax);
         if (wmax_glob) atomicMax((unsigned long long*)&ctl->max_words_sym_global, wmax_glob);
     }
 }
