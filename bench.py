@@ -348,6 +348,25 @@ def batched_vs_loop(count, steps):
         ev[1].record(batch.stream)
         ev[1].synchronize()
         numeric_times.append(ev[0].elapsed_time(ev[1]))
+    # the persistent queued kernel: both phases of every product, C space from
+    # the device bump allocator, per-product device time stamps (100 MHz clock)
+    batch.run_queued(int(batch.nnz))
+    torch.cuda.synchronize()
+    q_times, spans, from_launch = [], [], []
+    for _ in range(steps):
+        ev[0].record(batch.stream)
+        batch.run_queued(int(batch.nnz))
+        ev[1].record(batch.stream)
+        ev[1].synchronize()
+        q_times.append(ev[0].elapsed_time(ev[1]))
+        st_ = batch.q_stamps.cpu().numpy().reshape(-1, 2).astype(np.float64)
+        busy = st_[:, 1] > 0
+        spans.append((st_[busy, 1] - st_[busy, 0]) / 1e5)
+        from_launch.append((st_[busy, 1] - st_[busy, 0].min()) / 1e5)
+    q_ok = bool((batch.q_offsets.cpu().numpy() >= 0).all())
+    t_queued = float(np.median(q_times))
+    spans = np.concatenate(spans)
+    from_launch = np.concatenate(from_launch)
     st = batch.stats()
     products = st["products"]
     # loop of plain launches: every product symbolic + numeric + synchronise
@@ -381,6 +400,18 @@ def batched_vs_loop(count, steps):
             "batched_latency_ms": round(t_batch, 3),
             "batched_latency_note": "all products complete with the single graph launch: each product's "
                                     "latency from launch is the batch time",
+            "queued_ms": round(t_queued, 3),
+            "queued_gflops": round(2.0 * products / (t_queued * 1e-3) / 1e9, 2),
+            "queued_speedup_vs_graph": round(t_batch / t_queued, 3),
+            "queued_speedup_vs_loop": round(t_loop / t_queued, 2),
+            "queued_all_fitted": q_ok,
+            "queued_product_span_p50_ms": round(float(np.percentile(spans, 50)), 4),
+            "queued_product_span_p99_ms": round(float(np.percentile(spans, 99)), 4),
+            "queued_product_done_from_first_start_p50_ms": round(float(np.percentile(from_launch, 50)), 4),
+            "queued_product_done_from_first_start_p99_ms": round(float(np.percentile(from_launch, 99)), 4),
+            "queued_latency_note": "device clock per product: span = first work item start to last work item "
+                                   "end; done-from-first-start = last item end minus the earliest item start "
+                                   "of the run",
             "autotuned": {"work_per_lane": chosen[0], "binning": chosen[1], "hash_max_blocks": chosen[2],
                           "best_full_run_ms": round(tuned_ms, 3)},
             "generation_s": round(gen_s, 1)}

@@ -347,6 +347,32 @@ spg_status spg_batch_tune(spg_batch b, const void* a_val_pool, const void* b_val
                           int32_t* c_row_ptr, int32_t* c_col, void* c_val, int64_t capacity,
                           int32_t* chosen, float* best_ms);
 
+/* Both phases of every product in one persistent kernel over a device work
+   queue, with no host work between the products (section 3: many small
+   operations in one dispatch; section 2.2.2: launch latency).  Work items
+   are (product, block of 64 rows, phase); a product's symbolic items
+   compute its row sizes, the last of them to finish scans the product's
+   row pointer (a segmented scan over the batch), takes the product's C
+   space from a device bump allocator over the caller's pools and queues the
+   product's numeric items.  Needs no spg_batch_plan; the first call runs
+   one synchronised analysis of the batch (then the kernel is captured into
+   a graph, replayed while the pointers and capacity stay the same) and
+   returns SPG_ERR_UNSUPPORTED if a row of some C_i spans more than 4096
+   columns (spg_batch_run has no such limit).  Asynchronous.
+     c_row_ptr: device int32 pool of sum_i (m_i + 1) entries: C_i's row
+       pointer at entry sum_{j<i} (m_j + 1), holding offsets into c_col and
+       c_val (so C_i's entries are [c_row_ptr_i[0], c_row_ptr_i[m_i]));
+     c_col, c_val: device pools of `capacity` entries, handed out to the
+       products in the order their symbolic items finish;
+     c_offsets: device int64[count]: C_i's first pool entry, or -1 if C_i
+       did not fit in the pools (its numeric phase is skipped and its row
+       pointer block left unwritten);
+     stamps: device int64[2 * count] or NULL: per product the device clock
+       (wall_clock64, 100 MHz) when its first work item started and when its
+       last ended. */
+spg_status spg_batch_run_queued(spg_batch b, const void* a_val_pool, const void* b_val_pool, int32_t* c_row_ptr,
+                                int32_t* c_col, void* c_val, int64_t capacity, int64_t* c_offsets, int64_t* stamps);
+
 /* Statistics of the batch's last planned or tuned symbolic run and of its
    numeric launches (per-class rows, products, times when timing is on). */
 spg_status spg_batch_get_stats(spg_batch b, spg_stats* out, int32_t size);

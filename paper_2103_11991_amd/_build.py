@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libspg.so")
-SOURCES = ["spg_rows.hip", "spg_accum.hip", "spg_mlp.hip", "spg_capi.hip", "spg_add.hip", "spg_paper.hip"]
+SOURCES = ["spg_rows.hip", "spg_accum.hip", "spg_mlp.hip", "spg_capi.hip", "spg_add.hip", "spg_paper.hip", "spg_queue.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

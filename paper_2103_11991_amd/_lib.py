@@ -27,6 +27,7 @@ EXPORTS = ["spg_status_string", "spg_last_error", "spg_create", "spg_destroy", "
            "spg_export_rows", "spg_mlp_forward", "spg_mlp_backward", "spg_mlp_backward_noalloc", "spg_mlp_train",
            "spg_batch_create", "spg_batch_destroy", "spg_batch_last_error", "spg_batch_set_option",
            "spg_batch_set_mlp", "spg_batch_plan", "spg_batch_run", "spg_batch_tune", "spg_batch_get_stats",
+           "spg_batch_run_queued",
            "spg_add_create", "spg_add_destroy", "spg_add_last_error", "spg_add_symbolic", "spg_add_numeric"]
 
 
@@ -93,6 +94,7 @@ def load() -> ctypes.CDLL:
         "spg_batch_run": ([p, p, p, p, p, p, i64, i32], ctypes.c_int),
         "spg_batch_tune": ([p, p, p, p, p, p, i64, p, p], ctypes.c_int),
         "spg_batch_get_stats": ([p, ctypes.POINTER(spg_stats), i32], ctypes.c_int),
+        "spg_batch_run_queued": ([p, p, p, p, p, p, i64, p, p], ctypes.c_int),
         "spg_add_create": ([ctypes.POINTER(p), p], ctypes.c_int),
         "spg_add_destroy": ([p], ctypes.c_int),
         "spg_add_last_error": ([p], ctypes.c_char_p),
@@ -238,6 +240,12 @@ def spg_batch_tune(b: int, a_val_pool: int, b_val_pool: int, c_row_ptr: int, c_c
     _bcheck(load().spg_batch_tune(b, a_val_pool or None, b_val_pool or None, c_row_ptr, c_col or None, c_val or None,
                                   capacity, chosen, ctypes.byref(best)), b)
     return list(chosen), best.value
+
+
+def spg_batch_run_queued(b: int, a_val_pool: int, b_val_pool: int, c_row_ptr: int, c_col: int, c_val: int,
+                         capacity: int, c_offsets: int, stamps: int = 0) -> None:
+    _bcheck(load().spg_batch_run_queued(b, a_val_pool or None, b_val_pool or None, c_row_ptr or None, c_col or None,
+                                        c_val or None, capacity, c_offsets or None, stamps or None), b)
 
 
 def spg_batch_get_stats(b: int) -> spg_stats:

@@ -1002,6 +1002,15 @@ struct spg_batch_s {
     void* g_cval = nullptr;
     int g_numeric_only = -1;
     std::string err_msg;
+    // queued path: per-product tables (built once), the work queue, and its captured graph
+    bool q_ready = false;
+    int q_wmax = 0, q_vmax = 0, q_grid = 0;
+    int64_t q_items = 0;
+    DevBuf q_item_off, q_row_off, q_crp_off, q_ctl, q_left, q_queue, q_bm;
+    hipGraph_t q_graph = nullptr;
+    hipGraphExec_t q_exec = nullptr;
+    const void* qg_key[7] = {};
+    int64_t qg_cap = -1;
 };
 
 namespace {
@@ -1023,6 +1032,72 @@ void drop_graph(spg_batch b) {
 __global__ void k_copy_i32(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         dst[i] = src[i];
+}
+
+void drop_queue_graph(spg_batch b) {
+    if (b->q_exec) (void)hipStreamSynchronize(b->stream);
+    if (b->q_exec) (void)hipGraphExecDestroy(b->q_exec);
+    if (b->q_graph) (void)hipGraphDestroy(b->q_graph);
+    b->q_exec = nullptr;
+    b->q_graph = nullptr;
+}
+
+constexpr int QUEUE_ROWS_PER_ITEM = 64;
+
+// Once per batch: the row facts of the packed product (one synchronised
+// analysis), the widest row's range (which sizes the kernel's LDS windows, or
+// rules the queued path out), and the per-product item, row and row-pointer
+// offsets.
+spg_status queue_prepare(spg_batch b) {
+    if (b->q_ready) return SPG_OK;
+    spg_handle h = b->h;
+    SPG_TRY(sym_prepare(h));
+    sym_stage_analysis(h);
+    SPG_TRY(sync_ctl(h));
+    SPG_TRY(check_input_errors(h));
+    const Control c = *h->hctl;
+    if (c.max_words_all > QUEUE_MAX_WORDS)
+        return bfail(b, SPG_ERR_UNSUPPORTED,
+                     "a row of C spans " + std::to_string(c.max_words_all * 32) +
+                         " columns; the queued kernel holds rows of up to " + std::to_string(QUEUE_MAX_WORDS * 32) +
+                         " (use spg_batch_run)");
+    // compressed B for the symbolic items (the structure is fixed: built once)
+    SPG_TRY(ensure(h, h->bc, (size_t)std::max<int64_t>(c.bc_total, 1) * sizeof(int2)));
+    launch_compress_b(b->stream, h->n, h->brp, h->bci, h->binfo.as<int4>(), h->bcrp.as<int32_t>(),
+                      h->tile_status.as<uint64_t>(), &h->ctl.as<Control>()->tile_counter_b, h->bc.as<int2>(),
+                      h->bhdr.as<int4>());
+    b->q_wmax = (int)std::max<int64_t>(c.max_words_all, 1);
+    b->q_vmax = 32 * b->q_wmax;
+    const int32_t cnt = b->count;
+    std::vector<int64_t> item_off((size_t)cnt + 1, 0), crp_off((size_t)std::max(cnt, 1), 0);
+    int64_t crp = 0;
+    for (int32_t p = 0; p < cnt; ++p) {
+        const int64_t m = b->row_off[p + 1] - b->row_off[p];
+        item_off[p + 1] = item_off[p] + (m + QUEUE_ROWS_PER_ITEM - 1) / QUEUE_ROWS_PER_ITEM;
+        crp_off[p] = crp;
+        crp += m + 1;
+    }
+    b->q_items = item_off[cnt];
+    SPG_TRY(ensure(h, b->q_item_off, ((size_t)cnt + 1) * 8));
+    SPG_TRY(ensure(h, b->q_row_off, ((size_t)cnt + 1) * 8));
+    SPG_TRY(ensure(h, b->q_crp_off, (size_t)std::max(cnt, 1) * 8));
+    SPG_TRY(ensure(h, b->q_ctl, sizeof(QueueCtl)));
+    SPG_TRY(ensure(h, b->q_left, (size_t)std::max(cnt, 1) * 4));
+    SPG_TRY(ensure(h, b->q_queue, (size_t)std::max<int64_t>(b->q_items, 1) * 8));
+    // the rows' bitmaps from symbolic to numeric, when they take at most 4 GiB
+    const int64_t bm_bytes = b->m_total * b->q_wmax * 4;
+    if (bm_bytes <= (int64_t)4 << 30) SPG_TRY(ensure(h, b->q_bm, (size_t)std::max<int64_t>(bm_bytes, 4)));
+    HIP_TRY(h, hipMemcpyAsync(b->q_item_off.p, item_off.data(), item_off.size() * 8, hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(h, hipMemcpyAsync(b->q_row_off.p, b->row_off.data(), ((size_t)cnt + 1) * 8, hipMemcpyHostToDevice,
+                              b->stream));
+    HIP_TRY(h, hipMemcpyAsync(b->q_crp_off.p, crp_off.data(), crp_off.size() * 8, hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(h, hipStreamSynchronize(b->stream));
+    // as many workgroups as the compute units' LDS holds at once (at most 8 each)
+    const size_t lds = queue_lds_bytes(b->q_wmax, b->q_vmax, b->dt == SPG_F64 ? 8 : 4);
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (size_t)h->max_lds / std::max<size_t>(lds, 1)));
+    b->q_grid = h->n_cu * per_cu;
+    b->q_ready = true;
+    return SPG_OK;
 }
 
 // one synchronised symbolic run on the packed product: geometry, nnz, offsets
@@ -1143,7 +1218,9 @@ spg_status spg_batch_destroy(spg_batch b) {
     if (!b) return SPG_OK;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     drop_graph(b);
-    DevBuf* bufs[] = {&b->arp, &b->aci, &b->brp, &b->desc, &b->err, &b->crp_plan};
+    drop_queue_graph(b);
+    DevBuf* bufs[] = {&b->arp, &b->aci, &b->brp, &b->desc, &b->err, &b->crp_plan, &b->q_item_off, &b->q_row_off,
+                      &b->q_crp_off, &b->q_ctl, &b->q_left, &b->q_queue, &b->q_bm};
     for (DevBuf* x : bufs) release(*x, b->stream);
     if (b->h) spg_destroy(b->h);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
@@ -1303,6 +1380,62 @@ spg_status spg_batch_tune(spg_batch b, const void* a_val_pool, const void* b_val
         if (chosen) chosen[0] = bw, chosen[1] = bv, chosen[2] = bh;
         if (best_ms) *best_ms = best;
         return batch_replan(b);
+    } catch (...) {
+        return bfail(b, SPG_ERR_HIP, "host exception");
+    }
+}
+
+spg_status spg_batch_run_queued(spg_batch b, const void* a_val_pool, const void* b_val_pool, int32_t* c_row_ptr,
+                                int32_t* c_col, void* c_val, int64_t capacity, int64_t* c_offsets, int64_t* stamps) {
+    if (!b) return SPG_ERR_ARG;
+    try {
+        if (!c_row_ptr || !c_offsets || capacity < 0 || (capacity > 0 && (!c_col || !c_val)) ||
+            (b->annz_total > 0 && !a_val_pool) || (b->bnnz_total > 0 && !b_val_pool))
+            return bfail(b, SPG_ERR_ARG, "null pointer or negative capacity");
+        spg_handle h = b->h;
+        SPG_TRY(queue_prepare(b));
+        if (b->count == 0) return SPG_OK;
+        const void* key[7] = {a_val_pool, b_val_pool, c_row_ptr, c_col, c_val, c_offsets, stamps};
+        const bool same = b->q_exec && std::equal(std::begin(key), std::end(key), std::begin(b->qg_key)) &&
+                          b->qg_cap == capacity;
+        if (!same) {
+            drop_queue_graph(b);
+            QueueArgs a{};
+            a.count = b->count;
+            a.rb = QUEUE_ROWS_PER_ITEM;
+            a.n_items = b->q_items;
+            a.item_off = b->q_item_off.as<int64_t>();
+            a.row_off = b->q_row_off.as<int64_t>();
+            a.crp_off = b->q_crp_off.as<int64_t>();
+            a.arp = b->arp.as<int32_t>(), a.aci = b->aci.as<int32_t>(), a.av = a_val_pool;
+            a.brp = b->brp.as<int32_t>(), a.bci = b->bci_pool, a.bv = b_val_pool;
+            a.rinfo = h->rinfo.as<RowInfo>();
+            a.row_nnz = h->row_nnz.as<int32_t>();
+            a.c_row_ptr = c_row_ptr, a.ccol = c_col, a.cval = c_val, a.cap = capacity;
+            a.c_offsets = c_offsets, a.stamps = stamps;
+            a.qc = b->q_ctl.as<QueueCtl>();
+            a.sym_left = b->q_left.as<int32_t>();
+            a.queue = b->q_queue.as<int64_t>();
+            a.wmax = b->q_wmax, a.vmax = b->q_vmax;
+            a.qbm = b->q_bm.p ? b->q_bm.as<uint32_t>() : nullptr;
+            a.bc = h->bc.as<int2>(), a.bhdr = h->bhdr.as<int4>();
+            HIP_TRY(h, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            launch_queue(b->stream, a, b->dt == SPG_F64 ? 8 : 4, b->q_grid);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(b->stream, &g);
+            if (e != hipSuccess) return bfail(b, SPG_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+            b->q_graph = g;
+            e = hipGraphInstantiate(&b->q_exec, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                drop_queue_graph(b);
+                return bfail(b, SPG_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+            }
+            std::copy(std::begin(key), std::end(key), std::begin(b->qg_key));
+            b->qg_cap = capacity;
+        }
+        hipError_t e = hipGraphLaunch(b->q_exec, b->stream);
+        if (e != hipSuccess) return bfail(b, SPG_ERR_HIP, std::string("graph launch: ") + hipGetErrorString(e));
+        return SPG_OK;
     } catch (...) {
         return bfail(b, SPG_ERR_HIP, "host exception");
     }

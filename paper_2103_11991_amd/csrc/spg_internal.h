@@ -439,6 +439,49 @@ struct PaperLaunch {
 __host__ __device__ inline int paper_rows_per_wg(bool team) { return team ? 1 : 16; }
 int launch_paper(hipStream_t s, const PaperLaunch& p, bool numeric, int elem_bytes, int n_cu);
 
+// Batched products through one persistent kernel over a device work queue
+// (spg_queue.hip).
+struct QueueCtl {
+    int64_t head;   // next queue slot to take
+    int64_t tail;   // numeric slots appended so far
+    int64_t used;   // entries of the C pools handed out (bump allocator)
+    int64_t pad;    // nonzero if a numeric slot never filled (a wait gave up)
+};
+struct QueueArgs {
+    int32_t count;              // products
+    int32_t rb;                 // rows per work item
+    int64_t n_items;            // symbolic items (as many numeric ones)
+    const int64_t* item_off;    // count + 1: first symbolic item of each product
+    const int64_t* row_off;     // count + 1: first packed row of each product
+    const int64_t* crp_off;     // count: first entry of each product's row-pointer block (sum of m_q + 1)
+    const int32_t* arp;
+    const int32_t* aci;
+    const void* av;
+    const int32_t* brp;
+    const int32_t* bci;
+    const void* bv;
+    const RowInfo* rinfo;
+    int32_t* row_nnz;
+    int32_t* c_row_ptr;
+    int32_t* ccol;
+    void* cval;
+    int64_t cap;                // entries of the C pools
+    int64_t* c_offsets;         // count: each product's first pool entry, -1 if it did not fit
+    int64_t* stamps;            // 2 * count or null: first start, last end of each product's items
+    QueueCtl* qc;
+    int32_t* sym_left;          // count: symbolic items not yet done
+    int64_t* queue;             // n_items numeric slots: (product << 32 | block) + 1, negated to skip, 0 = empty
+    int32_t wmax;               // bitmap words of the widest row
+    int32_t vmax;               // columns of the widest row's range
+    uint32_t* qbm;              // each row's bitmap (wmax words per packed row) from the symbolic
+                                // items for the numeric ones, or null (numeric ORs B again)
+    const int2* bc;             // compressed B runs {block, mask} (symbolic), or null (entries)
+    const int4* bhdr;           // per B row {start, length, run start, run count}
+};
+constexpr int QUEUE_MAX_WORDS = 128;  // widest row range the queued kernel holds (4096 columns)
+size_t queue_lds_bytes(int wmax, int vmax, int elem_bytes);
+void launch_queue(hipStream_t s, const QueueArgs& a, int elem_bytes, int grid);
+
 // Tile offsets of B and the work items (once per symbolic result), then the
 // tiled numeric launch; returns the grid used.
 void launch_tile_build(hipStream_t s, const TileArgs& a);

@@ -353,6 +353,44 @@ class SpGEMMBatch:
         self.plan()
         return chosen, best
 
+    def run_queued(self, capacity: int, a_vals=None, b_vals=None, stamps: bool = True):
+        """Both phases of every product in one persistent kernel over a device
+        work queue (no plan, no host work between products).  Pools: row
+        pointers (sum of m_i + 1 entries), columns and values of `capacity`
+        entries; ``q_offsets[i]`` is C_i's first pool entry (-1 if it did not
+        fit) and ``q_stamps[2i:2i+2]`` the device clock (100 MHz) when C_i's
+        first work item started and its last ended."""
+        dev = self.a_rp.device
+        if getattr(self, "q_cap", None) != capacity:
+            with torch.cuda.stream(self.stream):
+                self.q_rp = torch.empty(int(self.m.astype(np.int64).sum()) + self.count, dtype=torch.int32,
+                                        device=dev)
+                self.q_col = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+                self.q_val = torch.empty(max(capacity, 1), dtype=self.dtype, device=dev)
+                self.q_offsets = torch.empty(max(self.count, 1), dtype=torch.int64, device=dev)
+                self.q_stamps = torch.empty(2 * max(self.count, 1), dtype=torch.int64, device=dev)
+            self.q_cap = capacity
+            self.q_rp_off = np.concatenate([[0], np.cumsum(self.m.astype(np.int64) + 1)])
+        a_vals = self.a_v if a_vals is None else a_vals
+        b_vals = self.b_v if b_vals is None else b_vals
+        cur = torch.cuda.current_stream()
+        self.stream.wait_stream(cur)
+        _lib.spg_batch_run_queued(self.b, a_vals.data_ptr() if a_vals.numel() else 0,
+                                  b_vals.data_ptr() if b_vals.numel() else 0, self.q_rp.data_ptr(),
+                                  self.q_col.data_ptr(), self.q_val.data_ptr(), capacity,
+                                  self.q_offsets.data_ptr(), self.q_stamps.data_ptr() if stamps else 0)
+        cur.wait_stream(self.stream)
+
+    def product_queued(self, i: int):
+        """(row_ptr from 0, col_idx, values) of C_i after run_queued, or None if it did not fit."""
+        off = int(self.q_offsets[i].item())
+        if off < 0:
+            return None
+        r0 = int(self.q_rp_off[i])
+        rp = self.q_rp[r0:r0 + int(self.m[i]) + 1].to(torch.int64) - off
+        n = int(rp[-1].item())
+        return rp, self.q_col[off:off + n], self.q_val[off:off + n]
+
     def product(self, i: int):
         """(row_ptr, col_idx, values) of C_i as views/copies on the device."""
         r0, r1 = int(self.c_row_off[i]), int(self.c_row_off[i + 1])

@@ -130,8 +130,8 @@ def test_galerkin_level0_changed_values_every_row():
 
 @pytest.mark.timeout(900)
 def test_banded_batch_1024_every_product():
-    """The 1024-product banded batch in one graph launch: every product's every
-    row against the oracle."""
+    """The 1024-product banded batch in one graph launch and through the queued
+    persistent kernel: every product's every row against the oracle."""
     import torch
     from paper_2103_11991_amd.spgemm import SpGEMMBatch
     pools = gen.banded_batch_pools(1024)
@@ -139,10 +139,14 @@ def test_banded_batch_1024_every_product():
     n = pools["n"]
     batch = SpGEMMBatch.from_pools(n, n, n, pools["a_nnz"], pools["b_nnz"], dev["a_rp"], dev["a_ci"], dev["a_v"],
                                    dev["b_rp"], dev["b_ci"], dev["b_v"])
-    batch.plan()
+    nnz = batch.plan()
     batch.run()
+    batch.run_queued(nnz)  # the same products through the persistent queued kernel
     torch.cuda.synchronize()
+    assert (batch.q_offsets.cpu().numpy() >= 0).all()
     pairs = gen.pools_to_pairs(pools)
     for i, (A, B) in enumerate(pairs):
         rp, c, v = batch.product(i)
         compare_all_rows(A, B, rp.cpu().numpy().astype(np.int64), c, v)
+        rq, cq, vq = batch.product_queued(i)
+        compare_all_rows(A, B, rq.cpu().numpy(), cq, vq)
