@@ -129,11 +129,40 @@ def cpu_baseline(A, target_s: float = 12.0):
     dt = float(np.median(times))
     prods = int(ppr[r0:r0 + rows].sum())
     what = "the whole product" if rows == A.m else f"rows {r0}..{r0 + rows - 1} ({rows} rows)"
-    return {"value": round(2.0 * prods / dt / 1e9, 4), "unit": "GFLOP/s", "cores": oracle.num_threads(),
+    cores = oracle.num_threads()
+    # one thread, on a row range of about 3 s
+    probe1 = min(A.m, 20000)
+    s1 = (A.m - probe1) // 2
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.spgemm(A, A, s1, s1 + probe1)
+        d1 = max(time.perf_counter() - t0, 1e-4)
+        rows1 = int(min(A.m, max(probe1, probe1 * 3.0 / d1)))
+        s1 = (A.m - rows1) // 2
+        t0 = time.perf_counter()
+        oracle.spgemm(A, A, s1, s1 + rows1)
+        d1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(cores)
+    prods1 = int(ppr[s1:s1 + rows1].sum())
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": round(2.0 * prods / dt / 1e9, 4), "unit": "GFLOP/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{what}: {prods} multiply-adds, nnz {int(rp[-1])}, symbolic+numeric, median of "
                       f"{len(times)} passes ({dt:.3f} s each, {sum(times):.1f} s total)",
-            "c_nnz_per_s": round(int(rp[-1]) / dt, 1)}
+            "c_nnz_per_s": round(int(rp[-1]) / dt, 1),
+            "cpu_model": model,
+            "value_1_thread": round(2.0 * prods1 / d1 / 1e9, 4),
+            "sample_1_thread": f"rows {s1}..{s1 + rows1 - 1}: {prods1} multiply-adds, one pass ({d1:.2f} s)"}
 
 
 def time_full_products(op, steps, warmup=0):
@@ -168,6 +197,58 @@ def time_full_products(op, steps, warmup=0):
     return float(np.median(sym)), float(np.median(num)), wall, st_timed, st
 
 
+def small_product_latency(steps):
+    """C = A*A for the 2D 5-point Laplacian on 64^2 (4096 rows, FP64): the
+    latency of one whole product (symbolic with its host synchronisation,
+    then numeric) over back-to-back products, and the graph-replayed and
+    queued batch forms of the same product as a one-product batch."""
+    import torch
+    from paper_2103_11991_amd import gen
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM, SpGEMMBatch
+    A = gen.laplace2d_5pt(64)
+    dA = DeviceCsr.from_host(A)
+    op = SpGEMM(dA, dA)
+    rp, nnz = op.symbolic()
+    col, val = op.numeric()
+    torch.cuda.synchronize()
+    reps = max(50, steps * 10)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        op.symbolic()
+        op.numeric(out_col=col, out_val=val)
+    torch.cuda.synchronize()
+    t_full = 1e3 * (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        op.numeric(out_col=col, out_val=val)
+    torch.cuda.synchronize()
+    t_num = 1e3 * (time.perf_counter() - t0) / reps
+    prods = int(op.stats()["products"])
+    batch = SpGEMMBatch([dA], [dA])
+    nb = batch.plan()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            ev[0].record(batch.stream)
+            fn()
+            ev[1].record(batch.stream)
+            ev[1].synchronize()
+            t.append(ev[0].elapsed_time(ev[1]))
+        return float(np.median(t))
+
+    t_graph = timed(lambda: batch.run())
+    t_queued = timed(lambda: batch.run_queued(nb))
+    return {"workload": "C=A*A, A = 2D 5-point Laplacian on 64^2 (FP64)", "rows": A.m, "nnz_c": int(nnz),
+            "multiply_adds": prods, "full_product_ms": round(t_full, 4), "numeric_reuse_ms": round(t_num, 4),
+            "one_product_graph_ms": round(t_graph, 4), "one_product_queued_ms": round(t_queued, 4),
+            "note": "full product = host-synchronised symbolic (nnz(C) returned) + numeric, wall time per "
+                    "back-to-back product; graph / queued: HIP events around one replay"}
+
+
 def learned_vs_plain(dA, steps, plain):
     """The same product with the symbolic tables sized three ways: the upper
     bound from each row's products, the default upper bound from the
@@ -195,6 +276,17 @@ def learned_vs_plain(dA, steps, plain):
         op.symbolic()
         op.numeric()
     sym, num, wall, _, st = time_full_products(op, steps)
+    # the ideal estimate: each row's exact occupied blocks (from the run just made)
+    opi = SpGEMM(dA, dA, timing=1, binning=2)
+    opi.symbolic()
+    opi.set_option("binning", 3)
+    for _ in range(2):
+        opi.symbolic()
+        opi.numeric()
+    sym_i, _, wall_i, _, _ = time_full_products(opi, steps)
+    del opi
+    out.update({"t_sym_ideal_ms": round(sym_i, 4), "t_full_ideal_ms": round(wall_i, 4),
+                "speedup_sym_ideal_vs_runs_bound": round(plain["sym"] / sym_i, 3)})
     out.update({"t_sym_learned_ms": round(sym, 4), "t_full_learned_ms": round(wall, 4),
                 "speedup_sym_vs_products_bound": round(sym0 / sym, 3),
                 "speedup_full_vs_products_bound": round(wall0 / wall, 3),
@@ -215,42 +307,66 @@ def _learned_opts():
     return w, {"binning": 1, "mlp_margin_milli": int(round(margin * 1000))}
 
 
-def rmat_learned_vs_plain(steps, scale=18, seed=1):
+def rmat_learned_vs_plain(steps, scale=18, seeds=(1, 2, 3)):
     """R-MAT scale 18 (FP32) A*A with the products bound, the compressed-run
-    bound and learned binning."""
+    bound, learned binning and the ideal estimate (each row's exact count),
+    on each test seed; the per-seed figures and their mean."""
     import torch
     from paper_2103_11991_amd import gen
     from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
-    A = gen.rmat(scale, seed=seed)
-    dA = DeviceCsr.from_host(A)
-    out = {"workload": f"C=A*A, A = R-MAT scale {scale} edge factor 16 (a=0.57, b=c=0.19), seed {seed}, FP32",
-           "rows": A.m, "nnz_a": A.nnz}
+    out = {"workload": f"C=A*A, A = R-MAT scale {scale} edge factor 16 (a=0.57, b=c=0.19), FP32, test seeds {list(seeds)}"}
     w, lopts = _learned_opts()
-    for label, opts in (("products_bound", {"binning": 0}), ("runs_bound", {"binning": 2}), ("learned", lopts)):
-        if opts is None:
-            out[label] = None
-            continue
-        op = SpGEMM(dA, dA, timing=1, **opts)
-        if opts.get("binning") == 1:
-            op.set_mlp(w)
-        for _ in range(2):
+    per_seed = []
+    for seed in seeds:
+        A = gen.rmat(scale, seed=seed)
+        dA = DeviceCsr.from_host(A)
+        ent = {"seed": seed, "rows": A.m, "nnz_a": A.nnz}
+        for label, opts in (("products_bound", {"binning": 0}), ("runs_bound", {"binning": 2}), ("learned", lopts),
+                            ("ideal", {"binning": 2, "ideal": 1})):
+            if opts is None:
+                ent[label] = None
+                continue
+            opts = dict(opts)
+            ideal = opts.pop("ideal", 0)
+            op = SpGEMM(dA, dA, timing=1, **opts)
+            if opts.get("binning") == 1:
+                op.set_mlp(w)
             op.symbolic()
-            op.numeric()
-        sym, num, wall, _, st = time_full_products(op, steps)
-        rows = st["m"] - st["empty_rows"]
-        out[label] = {"t_sym_ms": round(sym, 3), "t_num_ms": round(num, 3), "t_full_ms": round(wall, 3),
-                      "gflops": round(2.0 * st["products"] / (wall * 1e-3) / 1e9, 2),
-                      "c_nnz_per_s": round(st["nnz_c"] / (wall * 1e-3), 1),
-                      "retry_rate": round(st["retried_rows"] / max(rows, 1), 5),
-                      "mispredict_rate": round(st["mispredicted_rows"] / max(rows, 1), 5)}
-        out["multiply_adds"] = int(st["products"])
-        out["nnz_c"] = int(st["nnz_c"])
-        del op
+            if ideal:
+                op.set_option("binning", 3)
+            for _ in range(2):
+                op.symbolic()
+                op.numeric()
+            sym, num, wall, _, st = time_full_products(op, steps)
+            rows = st["m"] - st["empty_rows"]
+            rows_c = st["sym_rows"]
+            lds_mb = sum(rows_c[c] * (256 << (c % 10)) for c in range(30) if c % 10 != 9) / 2 ** 20
+            ent[label] = {"t_sym_ms": round(sym, 3), "t_num_ms": round(num, 3), "t_full_ms": round(wall, 3),
+                          "sym_table_bytes_summed_over_rows_mib": round(lds_mb, 2),
+                          "sym_rows_per_class": {c: rows_c[c] for c in range(30) if rows_c[c]},
+                          "gflops": round(2.0 * st["products"] / (wall * 1e-3) / 1e9, 2),
+                          "c_nnz_per_s": round(st["nnz_c"] / (wall * 1e-3), 1),
+                          "retry_rate": round(st["retried_rows"] / max(rows, 1), 5),
+                          "mispredict_rate": round(st["mispredicted_rows"] / max(rows, 1), 5)}
+            ent["multiply_adds"] = int(st["products"])
+            ent["nnz_c"] = int(st["nnz_c"])
+            del op
+            torch.cuda.synchronize()
+        per_seed.append(ent)
+        del dA
         torch.cuda.synchronize()
-    if out.get("learned"):
+    out["seeds"] = per_seed
+    labels = [k for k in ("products_bound", "runs_bound", "learned", "ideal") if all(e.get(k) for e in per_seed)]
+    mean = {k: {f: round(float(np.mean([e[k][f] for e in per_seed])), 4)
+                for f in ("t_sym_ms", "t_num_ms", "t_full_ms", "gflops", "retry_rate", "mispredict_rate")}
+            for k in labels}
+    out["mean"] = mean
+    if "learned" in mean:
         for ref in ("products_bound", "runs_bound"):
-            out[f"learned_speedup_full_vs_{ref}"] = round(out[ref]["t_full_ms"] / out["learned"]["t_full_ms"], 3)
-            out[f"learned_speedup_sym_vs_{ref}"] = round(out[ref]["t_sym_ms"] / out["learned"]["t_sym_ms"], 3)
+            out[f"learned_speedup_full_vs_{ref}"] = round(mean[ref]["t_full_ms"] / mean["learned"]["t_full_ms"], 3)
+            out[f"learned_speedup_sym_vs_{ref}"] = round(mean[ref]["t_sym_ms"] / mean["learned"]["t_sym_ms"], 3)
+    if "ideal" in mean:
+        out["ideal_speedup_sym_vs_runs_bound"] = round(mean["runs_bound"]["t_sym_ms"] / mean["ideal"]["t_sym_ms"], 3)
     return out
 
 
@@ -600,6 +716,7 @@ def main():
     ap.add_argument("--no-jacobi", action="store_true", help="skip the Jacobi-fused vs unfused comparison")
     ap.add_argument("--no-spadd", action="store_true", help="skip the sparse-addition leg")
     ap.add_argument("--no-ablation", action="store_true", help="skip the paper-design ablation")
+    ap.add_argument("--no-small", action="store_true", help="skip the 2D 5-point 64^2 latency leg")
     ap.add_argument("--opt", action="append", default=[], metavar="NAME=VALUE",
                     help="library option for the timed product (e.g. work_per_lane=32); repeatable")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -701,6 +818,8 @@ def main():
                   "num_ms": st["num_ms"]}
         print(json.dumps(detail), file=sys.stderr, flush=True)
     plain = {"sym": out["t_sym_ms"], "wall": ms_step, "mispredicted": st["mispredicted_rows"]}
+    if not args.no_small:
+        out["laplace2d_64"] = small_product_latency(args.steps)
     if not args.no_learned:
         out["learned_vs_plain"] = learned_vs_plain(dA, args.steps, plain)
     if args.batch > 0:

@@ -64,7 +64,10 @@ typedef enum {
        blocks): 0 = upper bound from the row's products, 1 = learned predictor
        set by spg_set_mlp, with overflow detection and an exact retry, 2 =
        upper bound from the compressed-B runs the row reads (tighter than 0,
-       default); all three are capped by the row's column range */
+       default), 3 = the exact count left by the previous spg_symbolic of the
+       same matrices (the ideal estimate, which bounds what any predictor can
+       gain; SPG_ERR_STATE without such a run); all are capped by the row's
+       column range */
     SPG_OPT_BINNING = 0,
     /* HIP events on the handle's stream, read with spg_get_stats: 0 = none
        (default), 1 = around both phases, their stages and every class launch,

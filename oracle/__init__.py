@@ -52,6 +52,8 @@ def lib() -> ctypes.CDLL:
         L.oracle_fill.argtypes = [i32, i32, i32, p, p, p, p, p, p, i32, i32, p, p, p, p]
         L.oracle_fill.restype = ctypes.c_int
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -66,6 +68,11 @@ def _i32(a):
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Host threads of later oracle calls."""
+    lib().oracle_set_num_threads(int(n))
 
 
 def row_nnz(A, B, r0: int = 0, r1: int | None = None) -> np.ndarray:

@@ -154,3 +154,6 @@ int oracle_fill(int32_t m, int32_t n, int32_t k,
 
 /* Number of host threads OpenMP will use (reported beside CPU timings). */
 int oracle_num_threads(void) { return omp_get_max_threads(); }
+
+/* Host threads later calls use (timing of the oracle with fewer threads). */
+void oracle_set_num_threads(int n) { if (n > 0) omp_set_num_threads(n); }

@@ -76,6 +76,7 @@ struct spg_handle_s {
     // symbolic result
     bool have_sym = false;
     bool have_feats = false;
+    bool blocks_valid = false;  // row_blocks holds the exact counts of the current matrices
     int32_t* crp = nullptr;
     int64_t nnz_c = 0;
     int32_t num_hist[NCLS] = {};
@@ -230,6 +231,7 @@ ClassCfg make_cfg(spg_handle h) {
     c.lds_limit = h->lds_limit;
     c.force_class = h->force_class;
     c.elem_bytes = h->dt == SPG_F64 ? 8 : 4;
+    c.bound_est = h->binning != 1;
     return c;
 }
 
@@ -549,6 +551,7 @@ spg_status sym_finish(spg_handle h, int32_t* c_row_ptr) {
     h->crp = c_row_ptr;
     h->have_sym = true;
     h->have_feats = h->binning == 1 || h->keep_features;
+    h->blocks_valid = h->method == 0;  // the paper's design also counts them, but per its own hash maps
     return SPG_OK;
 }
 
@@ -749,6 +752,7 @@ spg_status spg_set_matrices(spg_handle h, spg_dtype dt, int32_t m, int32_t n, in
     try {
         h->have_mats = false;
         h->have_sym = false;
+        h->blocks_valid = false;
         if (dt != SPG_F32 && dt != SPG_F64) return fail(h, SPG_ERR_ARG, "dtype must be SPG_F32 or SPG_F64");
         if (m < 0 || n < 0 || k < 0 || a_nnz < 0 || b_nnz < 0)
             return fail(h, SPG_ERR_ARG, "negative dimension or nnz");
@@ -774,6 +778,8 @@ spg_status spg_symbolic(spg_handle h, int32_t* c_row_ptr, int64_t* nnz_c) {
         if (!h->have_mats) return fail(h, SPG_ERR_STATE, "spg_set_matrices must come first");
         if (!c_row_ptr || !nnz_c) return fail(h, SPG_ERR_ARG, "null output");
         if (h->binning == 1 && !h->have_mlp) return fail(h, SPG_ERR_STATE, "learned binning needs spg_set_mlp");
+        if (h->binning == 3 && !h->blocks_valid)
+            return fail(h, SPG_ERR_STATE, "the exact-count estimate needs a previous symbolic result of these matrices");
         h->have_sym = false;
         if (h->timing) SPG_TRY(make_events(h));
         h->sym_timed = h->timing == 1;
@@ -859,7 +865,7 @@ spg_status spg_set_option(spg_handle h, int32_t opt, int64_t val) {
     if (!h) return SPG_ERR_ARG;
     switch (opt) {
         case SPG_OPT_BINNING:
-            if (val < 0 || val > 2) return fail(h, SPG_ERR_ARG, "binning must be 0, 1 or 2");
+            if (val < 0 || val > 3) return fail(h, SPG_ERR_ARG, "binning must be 0..3");
             h->binning = (int)val;
             break;
         case SPG_OPT_TIMING:

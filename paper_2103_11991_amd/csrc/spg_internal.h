@@ -100,7 +100,8 @@ struct ClassCfg {
     int32_t lds_limit;        // LDS bytes per row beyond which rows go global
     int32_t force_class;      // -1 or a class id
     int32_t elem_bytes;       // 4 (FP32) or 8 (FP64)
-    int32_t pad[3];
+    int32_t bound_est;        // symbolic tables sized from a guaranteed bound (1) or a prediction (0)
+    int32_t pad[2];
 };
 
 // Row facts gathered by the analysis pass.

@@ -130,8 +130,8 @@ __device__ inline float log2p1(int64_t v) { return log2f(1.0f + (float)v); }
 
 // A rows: products, column range, largest B row; symbolic class from an upper
 // bound on the row's occupied blocks (binning 0: its products, 2: the
-// compressed-B runs it reads) or features only (binning 1, learned: classified
-// by k_mlp_classify).
+// compressed-B runs it reads, 3: the exact count of a previous run) or
+// features only (binning 1, learned: classified by k_mlp_classify).
 __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const int32_t* __restrict__ arp,
                                                    const int32_t* __restrict__ aci, int64_t annz,
                                                    const int4* __restrict__ binfo, RowInfo* __restrict__ rinfo,
@@ -214,7 +214,10 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
                 atomicAdd(&prod_sum, (unsigned long long)ub);
                 atomicMax(&pmax, (unsigned long long)ub);
                 if (binning != 1) {
-                    cls = sym_class(ub, cmin, cmax, binning == 2 ? rs : ub, cfg, true);
+                    // binning 3 (ideal estimate): the row's exact occupied blocks, left in
+                    // row_blocks by a previous symbolic run of the same matrices
+                    const int64_t est = binning == 2 ? rs : binning == 3 ? (int64_t)row_blocks[row] : ub;
+                    cls = sym_class(ub, cmin, cmax, est, cfg, true);
                     sym_cls[row] = (uint8_t)cls;
                     atomicAdd(&hist[cls], 1);
                     if (cls % NTIER == TIER_GLOBAL) atomicMax(&wmax_glob, (unsigned long long)words);
@@ -492,7 +495,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(int32_t m, const int32_t*
                 c_cur += (unsigned long long)c;
                 p_cur += (unsigned long long)ri.z;
                 if (nc % NTIER == TIER_GLOBAL) atomicMax(&wmax_glob, (unsigned long long)row_words(ri.x, ri.y));
-                miss += sym_class(ri.z, ri.x, ri.y, blocks, cfg) != sym_cls[r];
+                // the class the exact size asks for, under the same sizing rule as the estimate's
+                miss += sym_class(ri.z, ri.x, ri.y, blocks, cfg, cfg.bound_est != 0) != sym_cls[r];
             }
         }
         run += c;

@@ -300,3 +300,61 @@ def test_learned_classes_follow_each_rows_own_prediction(reps):
     assert (got >= hist_lo).all() and (got <= hist_hi).all(), (got, hist_lo, hist_hi)
     assert miss_lo <= st["mispredicted_rows"] <= miss_hi
     assert len(np.nonzero(got)[0]) >= 2  # the runs land in several classes
+
+
+def _reserved_lds(st):
+    """Symbolic LDS bytes the rows' classes reserve (rows x tier bytes; rows
+    of the global path counted apart)."""
+    rows = np.asarray(st["sym_rows"], dtype=np.int64)
+    lds = sum(int(rows[c]) * (256 << (c % 10)) for c in range(30) if c % 10 != 9)
+    return lds, int(sum(rows[c] for c in range(30) if c % 10 == 9))
+
+
+def test_learned_binning_gain_on_a_held_out_seed():
+    """R-MAT scale 16, seed 3 (the predictor trained on seeds 1001-1016): the
+    symbolic tables the committed network sizes reserve less LDS than those
+    the plain method's product bound sizes, and no less than the ideal
+    estimate (each row's exact count) would; every variant's product equals
+    the oracle's structure."""
+    import os
+    import torch
+    import oracle
+    from paper_2103_11991_amd import learned
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
+    if not os.path.exists(learned.DEFAULT_MODEL):
+        pytest.skip("no committed predictor")
+    w, margin, _ = learned.load()
+    A = gen.rmat(16, seed=3)
+    dA = DeviceCsr.from_host(A)
+    orp, _, _, _ = oracle.spgemm(A, A)
+    out = {}
+    for label, opts in (("products", {"binning": 0}), ("runs", {"binning": 2}),
+                        ("learned", {"binning": 1, "mlp_margin_milli": int(round(margin * 1000))})):
+        op = SpGEMM(dA, dA, merge_classes=0, **opts)
+        if opts["binning"] == 1:
+            op.set_mlp(w)
+        rp, nnz = op.symbolic()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(rp.cpu().numpy().astype(np.int64), orp)
+        out[label] = _reserved_lds(op.stats())
+        if label == "runs":  # the ideal estimate on the same handle: exact counts of the run just made
+            op.set_option("binning", 3)
+            rp, nnz = op.symbolic()
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(rp.cpu().numpy().astype(np.int64), orp)
+            out["ideal"] = _reserved_lds(op.stats())
+    print({k: v for k, v in out.items()}, flush=True)
+    assert out["learned"][0] < out["products"][0]
+    assert out["ideal"][0] <= out["learned"][0]
+    assert out["ideal"][0] <= out["runs"][0] <= out["products"][0]
+
+
+def test_ideal_estimate_needs_a_previous_symbolic_result():
+    from paper_2103_11991_amd._lib import SpgError
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
+    A = gen.laplace2d_5pt(20)
+    dA = DeviceCsr.from_host(A)
+    op = SpGEMM(dA, dA, binning=3)
+    with pytest.raises(SpgError) as e:
+        op.symbolic()
+    assert e.value.status_name == "SPG_ERR_STATE"
