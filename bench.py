@@ -430,6 +430,47 @@ def galerkin_chain(sweeps=10, n0=128, levels=5):
     return out
 
 
+def single_leg(name, steps, warmup):
+    """One workload alone, for a profiler run: `steps` timed repetitions
+    after `warmup` untimed ones."""
+    import torch
+    from paper_2103_11991_amd import gen
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM, SpGEMMBatch
+    if name == "rmat":
+        A = gen.rmat(18, seed=1)
+        dA = DeviceCsr.from_host(A)
+        op = SpGEMM(dA, dA)
+        for _ in range(warmup):
+            op.symbolic()
+            op.numeric()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            op.symbolic()
+            op.numeric()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / max(steps, 1)
+        return {"leg": "C=A*A, A = R-MAT scale 18 seed 1 (FP32), plain two-phase", "steps": steps,
+                "ms_per_product": round(ms, 3), "nnz_c": int(op.nnz)}
+    pools = gen.banded_batch_pools(1024)
+    dev = {k: torch.from_numpy(v).cuda() for k, v in pools.items() if k not in ("n", "a_nnz", "b_nnz")}
+    n = pools["n"]
+    batch = SpGEMMBatch.from_pools(n, n, n, pools["a_nnz"], pools["b_nnz"], dev["a_rp"], dev["a_ci"], dev["a_v"],
+                                   dev["b_rp"], dev["b_ci"], dev["b_v"])
+    cap = int(batch.plan())
+    run = (lambda: batch.run_queued(cap)) if name == "queued" else batch.run
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / max(steps, 1)
+    return {"leg": f"1024 banded products (seed 12345), {'queued persistent kernel' if name == 'queued' else 'graph'}",
+            "steps": steps, "ms_per_batch": round(ms, 3)}
+
+
 def batched_vs_loop(count, steps):
     """The banded batch: one graph launch (autotuned) against a loop of plain
     two-phase products, each with its own handle."""
@@ -717,6 +758,9 @@ def main():
     ap.add_argument("--no-spadd", action="store_true", help="skip the sparse-addition leg")
     ap.add_argument("--no-ablation", action="store_true", help="skip the paper-design ablation")
     ap.add_argument("--no-small", action="store_true", help="skip the 2D 5-point 64^2 latency leg")
+    ap.add_argument("--leg", choices=("rmat", "queued", "graph"), default=None,
+                    help="run only one workload (for profiling): R-MAT scale 18 seed 1 plain products, or the "
+                         "1024-product banded batch through the queued kernel or its graph; prints its own line")
     ap.add_argument("--opt", action="append", default=[], metavar="NAME=VALUE",
                     help="library option for the timed product (e.g. work_per_lane=32); repeatable")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -741,6 +785,9 @@ def main():
     from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
 
     torch.cuda.set_device(0)
+    if args.leg:
+        print(json.dumps(single_leg(args.leg, args.steps, args.warmup)), flush=True)
+        return
     if args.copy_calibration:
         # a plain copy of known size: 2^27 doubles read and written (1 GiB each way)
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")

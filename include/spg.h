@@ -157,6 +157,11 @@ typedef struct {
     int32_t num_class_launches[SPG_NCLASS]; /* ... and the number of those launches */
     int32_t num_tiles;                  /* column tiles of the tiled global path (0: not used) */
     int32_t tile_fallback_rows;         /* global-path rows the last numeric call left to the segment path */
+    int32_t sym_waits;                  /* host waits for the device in the last spg_symbolic: 1 when the
+                                           buffers it fills could be sized before it ran (m x (k/32 + 1)
+                                           list pairs within 256 MiB), else 2 (a read-back after the
+                                           row analysis sizes them exactly) */
+    int32_t reserved;
 } spg_stats;
 
 /* Human-readable name of a status code (static string). */

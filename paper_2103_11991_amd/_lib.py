@@ -52,6 +52,7 @@ class spg_stats(ctypes.Structure):
         ("list_pairs", ctypes.c_int64),
         ("num_class_ms_total", ctypes.c_float * NCLASS), ("num_class_launches", ctypes.c_int32 * NCLASS),
         ("num_tiles", ctypes.c_int32), ("tile_fallback_rows", ctypes.c_int32),
+        ("sym_waits", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 

@@ -542,26 +542,17 @@ __device__ void flat_walk(const int32_t* __restrict__ aci, const int4* __restric
 // the mask OR-ed in, and the bits that were not yet set (and blocks that were
 // empty) are counted from the value the atomic OR returns.
 
+// One row of the symbolic phase in a table of MODE in the row's LDS share
+// (d = the slot's descriptor {row, A start, A end, list offset}).
 template <int G, int MODE>
-// (up to 128 lanes per row the symbolic kernel fits 64 VGPRs: full occupancy)
-__global__ __launch_bounds__(G * rows_per_wg<G>()) __attribute__((amdgpu_waves_per_eu(G <= 128 ? 8 : 4)))
-void k_sym(SymArgs a) {
-    constexpr int RPW = rows_per_wg<G>();
+__device__ __forceinline__ void sym_row(const SymArgs& a, const int4 d, const int sub, uint32_t* smem, int* red,
+                                        int* occ, int* ovf) {
     constexpr int KC = FLAT_KC;
     constexpr int VC = FLAT_VC_SYM;
-    extern __shared__ __align__(16) uint32_t smem[];
-    __shared__ int red[48];
-    __shared__ int occ[RPW];
-    __shared__ int ovf[RPW];
     const int bytes = tier_bytes(a.tier);
     const int per_row = bytes + sym_stage_bytes(G);
-    // a group of 64 or more lanes owns whole wavefronts: its row is wave-uniform
-    const int sub = G >= 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / G) : threadIdx.x / G;
     const int lane = threadIdx.x % G, wv = lane >> 6;
     const unsigned long long le = (2ull << (lane & 63)) - 1;
-    const int slot = xcd_block(blockIdx.x, gridDim.x) * RPW + sub;
-    if (slot >= a.count) return;  // uniform in the group (in the workgroup when G >= 128)
-    const int4 d = a.desc[slot];
     const int i = d.x, a0 = d.y, a1 = d.z;
     // the first chunk's B headers are gathered before the table is cleared
     int4 h0 = make_int4(0, 0, 0, 0);
@@ -811,6 +802,75 @@ void k_sym(SymArgs a) {
     }
 }
 
+// The symbolic rows of one LDS tier, all three table modes (the grouping
+// kernel placed them tier-major, one range of slots per mode; its control
+// block gives the ranges).  Persistent: each mode's row groups of RPW slots
+// are cut into 8 contiguous shares, one per XCD (workgroups are dispatched
+// round-robin over the XCDs, so workgroup b runs on XCD b % 8), and the
+// workgroups of an XCD take its share's groups in turn; neighbouring rows
+// share most of their B rows, which then stay in that XCD's L2.  The modes
+// run one after another, each in a loop of its own, so that each keeps the
+// register budget of its own table code.
+template <int G, int MODE>
+__device__ __forceinline__ void sym_tier_mode(const SymArgs& a, const int first, const int total, const int sub,
+                                              uint32_t* smem, int* red, int* occ, int* ovf) {
+    constexpr int RPW = rows_per_wg<G>();
+    constexpr int NXCD = 8;
+    const int groups = (total + RPW - 1) / RPW;
+    const int per = (groups + NXCD - 1) / NXCD;
+    const int x = blockIdx.x % NXCD, nw = gridDim.x / NXCD;
+    const int hi = min(groups, (x + 1) * per);
+    for (int g = x * per + (int)blockIdx.x / NXCD; g < hi; g += nw) {
+        const int k = g * RPW + sub;
+        if (k >= total) break;  // uniform in the group (in the workgroup when G >= 128)
+        group_sync<G>();        // the previous row's readers are done with the table
+        sym_row<G, MODE>(a, a.desc[first + k], sub, smem, red, occ, ovf);
+    }
+}
+
+template <int G>
+// (up to 128 lanes per row the symbolic kernel fits 64 VGPRs: full occupancy)
+__global__ __launch_bounds__(G * rows_per_wg<G>()) __attribute__((amdgpu_waves_per_eu(G <= 128 ? 8 : 4)))
+void k_sym_tier(SymArgs a) {
+    constexpr int RPW = rows_per_wg<G>();
+    extern __shared__ __align__(16) uint32_t smem[];
+    __shared__ int red[48];
+    __shared__ int occ[RPW];
+    __shared__ int ovf[RPW];
+    if (a.ctl->err & ERR_INPUT) return;
+    const int t = a.tier;
+    // a group of 64 or more lanes owns whole wavefronts: its row is wave-uniform
+    const int sub = G >= 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / G) : threadIdx.x / G;
+    const int c0 = MODE_DIRECT * NTIER + t, c1 = MODE_HASHED * NTIER + t, c2 = MODE_TWOLEVEL * NTIER + t;
+    if (a.ctl->sym_cnt[c0]) sym_tier_mode<G, MODE_DIRECT>(a, a.ctl->sym_off[c0], a.ctl->sym_cnt[c0], sub, smem, red, occ, ovf);
+    if (a.ctl->sym_cnt[c1]) {
+        group_sync<G>();
+        sym_tier_mode<G, MODE_HASHED>(a, a.ctl->sym_off[c1], a.ctl->sym_cnt[c1], sub, smem, red, occ, ovf);
+    }
+    if (a.ctl->sym_cnt[c2]) {
+        group_sync<G>();
+        sym_tier_mode<G, MODE_TWOLEVEL>(a, a.ctl->sym_off[c2], a.ctl->sym_cnt[c2], sub, smem, red, occ, ovf);
+    }
+}
+
+// One launch per symbolic class, sized on the host from the class histogram
+// (a.desc and a.count are the class's range): a workgroup per RPW rows.
+template <int G, int MODE>
+// (up to 128 lanes per row the symbolic kernel fits 64 VGPRs: full occupancy)
+__global__ __launch_bounds__(G * rows_per_wg<G>()) __attribute__((amdgpu_waves_per_eu(G <= 128 ? 8 : 4)))
+void k_sym(SymArgs a) {
+    constexpr int RPW = rows_per_wg<G>();
+    extern __shared__ __align__(16) uint32_t smem[];
+    __shared__ int red[48];
+    __shared__ int occ[RPW];
+    __shared__ int ovf[RPW];
+    // a group of 64 or more lanes owns whole wavefronts: its row is wave-uniform
+    const int sub = G >= 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / G) : threadIdx.x / G;
+    const int slot = xcd_block(blockIdx.x, gridDim.x) * RPW + sub;
+    if (slot >= a.count) return;  // uniform in the group (in the workgroup when G >= 128)
+    sym_row<G, MODE>(a, a.desc[slot], sub, smem, red, occ, ovf);
+}
+
 template <bool IN_LDS>
 __device__ inline uint32_t ld_tab(const uint32_t* p) {
     if constexpr (IN_LDS) return *p;
@@ -868,13 +928,15 @@ __device__ void wide_sym_row(const SymArgs& a, int i, uint32_t* masks, int2* off
 __global__ __launch_bounds__(WIDE_THREADS) void k_sym_wide(SymArgs a) {
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int red[48];
+    if (a.ctl->err & ERR_INPUT) return;
     const int count = a.count_dev ? *a.count_dev : a.count;
+    const int32_t* perm = a.off_dev ? a.perm + *a.off_dev : a.perm;
     uint32_t* slab = a.slab ? a.slab + (int64_t)blockIdx.x * a.slab_words : nullptr;
     uint8_t* stage = reinterpret_cast<uint8_t*>(smem) + a.wide_lds;
     int2* off = reinterpret_cast<int2*>(stage);
     Win* win = reinterpret_cast<Win*>(stage + WIDE_THREADS * 16);
     for (int r = blockIdx.x; r < count; r += gridDim.x) {
-        const int i = a.perm[r];
+        const int i = perm[r];
         const RowInfo ri = a.rinfo[i];
         const int64_t words = row_words(ri.x, ri.y);
         if (words * 4 <= a.wide_lds) wide_sym_row<true>(a, i, smem, off, win, red);
@@ -1555,14 +1617,6 @@ void sym_launch(hipStream_t s, const SymArgs& a) {
     hipLaunchKernelGGL((k_sym<G, MODE>), dim3(grid), dim3(G * RPW), smem, s, a);
 }
 
-template <int G, int MODE, typename T>
-void num_launch(hipStream_t s, const NumArgs& a) {
-    constexpr int RPW = rows_per_wg<G>();
-    const unsigned grid = (unsigned)((a.count + RPW - 1) / RPW);
-    const size_t smem = (size_t)RPW * (tier_bytes(a.tier) + stage_bytes(G));
-    hipLaunchKernelGGL((k_num<G, MODE, T>), dim3(grid), dim3(G * RPW), smem, s, a);
-}
-
 template <int MODE>
 void sym_dispatch(hipStream_t s, const SymArgs& a) {
     switch (tier_threads(a.tier)) {
@@ -1576,6 +1630,34 @@ void sym_dispatch(hipStream_t s, const SymArgs& a) {
         default: sym_launch<1024, MODE>(s, a); break;
     }
 }
+
+template <int G>
+int sym_tier_launch(hipStream_t s, const SymArgs& a, int64_t max_rows, int n_cu) {
+    constexpr int RPW = rows_per_wg<G>();
+    const size_t smem = (size_t)RPW * (tier_bytes(a.tier) + sym_stage_bytes(G));
+    // workgroups per compute unit at this LDS size, looked up once per tier
+    static int occupancy[NTIER] = {};
+    int occ = occupancy[a.tier];
+    if (occ <= 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sym_tier<G>, G * RPW, smem) != hipSuccess || occ < 1)
+            occ = 1;
+        occupancy[a.tier] = occ;
+    }
+    const int64_t groups = (max_rows + RPW - 1) / RPW;
+    int64_t grid = std::min<int64_t>((int64_t)occ * n_cu, std::max<int64_t>(groups, 1));
+    grid = (grid + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_sym_tier<G>, dim3((unsigned)grid), dim3(G * RPW), smem, s, a);
+    return (int)grid;
+}
+
+template <int G, int MODE, typename T>
+void num_launch(hipStream_t s, const NumArgs& a) {
+    constexpr int RPW = rows_per_wg<G>();
+    const unsigned grid = (unsigned)((a.count + RPW - 1) / RPW);
+    const size_t smem = (size_t)RPW * (tier_bytes(a.tier) + stage_bytes(G));
+    hipLaunchKernelGGL((k_num<G, MODE, T>), dim3(grid), dim3(G * RPW), smem, s, a);
+}
+
 
 template <int MODE, typename T>
 void num_dispatch(hipStream_t s, const NumArgs& a) {
@@ -1609,6 +1691,20 @@ int launch_sym_class(hipStream_t s, const SymArgs& a, int grid_cap) {
     else if (a.mode == MODE_HASHED) sym_dispatch<MODE_HASHED>(s, a);
     else sym_dispatch<MODE_TWOLEVEL>(s, a);
     return 1;
+}
+
+int launch_sym_tier(hipStream_t s, const SymArgs& a, int64_t max_rows, int n_cu) {
+    if (max_rows <= 0 || a.tier < 0 || a.tier >= TIER_GLOBAL) return 0;
+    switch (tier_threads(a.tier)) {
+        case 8: return sym_tier_launch<8>(s, a, max_rows, n_cu);
+        case 16: return sym_tier_launch<16>(s, a, max_rows, n_cu);
+        case 32: return sym_tier_launch<32>(s, a, max_rows, n_cu);
+        case 64: return sym_tier_launch<64>(s, a, max_rows, n_cu);
+        case 128: return sym_tier_launch<128>(s, a, max_rows, n_cu);
+        case 256: return sym_tier_launch<256>(s, a, max_rows, n_cu);
+        case 512: return sym_tier_launch<512>(s, a, max_rows, n_cu);
+        default: return sym_tier_launch<1024>(s, a, max_rows, n_cu);
+    }
 }
 
 int launch_num_class(hipStream_t s, const NumArgs& a, int elem_bytes, int grid_cap) {

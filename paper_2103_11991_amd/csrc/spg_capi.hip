@@ -83,6 +83,15 @@ struct spg_handle_s {
     int32_t num_off[NCLS] = {};
     int64_t slab_num_words = 0;
     int nslab_num = 0;
+    // symbolic buffers reserved before the phase runs (host-known bounds)
+    int64_t bc_runs = 0;          // compressed-B capacity in runs
+    int64_t list_cap = 0;         // list pairs the grouping may hand out
+    int64_t slab_sym_words = 0;   // per-workgroup slab of the symbolic global path (0: none)
+    int sym_global_grid = 0;      // its workgroups (0: no row can take the global path)
+    int64_t slab_retry_words = 0; // per-workgroup slab of the learned-size retry
+    int retry_grid = 0;
+    bool single_wait = false;     // this symbolic call waits for the device once
+    int sym_waits = 0;            // host waits of the last symbolic call
     bool paper_team = false;   // the paper's design: team method (else vector method)
     int paper_grid = 0;
     int64_t paper_sym_slots = 0, paper_num_slots = 0;
@@ -293,6 +302,8 @@ spg_status check_input_errors(spg_handle h) {
 // A batch replays analysis + rows + numeric from a captured graph with the
 // geometry of its first synchronised run (the structure is fixed).
 
+spg_status reserve_symbolic(spg_handle h);
+
 spg_status sym_prepare(spg_handle h) {
     const int32_t m = h->m;
     const bool learned = h->binning == 1;
@@ -317,6 +328,80 @@ spg_status sym_prepare(spg_handle h) {
     if (learned) SPG_TRY(ensure(h, h->ovf_list, M * 4));
     if (want_feats) SPG_TRY(ensure(h, h->feats, M * 12));
     h->cfg = make_cfg(h);
+    return reserve_symbolic(h);
+}
+
+// The symbolic phase waits for the device once (for the control block read
+// back after the row-pointer scan) when the buffers it fills can be sized
+// before it runs from what the host knows: compressed B holds at most one
+// run per entry of B, a row's list at most one pair per word of its column
+// range, a global-path slab the widest range a row can have.  Every launch
+// then reads its rows from the control block the grouping kernel wrote.  The
+// list bound m x (k/32 + 1) pairs is reserved for real, so this holds up to
+// SINGLE_WAIT_PAIRS pairs (256 MiB): the small, latency-bound products.  A
+// larger product reads the control block back after the analysis too (a
+// second wait, about 12 us) and allocates the exact list, slab and launch
+// sizes it finds there.
+constexpr int64_t SINGLE_WAIT_PAIRS = (int64_t)32 << 20;
+
+spg_status reserve_symbolic(spg_handle h) {
+    const int64_t words_k = ((int64_t)h->k + 31) / 32 + 1;
+    const int64_t list_bound = (int64_t)std::max(h->m, 1) * words_k;
+    h->single_wait = !h->method && list_bound <= std::min(SINGLE_WAIT_PAIRS, list_limit_pairs(h));
+    h->bc_runs = std::max<int64_t>(h->bnnz, 1);
+    SPG_TRY(ensure(h, h->bc, (size_t)h->bc_runs * sizeof(int2)));
+    h->slab_sym_words = 0;
+    h->sym_global_grid = 0;
+    h->slab_retry_words = 0;
+    h->retry_grid = (int)std::min<int64_t>(64, std::max<int64_t>(h->m, 1));
+    if (!h->single_wait) {
+        h->list_cap = list_limit_pairs(h);  // the grouping's limit; the list is allocated after the analysis
+        return SPG_OK;
+    }
+    SPG_TRY(ensure(h, h->lists, (size_t)list_bound * 8));
+    h->list_cap = list_bound;
+    const int wl = wide_lds(h);
+    const int64_t slab_words = (words_k + 63) & ~(int64_t)63;
+    const bool slab = words_k * 4 > wl;
+    // the symbolic global path: rows whose smallest table exceeds the LDS
+    // limit (impossible when a direct table of the widest range fits it),
+    // and rows forced there
+    const bool global = words_k * 4 > h->cfg.lds_limit || (h->force_class >= 0 && h->force_class % NTIER == TIER_GLOBAL);
+    if (global) {
+        h->sym_global_grid = (int)std::min<int64_t>(2 * h->n_cu, std::max<int64_t>(h->m, 1));
+        if (slab) {
+            SPG_TRY(ensure(h, h->slab_sym, (size_t)h->sym_global_grid * slab_words * 4));
+            h->slab_sym_words = slab_words;
+        }
+    }
+    if (h->binning == 1 && slab) {
+        SPG_TRY(ensure(h, h->slab_retry, (size_t)h->retry_grid * slab_words * 4));
+        h->slab_retry_words = slab_words;
+    }
+    return SPG_OK;
+}
+
+// The second-wait path: list, slabs and launch sizes from the analysis read
+// back into h->geom.
+spg_status size_from_analysis(spg_handle h) {
+    const Control& hc = h->geom;
+    const int wl = wide_lds(h);
+    SPG_TRY(ensure(h, h->lists, (size_t)std::max<int64_t>(std::min(hc.list_total, list_limit_pairs(h)), 1) * 8));
+    int32_t hist[NCLS];
+    uint8_t remap[NCLS];
+    merge_classes(hc.sym_hist, remap, hist, merging(h) != 0);
+    const int gcls = MODE_DIRECT * NTIER + TIER_GLOBAL;
+    h->sym_global_grid = std::min(hist[gcls], 2 * h->n_cu);
+    h->slab_sym_words = 0;
+    if (hist[gcls] > 0 && hc.max_words_sym_global * 4 > wl) {
+        h->slab_sym_words = (hc.max_words_sym_global + 63) & ~(int64_t)63;
+        SPG_TRY(ensure(h, h->slab_sym, (size_t)h->sym_global_grid * h->slab_sym_words * 4));
+    }
+    h->slab_retry_words = 0;
+    if (h->binning == 1 && hc.max_words_all * 4 > wl) {
+        h->slab_retry_words = (hc.max_words_all + 63) & ~(int64_t)63;
+        SPG_TRY(ensure(h, h->slab_retry, (size_t)h->retry_grid * h->slab_retry_words * 4));
+    }
     return SPG_OK;
 }
 
@@ -342,36 +427,41 @@ void sym_stage_analysis(spg_handle h) {
     launch_fill_i32(s, h->cursor.as<int32_t>(), 0, NCLS);
     launch_scatter(s, h->m, h->sym_cls.as<uint8_t>(), merging(h), ctl->sym_hist, h->cursor.as<int32_t>(),
                    h->perm_sym.as<int32_t>(), h->arp, nullptr, h->desc_sym.as<int4>(), h->lofs.as<int32_t>(), ctl,
-                   list_limit_pairs(h));
+                   h->list_cap);
     rec(h, EV_ANA1);
 }
 
 // (with read_back, the control block is copied to the host right after the
 // row-pointer scan and an event marks the copy: the host needs nothing the
 // numeric grouping after it changes, and need not wait for it)
-spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr, bool read_back = false) {
+// (host_sized: launch per class from the histogram in h->geom even when the
+// handle could size its launches on the device; a captured batch graph
+// replays launches sized once by its planning run)
+spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr, bool read_back = false, bool host_sized = false) {
     hipStream_t s = h->stream;
     const int32_t m = h->m;
     const bool learned = h->binning == 1;
-    const Control& hc = h->geom;
     Control* ctl = h->ctl.as<Control>();
     const int wl = wide_lds(h);
-    int32_t sym_hist[NCLS];  // rows per launch class
-    uint8_t sym_remap[NCLS];
-    merge_classes(hc.sym_hist, sym_remap, sym_hist, merging(h) != 0);
-    // compressed B, read by both phases
-    SPG_TRY(ensure(h, h->bc, (size_t)std::max<int64_t>(hc.bc_total, 1) * sizeof(int2)));
+    // compressed B, read by both phases (skipped on malformed input)
     launch_compress_b(s, h->n, h->brp, h->bci, h->binfo.as<int4>(), h->bcrp.as<int32_t>(), h->tile_status.as<uint64_t>(),
-                      &ctl->tile_counter_b, h->bc.as<int2>(), h->bhdr.as<int4>());
-    SPG_TRY(ensure(h, h->lists, (size_t)std::max<int64_t>(std::min(hc.list_total, list_limit_pairs(h)), 1) * 8));
-    int off[NCLS];
-    {
-        int run = 0;
-        for (int c = 0; c < NCLS; ++c) off[c] = run, run += sym_hist[c];
-    }
-    const int grid_cap = 2 * h->n_cu;
+                      &ctl->tile_counter_b, h->bc.as<int2>(), h->bhdr.as<int4>(), &ctl->err);
+    SymArgs base{};
+    base.arp = h->arp, base.aci = h->aci, base.brp = h->brp, base.bci = h->bci;
+    base.bcrp = h->bcrp.as<int32_t>(), base.bc = h->bc.as<int2>(), base.bhdr = h->bhdr.as<int4>();
+    base.bc_total = h->bc_runs;
+    base.rinfo = h->rinfo.as<RowInfo>();
+    base.row_nnz = h->row_nnz.as<int32_t>();
+    base.row_blocks = h->row_blocks.as<int32_t>();
+    base.ctl = ctl;
+    base.wide_lds = wl;
+    base.lofs = h->lofs.as<int32_t>();
+    base.lists = h->lists.as<int2>();
+    base.ovf_list = learned ? h->ovf_list.as<int32_t>() : nullptr;  // learned sizes may overflow: retried
     if (h->method) {
-        // the paper's design: one method for the whole matrix, two-level hash maps
+        // the paper's design: one method for the whole matrix, two-level hash
+        // maps; sized from the analysis read back before this stage
+        const Control& hc = h->geom;
         const int64_t rows = std::max<int64_t>(1, (int64_t)m - hc.empty_rows);
         h->paper_team = h->method == 3 || (h->method == 1 && hc.products >= (int64_t)PAPER_TEAM_PRODUCTS * rows);
         const int rpw = paper_rows_per_wg(h->paper_team);
@@ -402,68 +492,72 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr, bool read_back = fal
         launch_paper(s, p, false, h->dt == SPG_F64 ? 8 : 4, h->n_cu);
         rec(h, EV_SYMCLS + 1);
         h->sym_cls_timed[0] = h->timing == 1;
-    }
-    uint32_t* slab = nullptr;
-    int64_t slab_words = 0;
-    const int gcls = MODE_DIRECT * NTIER + TIER_GLOBAL;
-    if (!h->method && sym_hist[gcls] > 0 && hc.max_words_sym_global * 4 > wl) {
-        slab_words = (hc.max_words_sym_global + 63) & ~(int64_t)63;
-        int ns = std::min(sym_hist[gcls], grid_cap);
-        SPG_TRY(ensure(h, h->slab_sym, (size_t)ns * slab_words * 4));
-        slab = h->slab_sym.as<uint32_t>();
-    }
-    for (int c = 0; c < NCLS; ++c) {
-        if (!sym_hist[c] || h->method) continue;
-        SymArgs a{};
-        a.perm = h->perm_sym.as<int32_t>() + off[c];
-        a.desc = h->desc_sym.as<int4>() + off[c];
-        a.count = sym_hist[c];
-        a.tier = c % NTIER;
-        a.mode = c / NTIER;
-        a.arp = h->arp, a.aci = h->aci, a.brp = h->brp, a.bci = h->bci;
-        a.bcrp = h->bcrp.as<int32_t>(), a.bc = h->bc.as<int2>(), a.bhdr = h->bhdr.as<int4>();
-        a.bc_total = h->geom.bc_total;
-        a.rinfo = h->rinfo.as<RowInfo>();
-        a.row_nnz = h->row_nnz.as<int32_t>();
-        a.row_blocks = h->row_blocks.as<int32_t>();
-        a.ovf_list = learned ? h->ovf_list.as<int32_t>() : nullptr;
-        a.ctl = ctl;
-        a.slab = slab;
-        a.slab_words = slab_words;
-        a.count_dev = nullptr;
-        a.wide_lds = wl;
-        a.lofs = h->lofs.as<int32_t>();
-        a.lists = h->lists.as<int2>();
-        rec(h, EV_SYMCLS + 2 * c);
-        launch_sym_class(s, a, grid_cap);
-        rec(h, EV_SYMCLS + 2 * c + 1);
-        h->sym_cls_timed[c] = h->timing == 1;
+    } else if (h->single_wait && !host_sized) {
+        // one persistent launch per LDS tier (its three table modes); each
+        // reads its rows from the control block the grouping kernel wrote,
+        // so no launch waits for the host.  Tiers above the LDS limit never
+        // get rows.  Times are kept per tier (in the tier's direct class).
+        for (int t = 0; t < TIER_GLOBAL; ++t) {
+            if (tier_bytes(t) > h->cfg.lds_limit) continue;
+            SymArgs a = base;
+            a.perm = h->perm_sym.as<int32_t>();
+            a.desc = h->desc_sym.as<int4>();
+            a.tier = t;
+            rec(h, EV_SYMCLS + 2 * t);
+            launch_sym_tier(s, a, m, h->n_cu);
+            rec(h, EV_SYMCLS + 2 * t + 1);
+            h->sym_cls_timed[t] = h->timing == 1;
+        }
+        if (h->sym_global_grid > 0) {
+            const int gcls = MODE_DIRECT * NTIER + TIER_GLOBAL;
+            SymArgs a = base;
+            a.perm = h->perm_sym.as<int32_t>();
+            a.count_dev = &ctl->sym_cnt[gcls];
+            a.off_dev = &ctl->sym_off[gcls];
+            a.tier = TIER_GLOBAL;
+            a.mode = MODE_DIRECT;
+            a.slab = h->slab_sym_words ? h->slab_sym.as<uint32_t>() : nullptr;
+            a.slab_words = h->slab_sym_words;
+            rec(h, EV_SYMCLS + 2 * gcls);
+            launch_sym_class(s, a, h->sym_global_grid);
+            rec(h, EV_SYMCLS + 2 * gcls + 1);
+            h->sym_cls_timed[gcls] = h->timing == 1;
+        }
+    } else {
+        // one launch per populated class, sized from the analysis read back
+        int32_t hist[NCLS], off[NCLS];
+        uint8_t remap[NCLS];
+        merge_classes(h->geom.sym_hist, remap, hist, merging(h) != 0);
+        sym_class_offsets(hist, off);
+        for (int c = 0; c < NCLS; ++c) {
+            if (!hist[c]) continue;
+            SymArgs a = base;
+            a.perm = h->perm_sym.as<int32_t>() + off[c];
+            a.desc = h->desc_sym.as<int4>() + off[c];
+            a.count = hist[c];
+            a.tier = c % NTIER;
+            a.mode = c / NTIER;
+            if (a.tier == TIER_GLOBAL) {
+                a.slab = h->slab_sym_words ? h->slab_sym.as<uint32_t>() : nullptr;
+                a.slab_words = h->slab_sym_words;
+            }
+            rec(h, EV_SYMCLS + 2 * c);
+            launch_sym_class(s, a, 2 * h->n_cu);
+            rec(h, EV_SYMCLS + 2 * c + 1);
+            h->sym_cls_timed[c] = h->timing == 1;
+        }
     }
     if (learned && !h->method) {
         // exact retry of overflowed rows on the global path (row count read on the device)
-        SymArgs a{};
+        SymArgs a = base;
         a.perm = h->ovf_list.as<int32_t>();
         a.count = 0;
         a.count_dev = &ctl->overflow_rows;
         a.tier = TIER_GLOBAL;
         a.mode = MODE_DIRECT;
-        a.arp = h->arp, a.aci = h->aci, a.brp = h->brp, a.bci = h->bci;
-        a.bcrp = h->bcrp.as<int32_t>(), a.bc = h->bc.as<int2>(), a.bhdr = h->bhdr.as<int4>();
-        a.bc_total = h->geom.bc_total;
-        a.rinfo = h->rinfo.as<RowInfo>();
-        a.row_nnz = h->row_nnz.as<int32_t>();
-        a.row_blocks = h->row_blocks.as<int32_t>();
-        a.ctl = ctl;
-        a.wide_lds = wl;
-        a.lofs = h->lofs.as<int32_t>();
-        a.lists = h->lists.as<int2>();
-        const int retry_grid = std::min(grid_cap, 64);
-        if (hc.max_words_all * 4 > wl) {
-            a.slab_words = (hc.max_words_all + 63) & ~(int64_t)63;
-            SPG_TRY(ensure(h, h->slab_retry, (size_t)retry_grid * a.slab_words * 4));
-            a.slab = h->slab_retry.as<uint32_t>();
-        }
-        launch_sym_class(s, a, retry_grid);
+        a.slab = h->slab_retry_words ? h->slab_retry.as<uint32_t>() : nullptr;
+        a.slab_words = h->slab_retry_words;
+        launch_sym_class(s, a, h->retry_grid);
     }
     // row pointer and numeric classes
     rec(h, EV_SCAN0);
@@ -547,7 +641,7 @@ spg_status sym_finish(spg_handle h, int32_t* c_row_ptr) {
     st.retried_rows = hc2.overflow_rows;
     st.mispredicted_rows = hc2.mispredicted;
     st.binning = h->binning;
-    st.list_pairs = std::min(hc.list_total, list_limit_pairs(h));
+    st.list_pairs = std::min(hc.list_total, h->list_cap);
     h->crp = c_row_ptr;
     h->have_sym = true;
     h->have_feats = h->binning == 1 || h->keep_features;
@@ -643,7 +737,7 @@ spg_status num_launch_all(spg_handle h, const void* a_vals, const void* b_vals, 
         a.arp = h->arp, a.aci = h->aci, a.av = a_vals;
         a.brp = h->brp, a.bci = h->bci, a.bv = b_vals;
         a.bcrp = h->bcrp.as<int32_t>(), a.bc = h->bc.as<int2>(), a.bhdr = h->bhdr.as<int4>();
-        a.bc_total = h->geom.bc_total;
+        a.bc_total = h->bc_runs;
         a.bnnz = h->bnnz;
         a.crp = h->crp;
         a.rinfo = h->rinfo.as<RowInfo>();
@@ -790,6 +884,7 @@ spg_status spg_symbolic(spg_handle h, int32_t* c_row_ptr, int64_t* nnz_c) {
         if (h->m == 0) {
             launch_fill_i32(h->stream, c_row_ptr, 0, 1);
             SPG_TRY(sync_ctl(h));
+            h->sym_waits = 1;
             rec(h, EV_SYM1);
             *nnz_c = 0;
             h->nnz_c = 0;
@@ -801,14 +896,23 @@ spg_status spg_symbolic(spg_handle h, int32_t* c_row_ptr, int64_t* nnz_c) {
             h->have_feats = false;
             return SPG_OK;
         }
-        SPG_TRY(sync_ctl(h));  // first synchronisation: validity, class histogram, slab sizes
-        SPG_TRY(check_input_errors(h));
-        h->geom = *h->hctl;
+        h->sym_waits = 1;
+        if (!h->single_wait) {
+            // sizes from the analysis (a second wait; see reserve_symbolic)
+            h->sym_waits = 2;
+            SPG_TRY(sync_ctl(h));
+            SPG_TRY(check_input_errors(h));
+            h->geom = *h->hctl;
+            if (!h->method) SPG_TRY(size_from_analysis(h));
+        }
         SPG_TRY(sym_stage_rows(h, c_row_ptr, true));
         rec(h, EV_SYM1);
-        // second synchronisation: nnz(C) for the caller's allocation (the
-        // numeric grouping may still run; numeric is ordered after it)
+        // the one wait: the control block copied right after the row-pointer
+        // scan gives nnz(C), input errors and the numeric launch geometry
+        // (the numeric grouping may still run; numeric is ordered after it)
         HIP_TRY(h, hipEventSynchronize(h->ev_ctl));
+        h->geom = *h->hctl;
+        SPG_TRY(check_input_errors(h));
         SPG_TRY(sym_finish(h, c_row_ptr));
         *nnz_c = h->nnz_c;
         return SPG_OK;
@@ -951,6 +1055,7 @@ spg_status spg_get_stats(spg_handle h, spg_stats* out, int32_t size) {
         st.num_class_ms_total[c] = (float)h->num_acc_ms[c];
         st.num_class_launches[c] = h->num_acc_n[c];
     }
+    st.sym_waits = h->sym_waits;
     st.num_tiles = h->have_sym && h->tiled ? h->ntiles : 0;
     st.tile_fallback_rows = 0;
     if (st.num_tiles && h->tiled_built) {
@@ -1291,7 +1396,7 @@ spg_status spg_batch_run(spg_batch b, const void* a_val_pool, const void* b_val_
             spg_status st = SPG_OK;
             if (!numeric_only) {
                 sym_stage_analysis(h);
-                st = sym_stage_rows(h, c_row_ptr);
+                st = sym_stage_rows(h, c_row_ptr, false, true);
                 h->crp = c_row_ptr;
             } else {
                 const int64_t n1 = b->m_total + 1;

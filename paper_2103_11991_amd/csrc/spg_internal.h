@@ -52,6 +52,8 @@ constexpr int ERR_A_COL = 2;
 constexpr int ERR_B_ROWPTR = 4;
 constexpr int ERR_B_COL = 8;
 constexpr int ERR_NNZ_OVERFLOW = 16;
+// malformed input: kernels after the analysis exit at once when any is set
+constexpr int ERR_INPUT = ERR_A_ROWPTR | ERR_A_COL | ERR_B_ROWPTR | ERR_B_COL;
 constexpr int ERR_TABLE_OVERFLOW = 32;  // a bounded table overflowed (internal error)
 
 // Per-tier geometry: LDS bytes per row, threads per row, rows per workgroup.
@@ -274,6 +276,10 @@ struct Control {
     int32_t tile_light;           // tiled global path: rows of at most TILE_G entries (one unit per row)
     int32_t a_missing_diag;       // square A: rows without a stored diagonal entry
     int64_t max_products;         // most products of one row
+    // symbolic grouping (tier-major: the three modes of a tier are adjacent):
+    // rows and first slot of every launch class after the class merge
+    int32_t sym_cnt[NCLS];
+    int32_t sym_off[NCLS];
 };
 
 // ---- launch wrappers (spg_rows.hip) ----
@@ -286,8 +292,10 @@ void launch_b_rowinfo(hipStream_t s, int32_t n, int32_t k, const int32_t* brp, c
 // holds each row's run count; bcrp gets their exclusive scan (n+1 entries,
 // tile status scratch of scan_tiles(n)+1 words), bc the runs, and bhdr per B
 // row {first entry, length, first run, run count}.
+// err (device, may be null): both kernels exit at once when it holds an input error
 void launch_compress_b(hipStream_t s, int32_t n, const int32_t* brp, const int32_t* bci, const int4* binfo,
-                       int32_t* bcrp, uint64_t* tile_status, int32_t* tile_counter, int2* bc, int4* bhdr);
+                       int32_t* bcrp, uint64_t* tile_status, int32_t* tile_counter, int2* bc, int4* bhdr,
+                       const int32_t* err = nullptr);
 void launch_a_rowinfo(hipStream_t s, int32_t m, int32_t n, const int32_t* arp, const int32_t* aci, int64_t annz,
                       const int4* binfo, RowInfo* rinfo, float* feats, ClassCfg cfg, int binning,
                       uint8_t* sym_cls, int32_t* row_nnz, int32_t* row_blocks, int32_t* lofs, Control* ctl);
@@ -337,6 +345,7 @@ struct SymArgs {
     uint32_t* slab;               // global path: one mask table per workgroup
     int64_t slab_words;
     const int32_t* count_dev;     // global path: device-side row count (or null)
+    const int32_t* off_dev;       // global path: device-side first slot in perm (or null)
     int32_t wide_lds;             // global path: LDS bytes per workgroup
     const int32_t* lofs;          // per row: first pair of its list, -1 if it has none
     int2* lists;                  // {block, mask} pairs of the rows' occupied blocks
@@ -490,6 +499,23 @@ int launch_num_tiled(hipStream_t s, const TileArgs& a, int elem_bytes, int n_cu)
 
 // Launches one symbolic class; returns the grid size used.
 int launch_sym_class(hipStream_t s, const SymArgs& a, int grid_cap);
+// Launch offsets of the symbolic grouping: tier-major, so that the three
+// table modes of one tier are adjacent (one persistent launch takes them).
+__host__ __device__ inline void sym_class_offsets(const int32_t* rows, int32_t* off) {
+    int32_t run = 0;
+    for (int t = 0; t < NTIER; ++t)
+        for (int md = 0; md < 3; ++md) {
+            const int c = md * NTIER + t;
+            off[c] = run, run += rows[c];
+        }
+}
+// Symbolic rows of LDS tier a.tier (all three table modes), sized on the
+// device: the kernel reads the tier's rows and first slot from the control
+// block the grouping kernel wrote.  Persistent: the grid (a multiple of 8,
+// at most what the device holds at once, at most one workgroup per row
+// group of max_rows) walks the tier's row groups, each XCD a contiguous
+// share of them.  Returns the grid.
+int launch_sym_tier(hipStream_t s, const SymArgs& a, int64_t max_rows, int n_cu);
 int launch_num_class(hipStream_t s, const NumArgs& a, int elem_bytes, int grid_cap);
 
 }  // namespace spg

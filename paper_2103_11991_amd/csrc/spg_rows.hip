@@ -363,8 +363,16 @@ __global__ __launch_bounds__(256) void k_scatter(int32_t m, const uint8_t* __res
         int32_t h[NCLS], merged[NCLS];
         for (int c = 0; c < NCLS; ++c) h[c] = hist[c];
         merge_classes(h, remap, merged, merge != 0);
-        int32_t run = 0;
-        for (int c = 0; c < NCLS; ++c) off[c] = run, run += merged[c];
+        if (lofs) {
+            // symbolic rows tier-major (a persistent launch per tier takes its
+            // three modes as one range); the first workgroup publishes the ranges
+            sym_class_offsets(merged, off);
+            if (blockIdx.x == 0)
+                for (int c = 0; c < NCLS; ++c) ctl->sym_cnt[c] = merged[c], ctl->sym_off[c] = off[c];
+        } else {
+            int32_t run = 0;
+            for (int c = 0; c < NCLS; ++c) off[c] = run, run += merged[c];
+        }
     }
     const int64_t chunk = 256 * SCATTER_ITEMS;
     for (int64_t r0 = blockIdx.x * chunk; r0 < m; r0 += (int64_t)gridDim.x * chunk) {
@@ -615,10 +623,11 @@ __global__ __launch_bounds__(256) void k_pack(int32_t count, const int64_t* __re
 // pointer, single pass with decoupled look-back (same scheme as k_scan).
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_runs(int32_t n, const int4* __restrict__ binfo,
                                                             int32_t* __restrict__ bcrp, uint64_t* tile_status,
-                                                            int32_t* tile_counter) {
+                                                            int32_t* tile_counter, const int32_t* err) {
     __shared__ int32_t tile_sh;
     __shared__ int64_t wsum[SCAN_THREADS / 64];
     __shared__ int64_t tile_prefix;
+    if (err && (*err & ERR_INPUT)) return;  // the same for every workgroup: none waits on another
     if (threadIdx.x == 0) tile_sh = atomicAdd(tile_counter, 1);
     __syncthreads();
     const int tile = tile_sh;
@@ -682,8 +691,10 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_runs(int32_t n, const int
 // run's index (runs begun before it in the row).
 __global__ __launch_bounds__(256) void k_compress_b(int32_t n, const int32_t* __restrict__ brp,
                                                     const int32_t* __restrict__ bci, const int32_t* __restrict__ bcrp,
-                                                    int2* __restrict__ bc, int4* __restrict__ bhdr) {
+                                                    int2* __restrict__ bc, int4* __restrict__ bhdr,
+                                                    const int32_t* err) {
     constexpr int L = ROW_LANES;
+    if (err && (*err & ERR_INPUT)) return;
     static_assert(L == 8, "the DPP shifts and swizzles below assume 8-lane groups");
     const int sl = threadIdx.x % L;
     const int shift = (threadIdx.x & 63) & ~(L - 1);
@@ -787,16 +798,17 @@ void launch_b_rowinfo(hipStream_t s, int32_t n, int32_t k, const int32_t* brp, c
 }
 
 void launch_compress_b(hipStream_t s, int32_t n, const int32_t* brp, const int32_t* bci, const int4* binfo,
-                       int32_t* bcrp, uint64_t* tile_status, int32_t* tile_counter, int2* bc, int4* bhdr) {
+                       int32_t* bcrp, uint64_t* tile_status, int32_t* tile_counter, int2* bc, int4* bhdr,
+                       const int32_t* err) {
     if (n <= 0) {
         launch_fill_i32(s, bcrp, 0, 1);
         return;
     }
     launch_fill_u8(s, tile_status, 0, (scan_tiles(n) + 1) * 8);
     hipLaunchKernelGGL(k_scan_runs, dim3((unsigned)scan_tiles(n)), dim3(SCAN_THREADS), 0, s, n, binfo, bcrp,
-                       tile_status, tile_counter);
+                       tile_status, tile_counter, err);
     hipLaunchKernelGGL(k_compress_b, dim3(std::min(grid_for((int64_t)n * ROW_LANES, 256), 4096u)), dim3(256), 0, s, n,
-                       brp, bci, bcrp, bc, bhdr);
+                       brp, bci, bcrp, bc, bhdr, err);
 }
 
 void launch_a_rowinfo(hipStream_t s, int32_t m, int32_t n, const int32_t* arp, const int32_t* aci, int64_t annz,

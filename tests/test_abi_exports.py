@@ -38,5 +38,5 @@ def test_stats_struct_layout_matches_header():
     expect = 16 + 16 + 240 + 720 + 16 + 8 + 240 + 12
     expect += -expect % 8
     assert _lib.spg_stats.list_pairs.offset == expect
-    # then 30 floats, 30 int32 and two int32
-    assert ctypes.sizeof(_lib.spg_stats) == expect + 8 + 120 + 120 + 8
+    # then 30 floats, 30 int32 and four int32
+    assert ctypes.sizeof(_lib.spg_stats) == expect + 8 + 120 + 120 + 16

@@ -319,3 +319,52 @@ def test_nnz_beyond_int32_is_an_overflow_error():
             # the symbolic phase alone: C itself would take 26 GB
         del op
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_one_wait_and_two_wait_symbolic_agree(dtype):
+    """A product whose list bound m x (k/32 + 1) is small waits for the device
+    once (every launch sized on the device); with the list limit below that
+    bound the same product reads the analysis back first (two waits, exact
+    sizes).  Both match the oracle, and each other bit for bit in structure."""
+    A = gen.random_csr(3000, 2500, 0, 30, seed=21, dtype=dtype, empty_frac=0.1, duplicates=True)
+    B = gen.random_csr(2500, 40000, 0, 40, seed=22, dtype=dtype, sorted_rows=False)
+    rp1, c1, v1, op1 = run_gpu(A, B)
+    assert op1.stats()["sym_waits"] == 1
+    compare(A, B, rp1, c1, v1)
+    rp2, c2, v2, op2 = run_gpu(A, B, list_limit_mb=1)
+    assert op2.stats()["sym_waits"] == 2
+    compare(A, B, rp2, c2, v2)
+    np.testing.assert_array_equal(rp1, rp2)
+    np.testing.assert_array_equal(c1, c2)
+
+
+def test_one_wait_symbolic_global_path_and_learned_retry():
+    """One-wait products whose rows reach the symbolic global path (forced)
+    and whose learned sizes overflow (a constant predictor of 1 block): the
+    device-sized global launch and the exact retry give the oracle's product."""
+    A = gen.random_csr(700, 600, 0, 60, seed=23, empty_frac=0.2)
+    B = gen.random_csr(600, 20000, 0, 80, seed=24)
+    rp, c, v, op = run_gpu(A, B, force_class=9)
+    assert op.stats()["sym_waits"] == 1
+    compare(A, B, rp, c, v)
+    import torch
+    from paper_2103_11991_amd.spgemm import DeviceCsr, SpGEMM
+    w = np.zeros(1217, dtype=np.float32)
+    w[-1] = 1.0
+    op = SpGEMM(DeviceCsr.from_host(A), DeviceCsr.from_host(B), binning=1, mlp_margin_milli=0)
+    op.set_mlp(w)
+    rp, _ = op.symbolic()
+    col, val = op.numeric()
+    torch.cuda.synchronize()
+    st = op.stats()
+    assert st["sym_waits"] == 1 and st["retried_rows"] > 0
+    compare(A, B, rp.cpu().numpy().astype(np.int64), col.cpu().numpy(), val.cpu().numpy())
+
+
+def test_large_product_waits_twice():
+    A = gen.stencil27(40, seed=2)
+    rp, c, v, op = run_gpu(A, A)
+    assert op.stats()["sym_waits"] == 2  # 64000 rows x 2001 words > 2^25 list pairs
+    assert int(rp[-1]) == (5 * 40 - 6) ** 3
+    compare(A, A, rp, c, v, rows=[(0, 3000), (30000, 33000), (61000, 64000)])
