@@ -337,7 +337,7 @@ def rmat_learned_vs_plain(steps, scale=18, seeds=(1, 2, 3)):
             for _ in range(2):
                 op.symbolic()
                 op.numeric()
-            sym, num, wall, _, st = time_full_products(op, steps)
+            sym, num, wall, st_t, st = time_full_products(op, steps)
             rows = st["m"] - st["empty_rows"]
             rows_c = st["sym_rows"]
             lds_mb = sum(rows_c[c] * (256 << (c % 10)) for c in range(30) if c % 10 != 9) / 2 ** 20
@@ -348,6 +348,22 @@ def rmat_learned_vs_plain(steps, scale=18, seeds=(1, 2, 3)):
                           "c_nnz_per_s": round(st["nnz_c"] / (wall * 1e-3), 1),
                           "retry_rate": round(st["retried_rows"] / max(rows, 1), 5),
                           "mispredict_rate": round(st["mispredicted_rows"] / max(rows, 1), 5)}
+            if label == "runs_bound":
+                # the dominant numeric launch (the global class: tile build,
+                # tiled kernel and segment-path rest) against HBM, priced with
+                # FP32 values: 8 B per A entry of its rows, per C entry it
+                # writes and per B entry (its share of products), 12 B per row
+                dom = {c: st_t["num_class_ms_total"][c] / st_t["num_class_launches"][c]
+                       for c in range(30) if st_t["num_class_launches"][c]}
+                dc = max(dom, key=lambda c: dom[c])
+                alg = (st["num_a_nnz"][dc] * 8 + st["num_c_nnz"][dc] * 8
+                       + st["num_products"][dc] / max(st["products"], 1) * A.nnz * 8 + st["num_rows"][dc] * 12)
+                ach = alg / (dom[dc] * 1e-3) / 1e9
+                ent[label]["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                                          "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                                          "kernel": f"numeric class {dc}", "launch_ms": round(dom[dc], 3),
+                                          "algorithmic_bytes": int(alg), "products_share": round(
+                                              st["num_products"][dc] / max(st["products"], 1), 4)}
             ent["multiply_adds"] = int(st["products"])
             ent["nnz_c"] = int(st["nnz_c"])
             del op
