@@ -1490,10 +1490,14 @@ __global__ __launch_bounds__(TILE_G) void k_num_tiled(TileArgs a) {
     const T* bv = reinterpret_cast<const T*>(a.bv);
     T* cvals = reinterpret_cast<T*>(a.cval);
     auto load_cv = [&](int q, int end) { return load_b<T>(a.bci, bv, a.bnnz, q, end); };
-    // a tile's table before the walk: dense window cleared, window table
-    // cleared, its list pairs loaded (pr, scanned after the walk)
+    // The dense window is zero between tiles: cleared once here, and every
+    // entry a tile writes (its products and, fused, B(i,:) all fall on C's
+    // columns) is read once and set back to zero as the tile goes out.
+    for (int c = tid; c < W; c += G) dense[c] = T(0);
+    __syncthreads();
+    // a tile's table before the walk: window table cleared, its list pairs
+    // loaded (pr, scanned after the walk)
     auto begin_tile = [&](int p0, int np, int2& pr) {
-        for (int c = tid; c < W; c += G) dense[c] = T(0);
         win_clear<G, K>(win, tid);
         pr = make_int2(0, 0);
         if (tid < np) pr = a.lists[p0 + tid];
@@ -1527,6 +1531,7 @@ __global__ __launch_bounds__(TILE_G) void k_num_tiled(TileArgs a) {
             const int c = (e.x << 5) + kth_bit((uint32_t)e.y, q - pref[lo]);
             a.ccol[coff + q] = c;
             cvals[coff + q] = dense[c - col0];
+            dense[c - col0] = T(0);
         }
         __syncthreads();
     };
