@@ -25,7 +25,7 @@
 // stored and loaded at device scope; the queue entry is stored only after the
 // writer has waited for its data stores to complete.
 //
-// A row is one wavefront's (a group of RG = 64 lanes): a bitmap of the
+// A row is one group of RG = 32 lanes (two rows per wavefront): a bitmap of the
 // row's column range in LDS (each
 // product's B columns are OR-ed in, lanes over the flattened (A entry, B
 // entry) products), its popcount for the symbolic phase; in the numeric phase
@@ -44,7 +44,7 @@ namespace spg {
 namespace {
 
 constexpr int QWAVES = 4;  // wavefronts per workgroup
-constexpr int RG = 64;     // lanes per row (one row per wavefront)
+constexpr int RG = 32;     // lanes per row (two rows per wavefront)
 constexpr int QGROUPS = QWAVES * 64 / RG;
 constexpr int64_t QUEUE_SPIN_LIMIT = (int64_t)1 << 26;
 
@@ -65,6 +65,16 @@ __device__ inline int wscan_incl(int x) {
 }
 
 __device__ inline int wsum(int x) { return __shfl(wscan_incl(x), RG - 1, RG); }
+
+// Inclusive sum over the whole wavefront (64 lanes, whatever RG is).
+__device__ inline int wave_scan_incl(int x) {
+    const int lane = threadIdx.x & 63;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
 
 // Position of set bit number k (from 0) of m, which has more than k bits set.
 __device__ inline int nth_bit(uint32_t m, int k) {
@@ -304,7 +314,7 @@ __device__ void finish_product(const QueueArgs& a, int p, int64_t* red64, int* f
         for (int64_t b0 = 0; b0 < m; b0 += blockDim.x) {
             const int64_t i = b0 + tid;
             const int v = i < m ? ld_dev(&a.row_nnz[r0 + i]) : 0;
-            const int incl = wscan_incl(v);
+            const int incl = wave_scan_incl(v);
             __syncthreads();
             if ((tid & 63) == 63) red64[tid >> 6] = incl;
             __syncthreads();
