@@ -69,7 +69,7 @@ struct spg_handle_s {
     // scratch
     DevBuf binfo, rinfo, feats, sym_cls, num_cls, perm_sym, perm_num, desc_sym, desc_num, row_nnz, row_blocks,
         tile_status, cursor,
-        ovf_list, ctl, slab_sym, slab_retry, slab_num, mlp_w, bcrp, bc, bhdr, lofs, lists, toff, titems, tfb, slab_paper;
+        ovf_list, ctl, slab_sym, slab_retry, slab_num, mlp_w, bc, bhdr, lofs, lists, toff, titems, tfb, slab_paper;
     Control* hctl = nullptr;  // pinned host copy
     hipEvent_t ev_ctl = nullptr;  // marks the copy of the control block after the row-pointer scan
 
@@ -321,7 +321,6 @@ spg_status sym_prepare(spg_handle h) {
     SPG_TRY(ensure(h, h->row_nnz, M * 4));
     SPG_TRY(ensure(h, h->row_blocks, M * 4));
     SPG_TRY(ensure(h, h->tile_status, (size_t)(scan_tiles(std::max(m, h->n)) + 1) * 8));
-    SPG_TRY(ensure(h, h->bcrp, ((size_t)h->n + 1) * 4));
     SPG_TRY(ensure(h, h->bhdr, (size_t)std::max(h->n, 1) * sizeof(int4)));
     SPG_TRY(ensure(h, h->cursor, NCLS * 4));
     SPG_TRY(ensure(h, h->lofs, M * 4));
@@ -412,7 +411,8 @@ void sym_stage_analysis(spg_handle h) {
     Control* ctl = h->ctl.as<Control>();
     launch_fill_u8(s, ctl, 0, sizeof(Control));
     if (h->m == 0) return;
-    launch_b_rowinfo(s, h->n, h->k, h->brp, h->bci, h->bnnz, h->binfo.as<int4>(), ctl);
+    launch_b_rows(s, h->n, h->k, h->brp, h->bci, h->bnnz, h->binfo.as<int4>(), h->bc.as<int2>(), h->bhdr.as<int4>(),
+                  ctl);
     launch_a_rowinfo(s, h->m, h->n, h->arp, h->aci, h->annz, h->binfo.as<int4>(), h->rinfo.as<RowInfo>(),
                      want_feats ? h->feats.as<float>() : nullptr, h->cfg, h->binning, h->sym_cls.as<uint8_t>(),
                      h->row_nnz.as<int32_t>(), h->row_blocks.as<int32_t>(), h->lofs.as<int32_t>(), ctl);
@@ -443,12 +443,9 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr, bool read_back = fal
     const bool learned = h->binning == 1;
     Control* ctl = h->ctl.as<Control>();
     const int wl = wide_lds(h);
-    // compressed B, read by both phases (skipped on malformed input)
-    launch_compress_b(s, h->n, h->brp, h->bci, h->binfo.as<int4>(), h->bcrp.as<int32_t>(), h->tile_status.as<uint64_t>(),
-                      &ctl->tile_counter_b, h->bc.as<int2>(), h->bhdr.as<int4>(), &ctl->err);
     SymArgs base{};
     base.arp = h->arp, base.aci = h->aci, base.brp = h->brp, base.bci = h->bci;
-    base.bcrp = h->bcrp.as<int32_t>(), base.bc = h->bc.as<int2>(), base.bhdr = h->bhdr.as<int4>();
+    base.bc = h->bc.as<int2>(), base.bhdr = h->bhdr.as<int4>();
     base.bc_total = h->bc_runs;
     base.rinfo = h->rinfo.as<RowInfo>();
     base.row_nnz = h->row_nnz.as<int32_t>();
@@ -736,7 +733,7 @@ spg_status num_launch_all(spg_handle h, const void* a_vals, const void* b_vals, 
         a.mode = c / NTIER;
         a.arp = h->arp, a.aci = h->aci, a.av = a_vals;
         a.brp = h->brp, a.bci = h->bci, a.bv = b_vals;
-        a.bcrp = h->bcrp.as<int32_t>(), a.bc = h->bc.as<int2>(), a.bhdr = h->bhdr.as<int4>();
+        a.bc = h->bc.as<int2>(), a.bhdr = h->bhdr.as<int4>();
         a.bc_total = h->bc_runs;
         a.bnnz = h->bnnz;
         a.crp = h->crp;
@@ -820,7 +817,7 @@ spg_status spg_destroy(spg_handle h) {
     DevBuf* bufs[] = {&h->binfo, &h->rinfo, &h->feats, &h->sym_cls, &h->num_cls, &h->perm_sym, &h->perm_num,
                       &h->desc_sym, &h->desc_num,
                       &h->row_nnz, &h->row_blocks, &h->tile_status, &h->cursor, &h->ovf_list, &h->ctl,
-                      &h->slab_sym, &h->slab_retry, &h->slab_num, &h->mlp_w, &h->bcrp, &h->bc, &h->bhdr,
+                      &h->slab_sym, &h->slab_retry, &h->slab_num, &h->mlp_w, &h->bc, &h->bhdr,
                       &h->lofs, &h->lists, &h->toff, &h->titems, &h->tfb, &h->slab_paper};
     for (DevBuf* b : bufs) release(*b, h->stream);
     if (h->hctl) (void)hipHostFree(h->hctl);
@@ -1172,11 +1169,7 @@ spg_status queue_prepare(spg_batch b) {
                      "a row of C spans " + std::to_string(c.max_words_all * 32) +
                          " columns; the queued kernel holds rows of up to " + std::to_string(QUEUE_MAX_WORDS * 32) +
                          " (use spg_batch_run)");
-    // compressed B for the symbolic items (the structure is fixed: built once)
-    SPG_TRY(ensure(h, h->bc, (size_t)std::max<int64_t>(c.bc_total, 1) * sizeof(int2)));
-    launch_compress_b(b->stream, h->n, h->brp, h->bci, h->binfo.as<int4>(), h->bcrp.as<int32_t>(),
-                      h->tile_status.as<uint64_t>(), &h->ctl.as<Control>()->tile_counter_b, h->bc.as<int2>(),
-                      h->bhdr.as<int4>());
+    // compressed B for the symbolic items: built by the analysis above
     b->q_wmax = (int)std::max<int64_t>(c.max_words_all, 1);
     b->q_vmax = 32 * b->q_wmax;
     const int32_t cnt = b->count;

@@ -267,7 +267,6 @@ struct Control {
     int64_t num_c_nnz[NCLS];
     int64_t num_products[NCLS];
     int32_t tile_counter;         // dynamic tile id of the row-pointer scan
-    int32_t tile_counter_b;       // dynamic tile id of the compressed-B scan
     int64_t bc_total;             // runs of compressed B
     int64_t list_total;           // list pairs reserved by the grouping of the symbolic rows
     int32_t tile_fallback;        // tiled global path: rows left to the segment path
@@ -285,17 +284,13 @@ struct Control {
 // ---- launch wrappers (spg_rows.hip) ----
 void launch_fill_i32(hipStream_t s, int32_t* p, int32_t v, int64_t n);
 void launch_fill_u8(hipStream_t s, void* p, uint8_t v, int64_t bytes);
-void launch_b_rowinfo(hipStream_t s, int32_t n, int32_t k, const int32_t* brp, const int32_t* bci, int64_t bnnz,
-                      int4* binfo, Control* ctl);
-// compressed B (section 2.2.1): per B row, runs of consecutive entries in one
-// 32-column block become one {block, OR of the column bits} entry.  binfo.w
-// holds each row's run count; bcrp gets their exclusive scan (n+1 entries,
-// tile status scratch of scan_tiles(n)+1 words), bc the runs, and bhdr per B
-// row {first entry, length, first run, run count}.
-// err (device, may be null): both kernels exit at once when it holds an input error
-void launch_compress_b(hipStream_t s, int32_t n, const int32_t* brp, const int32_t* bci, const int4* binfo,
-                       int32_t* bcrp, uint64_t* tile_status, int32_t* tile_counter, int2* bc, int4* bhdr,
-                       const int32_t* err = nullptr);
+// B rows in one pass: validation, binfo {length, smallest column, largest
+// column, runs} and compressed B (section 2.2.1): per row its runs of entries
+// sharing a 32-column block as {block, OR of the column bits}, stored from the
+// row's own first entry on (bc holds b_nnz runs), and bhdr per row {first
+// entry, length, first run, run count}.
+void launch_b_rows(hipStream_t s, int32_t n, int32_t k, const int32_t* brp, const int32_t* bci, int64_t bnnz,
+                   int4* binfo, int2* bc, int4* bhdr, Control* ctl);
 void launch_a_rowinfo(hipStream_t s, int32_t m, int32_t n, const int32_t* arp, const int32_t* aci, int64_t annz,
                       const int4* binfo, RowInfo* rinfo, float* feats, ClassCfg cfg, int binning,
                       uint8_t* sym_cls, int32_t* row_nnz, int32_t* row_blocks, int32_t* lofs, Control* ctl);
@@ -333,8 +328,7 @@ struct SymArgs {
     const int32_t* aci;
     const int32_t* brp;
     const int32_t* bci;
-    const int32_t* bcrp;          // compressed B: row pointer and {block, mask} runs
-    const int2* bc;
+    const int2* bc;               // compressed B: {block, mask} runs (bhdr gives each row's)
     const int4* bhdr;             // per B row {start, length, run start, run count}
     int64_t bc_total;             // runs of compressed B (bound of the group loads)
     const RowInfo* rinfo;
@@ -363,7 +357,6 @@ struct NumArgs {
     const int32_t* brp;
     const int32_t* bci;
     const void* bv;
-    const int32_t* bcrp;
     const int2* bc;
     const int4* bhdr;             // per B row {start, length, run start, run count}
     int64_t bnnz;                 // entries of B and of compressed B (bounds of the

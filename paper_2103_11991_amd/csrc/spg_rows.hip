@@ -64,68 +64,6 @@ __device__ inline int64_t rowq_sum64(int64_t v) {
     return v;
 }
 
-// B rows: length, smallest and largest column, and the number of runs of
-// consecutive entries that share a 32-column block (the length of the row in
-// compressed B).  Checks B's row pointer and column indices; a malformed row
-// contributes nothing.  Grid-stride, one flush of the run total per workgroup.
-__global__ __launch_bounds__(256) void k_b_rowinfo(int32_t n, int32_t k, const int32_t* __restrict__ brp,
-                                                   const int32_t* __restrict__ bci, int64_t bnnz,
-                                                   int4* __restrict__ binfo, Control* ctl) {
-    __shared__ unsigned long long runs_sum;
-    if (threadIdx.x == 0) runs_sum = 0;
-    __syncthreads();
-    const int lane = (int)(threadIdx.x % AN_LANES);
-    const int64_t rows_per_block = blockDim.x / AN_LANES;
-    for (int64_t rb = blockIdx.x * rows_per_block; rb < n; rb += (int64_t)gridDim.x * rows_per_block) {
-        const int64_t row = rb + threadIdx.x / AN_LANES;
-        int len = 0, mn = INT_MAX, mx = -1, bad = 0, runs = 0;
-        if (row < n) {
-            int32_t s = brp[row], e = brp[row + 1];
-            if (s < 0 || e < s || (int64_t)e > bnnz || (row == 0 && s != 0) ||
-                (row == n - 1 && (int64_t)e != bnnz)) {
-                bad = ERR_B_ROWPTR;
-            } else {
-                len = e - s;
-                // independent entry loads per lane (with each entry's
-                // predecessor), then their checks
-                for (int32_t p0 = s + lane; p0 < e; p0 += AN_LOADS * AN_LANES) {
-                    int c[AN_LOADS], cp[AN_LOADS];
-#pragma unroll
-                    for (int u = 0; u < AN_LOADS; ++u) {
-                        const int32_t q = p0 + u * AN_LANES;
-                        c[u] = q < e ? bci[q] : 0;
-                        cp[u] = q < e && q > s ? bci[q - 1] : 0;
-                    }
-#pragma unroll
-                    for (int u = 0; u < AN_LOADS; ++u) {
-                        const int32_t q = p0 + u * AN_LANES;
-                        if (q >= e) continue;
-                        if (c[u] < 0 || c[u] >= k) {
-                            bad = ERR_B_COL;
-                            continue;
-                        }
-                        mn = min(mn, c[u]);
-                        mx = max(mx, c[u]);
-                        runs += q == s || (cp[u] >> 5) != (c[u] >> 5);
-                    }
-                }
-            }
-        }
-        mn = rowq_min(mn);
-        mx = rowq_max(mx);
-        runs = rowq_sum(runs);
-        int anybad = rowq_or(bad);
-        if (row < n && lane == 0) {
-            if (anybad) len = 0, mn = INT_MAX, mx = -1, runs = 0;
-            binfo[row] = make_int4(len, mn, mx, runs);
-            if (runs) atomicAdd(&runs_sum, (unsigned long long)runs);
-        }
-        if (bad) atomicOr(&ctl->err, bad);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0 && runs_sum) atomicAdd((unsigned long long*)&ctl->bc_total, runs_sum);
-}
-
 __device__ inline float log2p1(int64_t v) { return log2f(1.0f + (float)v); }
 
 // A rows: products, column range, largest B row; symbolic class from an upper
@@ -619,95 +557,50 @@ __global__ __launch_bounds__(256) void k_pack(int32_t count, const int64_t* __re
     }
 }
 
-// Exclusive scan of the run counts (binfo[j].w) into compressed B's row
-// pointer, single pass with decoupled look-back (same scheme as k_scan).
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_runs(int32_t n, const int4* __restrict__ binfo,
-                                                            int32_t* __restrict__ bcrp, uint64_t* tile_status,
-                                                            int32_t* tile_counter, const int32_t* err) {
-    __shared__ int32_t tile_sh;
-    __shared__ int64_t wsum[SCAN_THREADS / 64];
-    __shared__ int64_t tile_prefix;
-    if (err && (*err & ERR_INPUT)) return;  // the same for every workgroup: none waits on another
-    if (threadIdx.x == 0) tile_sh = atomicAdd(tile_counter, 1);
-    __syncthreads();
-    const int tile = tile_sh;
-    const int64_t r0 = (int64_t)tile * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
-    int64_t v[SCAN_ITEMS];
-    int64_t run = 0;
-#pragma unroll
-    for (int t = 0; t < SCAN_ITEMS; ++t) {
-        const int64_t r = r0 + t;
-        run += r < n ? binfo[r].w : 0;
-        v[t] = run;
-    }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int64_t x = run;
-    for (int d = 1; d < 64; d <<= 1) {
-        int64_t y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
-    if (lane == 63) wsum[wv] = x;
-    __syncthreads();
-    int64_t wpre = 0, agg = 0;
-    for (int u = 0; u < SCAN_THREADS / 64; ++u) {
-        if (u < wv) wpre += wsum[u];
-        agg += wsum[u];
-    }
-    if (threadIdx.x == 0) {
-        int64_t prefix = 0;
-        if (tile == 0) {
-            __hip_atomic_store(&tile_status[0], ST_PRE | (uint64_t)agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(&tile_status[tile], ST_AGG | (uint64_t)agg, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            for (int t = tile - 1; t >= 0; --t) {
-                uint64_t st;
-                do {
-                    st = __hip_atomic_load(&tile_status[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                } while ((st >> 62) == 0);
-                prefix += (int64_t)(st & ST_VAL);
-                if ((st >> 62) == 2) break;
-            }
-            __hip_atomic_store(&tile_status[tile], ST_PRE | (uint64_t)(prefix + agg), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        }
-        tile_prefix = prefix;
-    }
-    __syncthreads();
-    const int64_t base = tile_prefix + wpre + x - run;
-#pragma unroll
-    for (int t = 0; t < SCAN_ITEMS; ++t) {
-        const int64_t r = r0 + t;
-        if (r < n) bcrp[r + 1] = (int32_t)(base + v[t]);
-    }
-    if (tile == 0 && threadIdx.x == 0) bcrp[0] = 0;
+// Reduction over an aligned group of 8 lanes: quad swaps, then the half-row
+// mirror (lane i with lane 7 - i), after which every lane holds the result.
+template <typename Op>
+__device__ inline int row8_reduce(int v, Op op) {
+    v = op(v, __builtin_amdgcn_mov_dpp(v, 0xb1, 0xf, 0xf, false));   // quad_perm [1,0,3,2]
+    v = op(v, __builtin_amdgcn_mov_dpp(v, 0x4e, 0xf, 0xf, false));   // quad_perm [2,3,0,1]
+    v = op(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xf, 0xf, false));  // row_half_mirror
+    return v;
 }
 
-// Writes each B row's runs {block id, OR of the bits of its columns} and its
-// header {first entry, length, first run, run count}.  ROW_LANES lanes per row
-// read the row in coalesced chunks: an entry starts a run when its block
-// differs from the previous entry's, a segmented OR across the chunk gathers
-// each run's bits, and the lane holding a run's last entry writes it at the
-// run's index (runs begun before it in the row).
-__global__ __launch_bounds__(256) void k_compress_b(int32_t n, const int32_t* __restrict__ brp,
-                                                    const int32_t* __restrict__ bci, const int32_t* __restrict__ bcrp,
-                                                    int2* __restrict__ bc, int4* __restrict__ bhdr,
-                                                    const int32_t* err) {
+// B rows in one pass, ROW_LANES lanes per row reading it in coalesced chunks:
+// the row pointer and the columns are checked; the row's length, smallest
+// and largest column go to binfo; and the row is compressed (section 2.2.1):
+// every run of consecutive entries that share a 32-column block becomes one
+// {block, OR of the column bits} entry.  A row has at most as many runs as
+// entries, so its runs are stored from the row's own first entry on (no scan
+// places them), and the header {first entry, length, first run, run count}
+// and binfo's run count follow.  An entry starts a run when its block differs
+// from the previous entry's; a segmented OR across the chunk gathers each
+// run's bits, and the lane holding a run's last entry writes it at the run's
+// index (runs begun before it in the row).  A malformed row gets length and
+// runs 0 and raises the error flag, on which every later kernel exits.
+__global__ __launch_bounds__(256) void k_b_rows(int32_t n, int32_t k, const int32_t* __restrict__ brp,
+                                                const int32_t* __restrict__ bci, int64_t bnnz, int4* __restrict__ binfo,
+                                                int2* __restrict__ bc, int4* __restrict__ bhdr, Control* ctl) {
     constexpr int L = ROW_LANES;
-    if (err && (*err & ERR_INPUT)) return;
     static_assert(L == 8, "the DPP shifts and swizzles below assume 8-lane groups");
+    __shared__ unsigned long long runs_sum;
+    if (threadIdx.x == 0) runs_sum = 0;
+    __syncthreads();
     const int sl = threadIdx.x % L;
     const int shift = (threadIdx.x & 63) & ~(L - 1);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x / L;
     for (int64_t j = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / L; j < n; j += stride) {
         const int32_t s = brp[j], e = brp[j + 1];
-        const int32_t o = bcrp[j];
-        if (sl == 0) bhdr[j] = make_int4(s, e - s, o, bcrp[j + 1] - o);
+        int bad = 0;
+        if (s < 0 || e < s || (int64_t)e > bnnz || (j == 0 && s != 0) || (j == n - 1 && (int64_t)e != bnnz))
+            bad = ERR_B_ROWPTR;
         int done = 0;          // runs begun in earlier chunks
+        int mn = INT_MAX, mx = -1;
         uint32_t carry = 0;    // bits of the run still open at the end of the last chunk
         int last_blk = -1;     // block of the last chunk's final entry
         // four chunks' entries (and the entry after each chunk) are loaded at once
-        for (int32_t Q0 = s; Q0 < e; Q0 += 4 * L) {
+        for (int32_t Q0 = s; !bad && Q0 < e; Q0 += 4 * L) {
             int cc[4], nx[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -722,6 +615,11 @@ __global__ __launch_bounds__(256) void k_compress_b(int32_t n, const int32_t* __
             const int32_t q = q0 + sl;
             const bool v = q < e;
             const int c = cc[u];
+            if (v) {
+                if (c < 0 || c >= k) bad = ERR_B_COL;
+                mn = min(mn, c);
+                mx = max(mx, c);
+            }
             const int blk = v ? c >> 5 : -1;
             // neighbours inside the 8-lane group: DPP row shifts (a group is an
             // aligned half of a 16-lane row; the lanes whose neighbour lies
@@ -750,14 +648,30 @@ __global__ __launch_bounds__(256) void k_compress_b(int32_t n, const int32_t* __
             if (!f) m |= carry;
             const uint64_t starts = (__ballot(start) >> shift) & ((1ull << L) - 1);
             const int idx = done + __popcll(starts & ((2ull << sl) - 1)) - 1;
-            if (last) bc[o + idx] = make_int2(blk, (int)m);
+            if (last) bc[s + idx] = make_int2(blk, (int)m);
             done += __popcll(starts);
             // lane 7 of each group to the whole group: swizzle lane -> (lane & 0x18) | 7
             carry = (uint32_t)__builtin_amdgcn_ds_swizzle((int)m, 0xF8);
             last_blk = __builtin_amdgcn_ds_swizzle(blk, 0xF8);
             }
+            bad = row8_reduce(bad, [](int x, int y) { return x | y; });
+        }
+        mn = row8_reduce(mn, [](int x, int y) { return min(x, y); });
+        mx = row8_reduce(mx, [](int x, int y) { return max(x, y); });
+        if (sl == 0) {
+            if (bad) {
+                atomicOr(&ctl->err, bad);
+                binfo[j] = make_int4(0, INT_MAX, -1, 0);
+                bhdr[j] = make_int4(0, 0, 0, 0);
+            } else {
+                binfo[j] = make_int4(e - s, mn, mx, done);
+                bhdr[j] = make_int4(s, e - s, s, done);
+                if (done) atomicAdd(&runs_sum, (unsigned long long)done);
+            }
         }
     }
+    __syncthreads();
+    if (threadIdx.x == 0 && runs_sum) atomicAdd((unsigned long long*)&ctl->bc_total, runs_sum);
 }
 
 inline unsigned grid_for(int64_t threads, int per_block) {
@@ -790,25 +704,11 @@ void launch_fill_u8(hipStream_t s, void* p, uint8_t v, int64_t bytes) {
     hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)g), dim3(256), 0, s, (uint8_t*)p, v, bytes);
 }
 
-void launch_b_rowinfo(hipStream_t s, int32_t n, int32_t k, const int32_t* brp, const int32_t* bci, int64_t bnnz,
-                      int4* binfo, Control* ctl) {
+void launch_b_rows(hipStream_t s, int32_t n, int32_t k, const int32_t* brp, const int32_t* bci, int64_t bnnz,
+                   int4* binfo, int2* bc, int4* bhdr, Control* ctl) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_b_rowinfo, dim3(std::min(grid_for((int64_t)n * AN_LANES, 256), 4096u)), dim3(256), 0, s, n,
-                       k, brp, bci, bnnz, binfo, ctl);
-}
-
-void launch_compress_b(hipStream_t s, int32_t n, const int32_t* brp, const int32_t* bci, const int4* binfo,
-                       int32_t* bcrp, uint64_t* tile_status, int32_t* tile_counter, int2* bc, int4* bhdr,
-                       const int32_t* err) {
-    if (n <= 0) {
-        launch_fill_i32(s, bcrp, 0, 1);
-        return;
-    }
-    launch_fill_u8(s, tile_status, 0, (scan_tiles(n) + 1) * 8);
-    hipLaunchKernelGGL(k_scan_runs, dim3((unsigned)scan_tiles(n)), dim3(SCAN_THREADS), 0, s, n, binfo, bcrp,
-                       tile_status, tile_counter, err);
-    hipLaunchKernelGGL(k_compress_b, dim3(std::min(grid_for((int64_t)n * ROW_LANES, 256), 4096u)), dim3(256), 0, s, n,
-                       brp, bci, bcrp, bc, bhdr, err);
+    hipLaunchKernelGGL(k_b_rows, dim3(std::min(grid_for((int64_t)n * ROW_LANES, 256), 4096u)), dim3(256), 0, s, n, k,
+                       brp, bci, bnnz, binfo, bc, bhdr, ctl);
 }
 
 void launch_a_rowinfo(hipStream_t s, int32_t m, int32_t n, const int32_t* arp, const int32_t* aci, int64_t annz,
