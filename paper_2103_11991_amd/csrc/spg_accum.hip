@@ -1449,17 +1449,6 @@ __global__ __launch_bounds__(256) void k_tile_items(TileArgs a) {
     }
 }
 
-// Position of the k-th set bit (k from 0) of m, which has more than k bits set.
-__device__ inline int kth_bit(uint32_t m, int k) {
-    int pos = 0;
-#pragma unroll
-    for (int w = 16; w >= 1; w >>= 1) {
-        const int c = __popc(m & ((1u << w) - 1u));
-        if (k >= c) k -= c, m >>= w, pos += w;
-    }
-    return pos;
-}
-
 // Work units, strided over the grid: first one per (tile, row) of the rows
 // of more than TILE_G entries of A (their chunks are restaged per tile, and
 // the units of one row run on many workgroups), then one per other row, whose
@@ -1475,9 +1464,8 @@ __global__ __launch_bounds__(TILE_G) void k_num_tiled(TileArgs a) {
     constexpr int W = TILE_BYTES / (int)sizeof(T);  // columns per tile
     constexpr int NB = W / 32;                       // blocks per tile
     constexpr int K = sizeof(T) == 8 ? FLAT_KB_F64 : FLAT_KB_F32;
+    static_assert(NB <= G, "a tile's list pairs must fit one per lane");
     __shared__ T dense[W];
-    __shared__ int2 pc[NB];
-    __shared__ int pref[NB];
     __shared__ int2 off[G];
     __shared__ T ava[G];
     __shared__ Win win[K * (G / 64)];
@@ -1513,27 +1501,35 @@ __global__ __launch_bounds__(TILE_G) void k_num_tiled(TileArgs a) {
         for (int q = tr[t] + tid; q < tr[t + 1]; q += G) atomicAdd(&dense[a.bci[q] - col0], bv[q]);
         __syncthreads();
     };
-    // after the walk: ranks from the pairs, then columns and values out
+    // after the walk: the tile's columns in rank order, then columns and
+    // values out (coalesced).  Each lane holds one list pair (np <= W / 32 =
+    // G) and places its columns at their ranks (its exclusive prefix of
+    // popcounts on): chunk by chunk of 2G ranks into the staging area, which
+    // the walk no longer needs, and each chunk is then written out.
     auto end_tile = [&](int i, int col0, int4 d, int np, int2 pr) {
+        constexpr int CH = 2 * G;
+        int* cbuf = reinterpret_cast<int*>(off);
         int n_t;
-        const int ex = group_excl_scan<G>(tid < np ? __popc((uint32_t)pr.y) : 0, n_t, red);
-        if (tid < np) pc[tid] = pr, pref[tid] = ex;
-        __syncthreads();
+        int pos = group_excl_scan<G>(tid < np ? __popc((uint32_t)pr.y) : 0, n_t, red);
+        uint32_t rest = tid < np ? (uint32_t)pr.y : 0u;  // the pair's columns not yet placed
+        const int first = tid < np ? (pr.x << 5) - col0 : 0;
         const int64_t coff = (int64_t)a.crp[i] + d.w;
-        for (int q = tid; q < n_t; q += G) {
-            int lo = 0, hi = np - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (pref[mid] <= q) lo = mid;
-                else hi = mid - 1;
+        for (int q0 = 0; q0 < n_t; q0 += CH) {
+            while (rest && pos < q0 + CH) {
+                cbuf[pos - q0] = first + __builtin_ctz(rest);
+                rest &= rest - 1u;
+                ++pos;
             }
-            const int2 e = pc[lo];
-            const int c = (e.x << 5) + kth_bit((uint32_t)e.y, q - pref[lo]);
-            a.ccol[coff + q] = c;
-            cvals[coff + q] = dense[c - col0];
-            dense[c - col0] = T(0);
+            __syncthreads();
+            const int q1 = min(q0 + CH, n_t);
+            for (int q = q0 + tid; q < q1; q += G) {
+                const int cl = cbuf[q - q0];
+                a.ccol[coff + q] = col0 + cl;
+                cvals[coff + q] = dense[cl];
+                dense[cl] = T(0);
+            }
+            __syncthreads();
         }
-        __syncthreads();
     };
     for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
         if (u < (int64_t)nh * T_) {
