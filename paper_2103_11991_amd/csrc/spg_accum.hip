@@ -453,7 +453,43 @@ struct Batch {
         for (int k = 0; k < K; ++k)
             if (P0 + k * G + lane < P) apply(v[k], view.entry(k, wv, le));
     }
+    // every lane, with whether its slot holds a group (for cross-lane work)
+    template <typename F>
+    __device__ inline void consume_all(int P0, int P, int lane, F&& f) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) f(v[k], P0 + k * G + lane < P);
+    }
 };
+
+// ORs `bits` into l1[key].x; lanes next to each other in one group that hold
+// the same key are OR-ed together first (a segmented OR over each aligned
+// run of 16 lanes with DPP row shifts; segments also start at every group's
+// first lane), and one lane per segment does the LDS atomic, which saves the
+// atomics' serialisation on one address.  key < 0: nothing.
+template <int G>
+__device__ inline void or_word_merged(uint2* l1, int key, uint32_t bits) {
+    const int l16 = threadIdx.x & 15, lg = threadIdx.x % G;
+    const int kp = __builtin_amdgcn_mov_dpp(key, 0x111, 0xf, 0xf, false);  // row_shr:1
+    const int kn = __builtin_amdgcn_mov_dpp(key, 0x101, 0xf, 0xf, false);  // row_shl:1
+    int f = l16 == 0 || lg == 0 || kp != key;
+    uint32_t m = bits;
+    const auto step = [&](uint32_t mu, int fu, int d) {
+        if (l16 >= d && !f) {
+            m |= mu;
+            f = fu;
+        }
+    };
+    step((uint32_t)__builtin_amdgcn_mov_dpp((int)m, 0x111, 0xf, 0xf, false),
+         __builtin_amdgcn_mov_dpp(f, 0x111, 0xf, 0xf, false), 1);  // row_shr:1
+    step((uint32_t)__builtin_amdgcn_mov_dpp((int)m, 0x112, 0xf, 0xf, false),
+         __builtin_amdgcn_mov_dpp(f, 0x112, 0xf, 0xf, false), 2);  // row_shr:2
+    step((uint32_t)__builtin_amdgcn_mov_dpp((int)m, 0x114, 0xf, 0xf, false),
+         __builtin_amdgcn_mov_dpp(f, 0x114, 0xf, 0xf, false), 4);  // row_shr:4
+    step((uint32_t)__builtin_amdgcn_mov_dpp((int)m, 0x118, 0xf, 0xf, false),
+         __builtin_amdgcn_mov_dpp(f, 0x118, 0xf, 0xf, false), 8);  // row_shr:8
+    const bool last = l16 == 15 || lg == G - 1 || kn != key;
+    if (last && key >= 0) atomicOr(&l1[key].x, m);
+}
 
 // Turns apply(element, entry) into apply(group, entry) over the valid elements.
 template <typename F>
@@ -657,17 +693,32 @@ __device__ __forceinline__ void sym_row(const SymArgs& a, const int4 d, const in
             }
         }
     };
+    auto walk_runs_all = [&](auto&& f) {
+        for (int e0 = a0; e0 < a1; e0 += G) {
+            restage(e0);
+            for (int P0 = 0; P0 < PC; P0 += KC * G) {
+                rewin(P0);
+                Batch<G, KC, VC, decltype(load_run)> bt;
+                bt.issue(cq, win, P0, PC, lane, wv, le, load_run);
+                bt.consume_all(P0, PC, lane, f);
+            }
+        }
+    };
 
     int cnt = 0, nb = 0;
-    auto finish = [&](auto&& runs) {
+    // runs(apply): apply(run, entry) on every run; runs_all(f): f(group,
+    // valid) on every lane of every batch
+    auto finish = [&](auto&& runs, auto&& runs_all) {
         if constexpr (MODE == MODE_TWOLEVEL) {
             // pass A: occupied blocks; their count and compact indices from a
-            // prefix of popcounts; pass B: masks OR-ed in at the compact index
-            auto mark = [&](int2 run, int) {
-                const int w = run.x - base;
-                atomicOr(&l1[w >> 5].x, 1u << (w & 31));
+            // prefix of popcounts; pass B: masks OR-ed in at the compact index.
+            // Neighbouring lanes mostly mark blocks of one word (a B row's runs
+            // in one plane of a stencil): their bits are merged first.
+            auto mark = [&](const auto& g, bool valid) {
+                const int w = g.r[0].x - base;
+                or_word_merged<G>(l1, valid ? w >> 5 : -1, valid ? 1u << (w & 31) : 0u);
             };
-            runs(each(mark));
+            runs_all(mark);
             group_sync<G>();
             {
                 const int chunk = (w1 + G - 1) / G;
@@ -730,9 +781,10 @@ __device__ __forceinline__ void sym_row(const SymArgs& a, const int4 d, const in
         // the whole row in one batch: its runs stay in registers for every pass
         Batch<G, KC, VC, decltype(load_run)> br;
         br.issue(cq, win, 0, PC, lane, wv, le, load_run);
-        finish([&](auto&& apply) { br.consume(0, PC, lane, wv, le, apply); });
+        finish([&](auto&& apply) { br.consume(0, PC, lane, wv, le, apply); },
+               [&](auto&& f) { br.consume_all(0, PC, lane, f); });
     } else {
-        finish(walk_runs);
+        finish(walk_runs, walk_runs_all);
     }
     if constexpr (MODE != MODE_TWOLEVEL) {
         cnt = group_sum<G>(cnt, red);
