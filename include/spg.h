@@ -29,7 +29,8 @@
  *   - errors are reported as spg_status; no C++ exception crosses this ABI.
  *     spg_last_error returns a message for the last failing call on a handle;
  *   - all GPU work runs on the handle's stream, in order.  Only spg_symbolic
- *     waits for the device (it must return nnz(C) to the host).  One handle
+ *     waits for the device (it must return nnz(C) to the host; see there for
+ *     when it waits twice).  One handle
  *     must not be used from two host threads at once.
  */
 #ifndef SPG_H
@@ -97,7 +98,9 @@ typedef enum {
        block it may occupy (the smaller of its compressed-B run count and
        its column range in 32-column blocks); rows past the limit, and rows
        of the symbolic global path, are computed by numeric on its global
-       path instead. */
+       path instead.  When the bound m * (k/32 + 1) pairs is within both this
+       limit and 256 MiB, that bound is reserved before the phase runs (so
+       it waits once, see spg_symbolic). */
     SPG_OPT_LIST_LIMIT_MB = 9,
     /* run the rows of a class that has few rows in the next populated class
        of the same table mode with a larger tier (at most 4x the lanes per row,
@@ -194,7 +197,12 @@ spg_status spg_set_matrices(spg_handle h, spg_dtype dt, int32_t m, int32_t n, in
 
 /* Symbolic phase (section 2.2.1): writes C's row pointer into the caller's
    device array c_row_ptr[m+1] (c_row_ptr[0] = 0) and nnz(C) into *nnz_c
-   (host).  Waits for the stream.  c_row_ptr is borrowed by the handle and
+   (host).  Waits for the device once, for nnz(C), when the buffers the phase
+   fills fit bounds known before it runs (m * (k/32 + 1) list pairs within
+   256 MiB and the list limit); a larger product also reads the row analysis
+   back to size them exactly (two waits; spg_stats.sym_waits tells which).
+   Malformed input stops every kernel after the analysis on the device and
+   is reported after the wait.  c_row_ptr is borrowed by the handle and
    must stay valid and unchanged until the last spg_numeric.  The handle
    also keeps C's structure in compressed form (each row's occupied
    32-column blocks with their column bits, section 2.2.1's compressed
