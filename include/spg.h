@@ -366,7 +366,7 @@ spg_status spg_batch_tune(spg_batch b, const void* a_val_pool, const void* b_val
 /* Both phases of every product in one persistent kernel over a device work
    queue, with no host work between the products (section 3: many small
    operations in one dispatch; section 2.2.2: launch latency).  Work items
-   are (product, block of 64 rows, phase); a product's symbolic items
+   are (product, block of 128 rows, phase); a product's symbolic items
    compute its row sizes, the last of them to finish scans the product's
    row pointer (a segmented scan over the batch), takes the product's C
    space from a device bump allocator over the caller's pools and queues the

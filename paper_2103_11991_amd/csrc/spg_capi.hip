@@ -1150,7 +1150,7 @@ void drop_queue_graph(spg_batch b) {
     b->q_graph = nullptr;
 }
 
-constexpr int QUEUE_ROWS_PER_ITEM = 64;
+constexpr int QUEUE_ROWS_PER_ITEM = 128;
 
 // Once per batch: the row facts of the packed product (one synchronised
 // analysis), the widest row's range (which sizes the kernel's LDS windows, or
