@@ -170,11 +170,93 @@ void release(DevBuf& b, hipStream_t s) {
     b.pooled = false;
 }
 
+// Buffers (and pinned control blocks) of destroyed handles, kept per device
+// for the handles created after them: a chain of products that creates a
+// handle per product then allocates nothing after its first products (each
+// allocation or free is a runtime call of several microseconds, and a
+// handle has about twenty-five buffers).  A buffer enters only once its
+// handle's stream has finished (spg_destroy waits for it first), so a new
+// owner on another stream finds it idle.  At most 2 GiB are kept; a taken
+// buffer is at most twice (plus 1 MiB) the size asked for.
+struct CachedBuf {
+    void* p;
+    size_t cap;
+    int device;
+    bool pooled;
+};
+std::mutex g_cache_mu;
+std::vector<CachedBuf> g_cache;
+size_t g_cache_bytes = 0;
+std::vector<Control*> g_pinned;
+constexpr size_t CACHE_MAX_BYTES = (size_t)2 << 30;
+
+bool cache_take(int device, size_t bytes, DevBuf& b) {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    int best = -1;
+    for (int i = 0; i < (int)g_cache.size(); ++i) {
+        const CachedBuf& c = g_cache[i];
+        if (c.device != device || c.cap < bytes || c.cap > 2 * bytes + ((size_t)1 << 20)) continue;
+        if (best < 0 || c.cap < g_cache[best].cap) best = i;
+    }
+    if (best < 0) return false;
+    b.p = g_cache[best].p, b.cap = g_cache[best].cap, b.pooled = g_cache[best].pooled;
+    g_cache_bytes -= b.cap;
+    g_cache[best] = g_cache.back();
+    g_cache.pop_back();
+    return true;
+}
+
+// b's buffer into the cache (b idle), or freed when the cache is full.
+void cache_put(int device, DevBuf& b) {
+    if (!b.p) return;
+    {
+        std::lock_guard<std::mutex> lock(g_cache_mu);
+        if (g_cache_bytes + b.cap <= CACHE_MAX_BYTES) {
+            g_cache.push_back(CachedBuf{b.p, b.cap, device, b.pooled});
+            g_cache_bytes += b.cap;
+            b.p = nullptr, b.cap = 0, b.pooled = false;
+            return;
+        }
+    }
+    (void)hipFree(b.p);
+    b.p = nullptr, b.cap = 0, b.pooled = false;
+}
+
+Control* pinned_take() {
+    {
+        std::lock_guard<std::mutex> lock(g_cache_mu);
+        if (!g_pinned.empty()) {
+            Control* c = g_pinned.back();
+            g_pinned.pop_back();
+            return c;
+        }
+    }
+    Control* c = nullptr;
+    if (hipHostMalloc((void**)&c, sizeof(Control), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return c;
+}
+
+void pinned_put(Control* c) {
+    if (!c) return;
+    {
+        std::lock_guard<std::mutex> lock(g_cache_mu);
+        if (g_pinned.size() < 256) {
+            g_pinned.push_back(c);
+            return;
+        }
+    }
+    (void)hipHostFree(c);
+}
+
 // Grows b to at least `bytes` on the handle's stream (contents not kept).
 spg_status ensure(spg_handle h, DevBuf& b, size_t bytes) {
     if (bytes <= b.cap && b.p) return SPG_OK;
     release(b, h->stream);
     size_t want = std::max<size_t>(bytes, 256);
+    if (cache_take(h->device, want, b)) return SPG_OK;
     hipMemPool_t pool = lib_pool(h->device);
     hipError_t e = pool ? hipMallocFromPoolAsync(&b.p, want, pool, h->stream) : hipMalloc(&b.p, want);
     if (e != hipSuccess) {
@@ -797,7 +879,10 @@ spg_status spg_create(spg_handle* out, void* stream) {
         if (e == hipSuccess) e = hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
         if (e == hipSuccess)
             e = hipDeviceGetAttribute(&h->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device);
-        if (e == hipSuccess) e = hipHostMalloc((void**)&h->hctl, sizeof(Control), hipHostMallocDefault);
+        if (e == hipSuccess) {
+            h->hctl = pinned_take();
+            if (!h->hctl) e = hipErrorOutOfMemory;
+        }
         if (e != hipSuccess) {
             (void)hipGetLastError();
             delete h;
@@ -819,8 +904,8 @@ spg_status spg_destroy(spg_handle h) {
                       &h->row_nnz, &h->row_blocks, &h->tile_status, &h->cursor, &h->ovf_list, &h->ctl,
                       &h->slab_sym, &h->slab_retry, &h->slab_num, &h->mlp_w, &h->bc, &h->bhdr,
                       &h->lofs, &h->lists, &h->toff, &h->titems, &h->tfb, &h->slab_paper};
-    for (DevBuf* b : bufs) release(*b, h->stream);
-    if (h->hctl) (void)hipHostFree(h->hctl);
+    for (DevBuf* b : bufs) cache_put(h->device, *b);  // idle: the stream has finished
+    pinned_put(h->hctl);
     if (h->ev_made)
         for (auto& e : h->ev) (void)hipEventDestroy(e);
     if (h->ev_ctl) (void)hipEventDestroy(h->ev_ctl);
