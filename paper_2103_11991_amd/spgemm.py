@@ -76,6 +76,21 @@ class SpGEMM:
         self.h = _lib.spg_create(self.stream.cuda_stream)
         for k, v in options.items():
             _lib.spg_set_option(self.h, k, int(v))
+        self.set_matrices(A, B)
+
+    def set_matrices(self, A: DeviceCsr, B: DeviceCsr):
+        """New matrices on the same handle (its buffers are kept and grown as
+        needed); the symbolic result of the old ones is dropped."""
+        if A.n != B.m:
+            raise ValueError(f"inner dimensions differ: A is {A.m}x{A.n}, B is {B.m}x{B.n}")
+        if B.values.dtype != A.values.dtype:
+            raise TypeError("A and B values must have the same dtype")
+        for t, n, nm in ((A.row_ptr, A.m + 1, "A.row_ptr"), (B.row_ptr, B.m + 1, "B.row_ptr")):
+            _check_tensor(t, torch.int32, n, nm)
+        _check_tensor(A.col_idx, torch.int32, A.nnz, "A.col_idx")
+        _check_tensor(B.col_idx, torch.int32, B.nnz, "B.col_idx")
+        self.A, self.B = A, B
+        self.dtype = A.values.dtype
         _lib.spg_set_matrices(self.h, _dtype_code(self.dtype), A.m, A.n, B.n,
                               A.row_ptr.data_ptr(), A.col_idx.data_ptr(), A.nnz,
                               B.row_ptr.data_ptr(), B.col_idx.data_ptr(), B.nnz)
