@@ -205,14 +205,28 @@ constexpr int waves_of() {
     return G > 64 ? G / 64 : 1;
 }
 
-// Workgroups are spread round-robin over the XCDs; renumber them so that
-// each XCD takes a contiguous range of rows (its L2 then holds the B rows
-// that neighbouring rows share).  A bijection of [0, nblk).
+// Workgroups are dispatched in order, round-robin over the 8 XCDs; renumber
+// them so that each XCD takes runs of `span` consecutive slots (its L2 then
+// holds the B rows that neighbouring rows share) while the 8 XCDs work on
+// neighbouring runs at any time: rows are grouped in ascending row order,
+// and where row sizes drift along it (R-MAT's heavy rows have low indices)
+// one contiguous share per XCD would leave the first XCD with the heaviest
+// rows and the others waiting.  Workgroups of 256 lanes or more hold one
+// long row each: they keep the dispatch order (span 1), which balances
+// best; shorter rows take runs of 64 workgroups (measured: 27-point
+// stencil numeric 1.06 ms against 1.10 with span 1 and 1.13 with one share
+// per XCD; R-MAT's 1024-lane symbolic rows 4.5 ms with span 1, 4.9 with 64,
+// 9.3 with one share per XCD).  A bijection of [0, nblk): whole rounds of 8
+// runs are renumbered, the remainder is left in dispatch order.
+template <int G>
 __device__ inline int xcd_block(int b, int nblk) {
     constexpr int NXCD = 8;
-    const int q = nblk / NXCD, r = nblk % NXCD;
+    constexpr int span = G >= 256 ? 1 : 64;
+    if constexpr (span == 1) return b;
+    const int full = nblk / (NXCD * span) * (NXCD * span);
+    if (b >= full) return b;
     const int x = b % NXCD, k = b / NXCD;
-    return x * q + min(x, r) + k;
+    return ((k / span) * NXCD + x) * span + k % span;
 }
 
 template <int G>
@@ -433,16 +447,25 @@ struct Batch {
     using R = decltype(std::declval<Load>()(0, 0));
     R v[K];
     WinView<G, K> view;
+    // Every staged offset is read before the first load goes out, and no
+    // load of an earlier batch is still in flight here (the caller consumed
+    // it): the explicit wait tells the compiler so, which otherwise orders
+    // the K loads one after another behind waits for registers that the
+    // previous batch's loads wrote.
     __device__ inline void issue(const int2* off, const Win* win, int P0, int P, int lane, int wv,
                                  unsigned long long le, Load& load) {
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
         view.load(win, wv);
+        int2 o[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            o[k] = make_int2(0, 0);
+            if (P0 + k * G + lane < P) o[k] = off[view.entry(k, wv, le)];
+        }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int g = P0 + k * G + lane;
-            if (g < P) {
-                const int2 o = off[view.entry(k, wv, le)];
-                v[k] = load(o.x + V * g, o.y);
-            }
+            if (g < P) v[k] = load(o[k].x + V * g, o[k].y);
         }
     }
     // the entry is found again here rather than held in a register across the
@@ -918,7 +941,7 @@ void k_sym(SymArgs a) {
     __shared__ int ovf[RPW];
     // a group of 64 or more lanes owns whole wavefronts: its row is wave-uniform
     const int sub = G >= 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / G) : threadIdx.x / G;
-    const int slot = xcd_block(blockIdx.x, gridDim.x) * RPW + sub;
+    const int slot = xcd_block<G>(blockIdx.x, gridDim.x) * RPW + sub;
     if (slot >= a.count) return;  // uniform in the group (in the workgroup when G >= 128)
     sym_row<G, MODE>(a, a.desc[slot], sub, smem, red, occ, ovf);
 }
@@ -1037,7 +1060,7 @@ void k_num(NumArgs a) {
     const int sub = G >= 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x / G) : threadIdx.x / G;
     const int lane = threadIdx.x % G, wv = lane >> 6;
     const unsigned long long le = (2ull << (lane & 63)) - 1;
-    const int slot = xcd_block(blockIdx.x, gridDim.x) * RPW + sub;
+    const int slot = xcd_block<G>(blockIdx.x, gridDim.x) * RPW + sub;
     if (slot >= a.count) return;
     const int4 d = a.desc[slot];
     const int i = d.x, a0 = d.y, a1 = d.z, off = d.w;

@@ -404,7 +404,7 @@ spg_status sym_prepare(spg_handle h) {
     SPG_TRY(ensure(h, h->row_blocks, M * 4));
     SPG_TRY(ensure(h, h->tile_status, (size_t)(scan_tiles(std::max(m, h->n)) + 1) * 8));
     SPG_TRY(ensure(h, h->bhdr, (size_t)std::max(h->n, 1) * sizeof(int4)));
-    SPG_TRY(ensure(h, h->cursor, NCLS * 4));
+    SPG_TRY(ensure(h, h->cursor, scatter_state_bytes(m)));
     SPG_TRY(ensure(h, h->lofs, M * 4));
     if (learned) SPG_TRY(ensure(h, h->ovf_list, M * 4));
     if (want_feats) SPG_TRY(ensure(h, h->feats, M * 12));
@@ -506,7 +506,6 @@ void sym_stage_analysis(spg_handle h) {
     }
     // rows grouped by symbolic launch class (small classes merged); each
     // row's list placed (the total is read back)
-    launch_fill_i32(s, h->cursor.as<int32_t>(), 0, NCLS);
     launch_scatter(s, h->m, h->sym_cls.as<uint8_t>(), merging(h), ctl->sym_hist, h->cursor.as<int32_t>(),
                    h->perm_sym.as<int32_t>(), h->arp, nullptr, h->desc_sym.as<int4>(), h->lofs.as<int32_t>(), ctl,
                    h->list_cap);
@@ -650,7 +649,6 @@ spg_status sym_stage_rows(spg_handle h, int32_t* c_row_ptr, bool read_back = fal
         HIP_TRY(h, hipMemcpyAsync(h->hctl, h->ctl.p, sizeof(Control), hipMemcpyDeviceToHost, s));
         HIP_TRY(h, hipEventRecord(h->ev_ctl, s));
     }
-    launch_fill_i32(s, h->cursor.as<int32_t>(), 0, NCLS);
     launch_scatter(s, m, h->num_cls.as<uint8_t>(), merging(h), ctl->num_hist, h->cursor.as<int32_t>(),
                    h->perm_num.as<int32_t>(), h->arp, c_row_ptr, h->desc_num.as<int4>());
     hipError_t e = hipGetLastError();

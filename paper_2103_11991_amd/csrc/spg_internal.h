@@ -303,7 +303,10 @@ void launch_mlp_classify(hipStream_t s, int32_t m, const float* feats, const flo
 // path and rows past list_limit pairs), reserved from ctl->list_total; desc.w
 // gets the same offset.
 // With merge, rows are grouped by their launch class (merge_classes).
-void launch_scatter(hipStream_t s, int32_t m, const uint8_t* cls, int merge, const int32_t* hist, int32_t* cursor,
+// Each class's rows come in ascending row order up to the order inside a
+// chunk of 2048 rows.  state (scatter_state_bytes(m) bytes) is cleared here.
+size_t scatter_state_bytes(int32_t m);
+void launch_scatter(hipStream_t s, int32_t m, const uint8_t* cls, int merge, const int32_t* hist, int32_t* state,
                     int32_t* perm, const int32_t* arp, const int32_t* crp, int4* desc, int32_t* lofs = nullptr,
                     Control* ctl = nullptr, int64_t list_limit = 0);
 void launch_scan(hipStream_t s, int32_t m, const int32_t* row_nnz, const int32_t* row_blocks, const RowInfo* rinfo,

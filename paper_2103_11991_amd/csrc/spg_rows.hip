@@ -96,21 +96,32 @@ __global__ __launch_bounds__(256) void k_a_rowinfo(int32_t m, int32_t n, const i
                 bad = ERR_A_ROWPTR;
             } else {
                 len = e - s;
-                // independent index loads, then their gathers
+                // independent index loads, then their gathers.  Every load is
+                // unconditional (indices clamped into the row, and to B's
+                // first row for entries that are past the row's end or
+                // invalid; n > 0 whenever the row has an entry that can be
+                // valid) and its value is discarded afterwards where it does
+                // not count: a load under a condition with a default in the
+                // other branch makes the compiler wait for it before the
+                // next one is issued.
                 for (int32_t p0 = s + lane; p0 < e; p0 += AN_LOADS * AN_LANES) {
                     int jj[AN_LOADS];
     #pragma unroll
+                    for (int u = 0; u < AN_LOADS; ++u) jj[u] = aci[min(p0 + u * AN_LANES, e - 1)];
+    #pragma unroll
                     for (int u = 0; u < AN_LOADS; ++u) {
-                        const int32_t p = p0 + u * AN_LANES;
-                        jj[u] = p < e ? aci[p] : -1;
-                        if (p < e && (jj[u] < 0 || jj[u] >= n)) bad = ERR_A_COL, jj[u] = -1;
+                        const bool in_row = p0 + u * AN_LANES < e;
+                        if (in_row && (jj[u] < 0 || jj[u] >= n)) bad = ERR_A_COL;
+                        if (!in_row || jj[u] < 0 || jj[u] >= n) jj[u] = -1;
                         diag |= jj[u] == row;  // a stored diagonal entry (square A)
                     }
+                    if (n <= 0) continue;  // every entry is invalid: nothing to gather
                     int4 bb[AN_LOADS];
     #pragma unroll
-                    for (int u = 0; u < AN_LOADS; ++u) bb[u] = jj[u] >= 0 ? binfo[jj[u]] : make_int4(0, INT_MAX, -1, 0);
+                    for (int u = 0; u < AN_LOADS; ++u) bb[u] = binfo[max(jj[u], 0)];
     #pragma unroll
                     for (int u = 0; u < AN_LOADS; ++u) {
+                        if (jj[u] < 0) continue;
                         ub += bb[u].x;
                         rs += bb[u].w;
                         mx = max(mx, bb[u].x);
@@ -279,15 +290,28 @@ __global__ __launch_bounds__(256) void k_mlp_classify(int32_t m, const float* __
     if (threadIdx.x == 0 && wmax_glob) atomicMax((unsigned long long*)&ctl->max_words_sym_global, wmax_glob);
 }
 
-// Groups rows by class: a workgroup takes chunks of 2048 consecutive rows,
-// ranks each row inside its class with LDS atomics, reserves one range per
-// class and chunk with a single global atomic, and writes the row ids there,
-// with each row's descriptor {row, A start, A end, C start (or list offset)}
-// beside it.  For the symbolic rows it also places the rows' lists: a scan
-// of the chunk's capacities and one global atomic for the chunk's range.
+// Status word of a decoupled look-back: 2 flag bits over a 62-bit value.
+constexpr uint64_t ST_AGG = 1ull << 62;
+constexpr uint64_t ST_PRE = 2ull << 62;
+constexpr uint64_t ST_VAL = (1ull << 62) - 1;
+
+// Groups rows by class, each class in ascending row order up to the order
+// inside a chunk: a workgroup takes chunks of 2048 consecutive rows by
+// ticket, ranks each row inside its class with LDS atomics, and finds the
+// chunk's range in every class from the counts of the chunks before it (a
+// decoupled look-back per class over the chunks in ticket order), then
+// writes the row ids there, with each row's descriptor {row, A start, A end,
+// C start (or list offset)} beside it.  The order matters for speed: the
+// row kernels take their rows in this order, so rows that share B rows run
+// close together and, where row index and row size go together (R-MAT), the
+// longest rows start first.  For the symbolic rows it also places the rows'
+// lists: a scan of the chunk's capacities and one global atomic for the
+// chunk's range.  state: the ticket, then a status word per chunk and class
+// (scatter_state_bytes, all zero on entry).
 constexpr int SCATTER_ITEMS = 8;
+constexpr int SCATTER_CHUNK = 256 * SCATTER_ITEMS;
 __global__ __launch_bounds__(256) void k_scatter(int32_t m, const uint8_t* __restrict__ cls, int merge,
-                                                 const int32_t* __restrict__ hist, int32_t* __restrict__ cursor,
+                                                 const int32_t* __restrict__ hist, int32_t* __restrict__ state,
                                                  int32_t* __restrict__ perm, const int32_t* __restrict__ arp,
                                                  const int32_t* __restrict__ crp, int4* __restrict__ desc,
                                                  int32_t* __restrict__ lofs, Control* ctl, int64_t list_limit) {
@@ -297,6 +321,9 @@ __global__ __launch_bounds__(256) void k_scatter(int32_t m, const uint8_t* __res
     __shared__ int64_t wsum[4];
     __shared__ int64_t lbase;
     __shared__ uint8_t remap[NCLS];
+    __shared__ int32_t chunk_sh;
+    int32_t* ticket = state;
+    uint64_t* status = reinterpret_cast<uint64_t*>(state + 16);
     if (threadIdx.x == 0) {
         int32_t h[NCLS], merged[NCLS];
         for (int c = 0; c < NCLS; ++c) h[c] = hist[c];
@@ -312,15 +339,34 @@ __global__ __launch_bounds__(256) void k_scatter(int32_t m, const uint8_t* __res
             for (int c = 0; c < NCLS; ++c) off[c] = run, run += merged[c];
         }
     }
-    const int64_t chunk = 256 * SCATTER_ITEMS;
-    for (int64_t r0 = blockIdx.x * chunk; r0 < m; r0 += (int64_t)gridDim.x * chunk) {
+    const int64_t nchunks = ((int64_t)m + SCATTER_CHUNK - 1) / SCATTER_CHUNK;
+    for (;;) {
         if (threadIdx.x < NCLS) cnt[threadIdx.x] = 0;
+        if (threadIdx.x == 0) chunk_sh = atomicAdd(ticket, 1);
         __syncthreads();
+        const int64_t chunk = chunk_sh;
+        if (chunk >= nchunks) break;  // uniform
+        const int64_t r0 = chunk * SCATTER_CHUNK;
+        // the chunk's inputs first, as unconditional loads (a row past the end
+        // reads the last row's, unused; arp has m + 1 entries): a load under a
+        // condition would be waited for before the next one is issued
+        uint8_t raw[SCATTER_ITEMS];
+        int32_t lraw[SCATTER_ITEMS], a_lo[SCATTER_ITEMS], a_hi[SCATTER_ITEMS], cw[SCATTER_ITEMS];
+#pragma unroll
+        for (int t = 0; t < SCATTER_ITEMS; ++t) {
+            const int64_t row = r0 + t * 256 + threadIdx.x;
+            const int64_t rr = row < m ? row : m - 1;
+            raw[t] = cls[rr];
+            a_lo[t] = arp[rr];
+            a_hi[t] = arp[rr + 1];
+            lraw[t] = lofs ? lofs[rr] : 0;
+            cw[t] = crp ? crp[rr] : 0;
+        }
         int c[SCATTER_ITEMS], local[SCATTER_ITEMS];
 #pragma unroll
         for (int t = 0; t < SCATTER_ITEMS; ++t) {
             const int64_t row = r0 + t * 256 + threadIdx.x;
-            c[t] = row < m ? cls[row] : CLS_EMPTY;
+            c[t] = row < m ? raw[t] : CLS_EMPTY;
             if (c[t] != CLS_EMPTY) c[t] = remap[c[t]];
             local[t] = c[t] != CLS_EMPTY ? atomicAdd(&cnt[c[t]], 1) : 0;
         }
@@ -330,7 +376,7 @@ __global__ __launch_bounds__(256) void k_scatter(int32_t m, const uint8_t* __res
 #pragma unroll
         for (int t = 0; t < SCATTER_ITEMS; ++t) {
             cap[t] = 0;
-            if (lofs && c[t] != CLS_EMPTY && c[t] % NTIER != TIER_GLOBAL) cap[t] = lofs[r0 + t * 256 + threadIdx.x];
+            if (lofs && c[t] != CLS_EMPTY && c[t] % NTIER != TIER_GLOBAL) cap[t] = lraw[t];
             lsum += cap[t];
         }
         int64_t lex = 0;
@@ -354,7 +400,31 @@ __global__ __launch_bounds__(256) void k_scatter(int32_t m, const uint8_t* __res
                                               : 0;
         }
         __syncthreads();
-        if (threadIdx.x < NCLS && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
+        if (threadIdx.x < NCLS) {
+            // the chunk's start in class c: the counts of every chunk before it
+            // (chunks are taken in ticket order, so each one waited for is
+            // resident or finished and the wait ends)
+            const int c = threadIdx.x;
+            const uint64_t agg = (uint32_t)cnt[c];
+            uint64_t* mine = status + chunk * NCLS + c;
+            int64_t prefix = 0;
+            if (chunk == 0) {
+                __hip_atomic_store(mine, ST_PRE | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                __hip_atomic_store(mine, ST_AGG | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int64_t t = chunk - 1; t >= 0; --t) {
+                    uint64_t w;
+                    do {
+                        w = __hip_atomic_load(status + t * NCLS + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    } while ((w >> 62) == 0);
+                    prefix += (int64_t)(w & ST_VAL);
+                    if ((w >> 62) == 2) break;
+                }
+                __hip_atomic_store(mine, ST_PRE | (uint64_t)(prefix + (int64_t)agg), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+            base[c] = (int32_t)prefix;
+        }
         __syncthreads();
         int64_t lpos = lofs ? lbase + lex : 0;
 #pragma unroll
@@ -362,23 +432,18 @@ __global__ __launch_bounds__(256) void k_scatter(int32_t m, const uint8_t* __res
             if (c[t] == CLS_EMPTY) continue;
             const int32_t row = (int32_t)(r0 + t * 256 + threadIdx.x);
             const int32_t pos = off[c[t]] + base[c[t]] + local[t];
-            int32_t w = crp ? crp[row] : 0;
+            int32_t w = cw[t];
             if (lofs) {
                 w = cap[t] > 0 && lpos + cap[t] <= list_limit ? (int32_t)lpos : -1;
                 lofs[row] = w;
                 lpos += cap[t];
             }
             perm[pos] = row;
-            desc[pos] = make_int4(row, arp[row], arp[row + 1], w);
+            desc[pos] = make_int4(row, a_lo[t], a_hi[t], w);
         }
         __syncthreads();
     }
 }
-
-// Status word of the look-back scan: 2 flag bits over a 62-bit value.
-constexpr uint64_t ST_AGG = 1ull << 62;
-constexpr uint64_t ST_PRE = 2ull << 62;
-constexpr uint64_t ST_VAL = (1ull << 62) - 1;
 
 // Row pointer = exclusive prefix sum of row_nnz, in 64-bit, single pass with
 // decoupled look-back over tiles taken in launch order.  Also assigns each
@@ -408,6 +473,23 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(int32_t m, const int32_t*
     const int64_t r0 = (int64_t)tile * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
     int64_t v[SCAN_ITEMS];
     int64_t run = 0;
+    // every row's inputs first, as unconditional loads (a row past the end
+    // reads the last row's, unused; arp has m + 1 entries): a load under a
+    // condition would be waited for before the next one is issued
+    int32_t nz[SCAN_ITEMS], bl[SCAN_ITEMS], lo[SCAN_ITEMS], ap[SCAN_ITEMS + 1];
+    RowInfo rf[SCAN_ITEMS];
+    uint8_t sc[SCAN_ITEMS];
+#pragma unroll
+    for (int t = 0; t < SCAN_ITEMS; ++t) {
+        const int64_t rr = r0 + t < m ? r0 + t : m - 1;
+        nz[t] = row_nnz[rr];
+        rf[t] = rinfo[rr];
+        bl[t] = row_blocks[rr];
+        lo[t] = lofs[rr];
+        sc[t] = sym_cls[rr];
+    }
+#pragma unroll
+    for (int t = 0; t <= SCAN_ITEMS; ++t) ap[t] = arp[r0 + t < m ? r0 + t : m];
     // the thread's consecutive rows of one class are counted in registers and
     // added to the workgroup's counters once per run of equal classes
     int cur = CLS_EMPTY, n_cur = 0, miss = 0;
@@ -424,12 +506,12 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(int32_t m, const int32_t*
         int64_t r = r0 + t;
         int64_t c = 0;
         if (r < m) {
-            c = row_nnz[r];
-            RowInfo ri = rinfo[r];
-            int blocks = row_blocks[r];
+            c = nz[t];
+            const RowInfo ri = rf[t];
+            const int blocks = bl[t];
             int nc = num_class(ri.z, ri.x, ri.y, c, blocks, cfg);
             // a row kernel builds its table from the row's list: without one, the global path
-            if (nc != CLS_EMPTY && nc % NTIER != TIER_GLOBAL && lofs[r] < 0) nc = MODE_DIRECT * NTIER + TIER_GLOBAL;
+            if (nc != CLS_EMPTY && nc % NTIER != TIER_GLOBAL && lo[t] < 0) nc = MODE_DIRECT * NTIER + TIER_GLOBAL;
             num_cls[r] = (uint8_t)nc;
             if (nc != CLS_EMPTY) {
                 if (nc != cur) {
@@ -437,12 +519,12 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(int32_t m, const int32_t*
                     cur = nc, n_cur = 0, a_cur = c_cur = p_cur = 0;
                 }
                 n_cur += 1;
-                a_cur += (unsigned long long)(arp[r + 1] - arp[r]);
+                a_cur += (unsigned long long)(ap[t + 1] - ap[t]);
                 c_cur += (unsigned long long)c;
                 p_cur += (unsigned long long)ri.z;
                 if (nc % NTIER == TIER_GLOBAL) atomicMax(&wmax_glob, (unsigned long long)row_words(ri.x, ri.y));
                 // the class the exact size asks for, under the same sizing rule as the estimate's
-                miss += sym_class(ri.z, ri.x, ri.y, blocks, cfg, cfg.bound_est != 0) != sym_cls[r];
+                miss += sym_class(ri.z, ri.x, ri.y, blocks, cfg, cfg.bound_est != 0) != sc[t];
             }
         }
         run += c;
@@ -601,12 +683,15 @@ __global__ __launch_bounds__(256) void k_b_rows(int32_t n, int32_t k, const int3
         int last_blk = -1;     // block of the last chunk's final entry
         // four chunks' entries (and the entry after each chunk) are loaded at once
         for (int32_t Q0 = s; !bad && Q0 < e; Q0 += 4 * L) {
+            // unconditional loads, indices clamped into the row (a load under
+            // a condition would be waited for before the next one is issued);
+            // entries past the row's end are not used
             int cc[4], nx[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int32_t q = Q0 + u * L + sl;
-                cc[u] = q < e ? bci[q] : 0;
-                nx[u] = sl == L - 1 && q + 1 < e ? bci[q + 1] : 0;
+                cc[u] = bci[min(q, e - 1)];
+                nx[u] = bci[min(q + 1, e - 1)];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -727,12 +812,17 @@ void launch_mlp_classify(hipStream_t s, int32_t m, const float* feats, const flo
                        sym_cls, ctl);
 }
 
-void launch_scatter(hipStream_t s, int32_t m, const uint8_t* cls, int merge, const int32_t* hist, int32_t* cursor,
+size_t scatter_state_bytes(int32_t m) {
+    return 64 + (size_t)(((int64_t)std::max(m, 0) + SCATTER_CHUNK - 1) / SCATTER_CHUNK) * NCLS * 8;
+}
+
+void launch_scatter(hipStream_t s, int32_t m, const uint8_t* cls, int merge, const int32_t* hist, int32_t* state,
                     int32_t* perm, const int32_t* arp, const int32_t* crp, int4* desc, int32_t* lofs, Control* ctl,
                     int64_t list_limit) {
     if (m <= 0) return;
-    hipLaunchKernelGGL(k_scatter, dim3(std::min(grid_for(m, 256 * SCATTER_ITEMS), 1024u)), dim3(256), 0, s, m, cls,
-                       merge, hist, cursor, perm, arp, crp, desc, lofs, ctl, list_limit);
+    launch_fill_u8(s, state, 0, (int64_t)scatter_state_bytes(m));
+    hipLaunchKernelGGL(k_scatter, dim3(std::min(grid_for(m, SCATTER_CHUNK), 1024u)), dim3(256), 0, s, m, cls, merge,
+                       hist, state, perm, arp, crp, desc, lofs, ctl, list_limit);
 }
 
 void launch_scan(hipStream_t s, int32_t m, const int32_t* row_nnz, const int32_t* row_blocks, const RowInfo* rinfo,
