@@ -1094,6 +1094,11 @@ void k_num(NumArgs a) {
     Win* winb = reinterpret_cast<Win*>(row_lds + bytes + G * 16);     // B group windows
     // direct: {mask, prefix} per word.  two-level: l1 {bits, first list index}
     // per 32 blocks, then {mask, prefix} per occupied block.  hashed: slots.
+    // Indices and prefixes are kept as LDS byte offsets from the start of the
+    // dynamic LDS (the l1 index as the offset of its first {mask, prefix}
+    // entry, a prefix as the offset of its value), so that a lookup is one
+    // shift-and-add per level with the base folded into the LDS access.
+    uint8_t* const lds0 = reinterpret_cast<uint8_t*>(smem);
     uint2* dw = reinterpret_cast<uint2*>(tab);
     uint2* l1 = reinterpret_cast<uint2*>(tab);
     uint2* cm = l1 + w1;
@@ -1109,6 +1114,8 @@ void k_num(NumArgs a) {
         logT = 31 - __clz(TT);
         vals = reinterpret_cast<T*>(tab + (int64_t)TT * 16);
     }
+    const uint32_t vals_off = (uint32_t)(reinterpret_cast<uint8_t*>(vals) - lds0);
+    const uint32_t cm_off = (uint32_t)(reinterpret_cast<uint8_t*>(cm) - lds0);
     if constexpr (MODE == MODE_DIRECT) {
         // pairs of words per 16-byte store; an odd last word spills 8 bytes into vals, cleared below
         for (int c = 2 * lane; c < words; c += 2 * G) *reinterpret_cast<uint4*>(&dw[c]) = make_uint4(0, 0, 0, 0);
@@ -1189,17 +1196,18 @@ void k_num(NumArgs a) {
             if (t < nb) {
                 const int b = e.x;
                 uint32_t mk = (uint32_t)e.y;
+                const uint32_t vo = vals_off + (uint32_t)(ex * (int)sizeof(T));
                 if constexpr (MODE == MODE_DIRECT) {
-                    dw[b - base] = make_uint2(mk, (uint32_t)ex);
+                    dw[b - base] = make_uint2(mk, vo);
                 } else if constexpr (MODE == MODE_TWOLEVEL) {
-                    cm[t] = make_uint2(mk, (uint32_t)ex);
+                    cm[t] = make_uint2(mk, vo);
                     const int w = b - base;
                     atomicOr(&l1[w >> 5].x, 1u << (w & 31));
-                    atomicMin(&l1[w >> 5].y, (uint32_t)t);
+                    atomicMin(&l1[w >> 5].y, cm_off + 8u * (uint32_t)t);
                 } else {
                     const int h = slot_insert(slots, TT, logT, b);
                     slots[h].y = (int)mk;
-                    slots[h].z = ex;
+                    slots[h].z = (int)vo;
                 }
                 int r = ex;
                 while (mk) {
@@ -1210,15 +1218,17 @@ void k_num(NumArgs a) {
         }
         group_sync<G>();
     };
-    auto rank_of = [&](int c) {
+    // the value slot of column c of the row (in its table)
+    auto val_at = [&](int c) {
+        uint32_t vo;
         if constexpr (MODE == MODE_DIRECT) {
             const uint2 mp = dw[(c >> 5) - base];
-            return (int)mp.y + __popc(mp.x & below(c & 31));
+            vo = mp.y + (uint32_t)sizeof(T) * __popc(mp.x & below(c & 31));
         } else if constexpr (MODE == MODE_TWOLEVEL) {
             const int w = (c >> 5) - base;
             const uint2 L = l1[w >> 5];
-            const uint2 mp = cm[(int)L.y + __popc(L.x & below(w & 31))];
-            return (int)mp.y + __popc(mp.x & below(c & 31));
+            const uint2 mp = *reinterpret_cast<const uint2*>(lds0 + L.y + 8u * __popc(L.x & below(w & 31)));
+            vo = mp.y + (uint32_t)sizeof(T) * __popc(mp.x & below(c & 31));
         } else {
             const int key = c >> 5;
             int h = hash_slot(key, logT);
@@ -1227,19 +1237,20 @@ void k_num(NumArgs a) {
                 h = (h + 1) & (TT - 1);
                 sl = slots[h];
             }
-            return sl.z + __popc((uint32_t)sl.y & below(c & 31));
+            vo = (uint32_t)sl.z + (uint32_t)sizeof(T) * __popc((uint32_t)sl.y & below(c & 31));
         }
+        return reinterpret_cast<T*>(lds0 + vo);
     };
-    // a group's ranks are looked up together (elements past the group's end
+    // a group's slots are looked up together (elements past the group's end
     // repeat its first column), then its valid products are added
     auto add = [&](const BGroup<T>& g, int e) {
         const T x = ava[e];
-        int rk[4];
+        T* pv[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) rk[j] = rank_of(j < g.n ? g.c[j] : g.c[0]);
+        for (int j = 0; j < 4; ++j) pv[j] = val_at(j < g.n ? g.c[j] : g.c[0]);
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            if (j < g.n) atomicAdd(&vals[rk[j]], x * g.y[j]);
+            if (j < g.n) atomicAdd(pv[j], x * g.y[j]);
     };
 
     stage(a0, h0, v0);
@@ -1268,7 +1279,7 @@ void k_num(NumArgs a) {
         const T sc = -(T)a.omega * reinterpret_cast<const T*>(a.dinv)[i];
         for (int r = lane; r < n; r += G) vals[r] *= sc;
         group_sync<G>();
-        for (int q = a.brp[i] + lane; q < a.brp[i + 1]; q += G) atomicAdd(&vals[rank_of(a.bci[q])], bv[q]);
+        for (int q = a.brp[i] + lane; q < a.brp[i + 1]; q += G) atomicAdd(val_at(a.bci[q]), bv[q]);
     }
     group_sync<G>();
     T* cv = reinterpret_cast<T*>(a.cval) + off;

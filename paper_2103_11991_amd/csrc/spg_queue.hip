@@ -129,9 +129,26 @@ __device__ inline uint32_t or_runs(uint32_t v, int key, int lane, bool full) {
     return (lane == RG - 1 || next != key) ? v : 0u;
 }
 
+// Products per lane whose loads are issued together in the walks below.
+constexpr int QU = 2;
+
+// The entry of the staged chunk that holds flattened product q (pre: the
+// exclusive prefix of the entries' B row lengths, cnt entries).
+__device__ inline int entry_of(const int* pre, int cnt, int q) {
+    int lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= q) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // ORs the row's columns into bm (cleared by the caller) and, in the numeric
 // phase, adds its products at their ranks.  Lanes walk the flattened
-// products of chunks of RG A entries.
+// products of chunks of RG A entries, QU slices of RG products at a time:
+// every lane's QU loads go out together (a lane past the end loads the last
+// product again and drops it), which keeps them from waiting on each other.
 template <typename T, bool NUM>
 __device__ inline void row_walk(const QueueArgs& a, int64_t r, int base, const Win_<T>& w) {
     const int lane = threadIdx.x & (RG - 1);
@@ -139,39 +156,51 @@ __device__ inline void row_walk(const QueueArgs& a, int64_t r, int base, const W
     const T* av = reinterpret_cast<const T*>(a.av);
     const T* bv = reinterpret_cast<const T*>(a.bv);
     for (int e0 = a0; e0 < a1; e0 += RG) {
-        int len = 0, s0 = 0;
+        // the chunk's entries: unconditional loads (index clamped into the row)
+        const bool in_row = e0 + lane < a1;
+        const int e = min(e0 + lane, a1 - 1);
+        const int j = a.aci[e];
         T x = T(0);
-        if (e0 + lane < a1) {
-            const int j = a.aci[e0 + lane];
-            s0 = a.brp[j];
-            len = a.brp[j + 1] - s0;
-            if (NUM) x = av[e0 + lane];
-        }
+        if (NUM) x = av[e];
+        const int s0 = a.brp[j];
+        const int len = in_row ? a.brp[j + 1] - s0 : 0;
         const int incl = wscan_incl(len);
         const int total = __shfl(incl, RG - 1, RG);
         const int cnt = min(RG, a1 - e0);
         w.pre[lane] = incl - len, w.st[lane] = s0;
         if (NUM) w.av[lane] = x;
         qwave_sync();
-        for (int q = lane; q < total; q += RG) {
-            int lo = 0, hi = cnt - 1;  // the entry holding product q
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (w.pre[mid] <= q) lo = mid;
-                else hi = mid - 1;
+        for (int Q = 0; Q < total; Q += QU * RG) {
+            int lo[QU], bb[QU], cc[QU];
+            T yy[QU];
+#pragma unroll
+            for (int u = 0; u < QU; ++u) {
+                const int q = min(Q + u * RG + lane, total - 1);
+                lo[u] = entry_of(w.pre, cnt, q);
+                bb[u] = w.st[lo[u]] + (q - w.pre[lo[u]]);
             }
-            const int b = w.st[lo] + (q - w.pre[lo]);
-            const int c = a.bci[b];
-            const int wd = (c >> 5) - base;
-            if constexpr (!NUM) {
-                // neighbouring lanes mostly share a word (a B row's columns
-                // are close): OR the bits of each run of lanes on one word
-                // together, and only the run's last lane writes LDS
-                const uint32_t bits = or_runs(1u << (c & 31), q < total ? wd : -1, lane, q + RG - lane <= total);
-                if (bits) atomicOr(&w.bm[wd], bits);
-            } else {
-                const int rank = w.pf[wd] + __popc(w.bm[wd] & ((1u << (c & 31)) - 1u));
-                atomicAdd(&w.vals[rank], w.av[lo] * bv[b]);
+#pragma unroll
+            for (int u = 0; u < QU; ++u) {
+                cc[u] = a.bci[bb[u]];
+                if (NUM) yy[u] = bv[bb[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < QU; ++u) {
+                const int qs = Q + u * RG;  // the slice's first product (uniform in the group)
+                if (qs >= total) break;
+                const bool ok = qs + lane < total;
+                const int c = cc[u];
+                const int wd = (c >> 5) - base;
+                if constexpr (!NUM) {
+                    // neighbouring lanes mostly share a word (a B row's columns
+                    // are close): OR the bits of each run of lanes on one word
+                    // together, and only the run's last lane writes LDS
+                    const uint32_t bits = or_runs(1u << (c & 31), ok ? wd : -1, lane, qs + RG <= total);
+                    if (ok && bits) atomicOr(&w.bm[wd], bits);
+                } else if (ok) {
+                    const int rank = w.pf[wd] + __popc(w.bm[wd] & ((1u << (c & 31)) - 1u));
+                    atomicAdd(&w.vals[rank], w.av[lo[u]] * yy[u]);
+                }
             }
         }
         qwave_sync();
@@ -180,33 +209,37 @@ __device__ inline void row_walk(const QueueArgs& a, int64_t r, int base, const W
 
 // The row's compressed-B runs {block, mask} OR-ed into bm (cleared by the
 // caller): the symbolic phase's walk, over a B row's runs instead of its
-// entries (section 2.2.1, compressed B).
+// entries (section 2.2.1, compressed B), with the loads issued as above.
 template <typename T>
 __device__ inline void row_walk_runs(const QueueArgs& a, int64_t r, int base, const Win_<T>& w) {
     const int lane = threadIdx.x & (RG - 1);
     const int a0 = a.arp[r], a1 = a.arp[r + 1];
     for (int e0 = a0; e0 < a1; e0 += RG) {
-        int len = 0, s0 = 0;
-        if (e0 + lane < a1) {
-            const int4 h = a.bhdr[a.aci[e0 + lane]];
-            s0 = h.z, len = h.w;
-        }
+        const bool in_row = e0 + lane < a1;
+        const int4 h = a.bhdr[a.aci[min(e0 + lane, a1 - 1)]];
+        const int s0 = h.z, len = in_row ? h.w : 0;
         const int incl = wscan_incl(len);
         const int total = __shfl(incl, RG - 1, RG);
         const int cnt = min(RG, a1 - e0);
         w.pre[lane] = incl - len, w.st[lane] = s0;
         qwave_sync();
-        for (int q = lane; q < total; q += RG) {
-            int lo = 0, hi = cnt - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (w.pre[mid] <= q) lo = mid;
-                else hi = mid - 1;
+        for (int Q = 0; Q < total; Q += QU * RG) {
+            int2 run[QU];
+#pragma unroll
+            for (int u = 0; u < QU; ++u) {
+                const int q = min(Q + u * RG + lane, total - 1);
+                const int lo = entry_of(w.pre, cnt, q);
+                run[u] = a.bc[w.st[lo] + (q - w.pre[lo])];
             }
-            const int2 run = a.bc[w.st[lo] + (q - w.pre[lo])];
-            const int wd = run.x - base;
-            const uint32_t bits = or_runs((uint32_t)run.y, wd, lane, q + RG - lane <= total);
-            if (bits) atomicOr(&w.bm[wd], bits);
+#pragma unroll
+            for (int u = 0; u < QU; ++u) {
+                const int qs = Q + u * RG;
+                if (qs >= total) break;
+                const bool ok = qs + lane < total;
+                const int wd = run[u].x - base;
+                const uint32_t bits = or_runs((uint32_t)run[u].y, ok ? wd : -1, lane, qs + RG <= total);
+                if (ok && bits) atomicOr(&w.bm[wd], bits);
+            }
         }
         qwave_sync();
     }
