@@ -1595,7 +1595,7 @@ spg_status spg_batch_run_queued(spg_batch b, const void* a_val_pool, const void*
             a.row_off = b->q_row_off.as<int64_t>();
             a.crp_off = b->q_crp_off.as<int64_t>();
             a.arp = b->arp.as<int32_t>(), a.aci = b->aci.as<int32_t>(), a.av = a_val_pool;
-            a.brp = b->brp.as<int32_t>(), a.bci = b->bci_pool, a.bv = b_val_pool;
+            a.brp = b->brp.as<int32_t>(), a.bci = b->bci_pool, a.bv = b_val_pool, a.bnnz = b->bnnz_total;
             a.rinfo = h->rinfo.as<RowInfo>();
             a.row_nnz = h->row_nnz.as<int32_t>();
             a.c_row_ptr = c_row_ptr, a.ccol = c_col, a.cval = c_val, a.cap = capacity;

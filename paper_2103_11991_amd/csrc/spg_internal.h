@@ -483,6 +483,7 @@ struct QueueArgs {
                                 // items for the numeric ones, or null (numeric ORs B again)
     const int2* bc;             // compressed B runs {block, mask} (symbolic), or null (entries)
     const int4* bhdr;           // per B row {start, length, run start, run count}
+    int64_t bnnz;               // entries of B's pools
 };
 constexpr int QUEUE_MAX_WORDS = 128;  // widest row range the queued kernel holds (4096 columns)
 size_t queue_lds_bytes(int wmax, int vmax, int elem_bytes);
