@@ -109,10 +109,10 @@ typedef enum {
        rows by the class they ran in. */
     SPG_OPT_MERGE_CLASSES = 10,
     /* numeric rows of the global-memory path run tiled (1 = default): B's
-       columns are cut into tiles of 32 KB of values (8192 FP32 or 4096 FP64
-       columns), each (row, tile) pair sums its products in a dense window,
-       so each product is visited once.  Applies when C has at most 64 tiles
-       of columns; rows without a block list, and all rows when some B row's
+       columns are cut into tiles of 4096 columns, each (row, tile) pair sums
+       its products in a dense FP64 window (32 KB), so each product is
+       visited once.  Applies when C has at most 128 tiles of columns; rows
+       without a block list, and all rows when some B row's
        entries are not grouped by tile (rows in ascending column order always
        are), take the segment path (0 = always the segment path: the row's
        values summed one LDS segment of its ranks at a time) */

@@ -1547,11 +1547,16 @@ __global__ __launch_bounds__(256) void k_tile_items(TileArgs a) {
 template <typename T>
 __global__ __launch_bounds__(TILE_G) void k_num_tiled(TileArgs a) {
     constexpr int G = TILE_G;
-    constexpr int W = TILE_BYTES / (int)sizeof(T);  // columns per tile
+    // The window sums in FP64 whatever T is: LDS atomic adds of FP32 values
+    // ran at half the rate of FP64 ones here (R-MAT scale 18, FP32: 21.3 ms
+    // with an FP32 window of 8192 columns, 15.0 with this one of 4096), and
+    // the FP64 sum is the closer one to the exact result.
+    using D = double;
+    constexpr int W = TILE_BYTES / (int)sizeof(D);  // columns per tile
     constexpr int NB = W / 32;                       // blocks per tile
     constexpr int K = sizeof(T) == 8 ? FLAT_KB_F64 : FLAT_KB_F32;
     static_assert(NB <= G, "a tile's list pairs must fit one per lane");
-    __shared__ T dense[W];
+    __shared__ D dense[W];
     __shared__ int2 off[G];
     __shared__ T ava[G];
     __shared__ Win win[K * (G / 64)];
@@ -1567,7 +1572,7 @@ __global__ __launch_bounds__(TILE_G) void k_num_tiled(TileArgs a) {
     // The dense window is zero between tiles: cleared once here, and every
     // entry a tile writes (its products and, fused, B(i,:) all fall on C's
     // columns) is read once and set back to zero as the tile goes out.
-    for (int c = tid; c < W; c += G) dense[c] = T(0);
+    for (int c = tid; c < W; c += G) dense[c] = D(0);
     __syncthreads();
     // a tile's table before the walk: window table cleared, its list pairs
     // loaded (pr, scanned after the walk)
@@ -1581,10 +1586,10 @@ __global__ __launch_bounds__(TILE_G) void k_num_tiled(TileArgs a) {
     auto jacobi_tile = [&](int i, int t, int col0) {
         if (!a.dinv) return;
         const T sc = -(T)a.omega * reinterpret_cast<const T*>(a.dinv)[i];
-        for (int c = tid; c < W; c += G) dense[c] *= sc;
+        for (int c = tid; c < W; c += G) dense[c] *= (D)sc;
         __syncthreads();
         const int* tr = a.toff + (int64_t)i * (T_ + 1);
-        for (int q = tr[t] + tid; q < tr[t + 1]; q += G) atomicAdd(&dense[a.bci[q] - col0], bv[q]);
+        for (int q = tr[t] + tid; q < tr[t + 1]; q += G) atomicAdd(&dense[a.bci[q] - col0], (D)bv[q]);
         __syncthreads();
     };
     // after the walk: the tile's columns in rank order, then columns and
@@ -1611,8 +1616,8 @@ __global__ __launch_bounds__(TILE_G) void k_num_tiled(TileArgs a) {
             for (int q = q0 + tid; q < q1; q += G) {
                 const int cl = cbuf[q - q0];
                 a.ccol[coff + q] = col0 + cl;
-                cvals[coff + q] = dense[cl];
-                dense[cl] = T(0);
+                cvals[coff + q] = (T)dense[cl];
+                dense[cl] = D(0);
             }
             __syncthreads();
         }
@@ -1635,7 +1640,7 @@ __global__ __launch_bounds__(TILE_G) void k_num_tiled(TileArgs a) {
                 const T x = ava[e];
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    if (j < g.n) atomicAdd(&dense[g.c[j] - col0], x * g.y[j]);
+                    if (j < g.n) atomicAdd(&dense[g.c[j] - col0], (D)x * (D)g.y[j]);
             };
             const int* to = a.toff + t;
             auto hdr = [&](int j) {
@@ -1683,7 +1688,7 @@ __global__ __launch_bounds__(TILE_G) void k_num_tiled(TileArgs a) {
                     const T x = ava[e];
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
-                        if (j < g.n) atomicAdd(&dense[g.c[j] - col0], x * g.y[j]);
+                        if (j < g.n) atomicAdd(&dense[g.c[j] - col0], (D)x * (D)g.y[j]);
                 };
                 group_sync<G>();
                 walk_chunk<G, K, FLAT_VB, false, T>(h, v, off, ava, win, red, load_cv, add);

@@ -381,12 +381,12 @@ struct NumArgs {
 };
 
 // Tiled global path of the numeric phase (spg_accum.hip).  B's columns are
-// cut into tiles of TILE_BYTES / (element size) columns; a work item is one
-// (row, tile) pair of a long row.
+// cut into tiles of TILE_BYTES / 8 columns (the window sums in FP64 for
+// either value type); a work item is one (row, tile) pair of a long row.
 constexpr int TILE_BYTES = 32768;  // dense LDS window of one item
 constexpr int TILE_G = 256;        // lanes per row
-constexpr int TILE_MAX = 64;       // most tiles a matrix may have for this path
-__host__ __device__ inline int tile_cols(int elem_bytes) { return TILE_BYTES / elem_bytes; }
+constexpr int TILE_MAX = 128;      // most tiles a matrix may have for this path
+__host__ __device__ inline int tile_cols(int /*elem_bytes*/) { return TILE_BYTES / 8; }
 
 struct TileArgs {
     int32_t n;                    // rows of B

@@ -27,7 +27,7 @@ def test_long_rows_tiled_and_segment_paths(dtype, tiled):
     rp, c, v, op = run_gpu(A, B, tiled_global=tiled)
     st = op.stats()
     assert st["num_rows"][9] > 0
-    w = 32768 // np.dtype(dtype).itemsize
+    w = 4096  # tiles of 4096 columns (an FP64 window) for either dtype
     assert st["num_tiles"] == (-(-60000 // w) if tiled else 0)
     assert st["tile_fallback_rows"] == 0
     compare(A, B, rp, c, v)
@@ -99,9 +99,9 @@ def test_rows_without_lists_fall_back_and_numeric_reuse():
 
 
 def test_too_many_tiles_keeps_the_segment_path():
-    """FP64 with more than 64 tiles of 4096 columns: the segment path."""
+    """More than 128 tiles of 4096 columns: the segment path."""
     A = gen.random_csr(12, 600, 300, 400, seed=61)
-    B = gen.random_csr(600, 64 * 4096 + 1, 300, 500, seed=62)
+    B = gen.random_csr(600, 128 * 4096 + 1, 300, 500, seed=62)
     rp, c, v, op = run_gpu(A, B)
     st = op.stats()
     assert st["num_rows"][9] > 0 and st["num_tiles"] == 0
