@@ -534,14 +534,18 @@ __device__ inline auto each(F& f) {
 // One staged chunk of the walk: the lane's entry (if `has`) covers the piece
 // {first, length} = h of a B row with A value v.  The caller has cleared the
 // window table and synchronised the group.
+// extra: a value of the caller's scanned in the same pass, its exclusive
+// prefix and total returned in *extra_scan.
 template <int G, int K, int V, bool RUNS, typename T, typename Load, typename Apply>
-__device__ inline void walk_chunk(int2 h, T v, int2* off, T* ava, Win* win, int* red, Load& load, Apply&& apply) {
+__device__ inline void walk_chunk(int2 h, T v, int2* off, T* ava, Win* win, int* red, Load& load, Apply&& apply,
+                                  int extra = 0, int2* extra_scan = nullptr) {
     const int lane = threadIdx.x % G, wv = lane >> 6;
     const unsigned long long le = (2ull << (lane & 63)) - 1;
     const int start = h.x, len = h.y;
     const bool ne = len > 0;
     int3 tot;
-    const int3 ex = group_excl_scan3<G>(make_int3(ne, (len + V - 1) / V, 0), tot, red);
+    const int3 ex = group_excl_scan3<G>(make_int3(ne, (len + V - 1) / V, extra), tot, red);
+    if (extra_scan) *extra_scan = make_int2(ex.z, tot.z);
     const int P = tot.y;
     if (ne) {
         off[ex.x] = make_int2(start - V * ex.y, start + len);
@@ -1597,11 +1601,11 @@ __global__ __launch_bounds__(TILE_G) void k_num_tiled(TileArgs a) {
     // G) and places its columns at their ranks (its exclusive prefix of
     // popcounts on): chunk by chunk of 2G ranks into the staging area, which
     // the walk no longer needs, and each chunk is then written out.
-    auto end_tile = [&](int i, int col0, int4 d, int np, int2 pr) {
+    // pos: the lane's pair's first rank (the exclusive prefix of the pairs'
+    // popcounts), n_t: the tile's columns
+    auto place_tile = [&](int i, int col0, int4 d, int np, int2 pr, int pos, int n_t) {
         constexpr int CH = 2 * G;
         int* cbuf = reinterpret_cast<int*>(off);
-        int n_t;
-        int pos = group_excl_scan<G>(tid < np ? __popc((uint32_t)pr.y) : 0, n_t, red);
         uint32_t rest = tid < np ? (uint32_t)pr.y : 0u;  // the pair's columns not yet placed
         const int first = tid < np ? (pr.x << 5) - col0 : 0;
         const int64_t coff = (int64_t)a.crp[i] + d.w;
@@ -1621,6 +1625,11 @@ __global__ __launch_bounds__(TILE_G) void k_num_tiled(TileArgs a) {
             }
             __syncthreads();
         }
+    };
+    auto end_tile = [&](int i, int col0, int4 d, int np, int2 pr) {
+        int n_t;
+        const int pos = group_excl_scan<G>(tid < np ? __popc((uint32_t)pr.y) : 0, n_t, red);
+        place_tile(i, col0, d, np, pr, pos, n_t);
     };
     for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
         if (u < (int64_t)nh * T_) {
@@ -1670,8 +1679,19 @@ __global__ __launch_bounds__(TILE_G) void k_num_tiled(TileArgs a) {
             s_nxt = tj[1];
             if (T_ > 1) s_nn = tj[2];
         }
+        // items are fetched two tiles ahead and list pairs one tile ahead
+        // (every lane loads: a lane past the tile's pairs reloads its last);
+        // the pairs' rank prefix is scanned with the walk's staging
+        auto pairs_of = [&](int4 it) {
+            const int q0 = __builtin_amdgcn_readfirstlane(it.y);
+            const int nq = __builtin_amdgcn_readfirstlane(it.z) - q0;
+            return nq > 0 ? a.lists[q0 + min(tid, nq - 1)] : make_int2(0, 0);
+        };
+        int4 dn = T_ > 1 ? a.items[(int64_t)R + r] : make_int4(0, 0, 0, 0);
+        int2 pr = pairs_of(d);
         for (int t = 0; t < T_; ++t) {
-            const int4 dn = t + 1 < T_ ? a.items[(int64_t)(t + 1) * R + r] : make_int4(0, 0, 0, 0);
+            const int4 dnn = t + 2 < T_ ? a.items[(int64_t)(t + 2) * R + r] : make_int4(0, 0, 0, 0);
+            const int2 pr_next = t + 1 < T_ ? pairs_of(dn) : make_int2(0, 0);
             const int p0 = __builtin_amdgcn_readfirstlane(d.y);
             const int np = __builtin_amdgcn_readfirstlane(d.z) - p0;
             const int2 h = make_int2(s_cur, s_nxt - s_cur);
@@ -1682,8 +1702,7 @@ __global__ __launch_bounds__(TILE_G) void k_num_tiled(TileArgs a) {
             }
             if (np > 0) {
                 const int col0 = t * W;
-                int2 pr;
-                begin_tile(p0, np, pr);
+                win_clear<G, K>(win, tid);
                 auto add = [&](const BGroup<T>& g, int e) {
                     const T x = ava[e];
 #pragma unroll
@@ -1691,12 +1710,16 @@ __global__ __launch_bounds__(TILE_G) void k_num_tiled(TileArgs a) {
                         if (j < g.n) atomicAdd(&dense[g.c[j] - col0], (D)x * (D)g.y[j]);
                 };
                 group_sync<G>();
-                walk_chunk<G, K, FLAT_VB, false, T>(h, v, off, ava, win, red, load_cv, add);
+                int2 sc;
+                walk_chunk<G, K, FLAT_VB, false, T>(h, v, off, ava, win, red, load_cv, add,
+                                                    tid < np ? __popc((uint32_t)pr.y) : 0, &sc);
                 group_sync<G>();
                 jacobi_tile(i, t, col0);
-                end_tile(i, col0, d, np, pr);
+                place_tile(i, col0, d, np, pr, sc.x, sc.y);
             }
             d = dn;
+            dn = dnn;
+            pr = pr_next;
         }
     }
 }
