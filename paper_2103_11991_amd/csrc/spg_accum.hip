@@ -295,6 +295,19 @@ __device__ inline void win_scan(Win* wa, Win* wb, int before_a, int before_b, in
     constexpr int W = waves_of<G>();
     constexpr int NA = KA * W, NB = KB * W;
     constexpr int CA = (NA + G - 1) / G, CB = (NB + G - 1) / G;
+    if constexpr (G > 64 && NA + NB <= 64) {
+        // every window entry fits one wavefront: the group's first wavefront
+        // scans them (no workgroup barrier; the caller synchronises after)
+        if (threadIdx.x < 64) {
+            int v = 0;
+            if (lane < NA) v = __popcll(wa[lane].mask);
+            else if (lane < NA + NB) v = __popcll(wb[lane - NA].mask) << 16;
+            const int ex = wave_incl_scan<64>(v) - v;
+            if (lane < NA) wa[lane].cum = before_a + (ex & 0xffff);
+            else if (lane < NA + NB) wb[lane - NA].cum = before_b + (ex >> 16);
+        }
+        return;
+    }
     int local = 0;
 #pragma unroll
     for (int t = 0; t < CA; ++t)
