@@ -295,16 +295,23 @@ __device__ inline void win_scan(Win* wa, Win* wb, int before_a, int before_b, in
     constexpr int W = waves_of<G>();
     constexpr int NA = KA * W, NB = KB * W;
     constexpr int CA = (NA + G - 1) / G, CB = (NB + G - 1) / G;
-    if constexpr (G > 64 && NA + NB <= 64) {
-        // every window entry fits one wavefront: the group's first wavefront
-        // scans them (no workgroup barrier; the caller synchronises after)
+    if constexpr (G > 64 && NB == 0 && NA <= 256) {
+        // a few window entries per lane of one wavefront: the group's first
+        // wavefront scans them (no workgroup barrier; the caller synchronises
+        // after)
+        constexpr int C1 = (NA + 63) / 64;
         if (threadIdx.x < 64) {
-            int v = 0;
-            if (lane < NA) v = __popcll(wa[lane].mask);
-            else if (lane < NA + NB) v = __popcll(wb[lane - NA].mask) << 16;
-            const int ex = wave_incl_scan<64>(v) - v;
-            if (lane < NA) wa[lane].cum = before_a + (ex & 0xffff);
-            else if (lane < NA + NB) wb[lane - NA].cum = before_b + (ex >> 16);
+            int local = 0;
+#pragma unroll
+            for (int t = 0; t < C1; ++t)
+                if (lane * C1 + t < NA) local += __popcll(wa[lane * C1 + t].mask);
+            int ca = before_a + wave_incl_scan<64>(local) - local;
+#pragma unroll
+            for (int t = 0; t < C1; ++t)
+                if (lane * C1 + t < NA) {
+                    wa[lane * C1 + t].cum = ca;
+                    ca += __popcll(wa[lane * C1 + t].mask);
+                }
         }
         return;
     }
