@@ -26,13 +26,14 @@
 // writer has waited for its data stores to complete.
 //
 // A row is one group of RG = 32 lanes (two rows per wavefront): a bitmap of the
-// row's column range in LDS (each
-// product's B columns are OR-ed in, lanes over the flattened (A entry, B
-// entry) products), its popcount for the symbolic phase; in the numeric phase
-// the bitmap's prefix of popcounts gives every column its rank, products are
-// added at their ranks in an LDS value array, and the row leaves sorted.  The
-// LDS window of a group is sized for the batch's widest row (at most 128
-// words, 4096 columns).
+// row's column range in LDS (each product's B columns, or its compressed-B
+// runs, are OR-ed in, lanes over the flattened (A entry, B entry) products),
+// its popcount for the symbolic phase; in the numeric phase the bitmap's
+// prefix of popcounts gives every column its rank, products are added at
+// their ranks in an LDS value array (lanes over groups of four consecutive
+// entries of each B row), and the row leaves sorted.  The LDS window of a
+// group is sized for the batch's widest row (at most 128 words, 4096
+// columns).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
